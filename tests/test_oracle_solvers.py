@@ -1,0 +1,166 @@
+"""Pins of the oracle's Chebyshev, Arnoldi, transfers, V-cycle and Krylov solvers (CPU only).
+
+Sec. 2.2 (Krylov), 2.2.2 (Algorithm 1), 2.2.3 (Algorithm 2, Arnoldi bounds).
+"""
+import numpy as np
+import pytest
+
+from oracle import cheby, gll, mg
+from oracle.hierarchy import Solver
+from oracle.mesh import Numbering, level_coordinates
+from oracle.operator import dense_free_system
+from paper_2110_07663_amd import workloads as wl
+
+
+def chebT(n, x):
+    return np.cosh(n * np.arccosh(x)) if x >= 1 else np.cos(n * np.arccos(x)) if abs(x) <= 1 \
+        else (-1) ** n * np.cosh(n * np.arccosh(-x))
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_chebyshev_error_polynomial_closed_form(K):
+    """With S = I and A = diag(lam): 1 - lam q(lam) = T_{K+1}((theta-lam)/delta) / T_{K+1}(theta/delta)."""
+    lmin, lmax = 0.3, 2.0
+    theta, delta = (lmax + lmin) / 2, (lmax - lmin) / 2
+    lam = np.concatenate([np.linspace(lmin, lmax, 17), [0.05, 0.1]])
+    e = cheby.chebyshev(lambda v: lam * v, lambda v: v, lam * 1.0, None, lmin, lmax, K)
+    ref = np.array([chebT(K + 1, (theta - l) / delta) for l in lam]) / chebT(K + 1, theta / delta)
+    np.testing.assert_allclose(1.0 - e, ref, atol=1e-13)
+    # with an initial guess the correction is applied to the current error
+    x0 = np.full_like(lam, 0.25)
+    e2 = cheby.chebyshev(lambda v: lam * v, lambda v: v, lam * 1.0, x0, lmin, lmax, K)
+    np.testing.assert_allclose(1.0 - (x0 + e2), 0.75 * ref, atol=1e-13)
+
+
+def _small_solver(p_sched, smoother="jacobi", coarse="dense", n=2, lam=None, **kw):
+    pf = p_sched[0]
+    xi, _ = gll.gll_nodes_weights(pf)
+    xyz = wl.sampled_mesh(n, n, n, xi, wl.sin_map(0.05))
+    return Solver(n, n, n, xyz, pf, p_sched, smoother=smoother, coarse=coarse,
+                  lambda_override=lam, **kw)
+
+
+def _dense_operator(S, level=0):
+    L = S.levels[level]
+    A, free = dense_free_system(L.num, L.G)
+    return A, free
+
+
+def test_arnoldi_bounds_jacobi():
+    S = _small_solver([4, 1])
+    L = S.levels[0]
+    A, free = _dense_operator(S)
+    d = np.diag(A)
+    lmax = np.max(np.linalg.eigvals(A / d[:, None]).real)
+    H, V, k = cheby.arnoldi(lambda v: L.apply_S(L.apply_A(v)), S.start_vector(0), L.wdot, 10)
+    lt = cheby.lambda_tilde(H, k)
+    assert lt <= lmax * (1 + 1e-12)
+    assert lt > 0.9 * lmax
+    assert abs(lt - S.levels[0].lam_tilde) < 1e-12 * lt
+    # orthonormal basis, Hessenberg structure
+    G = np.array([[L.wdot(a, b) for b in V] for a in V])
+    np.testing.assert_allclose(G, np.eye(len(V)), atol=1e-12)
+    assert np.all(np.tril(H, -2) == 0)
+
+
+def test_arnoldi_bounds_ras_real_dominant():
+    S = _small_solver([5, 1], smoother="ras")
+    L = S.levels[0]
+    A, free = _dense_operator(S)
+    # dense S*A on the free nodes via unit vectors
+    n = L.num
+    cols = []
+    for g in free:
+        u = np.zeros(n.n)
+        u[g] = 1
+        cols.append(n.to_global(L.apply_S(L.apply_A(n.Q(u))))[free])
+    SA = np.array(cols).T
+    rho = np.max(np.abs(np.linalg.eigvals(SA)))
+    assert S.levels[0].lam_tilde <= rho * (1 + 1e-10)
+    assert S.levels[0].lam_tilde > 0.8 * rho
+
+
+@pytest.mark.parametrize("pc,pf", [(1, 3), (3, 7), (3, 5)])
+def test_transfer_adjoint_and_exactness(pc, pf):
+    n = 2
+    xyz = wl.layer_shift_vertices(n, seed=4)
+    nf, nc = Numbering(n, n, n, pf), Numbering(n, n, n, pc)
+    J = gll.interpolation(pc, pf)
+    r = np.random.default_rng(0)
+    ec = nc.mask * nc.Q(r.standard_normal(nc.n))
+    rf = nf.mask * nf.Q(r.standard_normal(nf.n))
+    lhs = np.dot(nf.to_global(mg.prolong(J, ec)), nf.to_global(rf))
+    rhs = np.dot(nc.to_global(ec), nc.to_global(mg.restrict(nf, nc, J, rf)))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    # coarse coordinate fields (trilinear mesh) are reproduced exactly
+    Xc = level_coordinates(xyz, 1, pc)
+    Xf = level_coordinates(xyz, 1, pf)
+    for a in range(3):
+        np.testing.assert_allclose(mg.prolong(J, Xc[a]), Xf[a], atol=1e-14)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ras"])
+def test_vcycle_same_degree_schedule_is_exact_solve(smoother):
+    """Schedule (p, p): P = I, A_C = A, exact coarse solve -> V-cycle returns A^{-1} r."""
+    S = _small_solver([4, 4], smoother=smoother, lam=[3.0, 0])
+    L = S.levels[0]
+    A, free = _dense_operator(S)
+    r = L.num.mask * L.num.Q(np.random.default_rng(2).standard_normal(L.num.n))
+    z = S.vcycle(r)
+    ref = np.zeros(L.num.n)
+    ref[free] = np.linalg.solve(A, L.num.to_global(r)[free])
+    np.testing.assert_allclose(L.num.to_global(z), ref, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ras", "asm"])
+def test_two_level_vcycle_contracts(smoother):
+    S = _small_solver([3, 1], smoother=smoother)
+    L = S.levels[0]
+    A, free = _dense_operator(S)
+    cols = []
+    for g in free:
+        u = np.zeros(L.num.n)
+        u[g] = 1
+        cols.append(L.num.to_global(S.vcycle(L.num.Q(u)))[free])
+    M = np.array(cols).T
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(len(free)) - M @ A)))
+    assert rho < 0.5, rho
+
+
+@pytest.mark.parametrize("krylov", ["pcg", "fcg", "fgmres"])
+def test_krylov_matches_dense_solve(krylov):
+    S = _small_solver([5, 3, 1], smoother="ras", coarse="pcg")
+    L = S.fine
+    A, free = _dense_operator(S)
+    f, _ = wl.sinusoid(1, 2, 1)
+    b = S.rhs(f(L.X[0], L.X[1], L.X[2]))
+    res = S.solve(b, tol=1e-13, maxit=200, krylov=krylov)
+    assert res.converged
+    ref = np.zeros(L.num.n)
+    ref[free] = np.linalg.solve(A, L.num.to_global(b)[free])
+    np.testing.assert_allclose(L.num.to_global(res.x), ref, atol=1e-11 * np.abs(ref).max())
+
+
+def test_jacobi_pcg_matches_dense_solve():
+    S = _small_solver([3, 1])
+    L = S.fine
+    A, free = _dense_operator(S)
+    b = L.num.mask * L.num.Q(np.random.default_rng(5).standard_normal(L.num.n))
+    res = S.jacobi_pcg(b, 1e-13, 500)
+    ref = np.zeros(L.num.n)
+    ref[free] = np.linalg.solve(A, L.num.to_global(b)[free])
+    np.testing.assert_allclose(L.num.to_global(res.x), ref, atol=1e-11 * np.abs(ref).max())
+
+
+def test_chebyshev_bounds_sensitivity_underestimate_hurts():
+    """Underestimating lambda_max costs iterations (Sec. 2.2.3, Table 1 trend)."""
+    S_good = _small_solver([5, 3, 1], smoother="jacobi", coarse="pcg", n=3)
+    lt = [L.lam_tilde for L in S_good.levels[:-1]] + [0]
+    S_bad = _small_solver([5, 3, 1], smoother="jacobi", coarse="pcg", n=3,
+                          lam=lt, lmin_fac=0.1, lmax_fac=0.5)
+    L = S_good.fine
+    f, _ = wl.sinusoid(1, 1, 1)
+    b = S_good.rhs(f(L.X[0], L.X[1], L.X[2]))
+    it_good = S_good.solve(b, tol=1e-8, maxit=300).iters
+    it_bad = S_bad.solve(b, tol=1e-8, maxit=300).iters
+    assert it_bad > it_good, (it_good, it_bad)
