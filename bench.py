@@ -1,0 +1,213 @@
+"""Benchmark: time-to-1e-8 of the pMG-preconditioned SE Poisson solve on one MI355X.
+
+Workload (default): the anisotropic "layer-shift" box, 32^3 = 32768 hexahedra,
+p = 7 (11,390,625 unique nodes, 16,777,216 local points), homogeneous
+Dirichlet, f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z); preconditioner Cheby-RAS(2)
+p-multigrid (7,3,1) with the smoother in FP32 and FDM local solves, coarse
+p = 1 Jacobi-PCG to 1e-10, outer FP64 flexible CG to relative residual 1e-8.
+
+One step = one full solve from x = 0 (inputs resident in HBM, setup excluded).
+value = unique DOF solved per second (GDOF/s) over the timed steps.  Kernel
+durations come from HIP events the library records around every finest-level
+launch during the timed steps (sem_profile), on the stream the kernels run on.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32, help="elements per direction")
+    ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kind, p, E):
+    """HBM bytes one launch must move (each operand read or written once)."""
+    N3 = (p + 1) ** 3
+    pb = p + 3
+    if kind == "ax64":   # u, v and 6 geometric factors, FP64
+        return E * N3 * 8 * 8
+    if kind == "ax32":   # FP32 u, v, G
+        return E * N3 * 8 * 4
+    if kind == "fdm":    # FP32: input, RAS weight, output E-vectors; S (3 pb^2); lambda (3 pb)
+        return E * (3 * N3 * 4 + 3 * pb * pb * 4 + 3 * pb * 4)
+    raise ValueError(kind)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2110_07663_amd import sem
+    from paper_2110_07663_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    n, p = a.n, a.p
+    sched = (p, 3, 1) if p > 3 else (p, 1)
+    xyz = wl.layer_shift_vertices(n, seed=3)
+    f, _ = wl.sinusoid(1, 1, 1)
+
+    def make(prec):
+        opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
+                             smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=1e-10)
+        t0 = time.perf_counter()
+        s = sem.Solver(n, n, n, xyz, 1, p, opts=opts)
+        torch.cuda.synchronize()
+        return s, time.perf_counter() - t0
+
+    mixed, t_setup = make(sem.F32)
+    X = mixed.coords(0)
+    fl = torch.as_tensor(f(*(X.cpu().numpy())), dtype=torch.float64).cuda()
+    b = mixed.rhs(fl)
+    L0 = mixed.levels[0]
+    print(f"[bench] setup {t_setup:.2f}s  E={L0.E} p={p} n_unique={L0.nglobal} "
+          f"local={L0.nlocal}", file=sys.stderr, flush=True)
+
+    for _ in range(a.warmup):
+        mixed.solve(b, rtol=1e-8, maxit=200)
+    torch.cuda.synchronize()
+    mixed.profile(True)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        x, info = mixed.solve(b, rtol=1e-8, maxit=200)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    prof = mixed.profile_read()
+    mixed.profile(False)
+    ms_step = 1e3 * t_total / a.steps
+    value = L0.nglobal / (t_total / a.steps) / 1e9
+    iters = [i.iters for i in infos]
+    print(f"[bench] mixed solve {ms_step:.2f} ms/step iters={iters} "
+          f"true_rel_res={infos[-1].true_rel_res:.2e}", file=sys.stderr, flush=True)
+
+    # per-kernel rooflines from the event timings of the timed steps
+    kern = {}
+    for k in ("ax64", "ax32", "fdm"):
+        ms, cnt = prof[k]
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        byt = algorithmic_bytes(k, p, L0.E)
+        kern[k] = {"avg_us": 1e3 * avg, "launches": cnt, "total_ms": ms,
+                   "bytes_per_launch": byt, "GBs": byt / (avg * 1e-3) / 1e9}
+    for k in ("gs64", "gs32"):
+        ms, cnt = prof[k]
+        if cnt:
+            kern[k] = {"avg_us": 1e3 * ms / cnt, "launches": cnt, "total_ms": ms}
+    dom = max((k for k in kern if k in ("ax64", "ax32", "fdm")), key=lambda k: kern[k]["total_ms"])
+    d = kern[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": None}
+    ax = kern.get("ax64")
+    ax_gdofs = L0.nglobal / (ax["avg_us"] * 1e-6) / 1e9 if ax else None
+
+    # plain FP64 solve for the mixed-vs-FP64 time-to-solution factor
+    fp64 = None
+    if not a.no_fp64:
+        del x
+        plain, _ = make(sem.F64)
+        plain.solve(b, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xp, ip = plain.solve(b, rtol=1e-8, maxit=200)
+        torch.cuda.synchronize()
+        t_fp64 = time.perf_counter() - t1
+        fp64 = {"ms": round(1e3 * t_fp64, 2), "iters": ip.iters,
+                "true_rel_res": ip.true_rel_res}
+        print(f"[bench] fp64 solve {1e3 * t_fp64:.2f} ms iters={ip.iters}", file=sys.stderr,
+              flush=True)
+        plain.close()
+        del plain, xp
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(xyz, n, p, sched, f, L0.nglobal, int(np.median(iters)), a.cpu_iters)
+        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "Ax GDOF/s + %HBM roofline at p=7; time-to-1e-8 mixed vs FP64 solve",
+        "value": round(value, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 outer / f32 smoother",
+        "data": "synthetic",
+        "config": {"workload": f"layer-shift box {n}^3 hex, p={p}, Dirichlet, sin RHS; "
+                               f"FCG + pMG{sched} Cheby-RAS(2) FP32, coarse Jacobi-PCG 1e-10, tol 1e-8",
+                   "elements": int(L0.E), "p": p, "n_unique": int(L0.nglobal),
+                   "n_local": int(L0.nlocal), "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "iters": iters,
+        "true_rel_res": infos[-1].true_rel_res,
+        "setup_s": round(t_setup, 3),
+        "ax64_gdof_s": round(ax_gdofs, 3) if ax_gdofs else None,
+        "ax64_hbm_frac": round(ax["GBs"] / HBM_PEAK_GBS, 4) if ax else None,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "fp64_solve": fp64,
+        "speedup_mixed_vs_fp64": round(fp64["ms"] / ms_step, 3) if fp64 else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters):
+    """The oracle (plain NumPy FP64) timed on the host: setup once (untimed), then
+    `iters` FCG iterations of the same solve; GDOF/s is scaled to the GPU's
+    iteration count (same algorithm, same iteration count)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters)
+
+
+def _cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters):
+    from oracle.hierarchy import Solver as OSolver
+    t0 = time.perf_counter()
+    o = OSolver(n, n, n, xyz, 1, sched, smoother="ras", cheb_order=2, lambda_override=[2.0, 2.0, 0],
+                coarse_tol=1e-10)
+    t_setup = time.perf_counter() - t0
+    Xo = o.fine.X
+    bo = o.rhs(f(Xo[0], Xo[1], Xo[2]))
+    t0 = time.perf_counter()
+    o.solve(bo, tol=1e-30, maxit=iters)
+    t_it = (time.perf_counter() - t0) / iters
+    t_solve = t_it * gpu_iters
+    return {"value": round(nglobal / t_solve / 1e9, 6), "unit": "GDOF/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"NumPy FP64 oracle on the same mesh: {iters} FCG iteration(s) timed "
+                      f"({t_it:.1f} s each, setup {t_setup:.0f} s untimed), scaled to the GPU's "
+                      f"{gpu_iters} iterations; one thread (BLAS limited to 1)"}
+
+
+if __name__ == "__main__":
+    main()

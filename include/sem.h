@@ -1,0 +1,217 @@
+/*
+ * sem.h -- C ABI of the MI355X spectral-element Poisson library.
+ *
+ * Solves the spectral-element (SE) discretisation of -lap u = f (arXiv:2110.07663,
+ * Sec. 2.1, eqs. 1-3: A u = B f with A = Q^T A_L Q, B = Q^T B_L Q) on a structured
+ * mesh of hexahedra with isoparametric GLL nodes, preconditioned by a single-pass
+ * p-multigrid V-cycle (Sec. 2.2.2, Algorithm 1) whose smoother is Chebyshev
+ * acceleration (Sec. 2.2.3, Algorithm 2) of Jacobi or of overlapping Schwarz solved
+ * by the fast diagonalisation method (Sec. 2.2.2, eqs. 4-9), inside flexible CG or
+ * flexible GMRES (Sec. 2.2).
+ *
+ * Conventions shared by every call:
+ *  - Status: every function returns sem_status (0 = OK, < 0 = error); nothing is
+ *    thrown across the ABI.  sem_last_error() returns a thread-local message for the
+ *    last non-OK status of the calling thread.
+ *  - Memory: the library never allocates device memory.  The caller asks sem_plan
+ *    for the workspace size and passes one device buffer of at least that many bytes
+ *    to sem_setup; the context keeps pointers into it.  The caller owns the mesh
+ *    arrays (host, read during setup only), the workspace and every vector.  The
+ *    context object itself is host memory owned by the library, released by
+ *    sem_destroy (which does not touch the workspace).
+ *  - Streams: `stream` is a hipStream_t passed as void* (0 = the null stream).  All
+ *    device work of a call is enqueued on it, in order.  Calls that return host
+ *    scalars (setup, solve) synchronise the stream before returning.
+ *  - Vectors: device "E-vectors" of one level, layout [E][N][N][N] with
+ *    N = p+1, element e = (ez*ney + ey)*nex + ex and node (i,j,k) of an element at
+ *    ((k*N + j)*N + i), i fastest.  Values on nodes shared by several elements are
+ *    consistent copies; values on Dirichlet nodes are zero on output.  Precision is
+ *    double (SEM_F64) or float (SEM_F32) as the call states.
+ *  - Numbering: global node (gx, gy, gz) on the (nex*p+1) x (ney*p+1) x (nez*p+1)
+ *    node grid with gx = ex*p + i (likewise y, z); gid = (gz*ny + gy)*nx + gx.
+ *  - Calls on one context must not overlap (they share its workspace vectors).
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_EINVAL = -1,       /* bad argument (shape, degree, schedule, null pointer)       */
+  SEM_EWORKSPACE = -2,   /* workspace smaller than sem_plan's size                      */
+  SEM_EHIP = -3,         /* a HIP runtime call failed (message names it)                */
+  SEM_ENOCONV = -4,      /* solve stopped at maxit; x and info hold the last iterate     */
+  SEM_ENAN = -5,         /* NaN/Inf met in a residual norm or an inner product          */
+  SEM_EUNSUPPORTED = -6, /* valid request this build does not implement                 */
+  SEM_EGEOM = -7         /* non-positive Jacobian determinant (inverted element)        */
+} sem_status;
+
+typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2, SEM_F16 = 3 } sem_prec;
+
+typedef enum {              /* surrogate smoother S inside Chebyshev (Sec. 2.2.3)       */
+  SEM_SMOOTH_JACOBI = 0,    /* S = diag(A)^{-1}                                          */
+  SEM_SMOOTH_RAS = 1,       /* restrictive additive Schwarz, FDM local solves            */
+  SEM_SMOOTH_ASM = 2        /* additive Schwarz (eq. 4) with 1/#boxes post-weights       */
+} sem_smoother;
+
+typedef enum { SEM_KRYLOV_PCG = 0, SEM_KRYLOV_FCG = 1, SEM_KRYLOV_FGMRES = 2 } sem_krylov;
+typedef enum { SEM_PRECOND_PMG = 0, SEM_PRECOND_JACOBI = 1 } sem_precond;
+
+/* Mesh: structured nex x ney x nez hexahedra.  xyz (host, read only during setup)
+ * holds the node coordinates of every element at the tensor GLL points of degree
+ * p_geom, layout [E][(p_geom+1)^3][3], node (i,j,k) at (k*Ng + j)*Ng + i.  p_geom = 1
+ * gives the 8 vertices (trilinear elements).  Coordinates of every multigrid level
+ * are the degree-p_geom isoparametric interpolant (Sec. 2.1) at that level's nodes. */
+typedef struct {
+  int32_t nex, ney, nez;
+  int32_t p_geom;
+  const double *xyz;
+} sem_mesh;
+
+/* Solver options; sem_default_opts fills the paper's defaults:
+ * pMG schedule (p, ..., 1) given in p_levels, Chebyshev order 2, bounds
+ * (0.1, 1.1) * lambda~ from 10 Arnoldi steps (Sec. 2.2.3), FCG, coarse Jacobi-PCG
+ * to 1e-10 relative residual. */
+typedef struct {
+  int32_t nlevels;            /* entries used in p_levels; p_levels[0] must equal p       */
+  int32_t p_levels[8];        /* strictly decreasing degrees, e.g. {7, 3, 1}              */
+  int32_t precond;            /* sem_precond                                              */
+  int32_t smoother;           /* sem_smoother, used on every level except the coarsest    */
+  int32_t cheb_order;         /* K of Algorithm 2 (K products with A per application)     */
+  double lmin_fac, lmax_fac;  /* (lambda_min, lambda_max) = (lmin_fac, lmax_fac)*lambda~  */
+  int32_t arnoldi_steps;      /* Arnoldi steps on S*A for lambda~ (<= 16)                 */
+  uint64_t seed;              /* Arnoldi start vector: SplitMix64(seed XOR gid) in [-1,1) */
+  double lambda_override[8];  /* > 0: use this lambda~ on level l instead of Arnoldi      */
+  int32_t smoother_prec;      /* SEM_F64 or SEM_F32: precision of the V-cycle levels      */
+  int32_t fdm_prec;           /* FDM contraction inputs: F64/F32 (= smoother_prec), or    */
+                              /* SEM_BF16 / SEM_F16 on MFMA with FP32 accumulation        */
+  int32_t krylov;             /* sem_krylov                                               */
+  int32_t gmres_restart;      /* m of FGMRES(m), <= 64                                    */
+  double coarse_tol;          /* relative residual of the coarse Jacobi-PCG; 0 = run      */
+  int32_t coarse_maxit;       /*   exactly coarse_maxit iterations                        */
+} sem_opts;
+
+typedef struct {
+  int32_t iters;              /* outer Krylov iterations                                  */
+  int32_t converged;          /* 1 if the true relative residual met rtol                 */
+  double rel_res;             /* final ||r||/||r0|| of the recurrence                     */
+  double true_rel_res;        /* ||b - A x||/||r0|| recomputed in FP64 at exit            */
+  double r0_norm;             /* ||b - A x0||                                             */
+  int32_t coarse_iters;       /* coarse PCG iterations of the last V-cycle                */
+  double lambda_tilde[8];     /* lambda~ used on each level (0 on the coarsest)           */
+} sem_solve_info;
+
+typedef struct {
+  int32_t p, N;               /* degree and points per direction (N = p + 1)              */
+  int64_t E;                  /* elements                                                 */
+  int64_t nlocal;             /* E * N^3, entries of one E-vector                         */
+  int64_t nglobal;            /* unique nodes (nex*p+1)(ney*p+1)(nez*p+1)                 */
+  int64_t nshared;            /* gather-scatter segments (shared or Dirichlet nodes)      */
+  double lmin, lmax;          /* Chebyshev bounds of this level (0 on the coarsest)       */
+} sem_level_desc;
+
+void sem_default_opts(sem_opts *opts);
+
+/* Workspace bytes sem_setup needs for this problem.  bc[6] = Dirichlet (1) or
+ * Neumann (0) flag of the faces x-, x+, y-, y+, z-, z+ (Sec. 2.1).  Fails with
+ * SEM_EINVAL on an invalid schedule or mesh, SEM_EUNSUPPORTED for p > 15. */
+sem_status sem_plan(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const sem_opts *opts,
+                    size_t *workspace_bytes);
+
+typedef struct sem_ctx sem_ctx;
+
+/* Builds every level: GLL basis, coordinates, geometric factors G and mass B_L
+ * (Sec. 2.1), the sorted gather-scatter numbering, Jacobi diagonals, FDM data
+ * (eqs. 5-9), transfer matrices, and the Chebyshev bounds by Arnoldi (Sec. 2.2.3).
+ * `workspace` is a device buffer of workspace_bytes >= sem_plan's size, 256-byte
+ * aligned.  Synchronises `stream`.  Returns SEM_EGEOM if an element is inverted. */
+sem_status sem_setup(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const sem_opts *opts,
+                     void *workspace, size_t workspace_bytes, void *stream, sem_ctx **out);
+
+/* Releases the host context (not the caller's workspace).  Accepts NULL. */
+sem_status sem_destroy(sem_ctx *ctx);
+
+const char *sem_last_error(void);
+
+/* Shape of level `level` (0 = finest). */
+sem_status sem_level_info(const sem_ctx *ctx, int32_t level, sem_level_desc *out);
+
+/* GLL nodes of degree p (Sec. 2.1), computed on the device into nodes_dev[p+1]
+ * and weights_dev[p+1] (device doubles; weights_dev may be NULL). */
+sem_status sem_gll(int32_t p, double *nodes_dev, double *weights_dev, void *stream);
+
+/* Node coordinates of a level: xyz_dev[3][nlocal] (device doubles). */
+sem_status sem_coords(const sem_ctx *ctx, int32_t level, double *xyz_dev, void *stream);
+
+/* Boolean gather u_L = Q u (Sec. 2.1): u_global_dev[nglobal] -> u_local_dev[nlocal]. */
+sem_status sem_gather(const sem_ctx *ctx, int32_t level, const double *u_global_dev,
+                      double *u_local_dev, void *stream);
+
+/* Right side b = mask * QQ^T (B_L f) on the finest level (eq. 3); f is the source
+ * sampled at the fine nodes (E-vector), b an E-vector; both FP64 device. */
+sem_status sem_rhs(sem_ctx *ctx, const double *f_dev, double *b_dev, void *stream);
+
+/* Au = mask * QQ^T A_L u on `level` (Sec. 2.1, A = Q^T A_L Q applied by sum
+ * factorisation).  prec SEM_F64 (double E-vectors, FP64 G) or SEM_F32 (float
+ * E-vectors, G stored in FP32).  u and Au must not alias. */
+sem_status sem_apply_A(sem_ctx *ctx, int32_t level, int32_t prec, const void *u, void *Au,
+                       void *stream);
+
+/* z = S r, the level's surrogate smoother (Jacobi diagonal inverse, or the Schwarz
+ * sum of eq. 4 with RAS/ASM weights and FDM local solves of eq. 8), masked.
+ * prec SEM_F64 or SEM_F32 (E-vectors of that type); for Schwarz, the FDM
+ * contraction precision is the context's fdm_prec when prec is SEM_F32. */
+sem_status sem_apply_S(sem_ctx *ctx, int32_t level, int32_t prec, const void *r, void *z,
+                       void *stream);
+
+/* x <- x + Cheb(b - A x) on `level` (Algorithm 2 with the level's bounds and
+ * order; the result of the algorithm is read as a correction added to x). */
+sem_status sem_smooth(sem_ctx *ctx, int32_t level, int32_t prec, const void *b, void *x,
+                      void *stream);
+
+/* Transfers between level l (fine) and l+1 (coarse) (Algorithm 1):
+ * prolong: xf += P xc; restrict: rc = mask_c * P^T rf. */
+sem_status sem_prolong(sem_ctx *ctx, int32_t level, int32_t prec, const void *xc, void *xf,
+                       void *stream);
+sem_status sem_restrict(sem_ctx *ctx, int32_t level, int32_t prec, const void *rf, void *rc,
+                        void *stream);
+
+/* z = M r: one V-cycle of Algorithm 1 from x = 0 on the finest level (levels in the
+ * context's smoother precision, coarse solve in FP64), FP64 in and out.  With
+ * precond = SEM_PRECOND_JACOBI, z = diag(A)^{-1} r. */
+sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
+
+/* Solves A x = b to ||b - A x|| <= rtol ||b - A x0|| (2-norm over unique free
+ * nodes) with the context's Krylov method, x_inout the initial guess and result.
+ * Returns SEM_ENOCONV at maxit (x and info hold the last iterate), SEM_ENAN on a
+ * NaN/Inf residual.  info may be NULL. */
+sem_status sem_solve(sem_ctx *ctx, const double *b, double *x_inout, double rtol, int32_t maxit,
+                     sem_solve_info *info, void *stream);
+
+/* Kernel timing of the finest level, for roofline reporting.  While enabled, the
+ * library records a pair of HIP events on the call's stream around every launch
+ * of the instrumented kernels below (finest level only), so durations are those
+ * of the kernels themselves.  Enabling clears the counters.  sem_profile_read
+ * synchronises on the recorded events and returns, per class, the summed
+ * duration in ms (total_ms[SEM_PROF_COUNT]) and the launch count. */
+typedef enum {
+  SEM_PROF_AX64 = 0,   /* sum-factorised A_L, FP64 (outer Krylov operator)          */
+  SEM_PROF_AX32 = 1,   /* sum-factorised A_L, FP32 (smoother operator)              */
+  SEM_PROF_FDM = 2,    /* Schwarz FDM local solves (any precision)                  */
+  SEM_PROF_GS64 = 3,   /* QQ^T gather-scatter + mask, FP64                          */
+  SEM_PROF_GS32 = 4,   /* QQ^T gather-scatter + mask, FP32                          */
+  SEM_PROF_COUNT = 5
+} sem_prof_kernel;
+sem_status sem_profile(sem_ctx *ctx, int32_t enable);
+sem_status sem_profile_read(sem_ctx *ctx, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

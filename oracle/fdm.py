@@ -28,8 +28,9 @@ Readings where the paper gives no formula:
     boundary node is decoupled too.  A decoupled node is excluded from the
     local solve (its output is zero), represented by an identity column of
     S and lambda = +inf;
-  * a zero eigenvalue sum (the constant mode of a box floating on Neumann
-    faces in all three directions) is dropped from the local solve;
+  * a 1D eigenvalue below 1e-12 of the largest one is set to 0; a zero
+    eigenvalue sum (the constant mode of a box floating on Neumann faces in
+    all three directions) is dropped from the local solve;
   * ASM weight W(node) = 1 / (number of extended boxes containing the node);
     RAS weight on an element's own nodes = 1 / (number of elements owning
     the node), zero on the overlap shell.
@@ -103,6 +104,9 @@ def generalized_eig(K, M, coupled):
     Kc = K[np.ix_(c, c)]
     mh = 1.0 / np.sqrt(np.diag(M)[c])
     lc, V = np.linalg.eigh(mh[:, None] * Kc * mh[None, :])
+    # the constant mode of a line floating on Neumann ends has eigenvalue 0
+    # (up to rounding): make it exactly 0 so that the local solve can drop it
+    lc = np.where(np.abs(lc) <= 1e-12 * np.abs(lc).max(), 0.0, lc)
     S[np.ix_(c, np.arange(len(c)))] = mh[:, None] * V
     lam[:len(c)] = lc
     for t, i in enumerate(d):
@@ -166,8 +170,7 @@ class FDM:
               + self.lam[:, 0][:, None, None, :])
         # a box floating on Neumann faces in all three directions has a zero
         # eigenvalue sum (its constant mode); that mode is dropped
-        Dfin = np.where(np.isfinite(Dm), Dm, 0.0).reshape(len(Dm), -1).max(axis=1)
-        keep = Dm > 1e-12 * Dfin[:, None, None, None]
+        keep = Dm > 0.0
         t = np.where(keep, t / np.where(keep, Dm, 1.0), 0.0)
         t = np.einsum('eia,ecba->ecbi', Sx, t)
         t = np.einsum('ejb,ecbi->ecji', Sy, t)

@@ -1,0 +1,185 @@
+// Local SE stiffness action v = A_L u by tensor-product sum factorisation
+// (Sec. 2.1; about 7 E (p+1)^3 reads and 12 E (p+1)^4 operations, Sec. 1):
+//
+//   g = (D_r u, D_s u, D_t u)      three 1D contractions with Dhat
+//   h = G g                         3x3 symmetric factors (6 per point)
+//   v = D_r^T h_r + D_s^T h_s + D_t^T h_t
+//
+// Layout: u, v E-vectors [E][N][N][N] (i fastest); G [E][6][N^3].
+// Mapping: one (i, j) column per thread with the t-line (k) in registers, so
+// only the r and s contractions go through LDS; N^2 threads per element, EPB
+// elements per workgroup.  Every G entry, u and v value is touched once per
+// launch: loads of a k-plane by the N^2 lanes of an element are contiguous.
+#include "sem_internal.h"
+
+namespace sem {
+
+template <int N>
+struct AxShape {
+  static constexpr int NN = N * N;
+  static constexpr int N3 = N * NN;
+  static constexpr int EPB = NN >= 256 ? 1 : 256 / NN;     // elements per workgroup
+  static constexpr int BS = ((EPB * NN + 63) / 64) * 64;   // whole wavefronts
+  static constexpr int RS = (N % 2 == 0) ? N + 1 : N;      // padded LDS row stride
+  static constexpr int PS = N * RS;                        // LDS plane stride
+};
+
+template <int N, typename T>
+__global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__restrict__ u,
+                                                       const T *__restrict__ G,
+                                                       const T *__restrict__ Dg,
+                                                       T *__restrict__ v) {
+  using S = AxShape<N>;
+  constexpr int NN = S::NN, N3 = S::N3, EPB = S::EPB, RS = S::RS, PS = S::PS;
+  __shared__ T sD[NN];
+  __shared__ T s_a[EPB][N * PS];
+  __shared__ T s_b[EPB][N * PS];
+
+  const int tid = threadIdx.x;
+  const int le = tid / NN;
+  const int ij = tid - le * NN;
+  const int i = ij % N, j = ij / N;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool active = le < EPB && e < E;
+
+  for (int t = tid; t < NN; t += S::BS) sD[t] = Dg[t];
+
+  // phase 1: the element's u into registers (t-lines) and LDS (planes)
+  T uk[N];
+  if (active) {
+    const T *ue = u + e * N3 + ij;
+#pragma unroll
+    for (int k = 0; k < N; ++k) uk[k] = ue[k * NN];
+#pragma unroll
+    for (int k = 0; k < N; ++k) s_a[le][k * PS + j * RS + i] = uk[k];
+  }
+  __syncthreads();
+
+  // phase 2: r and s derivatives from LDS
+  T Di[N], Dj[N], ur[N], us[N];
+  if (active) {
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      Di[l] = sD[i * N + l];
+      Dj[l] = sD[j * N + l];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      T a = 0, b = 0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        a += Di[l] * s_a[le][k * PS + j * RS + l];
+        b += Dj[l] * s_a[le][k * PS + l * RS + i];
+      }
+      ur[k] = a;
+      us[k] = b;
+    }
+  }
+  __syncthreads();
+
+  // phase 3: t derivative in registers, h = G g; h_r, h_s to LDS, h_t stays
+  T wt[N];
+  if (active) {
+    const T *Ge = G + e * 6 * N3 + ij;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      T ut = 0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) ut += sD[k * N + l] * uk[l];
+      const T g0 = Ge[0 * N3 + k * NN], g1 = Ge[1 * N3 + k * NN], g2 = Ge[2 * N3 + k * NN];
+      const T g3 = Ge[3 * N3 + k * NN], g4 = Ge[4 * N3 + k * NN], g5 = Ge[5 * N3 + k * NN];
+      s_a[le][k * PS + j * RS + i] = g0 * ur[k] + g1 * us[k] + g2 * ut;
+      s_b[le][k * PS + j * RS + i] = g1 * ur[k] + g3 * us[k] + g4 * ut;
+      wt[k] = g2 * ur[k] + g4 * us[k] + g5 * ut;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // phase 4: v = D_r^T h_r + D_s^T h_s + D_t^T h_t
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    Di[l] = sD[l * N + i];
+    Dj[l] = sD[l * N + j];
+  }
+  T *ve = v + e * N3 + ij;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      acc += Di[l] * s_a[le][k * PS + j * RS + l];
+      acc += Dj[l] * s_b[le][k * PS + l * RS + i];
+      acc += sD[l * N + k] * wt[l];
+    }
+    ve[k * NN] = acc;
+  }
+}
+
+template <typename T, int N>
+static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, hipStream_t s) {
+  using S = AxShape<N>;
+  unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB);
+  hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v);
+  SEM_LAUNCH("k_ax");
+}
+
+template <typename T>
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s) {
+  const T *G;
+  const T *D;
+  if constexpr (sizeof(T) == 8) {
+    G = (const T *)L.G64;
+    D = (const T *)L.D64;
+  } else {
+    G = (const T *)L.G32;
+    D = (const T *)L.D32;
+  }
+  if (!G || !D) fail(SEM_EINVAL, "geometric factors of this precision were not built");
+  switch (L.N) {
+    case 2: ax_n<T, 2>(L, u, v, G, D, s); break;
+    case 3: ax_n<T, 3>(L, u, v, G, D, s); break;
+    case 4: ax_n<T, 4>(L, u, v, G, D, s); break;
+    case 5: ax_n<T, 5>(L, u, v, G, D, s); break;
+    case 6: ax_n<T, 6>(L, u, v, G, D, s); break;
+    case 7: ax_n<T, 7>(L, u, v, G, D, s); break;
+    case 8: ax_n<T, 8>(L, u, v, G, D, s); break;
+    case 9: ax_n<T, 9>(L, u, v, G, D, s); break;
+    case 10: ax_n<T, 10>(L, u, v, G, D, s); break;
+    case 11: ax_n<T, 11>(L, u, v, G, D, s); break;
+    default: fail(SEM_EUNSUPPORTED, "Ax: unsupported degree");
+  }
+}
+template void launch_ax<double>(const Level &, const double *, double *, hipStream_t);
+template void launch_ax<float>(const Level &, const float *, float *, hipStream_t);
+
+// diag(A^e) per point: only q' on the r-, s- or t-line through q contribute, and
+// the cross terms only at q' = q.
+__global__ void k_diag(int64_t E, int N, const double *__restrict__ G, const double *__restrict__ D,
+                       double *__restrict__ d) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int N3 = N * N * N;
+  if (t >= E * N3) return;
+  int64_t e = t / N3;
+  int q = (int)(t - e * N3);
+  int i = q % N, j = (q / N) % N, k = q / (N * N);
+  const double *Ge = G + e * 6 * N3;
+  double acc = 0;
+  for (int l = 0; l < N; ++l) {
+    double a = D[l * N + i], b = D[l * N + j], c = D[l * N + k];
+    acc += a * a * Ge[0 * N3 + (k * N + j) * N + l];
+    acc += b * b * Ge[3 * N3 + (k * N + l) * N + i];
+    acc += c * c * Ge[5 * N3 + (l * N + j) * N + i];
+  }
+  double di = D[i * N + i], dj = D[j * N + j], dk = D[k * N + k];
+  acc += 2 * di * dj * Ge[1 * N3 + q] + 2 * di * dk * Ge[2 * N3 + q] + 2 * dj * dk * Ge[4 * N3 + q];
+  d[t] = acc;
+}
+
+void launch_diag(const Level &L, double *d, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)((L.nloc + 255) / 256)), dim3(256), 0, s, L.E, L.N,
+                     L.G64, L.D64, d);
+  SEM_LAUNCH("k_diag");
+}
+
+}  // namespace sem

@@ -1,0 +1,409 @@
+// Vector kernels of the Krylov, Chebyshev and coarse-grid drivers.
+//
+// Inner products are 2-norm products over unique free nodes, computed on
+// E-vectors with the weight w = mask / multiplicity.  Every reduction uses a
+// fixed launch shape and a fixed summation tree (per-thread strided partial
+// sums, an LDS tree per block, then the last block to finish sums the block
+// partials in block order), so results are bitwise repeatable.
+#include "sem_internal.h"
+
+namespace sem {
+
+static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+static inline unsigned red_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > kRedBlocks) g = kRedBlocks;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+template <typename T>
+__global__ void k_scale(int64_t n, const T *__restrict__ w, const T *__restrict__ x,
+                        T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = w[t] * x[t];
+}
+template <typename T>
+void launch_scale(int64_t n, const T *w, const T *x, T *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, w, x, y);
+  SEM_LAUNCH("k_scale");
+}
+template void launch_scale<double>(int64_t, const double *, const double *, double *, hipStream_t);
+template void launch_scale<float>(int64_t, const float *, const float *, float *, hipStream_t);
+
+__global__ void k_d2f(int64_t n, const double *__restrict__ x, float *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = (float)x[t];
+}
+__global__ void k_f2d(int64_t n, const float *__restrict__ x, double *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = (double)x[t];
+}
+void launch_copy_cvt_d2f(int64_t n, const double *x, float *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_d2f, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
+  SEM_LAUNCH("k_d2f");
+}
+void launch_copy_cvt_f2d(int64_t n, const float *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_f2d, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
+  SEM_LAUNCH("k_f2d");
+}
+
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = a * x[t] + b * y[t];
+}
+template <typename T>
+void launch_axpby(int64_t n, T a, const T *x, T b, T *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+  SEM_LAUNCH("k_axpby");
+}
+template void launch_axpby<double>(int64_t, double, const double *, double, double *, hipStream_t);
+template void launch_axpby<float>(int64_t, float, const float *, float, float *, hipStream_t);
+
+template <typename T>
+__global__ void k_sub(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+                      T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = a[t] - b[t];
+}
+template <typename T>
+void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, a, b, y);
+  SEM_LAUNCH("k_sub");
+}
+template void launch_sub<double>(int64_t, const double *, const double *, double *, hipStream_t);
+template void launch_sub<float>(int64_t, const float *, const float *, float *, hipStream_t);
+
+// Chebyshev (Algorithm 2): d = r / theta, x = 0 when starting from zero
+template <typename T>
+__global__ void k_cheb_init(int64_t n, T *__restrict__ x, const T *__restrict__ r,
+                            T *__restrict__ d, T inv_theta, int x_zero) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  d[t] = r[t] * inv_theta;
+  if (x_zero) x[t] = T(0);
+}
+template <typename T>
+void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zero, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_init<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, inv_theta,
+                     (int)x_zero);
+  SEM_LAUNCH("k_cheb_init");
+}
+template void launch_cheb_init<double>(int64_t, double *, const double *, double *, double, bool,
+                                       hipStream_t);
+template void launch_cheb_init<float>(int64_t, float *, const float *, float *, float, bool,
+                                      hipStream_t);
+
+// one pass of the loop body: x += d_k; r -= S A d_k (= t); d = a d_k + c r
+template <typename T>
+__global__ void k_cheb_update(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
+                              const T *__restrict__ tv, T a, T c) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  T dk = d[t];
+  x[t] += dk;
+  T rn = r[t] - tv[t];
+  r[t] = rn;
+  d[t] = a * dk + c * rn;
+}
+template <typename T>
+void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c);
+  SEM_LAUNCH("k_cheb_update");
+}
+template void launch_cheb_update<double>(int64_t, double *, double *, double *, const double *,
+                                         double, double, hipStream_t);
+template void launch_cheb_update<float>(int64_t, float *, float *, float *, const float *, float,
+                                        float, hipStream_t);
+
+__global__ void k_jacobi_inv(int64_t n, const double *__restrict__ diag, const double *__restrict__ w,
+                             double *__restrict__ dinv, float *__restrict__ dinv32) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double v = (w[t] != 0.0) ? 1.0 / diag[t] : 0.0;
+  dinv[t] = v;
+  if (dinv32) dinv32[t] = (float)v;
+}
+void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi_inv, dim3(nb(n, 256)), dim3(256), 0, s, n, diag, w, dinv, dinv32);
+  SEM_LAUNCH("k_jacobi_inv");
+}
+
+__global__ void k_fill(int64_t n, double v, double *x) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+__global__ void k_fillf(int64_t n, float v, float *x) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+void launch_fill(int64_t n, double v, double *x, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(nb(n, 256)), dim3(256), 0, s, n, v, x);
+  SEM_LAUNCH("k_fill");
+}
+void launch_fillf(int64_t n, float v, float *x, hipStream_t s) {
+  hipLaunchKernelGGL(k_fillf, dim3(nb(n, 256)), dim3(256), 0, s, n, v, x);
+  SEM_LAUNCH("k_fillf");
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+template <int ND>
+__device__ inline void block_reduce(double (&acc)[ND], double (*sh)[256]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
+    }
+    __syncthreads();
+  }
+}
+
+// Writes this block's partials; returns true in the block that finishes last,
+// after the block partials have been summed in block order into acc (thread 0).
+template <int ND>
+__device__ inline bool last_block_sum(double (&acc)[ND], double *partials, unsigned *counter) {
+  __shared__ double sh[ND][256];
+  __shared__ bool is_last;
+  block_reduce<ND>(acc, sh);
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = sh[j][0];
+    __threadfence();
+    unsigned ticket = atomicAdd(counter, 1u);
+    is_last = (ticket == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += 256) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      acc[j] += __hip_atomic_load(&partials[b * 8 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_reduce<ND>(acc, sh);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = sh[j][0];
+  if (tid == 0) *counter = 0u;
+  return true;
+}
+
+struct Ptr4 {
+  const double *p[4];
+};
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_wdots(int64_t n, const double *__restrict__ w, Ptr4 a,
+                                               Ptr4 b, double *partials, unsigned *counter,
+                                               double *out) {
+  double acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double wt = w[t];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += wt * a.p[j][t] * b.p[j][t];
+  }
+  if (last_block_sum<ND>(acc, partials, counter) && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) out[j] = acc[j];
+  }
+}
+
+void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
+                  const double *const *b, double *out, hipStream_t s) {
+  Ptr4 pa{}, pb{};
+  for (int j = 0; j < nd; ++j) {
+    pa.p[j] = a[j];
+    pb.p[j] = b[j];
+  }
+  unsigned g = red_grid(n);
+  switch (nd) {
+    case 1: hipLaunchKernelGGL(k_wdots<1>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
+    case 2: hipLaunchKernelGGL(k_wdots<2>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
+    case 3: hipLaunchKernelGGL(k_wdots<3>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
+    case 4: hipLaunchKernelGGL(k_wdots<4>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
+    default: fail(SEM_EINVAL, "wdots: at most 4 products");
+  }
+  SEM_LAUNCH("k_wdots");
+}
+
+// block of inner products <V_j, x>_w for j < k (k <= 8 per pass)
+template <int KB>
+__global__ __launch_bounds__(256) void k_mdot(int64_t n, const double *__restrict__ w,
+                                              const double *__restrict__ V, int64_t ld,
+                                              const double *__restrict__ x, double *partials,
+                                              unsigned *counter, double *out) {
+  double acc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double wx = w[t] * x[t];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] += wx * V[j * ld + t];
+  }
+  if (last_block_sum<KB>(acc, partials, counter) && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) out[j] = acc[j];
+  }
+}
+
+void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *V, int64_t ld,
+                 const double *x, double *out, hipStream_t s) {
+  unsigned g = red_grid(n);
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    int kb = k - j0 < 8 ? k - j0 : 8;
+    const double *Vj = V + j0 * ld;
+    double *o = out + j0;
+#define MD(KB) hipLaunchKernelGGL(k_mdot<KB>, dim3(g), dim3(256), 0, s, n, w, Vj, ld, x, c.partials, c.counter, o)
+    switch (kb) {
+      case 1: MD(1); break;
+      case 2: MD(2); break;
+      case 3: MD(3); break;
+      case 4: MD(4); break;
+      case 5: MD(5); break;
+      case 6: MD(6); break;
+      case 7: MD(7); break;
+      case 8: MD(8); break;
+    }
+#undef MD
+    SEM_LAUNCH("k_mdot");
+  }
+}
+
+__global__ void k_mupdate(int64_t n, int k, const double *__restrict__ V, int64_t ld,
+                          const double *__restrict__ h, double *__restrict__ x, double sign) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < k; ++j) acc += h[j] * V[j * ld + t];
+  x[t] += sign * acc;
+}
+
+void launch_mupdate(int64_t n, int k, const double *V, int64_t ld, const double *h, double *x,
+                    double sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, dim3(nb(n, 256)), dim3(256), 0, s, n, k, V, ld, h, x, sign);
+  SEM_LAUNCH("k_mupdate");
+}
+
+// ---------------------------------------------------------------------------
+// coarse-grid Jacobi-PCG with every scalar kept on the device; each kernel is
+// a no-op once `done` is set, so a fixed number of iterations can be enqueued
+// ahead of the convergence test.
+__global__ __launch_bounds__(256) void k_cpcg_init(int64_t n, const double *__restrict__ w,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ z, double *__restrict__ p,
+                                                   double *partials, unsigned *counter,
+                                                   DevScalars *sc, double tol2, int maxit) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double rv = b[t];
+    double zv = dinv[t] * rv;
+    x[t] = 0.0;
+    r[t] = rv;
+    z[t] = zv;
+    p[t] = zv;
+    acc[0] += w[t] * rv * zv;
+    acc[1] += w[t] * rv * rv;
+  }
+  if (last_block_sum<2>(acc, partials, counter) && threadIdx.x == 0) {
+    sc->rz = acc[0];
+    sc->rr = acc[1];
+    sc->rr0 = acc[1];
+    sc->tol2 = tol2;
+    sc->maxit = maxit;
+    sc->beta = 0.0;
+    sc->iters = 0;
+    sc->done = (acc[1] == 0.0 || maxit <= 0) ? 1 : 0;
+  }
+}
+
+__global__ void k_cpcg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                         const DevScalars *sc) {
+  if (sc->done) return;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) p[t] = z[t] + sc->beta * p[t];
+}
+
+__global__ __launch_bounds__(256) void k_cpcg_pq(int64_t n, const double *__restrict__ w,
+                                                 const double *__restrict__ p,
+                                                 const double *__restrict__ q, double *partials,
+                                                 unsigned *counter, DevScalars *sc) {
+  if (sc->done) return;
+  double acc[1] = {0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    acc[0] += w[t] * p[t] * q[t];
+  if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) {
+    sc->pq = acc[0];
+    sc->alpha = sc->rz / acc[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cpcg_update(int64_t n, const double *__restrict__ w,
+                                                     const double *__restrict__ dinv,
+                                                     double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ z,
+                                                     const double *__restrict__ p,
+                                                     const double *__restrict__ q, double *partials,
+                                                     unsigned *counter, DevScalars *sc) {
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    x[t] += alpha * p[t];
+    double rv = r[t] - alpha * q[t];
+    double zv = dinv[t] * rv;
+    r[t] = rv;
+    z[t] = zv;
+    acc[0] += w[t] * rv * zv;
+    acc[1] += w[t] * rv * rv;
+  }
+  if (last_block_sum<2>(acc, partials, counter) && threadIdx.x == 0) {
+    sc->beta = acc[0] / sc->rz;
+    sc->rz = acc[0];
+    sc->rr = acc[1];
+    sc->iters += 1;
+    bool conv = sc->tol2 > 0.0 && acc[1] <= sc->tol2 * sc->rr0;
+    if (conv || sc->iters >= sc->maxit || !(acc[1] == acc[1])) sc->done = 1;
+  }
+}
+
+void launch_cpcg_init(const Ctx &c, const Level &L, double tol2, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_cpcg_init, dim3(red_grid(L.nloc)), dim3(256), 0, s, L.nloc, L.w64, L.dinv64,
+                     L.d_b, c.cx, c.cr, c.cz, c.cp, c.partials, c.counter, c.dsc, tol2, maxit);
+  SEM_LAUNCH("k_cpcg_init");
+}
+
+void launch_cpcg_iteration(const Ctx &c, const Level &L, bool first, hipStream_t s) {
+  if (!first) {
+    hipLaunchKernelGGL(k_cpcg_p, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, c.cz, c.cp, c.dsc);
+    SEM_LAUNCH("k_cpcg_p");
+  }
+  launch_ax<double>(L, c.cp, c.cq, s);
+  launch_gs<double>(L, c.cq, s);
+  hipLaunchKernelGGL(k_cpcg_pq, dim3(red_grid(L.nloc)), dim3(256), 0, s, L.nloc, L.w64, c.cp, c.cq,
+                     c.partials, c.counter, c.dsc);
+  SEM_LAUNCH("k_cpcg_pq");
+  hipLaunchKernelGGL(k_cpcg_update, dim3(red_grid(L.nloc)), dim3(256), 0, s, L.nloc, L.w64,
+                     L.dinv64, c.cx, c.cr, c.cz, c.cp, c.cq, c.partials, c.counter, c.dsc);
+  SEM_LAUNCH("k_cpcg_update");
+}
+
+}  // namespace sem

@@ -1,0 +1,333 @@
+// Overlapping Schwarz smoother with fast-diagonalisation local solves
+// (Sec. 2.2.2, eqs. 4-9).
+//
+// Setup, per element, level and direction: the element is approximated by a
+// box whose length along r is the mean of its four r-edges; the 1D stiffness
+// (2/L) Dhat^T W Dhat and mass (L/2) W are assembled over the element and its
+// two neighbours and restricted to the extended grid (left neighbour's node
+// p-1, own nodes 0..p, right neighbour's node 1), so pbar = p+3.  Nodes with no
+// neighbour (domain boundary), and the element's own boundary node on a
+// Dirichlet face, are decoupled.  The generalised eigenproblem A s = lambda B s
+// (eq. 6) of the coupled block is solved with B diagonal: cyclic Jacobi on
+// B^{-1/2} A B^{-1/2} = V Lambda V^T, S = B^{-1/2} V, so S^T A S = Lambda and
+// S^T B S = I (eq. 7).  Decoupled nodes get identity columns and lambda = +inf.
+//
+// Apply (eq. 8): gather the (p+3)^3 box from the consistent E-vector (overlap
+// values come from face, edge and corner neighbours; outside the domain 0),
+// contract with S_x^T, S_y^T, S_z^T, divide by lambda_x + lambda_y + lambda_z
+// (eq. 9), contract back with S, and keep the element's own (p+1)^3 nodes
+// times the RAS weight 1/multiplicity; the caller then assembles (QQ^T).
+#include "sem_internal.h"
+
+namespace sem {
+
+constexpr int kMaxPB = kMaxP + 3;
+
+__global__ __launch_bounds__(64) void k_fdm_setup(int64_t E, int p, int nex, int ney, int nez,
+                                                  int bc0, int bc1, int bc2, int bc3, int bc4,
+                                                  int bc5, const double *__restrict__ D,
+                                                  const double *__restrict__ wq,
+                                                  const double *__restrict__ boxlen,
+                                                  double *__restrict__ S64,
+                                                  double *__restrict__ lam64,
+                                                  float *__restrict__ S32,
+                                                  float *__restrict__ lam32) {
+  const int N = p + 1, pb = p + 3;
+  __shared__ double Ah[(kMaxP + 1) * (kMaxP + 1)];
+  __shared__ double ws[kMaxP + 1];
+  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+    int a = t / N, b = t % N;
+    double s = 0;
+    for (int q = 0; q < N; ++q) s += D[q * N + a] * wq[q] * D[q * N + b];
+    Ah[t] = s;
+  }
+  for (int t = threadIdx.x; t < N; t += blockDim.x) ws[t] = wq[t];
+  __syncthreads();
+
+  int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (task >= 3 * E) return;
+  const int64_t e = task / 3;
+  const int d = (int)(task - e * 3);
+  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  const int64_t pos = d == 0 ? ex : d == 1 ? ey : ez;
+  const int64_t cnt = d == 0 ? nex : d == 1 ? ney : nez;
+  const int64_t stride = d == 0 ? 1 : d == 1 ? nex : (int64_t)nex * ney;
+  const bool has_l = pos > 0, has_r = pos < cnt - 1;
+  const int dir_l = d == 0 ? bc0 : d == 1 ? bc2 : bc4;
+  const int dir_r = d == 0 ? bc1 : d == 1 ? bc3 : bc5;
+  const double Lc = boxlen[e * 3 + d];
+  const double Lm = has_l ? boxlen[(e - stride) * 3 + d] : 0.0;
+  const double Lp = has_r ? boxlen[(e + stride) * 3 + d] : 0.0;
+
+  // extended node q sits at chain index c = p - 1 + q of the 3-element chain
+  double K[kMaxPB * kMaxPB], M[kMaxPB];
+  for (int q1 = 0; q1 < pb; ++q1) {
+    M[q1] = 0.0;
+    for (int q2 = 0; q2 < pb; ++q2) K[q1 * kMaxPB + q2] = 0.0;
+  }
+  for (int t = 0; t < 3; ++t) {
+    bool present = t == 1 || (t == 0 && has_l) || (t == 2 && has_r);
+    if (!present) continue;
+    double Le = t == 0 ? Lm : t == 1 ? Lc : Lp;
+    for (int q1 = 0; q1 < pb; ++q1) {
+      int a = p - 1 + q1 - t * p;
+      if (a < 0 || a > p) continue;
+      M[q1] += 0.5 * Le * ws[a];
+      for (int q2 = 0; q2 < pb; ++q2) {
+        int b = p - 1 + q2 - t * p;
+        if (b < 0 || b > p) continue;
+        K[q1 * kMaxPB + q2] += (2.0 / Le) * Ah[a * N + b];
+      }
+    }
+  }
+  bool cpl[kMaxPB];
+  for (int q = 0; q < pb; ++q) cpl[q] = true;
+  if (!has_l) {
+    cpl[0] = false;
+    if (dir_l) cpl[1] = false;
+  }
+  if (!has_r) {
+    cpl[pb - 1] = false;
+    if (dir_r) cpl[pb - 2] = false;
+  }
+  int idx[kMaxPB], m = 0;
+  for (int q = 0; q < pb; ++q)
+    if (cpl[q]) idx[m++] = q;
+
+  // C = M^{-1/2} K M^{-1/2} on the coupled nodes; cyclic Jacobi C = V Lambda V^T
+  double C[kMaxPB * kMaxPB], V[kMaxPB * kMaxPB], mh[kMaxPB];
+  for (int a = 0; a < m; ++a) mh[a] = 1.0 / sqrt(M[idx[a]]);
+  double fro = 0.0;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b) {
+      double v = mh[a] * K[idx[a] * kMaxPB + idx[b]] * mh[b];
+      C[a * kMaxPB + b] = v;
+      V[a * kMaxPB + b] = (a == b) ? 1.0 : 0.0;
+      fro += v * v;
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+    for (int a = 0; a < m; ++a)
+      for (int b = a + 1; b < m; ++b) off += C[a * kMaxPB + b] * C[a * kMaxPB + b];
+    if (off <= 1e-32 * fro) break;
+    for (int a = 0; a < m; ++a)
+      for (int b = a + 1; b < m; ++b) {
+        double apq = C[a * kMaxPB + b];
+        if (fabs(apq) < 1e-300) continue;
+        double theta = (C[b * kMaxPB + b] - C[a * kMaxPB + a]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < m; ++k) {  // columns a, b
+          double ka = C[k * kMaxPB + a], kb = C[k * kMaxPB + b];
+          C[k * kMaxPB + a] = c * ka - s * kb;
+          C[k * kMaxPB + b] = s * ka + c * kb;
+        }
+        for (int k = 0; k < m; ++k) {  // rows a, b
+          double ak = C[a * kMaxPB + k], bk = C[b * kMaxPB + k];
+          C[a * kMaxPB + k] = c * ak - s * bk;
+          C[b * kMaxPB + k] = s * ak + c * bk;
+        }
+        C[a * kMaxPB + b] = 0.0;
+        C[b * kMaxPB + a] = 0.0;
+        for (int k = 0; k < m; ++k) {
+          double va = V[k * kMaxPB + a], vb = V[k * kMaxPB + b];
+          V[k * kMaxPB + a] = c * va - s * vb;
+          V[k * kMaxPB + b] = s * va + c * vb;
+        }
+      }
+  }
+  double lmax = 0.0;
+  for (int a = 0; a < m; ++a) lmax = fmax(lmax, fabs(C[a * kMaxPB + a]));
+
+  // S[q][col] (row = extended node, column = mode), lambda[col]
+  double *Se = S64 + (e * 3 + d) * pb * pb;
+  double *le = lam64 + (e * 3 + d) * pb;
+  for (int q = 0; q < pb; ++q)
+    for (int a = 0; a < pb; ++a) Se[q * pb + a] = 0.0;
+  for (int a = 0; a < m; ++a) {
+    double lv = C[a * kMaxPB + a];
+    le[a] = fabs(lv) <= 1e-12 * lmax ? 0.0 : lv;
+    for (int r = 0; r < m; ++r) Se[idx[r] * pb + a] = mh[r] * V[r * kMaxPB + a];
+  }
+  int col = m;
+  for (int q = 0; q < pb; ++q)
+    if (!cpl[q]) {
+      Se[q * pb + col] = 1.0;
+      le[col] = __builtin_huge_val();
+      ++col;
+    }
+  if (S32) {
+    float *Sf = S32 + (e * 3 + d) * pb * pb;
+    float *lf = lam32 + (e * 3 + d) * pb;
+    for (int q = 0; q < pb * pb; ++q) Sf[q] = (float)Se[q];
+    for (int a = 0; a < pb; ++a) lf[a] = (float)le[a];
+  }
+}
+
+void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s) {
+  int64_t tasks = 3 * L.E;
+  hipLaunchKernelGGL(k_fdm_setup, dim3((unsigned)((tasks + 63) / 64)), dim3(64), 0, s, L.E, L.p,
+                     c.nex, c.ney, c.nez, c.bc[0], c.bc[1], c.bc[2], c.bc[3], c.bc[4], c.bc[5],
+                     L.D64, L.wq, L.boxlen, L.S64, L.lam64, L.S32, L.lam32);
+  SEM_LAUNCH("k_fdm_setup");
+}
+
+// ---------------------------------------------------------------------------
+// apply: one element per workgroup, thread (a, b) owns the box column
+// (a, b, 0..pb-1) in registers; the x and y contractions go through LDS.
+template <int P>
+struct FdmShape {
+  static constexpr int PB = P + 3;
+  static constexpr int N = P + 1;
+  static constexpr int BS = ((PB * PB + 63) / 64) * 64;
+  static constexpr int RS = PB + 1;
+  static constexpr int PS = PB * RS;
+};
+
+template <typename T>
+__device__ inline T fdm_inv(T d) {
+  return d > T(0) ? T(1) / d : T(0);  // +inf -> 0 (decoupled), 0 -> dropped mode
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
+    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
+    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
+  using F = FdmShape<P>;
+  constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
+  constexpr int N3 = N * N * N;
+  __shared__ T sS[3][PB * PB];
+  __shared__ T sL[3][PB];
+  __shared__ T buf0[PB * PS];
+  __shared__ T buf1[PB * PS];
+
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int a = tid % PB, b = tid / PB;
+  const bool act = tid < PB * PB;
+  for (int t = tid; t < 3 * PB * PB; t += F::BS) sS[t / (PB * PB)][t % (PB * PB)] = Sg[e * 3 * PB * PB + t];
+  for (int t = tid; t < 3 * PB; t += F::BS) sL[t / PB][t % PB] = lamg[e * 3 * PB + t];
+
+  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  T col[PB];
+  if (act) {
+    // box node (a, b, c): direction offsets and local indices
+    int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0);
+    int li = a == 0 ? P - 1 : (a == PB - 1 ? 1 : a - 1);
+    int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
+    int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+    bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
+      int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
+      bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
+      T v = T(0);
+      if (ok) {
+        int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
+        v = r[en * N3 + (lk * N + lj) * N + li];
+      }
+      col[c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
+  }
+  __syncthreads();
+  // x: t[c][b][a] = sum_i Sx[i][a] box[c][b][i]
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) s += sS[0][i * PB + a] * buf0[c * PS + b * RS + i];
+      buf1[c * PS + b * RS + a] = s;
+    }
+  }
+  __syncthreads();
+  // y: t[c][b][a] = sum_j Sy[j][b] t[c][j][a]; then z in registers
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) s += sS[1][j * PB + b] * buf1[c * PS + j * RS + a];
+      col[c] = s;
+    }
+    T h[PB];
+#pragma unroll
+    for (int cc = 0; cc < PB; ++cc) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < PB; ++k) s += sS[2][k * PB + cc] * col[k];
+      h[cc] = s * fdm_inv<T>(sL[0][a] + sL[1][b] + sL[2][cc]);
+    }
+    // back along z
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      T s = 0;
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) s += sS[2][k * PB + cc] * h[cc];
+      col[k] = s;
+    }
+#pragma unroll
+    for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
+  }
+  __syncthreads();
+  // back along y: y[c][j][a] = sum_bb Sy[j][bb] t[c][bb][a]   (thread (a, j = b))
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int bb = 0; bb < PB; ++bb) s += sS[1][b * PB + bb] * buf0[c * PS + bb * RS + a];
+      buf1[c * PS + b * RS + a] = s;
+    }
+  }
+  __syncthreads();
+  // back along x and the RAS output on own nodes: out[c][j][i] = sum_aa Sx[i][aa] y[c][j][aa]
+  if (act && a >= 1 && a <= P + 1 && b >= 1 && b <= P + 1) {
+    const int64_t obase = e * N3 + (b - 1) * N + (a - 1);
+#pragma unroll
+    for (int c = 1; c <= P + 1; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int aa = 0; aa < PB; ++aa) s += sS[0][a * PB + aa] * buf1[c * PS + b * RS + aa];
+      const int64_t o = obase + (int64_t)(c - 1) * N * N;
+      z[o] = W[o] * s;
+    }
+  }
+}
+
+template <typename T, int P>
+static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
+  const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
+  const T *lam = sizeof(T) == 8 ? (const T *)L.lam64 : (const T *)L.lam32;
+  const T *W = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
+  if (!S || !lam || !W) fail(SEM_EINVAL, "FDM data of this precision were not built");
+  hipLaunchKernelGGL((k_fdm<P, T>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E, c.nex,
+                     c.ney, c.nez, r, S, lam, W, z);
+  SEM_LAUNCH("k_fdm");
+}
+
+template <typename T>
+void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
+  if (asm_mode) fail(SEM_EUNSUPPORTED, "ASM weights are not implemented");
+  switch (L.p) {
+    case 2: fdm_p<T, 2>(c, L, r, z, s); break;
+    case 3: fdm_p<T, 3>(c, L, r, z, s); break;
+    case 4: fdm_p<T, 4>(c, L, r, z, s); break;
+    case 5: fdm_p<T, 5>(c, L, r, z, s); break;
+    case 6: fdm_p<T, 6>(c, L, r, z, s); break;
+    case 7: fdm_p<T, 7>(c, L, r, z, s); break;
+    case 8: fdm_p<T, 8>(c, L, r, z, s); break;
+    case 9: fdm_p<T, 9>(c, L, r, z, s); break;
+    case 10: fdm_p<T, 10>(c, L, r, z, s); break;
+    default: fail(SEM_EUNSUPPORTED, "FDM: unsupported degree");
+  }
+}
+template void launch_fdm<double>(const Ctx &, const Level &, const double *, double *, bool,
+                                 hipStream_t);
+template void launch_fdm<float>(const Ctx &, const Level &, const float *, float *, bool,
+                                hipStream_t);
+
+}  // namespace sem

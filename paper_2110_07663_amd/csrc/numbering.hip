@@ -1,0 +1,257 @@
+// Global numbering, the Boolean gather Q and direct stiffness summation QQ^T
+// (Sec. 2.1: u_L = Q u; A = Q^T A_L Q).
+//
+// QQ^T only changes nodes held by more than one element.  The setup sorts the
+// local indices of every shared node (and of every Dirichlet node, which the
+// same pass zeroes) by global id, stably, so each global node becomes one
+// contiguous segment of `perm`; `off[s]` is the segment start with bit 31 set
+// for Dirichlet segments.  The summation then visits each segment once, adds
+// its copies in ascending local index (a fixed order: results are bitwise
+// repeatable, no floating-point atomics) and writes the sum to every copy.
+#include <hipcub/hipcub.hpp>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+struct GridInfo {
+  int nex, ney, nez, p, N;
+  int64_t nx, ny, nz;
+  int bc[6];
+};
+
+static GridInfo grid_of(const Ctx &c, const Level &L) {
+  GridInfo g;
+  g.nex = c.nex; g.ney = c.ney; g.nez = c.nez; g.p = L.p; g.N = L.N;
+  g.nx = (int64_t)c.nex * L.p + 1;
+  g.ny = (int64_t)c.ney * L.p + 1;
+  g.nz = (int64_t)c.nez * L.p + 1;
+  for (int f = 0; f < 6; ++f) g.bc[f] = c.bc[f];
+  return g;
+}
+
+__device__ inline void global_coords(const GridInfo &g, int64_t t, int64_t &gx, int64_t &gy,
+                                     int64_t &gz) {
+  int N3 = g.N * g.N * g.N;
+  int64_t e = t / N3;
+  int q = (int)(t - e * N3);
+  int i = q % g.N, j = (q / g.N) % g.N, k = q / (g.N * g.N);
+  int64_t ex = e % g.nex, ey = (e / g.nex) % g.ney, ez = e / ((int64_t)g.nex * g.ney);
+  gx = ex * g.p + i;
+  gy = ey * g.p + j;
+  gz = ez * g.p + k;
+}
+
+__device__ inline bool is_dirichlet(const GridInfo &g, int64_t gx, int64_t gy, int64_t gz) {
+  return (g.bc[0] && gx == 0) || (g.bc[1] && gx == g.nx - 1) || (g.bc[2] && gy == 0) ||
+         (g.bc[3] && gy == g.ny - 1) || (g.bc[4] && gz == 0) || (g.bc[5] && gz == g.nz - 1);
+}
+
+__device__ inline bool on_interface(int64_t gc, int p, int64_t n) {
+  return gc % p == 0 && gc > 0 && gc < n - 1;
+}
+
+// key = global id of shared or Dirichlet local nodes, INT32_MAX otherwise
+__global__ void k_gs_keys(GridInfo g, int64_t nloc, int32_t *keys, int32_t *vals) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nloc) return;
+  int64_t gx, gy, gz;
+  global_coords(g, t, gx, gy, gz);
+  bool shared = on_interface(gx, g.p, g.nx) || on_interface(gy, g.p, g.ny) ||
+                on_interface(gz, g.p, g.nz);
+  bool dir = is_dirichlet(g, gx, gy, gz);
+  keys[t] = (shared || dir) ? (int32_t)((gz * g.ny + gy) * g.nx + gx) : INT32_MAX;
+  vals[t] = (int32_t)t;
+}
+
+__global__ void k_gs_heads(int64_t nloc, const int32_t *skeys, int32_t *head) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nloc) return;
+  int32_t k = skeys[t];
+  head[t] = (k != INT32_MAX && (t == 0 || skeys[t - 1] != k)) ? 1 : 0;
+}
+
+__global__ void k_gs_offsets(GridInfo g, int64_t nloc, const int32_t *skeys, const int32_t *head,
+                             const int32_t *segid, int32_t *off, int32_t *counts) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nloc) return;
+  int32_t k = skeys[t];
+  if (head[t]) {
+    int64_t gid = k;
+    int64_t gx = gid % g.nx, gy = (gid / g.nx) % g.ny, gz = gid / (g.nx * g.ny);
+    bool dir = is_dirichlet(g, gx, gy, gz);
+    off[segid[t]] = (int32_t)t | (dir ? (int32_t)0x80000000u : 0);
+  }
+  // last member of the member list: record the totals
+  if (k != INT32_MAX && (t == nloc - 1 || skeys[t + 1] == INT32_MAX)) {
+    counts[0] = (int32_t)(t + 1);         // members
+    counts[1] = segid[t] + head[t];       // segments
+  }
+}
+
+__global__ void k_gs_close(int32_t *off, const int32_t *counts) {
+  off[counts[1]] = counts[0];
+}
+
+template <typename T>
+__global__ void k_gs(T *__restrict__ v, const int32_t *__restrict__ perm,
+                     const int32_t *__restrict__ off, int nseg) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  int32_t a = off[s];
+  int32_t b = off[s + 1] & 0x7fffffff;
+  bool dir = a < 0;
+  a &= 0x7fffffff;
+  if (dir) {
+    for (int m = a; m < b; ++m) v[perm[m]] = T(0);
+    return;
+  }
+  // at most 8 copies on a conforming hex mesh
+  int32_t idx[8];
+  int n = b - a;
+  T sum = T(0);
+  for (int m = 0; m < n && m < 8; ++m) {
+    idx[m] = perm[a + m];
+    sum += v[idx[m]];
+  }
+  for (int m = 0; m < n && m < 8; ++m) v[idx[m]] = sum;
+}
+
+// w = mask / multiplicity
+__global__ void k_weights(const int32_t *__restrict__ perm, const int32_t *__restrict__ off,
+                          int nseg, double *w64, float *w32) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  int32_t a = off[s];
+  int32_t b = off[s + 1] & 0x7fffffff;
+  bool dir = a < 0;
+  a &= 0x7fffffff;
+  double v = dir ? 0.0 : 1.0 / (b - a);
+  for (int m = a; m < b; ++m) {
+    w64[perm[m]] = v;
+    if (w32) w32[perm[m]] = (float)v;
+  }
+}
+
+__global__ void k_fill1(int64_t n, double *w64, float *w32) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  w64[t] = 1.0;
+  if (w32) w32[t] = 1.0f;
+}
+
+__global__ void k_gather(GridInfo g, int64_t nloc, const double *__restrict__ ug,
+                         double *__restrict__ ul) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nloc) return;
+  int64_t gx, gy, gz;
+  global_coords(g, t, gx, gy, gz);
+  ul[t] = ug[(gz * g.ny + gy) * g.nx + gx];
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) of (seed XOR gid), top 53 bits -> [-1, 1)
+__device__ inline double splitmix_pm1(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
+__global__ void k_start_vector(GridInfo g, int64_t nloc, uint64_t seed, const double *__restrict__ w,
+                               double *__restrict__ v) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nloc) return;
+  int64_t gx, gy, gz;
+  global_coords(g, t, gx, gy, gz);
+  uint64_t gid = (uint64_t)((gz * g.ny + gy) * g.nx + gx);
+  v[t] = (w[t] != 0.0) ? splitmix_pm1(seed ^ gid) : 0.0;
+}
+
+static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Host-only upper bound of the sort/scan temporary storage (planning must not
+// touch the device): the radix sort ping-pongs keys and values through a
+// second buffer pair, plus per-pass histograms; build_gather_scatter checks
+// the exact requirement against this bound.
+size_t gs_sort_temp_bytes(int64_t nloc) {
+  return (size_t)nloc * 2 * (sizeof(int32_t) + sizeof(int32_t)) + ((size_t)8 << 20);
+}
+
+static size_t gs_sort_temp_exact(int64_t nloc) {
+  size_t bytes = 0;
+  SEM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (int32_t *)nullptr,
+                                             (int32_t *)nullptr, (int32_t *)nullptr,
+                                             (int32_t *)nullptr, (int)nloc));
+  size_t scan = 0;
+  SEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int32_t *)nullptr, (int32_t *)nullptr,
+                                           (int)nloc));
+  return bytes > scan ? bytes : scan;
+}
+
+void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s) {
+  GridInfo g = grid_of(c, L);
+  int64_t n = L.nloc;
+  int32_t *keys = scratch.take<int32_t>(n);
+  int32_t *vals = scratch.take<int32_t>(n);
+  int32_t *skeys = scratch.take<int32_t>(n);
+  int32_t *head = scratch.take<int32_t>(n);
+  int32_t *segid = scratch.take<int32_t>(n);
+  int32_t *counts = scratch.take<int32_t>(4);
+  size_t tb = gs_sort_temp_exact(n);
+  if (tb > gs_sort_temp_bytes(n)) fail(SEM_EHIP, "sort scratch larger than planned");
+  char *tmp = scratch.take<char>(tb);
+  hipLaunchKernelGGL(k_gs_keys, dim3(nb(n, 256)), dim3(256), 0, s, g, n, keys, vals);
+  SEM_LAUNCH("k_gs_keys");
+  size_t tb2 = tb;
+  SEM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb2, keys, skeys, vals, L.perm, (int)n, 0,
+                                             32, s));
+  hipLaunchKernelGGL(k_gs_heads, dim3(nb(n, 256)), dim3(256), 0, s, n, skeys, head);
+  SEM_LAUNCH("k_gs_heads");
+  tb2 = tb;
+  SEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb2, head, segid, (int)n, s));
+  SEM_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_gs_offsets, dim3(nb(n, 256)), dim3(256), 0, s, g, n, skeys, head, segid,
+                     L.off, counts);
+  SEM_LAUNCH("k_gs_offsets");
+  hipLaunchKernelGGL(k_gs_close, dim3(1), dim3(1), 0, s, L.off, counts);
+  SEM_LAUNCH("k_gs_close");
+  int32_t h[4];
+  SEM_HIP(hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  L.nperm = h[0];
+  L.nseg = h[1];
+}
+
+template <typename T>
+void launch_gs(const Level &L, T *v, hipStream_t s) {
+  if (L.nseg == 0) return;
+  hipLaunchKernelGGL(k_gs<T>, dim3(nb(L.nseg, 256)), dim3(256), 0, s, v, L.perm, L.off, L.nseg);
+  SEM_LAUNCH("k_gs");
+}
+template void launch_gs<double>(const Level &, double *, hipStream_t);
+template void launch_gs<float>(const Level &, float *, hipStream_t);
+
+void launch_weights(const Level &L, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill1, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, L.w64, L.w32);
+  SEM_LAUNCH("k_fill1");
+  if (L.nseg == 0) return;
+  hipLaunchKernelGGL(k_weights, dim3(nb(L.nseg, 256)), dim3(256), 0, s, L.perm, L.off, L.nseg,
+                     L.w64, L.w32);
+  SEM_LAUNCH("k_weights");
+}
+
+void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s) {
+  GridInfo g = grid_of(c, L);
+  hipLaunchKernelGGL(k_gather, dim3(nb(L.nloc, 256)), dim3(256), 0, s, g, L.nloc, ug, ul);
+  SEM_LAUNCH("k_gather");
+}
+
+void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s) {
+  GridInfo g = grid_of(c, L);
+  hipLaunchKernelGGL(k_start_vector, dim3(nb(L.nloc, 256)), dim3(256), 0, s, g, L.nloc, seed,
+                     L.w64, v);
+  SEM_LAUNCH("k_start_vector");
+}
+
+}  // namespace sem

@@ -1,0 +1,229 @@
+// Internal declarations of the SE Poisson library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sem.h"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws sem::Error; the ABI layer converts it to a status
+struct Error {
+  sem_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(sem_status st, const std::string &msg);
+void check_hip(hipError_t e, const char *what, const char *file, int line);
+#define SEM_HIP(call) ::sem::check_hip((call), #call, __FILE__, __LINE__)
+#define SEM_LAUNCH(what) ::sem::check_hip(hipGetLastError(), what, __FILE__, __LINE__)
+
+constexpr int kMaxP = 10;      // highest supported polynomial degree
+constexpr int kMaxLevels = 8;
+constexpr int kMaxArnoldi = 16;
+constexpr int kMaxRestart = 64;
+
+// ---------------------------------------------------------------------------
+// bump allocator over the caller's workspace; with base == nullptr it only
+// counts bytes (planning pass), so plan and setup walk the same sequence
+struct Arena {
+  char *base = nullptr;
+  size_t off = 0, cap = 0;
+  template <typename T>
+  T *take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    size_t at = off;
+    off += n * sizeof(T);
+    if (!base) return nullptr;
+    if (off > cap) fail(SEM_EWORKSPACE, "workspace exhausted while carving buffers");
+    return reinterpret_cast<T *>(base + at);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// one multigrid level
+struct Level {
+  int p = 0, N = 0, N3 = 0, pb = 0;  // pb = p + 3 (extended Schwarz box)
+  int64_t E = 0, nloc = 0, nglob = 0;
+  int nseg = 0, nperm = 0;           // gather-scatter segments and member count
+  bool fine = false, coarse = false;
+  bool lowp = false;                 // level kept in FP32 for the smoother
+
+  // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
+  double *xi = nullptr, *wq = nullptr, *D64 = nullptr;
+  float *D32 = nullptr;
+  // interpolation from the next coarser level: J[N][Nc], J[i][j] = h^c_j(xi_i)
+  double *J64 = nullptr;
+  float *J32 = nullptr;
+
+  // geometry (device)
+  double *X = nullptr;     // [3][nloc] node coordinates
+  double *G64 = nullptr;   // [E][6][N3] (rr, rs, rt, ss, st, tt)
+  float *G32 = nullptr;    // FP32 copy for the smoother
+  double *BL = nullptr;    // [nloc] diagonal mass (finest level)
+  double *w64 = nullptr;   // [nloc] mask / multiplicity (dot weight, RAS weight)
+  float *w32 = nullptr;
+  double *dinv64 = nullptr;  // [nloc] Jacobi: 1/diag(A), 0 on Dirichlet nodes
+  float *dinv32 = nullptr;
+
+  // gather-scatter: perm[] = local indices of shared/Dirichlet nodes sorted by
+  // global id; off[s] = start of segment s, bit 31 set for Dirichlet segments
+  int32_t *perm = nullptr, *off = nullptr;
+
+  // FDM (Schwarz) data: S[E][3][pb][pb] (column a of direction d at [e][d][.][a]),
+  // lam[E][3][pb] (+inf marks a decoupled node)
+  double *S64 = nullptr, *lam64 = nullptr;
+  float *S32 = nullptr, *lam32 = nullptr;
+  uint16_t *S16 = nullptr;  // S in BF16 or FP16 bit patterns for the MFMA path
+  double *boxlen = nullptr; // [E][3]
+  double *wasm64 = nullptr; // [nloc] ASM weight 1/#boxes (0 on Dirichlet)
+  float *wasm32 = nullptr;
+
+  // Chebyshev parameters
+  double lam_tilde = 0, lmin = 0, lmax = 0;
+  int K = 0;
+
+  // work E-vectors of this level: FP64 set and FP32 set
+  double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_d = nullptr, *d_w = nullptr,
+         *d_t = nullptr;
+  float *f_b = nullptr, *f_x = nullptr, *f_r = nullptr, *f_d = nullptr, *f_w = nullptr,
+        *f_t = nullptr;
+};
+
+// device-resident scalars of the coarse PCG and of reductions
+struct DevScalars {
+  double rz, pq, alpha, beta, rr, rr0, tol2;
+  int done, iters, maxit, pad;
+};
+
+// HIP-event timing of finest-level kernels (sem_profile)
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;  // events of the current session
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  size_t used = 0;
+  void begin(int kind, hipStream_t s);
+  void end(hipStream_t s);
+  void reset();
+  ~Profiler();
+};
+
+struct Ctx {
+  int nex = 0, ney = 0, nez = 0;
+  Profiler *prof = nullptr;
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  sem_opts opts{};
+  int nlev = 0;
+  Level lev[kMaxLevels];
+  bool lowp = false;  // smoother levels in FP32
+
+  // reductions
+  double *partials = nullptr;   // [kRedBlocks][8]
+  unsigned *counter = nullptr;  // last-block counter
+  double *dres = nullptr;       // [64] reduction results
+  DevScalars *dsc = nullptr;
+  double *hres = nullptr;       // host copy (pinned)
+
+  // outer Krylov vectors (FP64, finest level)
+  double *kr = nullptr, *kz = nullptr, *kzold = nullptr, *kp = nullptr, *kq = nullptr,
+         *kx = nullptr;
+  double *gV = nullptr, *gZ = nullptr;  // FGMRES bases [(m+1)][nloc], [m][nloc]
+  // coarse PCG vectors (FP64, coarsest level)
+  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
+  int last_coarse_iters = 0;
+  // Arnoldi basis (FP64, largest level)
+  double *av = nullptr;
+  int fdm_prec = SEM_F32;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each enqueues on `s`)
+constexpr int kRedBlocks = 1024;
+
+// basis.hip
+void launch_gll(int p, double *xi, double *w, hipStream_t s);
+void launch_dmat(int p, const double *xi, double *D, float *D32, hipStream_t s);
+void launch_interp(int pc, int pf, const double *xic, const double *xif, double *J, float *J32,
+                   hipStream_t s);
+
+// geom.hip
+void launch_level_coords(const Ctx &c, const double *xyz_in, int p_geom, const double *Jg,
+                         Level &L, hipStream_t s);
+void launch_geom(const Ctx &c, Level &L, int *bad_flag, hipStream_t s);
+void launch_boxlen(const Ctx &c, Level &L, hipStream_t s);
+void launch_rhs(const Level &L, const double *f, double *b, hipStream_t s);
+
+// numbering.hip
+size_t gs_sort_temp_bytes(int64_t nloc);
+void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s);
+void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s);
+template <typename T>
+void launch_gs(const Level &L, T *v, hipStream_t s);
+void launch_weights(const Level &L, hipStream_t s);
+void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s);
+
+// ax.hip
+template <typename T>
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s);
+void launch_diag(const Level &L, double *d, hipStream_t s);
+
+// blas.hip
+template <typename T>
+void launch_scale(int64_t n, const T *w, const T *x, T *y, hipStream_t s);  // y = w.*x
+void launch_copy_cvt_d2f(int64_t n, const double *x, float *y, hipStream_t s);
+void launch_copy_cvt_f2d(int64_t n, const float *x, double *y, hipStream_t s);
+template <typename T>
+void launch_axpby(int64_t n, T a, const T *x, T b, T *y, hipStream_t s);  // y = a x + b y
+template <typename T>
+void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s);  // y = a - b
+template <typename T>
+void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s);
+template <typename T>
+void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zero, hipStream_t s);
+void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
+                       hipStream_t s);
+// weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)
+void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
+                  const double *const *b, double *out, hipStream_t s);
+// block dots for Gram-Schmidt: out[j] = sum_i w_i V_j(i) x(i), j < k
+void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *V, int64_t ld,
+                 const double *x, double *out, hipStream_t s);
+// x -= sum_j h_j V_j  (h on device)
+void launch_mupdate(int64_t n, int k, const double *V, int64_t ld, const double *h, double *x,
+                    double sign, hipStream_t s);
+void launch_fill(int64_t n, double v, double *x, hipStream_t s);
+void launch_fillf(int64_t n, float v, float *x, hipStream_t s);
+
+// coarse PCG kernels with device scalars (blas.hip)
+void launch_cpcg_init(const Ctx &c, const Level &L, double tol2, int maxit, hipStream_t s);
+void launch_cpcg_iteration(const Ctx &c, const Level &L, bool first, hipStream_t s);
+
+// transfer.hip
+template <typename T>
+void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s);
+template <typename T>
+void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s);
+
+// fdm.hip
+void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s);
+template <typename T>
+void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s);
+void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
+                     int prec, hipStream_t s);
+void launch_asm_weights(const Ctx &c, Level &L, hipStream_t s);
+
+// hessenberg.cpp
+double hessenberg_max_abs_eig(const double *H, int ldh, int k);
+
+}  // namespace sem

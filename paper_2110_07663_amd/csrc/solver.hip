@@ -1,0 +1,985 @@
+// Setup, multigrid and Krylov drivers, and the C ABI of include/sem.h.
+//
+// Sec. 2.2 / 2.2.2 / 2.2.3 of arXiv:2110.07663: a single-pass p-multigrid
+// V-cycle (Algorithm 1) with Chebyshev-accelerated (Algorithm 2) Jacobi or
+// Schwarz smoothing, bounds (0.1, 1.1) lambda~ from Arnoldi on S A, inside
+// flexible CG or flexible GMRES.  Every vector operation runs in the HIP
+// kernels of this library; the host only sequences launches and reads back
+// the few scalars the Krylov recurrences and the Arnoldi eigenvalue need.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+static thread_local std::string g_last_error;
+
+void fail(sem_status st, const std::string &msg) { throw Error{st, msg}; }
+
+void check_hip(hipError_t e, const char *what, const char *file, int line) {
+  if (e != hipSuccess) {
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    fail(SEM_EHIP, buf);
+  }
+}
+
+template <typename F>
+static sem_status guarded(F &&f) {
+  try {
+    f();
+    return SEM_OK;
+  } catch (const Error &e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return SEM_EHIP;
+  } catch (...) {
+    g_last_error = "unexpected exception";
+    return SEM_EHIP;
+  }
+}
+
+static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// workspace layout (planning and setup walk the same sequence)
+struct SetupScratch {
+  double *xyz = nullptr, *xig = nullptr, *Jg = nullptr, *diag = nullptr;
+  int *bad = nullptr;
+  Arena gs;  // sort scratch, reset per level
+};
+
+static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts *o) {
+  if (!m || !bc || !o) fail(SEM_EINVAL, "null mesh, bc or opts");
+  if (m->nex < 1 || m->ney < 1 || m->nez < 1) fail(SEM_EINVAL, "element counts must be >= 1");
+  if (m->p_geom < 1 || m->p_geom > kMaxP) fail(SEM_EINVAL, "p_geom must be in [1, 10]");
+  if (p < 1) fail(SEM_EINVAL, "p must be >= 1");
+  if (p > kMaxP) fail(SEM_EUNSUPPORTED, "p > 10 is not supported");
+  if (o->precond == SEM_PRECOND_PMG) {
+    if (o->nlevels < 1 || o->nlevels > kMaxLevels) fail(SEM_EINVAL, "nlevels must be in [1, 8]");
+    if (o->p_levels[0] != p) fail(SEM_EINVAL, "p_levels[0] must equal p");
+    for (int l = 1; l < o->nlevels; ++l)
+      if (o->p_levels[l] >= o->p_levels[l - 1] || o->p_levels[l] < 1)
+        fail(SEM_EINVAL, "p_levels must be strictly decreasing and >= 1");
+    if (o->smoother != SEM_SMOOTH_JACOBI && o->smoother != SEM_SMOOTH_RAS)
+      fail(o->smoother == SEM_SMOOTH_ASM ? SEM_EUNSUPPORTED : SEM_EINVAL, "unsupported smoother");
+    if (o->smoother == SEM_SMOOTH_RAS)
+      for (int l = 0; l + 1 < o->nlevels; ++l)
+        if (o->p_levels[l] < 2) fail(SEM_EINVAL, "Schwarz smoothing needs p >= 2 on smoothed levels");
+    if (o->cheb_order < 0 || o->cheb_order > 32) fail(SEM_EINVAL, "cheb_order out of range");
+    if (!(o->lmax_fac > o->lmin_fac) || !(o->lmin_fac >= 0)) fail(SEM_EINVAL, "bad Chebyshev factors");
+  } else if (o->precond != SEM_PRECOND_JACOBI) {
+    fail(SEM_EINVAL, "unknown preconditioner");
+  }
+  if (o->smoother_prec != SEM_F64 && o->smoother_prec != SEM_F32)
+    fail(SEM_EINVAL, "smoother_prec must be SEM_F64 or SEM_F32");
+  if (o->fdm_prec < SEM_F64 || o->fdm_prec > SEM_F16) fail(SEM_EINVAL, "bad fdm_prec");
+  if ((o->fdm_prec == SEM_BF16 || o->fdm_prec == SEM_F16) && o->smoother_prec != SEM_F32)
+    fail(SEM_EINVAL, "BF16/FP16 FDM needs smoother_prec = SEM_F32");
+  if (o->arnoldi_steps < 1 || o->arnoldi_steps > kMaxArnoldi) fail(SEM_EINVAL, "arnoldi_steps in [1,16]");
+  if (o->krylov < SEM_KRYLOV_PCG || o->krylov > SEM_KRYLOV_FGMRES) fail(SEM_EINVAL, "bad krylov");
+  if (o->krylov == SEM_KRYLOV_FGMRES && (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart))
+    fail(SEM_EINVAL, "gmres_restart in [1, 64]");
+  if (o->coarse_maxit < 1) fail(SEM_EINVAL, "coarse_maxit must be >= 1");
+  for (int f = 0; f < 6; ++f)
+    if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
+  int64_t E = (int64_t)m->nex * m->ney * m->nez;
+  int64_t nloc = E * (p + 1) * (p + 1) * (p + 1);
+  if (nloc >= (int64_t)1 << 31) fail(SEM_EUNSUPPORTED, "more than 2^31 local nodes");
+}
+
+// carve every buffer; with a null arena base this only sizes the workspace
+static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
+  const sem_opts &o = c.opts;
+  const bool lowp = c.lowp;
+  const bool schwarz = o.precond == SEM_PRECOND_PMG && o.smoother == SEM_SMOOTH_RAS;
+  for (int l = 0; l < c.nlev; ++l) {
+    Level &L = c.lev[l];
+    const bool smoothed = !L.coarse;
+    L.xi = A.take<double>(L.N);
+    L.wq = A.take<double>(L.N);
+    L.D64 = A.take<double>(L.N * L.N);
+    L.D32 = A.take<float>(L.N * L.N);
+    if (l + 1 < c.nlev) {
+      L.J64 = A.take<double>(L.N * c.lev[l + 1].N);
+      L.J32 = A.take<float>(L.N * c.lev[l + 1].N);
+    }
+    L.X = A.take<double>(3 * L.nloc);
+    L.G64 = A.take<double>(6 * L.nloc);
+    if (lowp) L.G32 = A.take<float>(6 * L.nloc);
+    if (L.fine) L.BL = A.take<double>(L.nloc);
+    L.w64 = A.take<double>(L.nloc);
+    if (lowp) L.w32 = A.take<float>(L.nloc);
+    L.dinv64 = A.take<double>(L.nloc);
+    if (lowp) L.dinv32 = A.take<float>(L.nloc);
+    L.perm = A.take<int32_t>(L.nloc);
+    L.off = A.take<int32_t>(L.nglob + 1);
+    if (schwarz && smoothed) {
+      int pb = L.pb;
+      L.boxlen = A.take<double>(3 * L.E);
+      L.S64 = A.take<double>(3 * L.E * pb * pb);
+      L.lam64 = A.take<double>(3 * L.E * pb);
+      if (lowp) {
+        L.S32 = A.take<float>(3 * L.E * pb * pb);
+        L.lam32 = A.take<float>(3 * L.E * pb);
+        if (o.fdm_prec == SEM_BF16 || o.fdm_prec == SEM_F16)
+          L.S16 = A.take<uint16_t>(3 * L.E * 16 * 16);
+      }
+    }
+    L.d_b = A.take<double>(L.nloc);
+    L.d_x = A.take<double>(L.nloc);
+    L.d_r = A.take<double>(L.nloc);
+    L.d_d = A.take<double>(L.nloc);
+    L.d_w = A.take<double>(L.nloc);
+    L.d_t = A.take<double>(L.nloc);
+    if (lowp) {
+      L.f_b = A.take<float>(L.nloc);
+      L.f_x = A.take<float>(L.nloc);
+      L.f_r = A.take<float>(L.nloc);
+      L.f_d = A.take<float>(L.nloc);
+      L.f_w = A.take<float>(L.nloc);
+      L.f_t = A.take<float>(L.nloc);
+    }
+  }
+  c.partials = A.take<double>(kRedBlocks * 8);
+  c.counter = A.take<unsigned>(64);
+  c.dres = A.take<double>(2 * kMaxRestart + 64);
+  c.dsc = A.take<DevScalars>(1);
+  const Level &F = c.lev[0];
+  c.kr = A.take<double>(F.nloc);
+  c.kz = A.take<double>(F.nloc);
+  c.kzold = A.take<double>(F.nloc);
+  c.kp = A.take<double>(F.nloc);
+  c.kq = A.take<double>(F.nloc);
+  c.kx = A.take<double>(F.nloc);
+  if (o.krylov == SEM_KRYLOV_FGMRES) {
+    c.gV = A.take<double>((size_t)(o.gmres_restart + 1) * F.nloc);
+    c.gZ = A.take<double>((size_t)o.gmres_restart * F.nloc);
+  }
+  const Level &C = c.lev[c.nlev - 1];
+  c.cx = A.take<double>(C.nloc);
+  c.cr = A.take<double>(C.nloc);
+  c.cz = A.take<double>(C.nloc);
+  c.cp = A.take<double>(C.nloc);
+  c.cq = A.take<double>(C.nloc);
+  if (o.precond == SEM_PRECOND_PMG && c.nlev > 1)
+    c.av = A.take<double>((size_t)(o.arnoldi_steps + 1) * F.nloc);
+  // setup-only scratch
+  int Ng = m->p_geom + 1;
+  int64_t E = F.E;
+  sc.xyz = A.take<double>((size_t)E * Ng * Ng * Ng * 3);
+  sc.xig = A.take<double>(Ng);
+  sc.Jg = A.take<double>(Ng * (kMaxP + 1));
+  sc.bad = A.take<int>(64);
+  size_t gsb = 5 * F.nloc * sizeof(int32_t) + 16 + gs_sort_temp_bytes(F.nloc) + 8 * 256;
+  char *g = A.take<char>(gsb);
+  sc.gs.base = g;
+  sc.gs.cap = gsb;
+}
+
+static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const sem_opts *o) {
+  c.nex = m->nex;
+  c.ney = m->ney;
+  c.nez = m->nez;
+  for (int f = 0; f < 6; ++f) c.bc[f] = bc[f];
+  c.opts = *o;
+  c.lowp = o->smoother_prec == SEM_F32;
+  c.fdm_prec = o->fdm_prec == SEM_F64 ? (c.lowp ? SEM_F32 : SEM_F64) : o->fdm_prec;
+  if (c.fdm_prec == SEM_F64 && c.lowp) c.fdm_prec = SEM_F32;
+  if (o->precond == SEM_PRECOND_JACOBI) {
+    c.nlev = 1;
+    c.opts.p_levels[0] = p;
+  } else {
+    c.nlev = o->nlevels;
+  }
+  int64_t E = (int64_t)m->nex * m->ney * m->nez;
+  for (int l = 0; l < c.nlev; ++l) {
+    Level &L = c.lev[l];
+    L = Level();
+    L.p = c.opts.p_levels[l];
+    L.N = L.p + 1;
+    L.N3 = L.N * L.N * L.N;
+    L.pb = L.p + 3;
+    L.E = E;
+    L.nloc = E * L.N3;
+    L.nglob = ((int64_t)m->nex * L.p + 1) * ((int64_t)m->ney * L.p + 1) * ((int64_t)m->nez * L.p + 1);
+    L.fine = l == 0;
+    L.coarse = l == c.nlev - 1;
+    L.lowp = c.lowp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// operator pieces in precision T
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  static double *b(Level &L) { return L.d_b; }
+  static double *x(Level &L) { return L.d_x; }
+  static double *r(Level &L) { return L.d_r; }
+  static double *d(Level &L) { return L.d_d; }
+  static double *w(Level &L) { return L.d_w; }
+  static double *t(Level &L) { return L.d_t; }
+  static const double *dinv(const Level &L) { return L.dinv64; }
+};
+template <>
+struct Vec<float> {
+  static float *b(Level &L) { return L.f_b; }
+  static float *x(Level &L) { return L.f_x; }
+  static float *r(Level &L) { return L.f_r; }
+  static float *d(Level &L) { return L.f_d; }
+  static float *w(Level &L) { return L.f_w; }
+  static float *t(Level &L) { return L.f_t; }
+  static const float *dinv(const Level &L) { return L.dinv32; }
+};
+
+void Profiler::begin(int kind, hipStream_t s) {
+  if (used == pool.size()) {
+    hipEvent_t a, b;
+    SEM_HIP(hipEventCreate(&a));
+    SEM_HIP(hipEventCreate(&b));
+    pool.push_back({a, b});
+  }
+  Rec r{kind, pool[used].first, pool[used].second};
+  ++used;
+  SEM_HIP(hipEventRecord(r.a, s));
+  recs.push_back(r);
+}
+void Profiler::end(hipStream_t s) { (void)hipEventRecord(recs.back().b, s); }
+void Profiler::reset() {
+  recs.clear();
+  used = 0;
+}
+Profiler::~Profiler() {
+  for (auto &e : pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+}
+
+// records the enclosed launches when profiling a finest-level kernel
+struct ProfScope {
+  Profiler *p;
+  hipStream_t s;
+  ProfScope(const Ctx &c, const Level &L, int kind, hipStream_t st)
+      : p((c.prof && c.prof->on && L.fine) ? c.prof : nullptr), s(st) {
+    if (p) p->begin(kind, s);
+  }
+  ~ProfScope() {
+    if (p) p->end(s);
+  }
+};
+
+template <typename T>
+static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s) {
+  {
+    ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_AX64 : SEM_PROF_AX32, s);
+    launch_ax<T>(L, u, Au, s);
+  }
+  ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
+  launch_gs<T>(L, Au, s);
+}
+
+template <typename T>
+static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
+  const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother == SEM_SMOOTH_RAS &&
+                       !L.coarse;
+  if (!schwarz) {
+    const T *dinv = Vec<T>::dinv(L);
+    if (!dinv) fail(SEM_EINVAL, "Jacobi data of this precision were not built");
+    launch_scale<T>(L.nloc, dinv, r, z, s);
+    return;
+  }
+  {
+    ProfScope ps(c, L, SEM_PROF_FDM, s);
+    bool mma = false;
+    if constexpr (sizeof(T) == 4) {
+      if (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16) {
+        launch_fdm_mfma(c, L, (const float *)r, (float *)z, false, c.fdm_prec, s);
+        mma = true;
+      }
+    }
+    if (!mma) launch_fdm<T>(c, L, r, z, false, s);
+  }
+  ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
+  launch_gs<T>(L, z, s);
+}
+
+// Algorithm 2 read as a correction: x <- x + e (x_zero: x <- e)
+template <typename T>
+static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hipStream_t s) {
+  T *r = Vec<T>::r(L), *d = Vec<T>::d(L), *w = Vec<T>::w(L), *t = Vec<T>::t(L);
+  const double theta = 0.5 * (L.lmax + L.lmin), delta = 0.5 * (L.lmax - L.lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (x_zero) {
+    opS<T>(c, L, b, r, s);
+  } else {
+    opA<T>(c, L, x, w, s);
+    launch_sub<T>(L.nloc, b, w, w, s);
+    opS<T>(c, L, w, r, s);
+  }
+  launch_cheb_init<T>(L.nloc, x, r, d, (T)(1.0 / theta), x_zero, s);
+  for (int k = 0; k < L.K; ++k) {
+    opA<T>(c, L, d, w, s);
+    opS<T>(c, L, w, t, s);
+    double rho_new = 1.0 / (2.0 * sigma - rho);
+    launch_cheb_update<T>(L.nloc, x, r, d, t, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
+    rho = rho_new;
+  }
+  launch_axpby<T>(L.nloc, (T)1, d, (T)1, x, s);
+}
+
+static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
+  SEM_HIP(hipMemcpyAsync(c.hres, dev, bytes, hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+}
+
+// coarse Jacobi-PCG from x = 0: C.d_b -> c.cx (all scalars on the device)
+static void coarse_solve(Ctx &c, Level &C, hipStream_t s) {
+  const double tol = c.opts.coarse_tol;
+  const int maxit = c.opts.coarse_maxit;
+  DevScalars init{};
+  init.tol2 = tol * tol;
+  init.maxit = maxit;
+  launch_cpcg_init(c, C, init.tol2, maxit, s);
+  int done_iters = 0;
+  bool first = true;
+  if (tol <= 0.0) {
+    for (int it = 0; it < maxit; ++it) {
+      launch_cpcg_iteration(c, C, first, s);
+      first = false;
+    }
+    c.last_coarse_iters = maxit;
+    return;
+  }
+  int chunk = std::max(8, c.last_coarse_iters + 2);
+  while (true) {
+    int n = std::min(chunk, maxit - done_iters);
+    for (int it = 0; it < n; ++it) {
+      launch_cpcg_iteration(c, C, first, s);
+      first = false;
+    }
+    done_iters += n;
+    host_scalars(c, c.dsc, sizeof(DevScalars), s);
+    const DevScalars *h = reinterpret_cast<const DevScalars *>(c.hres);
+    if (h->done || done_iters >= maxit) {
+      c.last_coarse_iters = h->iters;
+      if (!(h->rr == h->rr)) fail(SEM_ENAN, "NaN in the coarse-grid solve");
+      return;
+    }
+    chunk = 8;
+  }
+}
+
+// one V-cycle of Algorithm 1 from x = 0 on level l (levels l.. in precision T)
+template <typename T>
+static void vcycle_level(Ctx &c, int l, hipStream_t s) {
+  Level &L = c.lev[l];
+  if (L.coarse) {
+    if constexpr (sizeof(T) == 4) launch_copy_cvt_f2d(L.nloc, L.f_b, L.d_b, s);
+    coarse_solve(c, L, s);
+    if constexpr (sizeof(T) == 4)
+      launch_copy_cvt_d2f(L.nloc, c.cx, L.f_x, s);
+    else
+      SEM_HIP(hipMemcpyAsync(L.d_x, c.cx, L.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  Level &C = c.lev[l + 1];
+  T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *r = Vec<T>::r(L), *w = Vec<T>::w(L);
+  chebyshev<T>(c, L, b, x, true, s);                    // x = M b
+  opA<T>(c, L, x, w, s);                                // r = b - A x
+  launch_sub<T>(L.nloc, b, w, r, s);
+  launch_restrict<T>(L, C, r, Vec<T>::b(C), s);         // r_C = P^T r
+  launch_gs<T>(C, Vec<T>::b(C), s);
+  vcycle_level<T>(c, l + 1, s);                         // e_C
+  launch_prolong<T>(L, C, Vec<T>::x(C), x, s);          // x += P e_C
+  chebyshev<T>(c, L, b, x, false, s);                   // post-smoothing
+}
+
+// z = M r on the finest level, FP64 in and out
+static void precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
+  Level &F = c.lev[0];
+  if (c.opts.precond == SEM_PRECOND_JACOBI) {
+    launch_scale<double>(F.nloc, F.dinv64, r, z, s);
+    return;
+  }
+  if (F.coarse) {  // single-level schedule: the coarse solve itself, in FP64
+    SEM_HIP(hipMemcpyAsync(F.d_b, r, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    coarse_solve(c, F, s);
+    SEM_HIP(hipMemcpyAsync(z, c.cx, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  if (c.lowp) {
+    launch_copy_cvt_d2f(F.nloc, r, F.f_b, s);
+    vcycle_level<float>(c, 0, s);
+    launch_copy_cvt_f2d(F.nloc, F.f_x, z, s);
+  } else {
+    SEM_HIP(hipMemcpyAsync(F.d_b, r, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    vcycle_level<double>(c, 0, s);
+    SEM_HIP(hipMemcpyAsync(z, F.d_x, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// weighted dots on the finest level, read back to the host
+static void dots(Ctx &c, const Level &L, int nd, const double *const *a, const double *const *b,
+                 double *out, hipStream_t s) {
+  launch_wdots(c, L.nloc, L.w64, nd, a, b, c.dres, s);
+  host_scalars(c, c.dres, nd * sizeof(double), s);
+  for (int j = 0; j < nd; ++j) {
+    out[j] = c.hres[j];
+    if (!std::isfinite(out[j])) fail(SEM_ENAN, "NaN/Inf in an inner product");
+  }
+}
+
+static double wnorm(Ctx &c, const Level &L, const double *v, hipStream_t s) {
+  const double *a[1] = {v};
+  double r;
+  dots(c, L, 1, a, a, &r, s);
+  return std::sqrt(r);
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi on S A (FP64), lambda~ = largest |Ritz value|
+static double arnoldi(Ctx &c, int l, hipStream_t s) {
+  Level &L = c.lev[l];
+  const int m = c.opts.arnoldi_steps;
+  const int64_t ld = c.lev[0].nloc;
+  double *V = c.av;
+  std::vector<double> H((kMaxArnoldi + 1) * kMaxArnoldi, 0.0);
+  const int ldh = kMaxArnoldi;
+  launch_start_vector(c, L, c.opts.seed, V, s);
+  double nrm = wnorm(c, L, V, s);
+  if (nrm == 0.0) return 0.0;
+  launch_axpby<double>(L.nloc, 1.0 / nrm, V, 0.0, V, s);
+  int k = 0;
+  double hmax = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double *w = V + (j + 1) * ld;
+    opA<double>(c, L, V + j * ld, L.d_t, s);
+    opS<double>(c, L, L.d_t, w, s);
+    // classical Gram-Schmidt, twice
+    std::vector<double> h(j + 1, 0.0);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_mdot(c, L.nloc, L.w64, j + 1, V, ld, w, c.dres, s);
+      launch_mupdate(L.nloc, j + 1, V, ld, c.dres, w, -1.0, s);
+      host_scalars(c, c.dres, (j + 1) * sizeof(double), s);
+      for (int i = 0; i <= j; ++i) h[i] += c.hres[i];
+    }
+    double hn = wnorm(c, L, w, s);
+    for (int i = 0; i <= j; ++i) {
+      H[i * ldh + j] = h[i];
+      hmax = std::max(hmax, std::fabs(h[i]));
+    }
+    H[(j + 1) * ldh + j] = hn;
+    hmax = std::max(hmax, hn);
+    k = j + 1;
+    if (hn <= 1e-14 * hmax) break;
+    launch_axpby<double>(L.nloc, 1.0 / hn, w, 0.0, w, s);
+  }
+  return hessenberg_max_abs_eig(H.data(), ldh, k);
+}
+
+// ---------------------------------------------------------------------------
+static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t s) {
+  Arena A;
+  A.base = static_cast<char *>(ws);
+  A.cap = bytes;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) fail(SEM_EINVAL, "workspace must be 256-byte aligned");
+  SetupScratch sc;
+  layout(c, m, A, sc);
+  SEM_HIP(hipHostMalloc((void **)&c.hres, 4096, hipHostMallocDefault));
+
+  const int Ng = m->p_geom + 1;
+  const int64_t E = c.lev[0].E;
+  SEM_HIP(hipMemcpyAsync(sc.xyz, m->xyz, (size_t)E * Ng * Ng * Ng * 3 * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  SEM_HIP(hipMemsetAsync(sc.bad, 0, 64 * sizeof(int), s));
+  SEM_HIP(hipMemsetAsync(c.counter, 0, 64 * sizeof(unsigned), s));
+  launch_gll(m->p_geom, sc.xig, nullptr, s);
+
+  for (int l = 0; l < c.nlev; ++l) {
+    Level &L = c.lev[l];
+    launch_gll(L.p, L.xi, L.wq, s);
+    launch_dmat(L.p, L.xi, L.D64, L.D32, s);
+    launch_interp(m->p_geom, L.p, sc.xig, L.xi, sc.Jg, nullptr, s);
+    launch_level_coords(c, sc.xyz, m->p_geom, sc.Jg, L, s);
+    launch_geom(c, L, sc.bad, s);
+    sc.gs.off = 0;
+    build_gather_scatter(c, L, sc.gs, s);
+    launch_weights(L, s);
+    launch_diag(L, L.d_t, s);
+    launch_gs<double>(L, L.d_t, s);
+    launch_jacobi_inv(L.nloc, L.d_t, L.w64, L.dinv64, L.dinv32, s);
+    if (L.boxlen) {
+      launch_boxlen(c, L, s);
+      launch_fdm_setup(c, L, s);
+    }
+  }
+  for (int l = 0; l + 1 < c.nlev; ++l) {
+    Level &F = c.lev[l], &C = c.lev[l + 1];
+    launch_interp(C.p, F.p, C.xi, F.xi, F.J64, F.J32, s);
+  }
+  int bad = 0;
+  SEM_HIP(hipMemcpyAsync(&bad, sc.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  if (bad) fail(SEM_EGEOM, "an element has a non-positive Jacobian determinant");
+  if (c.lowp) {
+    for (int l = 0; l < c.nlev; ++l)
+      if (c.lev[l].S16) launch_fdm_mfma(c, c.lev[l], nullptr, nullptr, false, -1, s);  // pack S
+  }
+
+  if (c.opts.precond == SEM_PRECOND_PMG) {
+    for (int l = 0; l + 1 < c.nlev; ++l) {
+      Level &L = c.lev[l];
+      double lt = c.opts.lambda_override[l] > 0 ? c.opts.lambda_override[l] : arnoldi(c, l, s);
+      if (!(lt > 0) || !std::isfinite(lt)) fail(SEM_ENAN, "Arnoldi gave no usable lambda~");
+      L.lam_tilde = lt;
+      L.lmin = c.opts.lmin_fac * lt;
+      L.lmax = c.opts.lmax_fac * lt;
+      L.K = c.opts.cheb_order;
+    }
+  }
+  SEM_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Krylov solvers (FP64 on the finest level)
+static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, bool flexible,
+                    sem_solve_info *info, hipStream_t s) {
+  Level &F = c.lev[0];
+  const int64_t n = F.nloc;
+  double *r = c.kr, *z = c.kz, *zo = c.kzold, *p = c.kp, *q = c.kq;
+  opA<double>(c, F, x, q, s);
+  launch_sub<double>(n, b, q, r, s);
+  const double r0 = wnorm(c, F, r, s);
+  info->r0_norm = r0;
+  if (r0 == 0.0) {
+    info->rel_res = info->true_rel_res = 0.0;
+    info->converged = 1;
+    return 0;
+  }
+  int it = 0;
+  double rel = 1.0;
+  while (it < maxit) {
+    precondition(c, r, z, s);
+    SEM_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double rz;
+    {
+      const double *a[1] = {r}, *bb[1] = {z};
+      dots(c, F, 1, a, bb, &rz, s);
+    }
+    while (it < maxit) {
+      opA<double>(c, F, p, q, s);
+      double pq;
+      {
+        const double *a[1] = {p}, *bb[1] = {q};
+        dots(c, F, 1, a, bb, &pq, s);
+      }
+      const double alpha = rz / pq;
+      launch_axpby<double>(n, alpha, p, 1.0, x, s);
+      launch_axpby<double>(n, -alpha, q, 1.0, r, s);
+      ++it;
+      rel = wnorm(c, F, r, s) / r0;
+      if (rel <= rtol) break;
+      std::swap(z, zo);
+      precondition(c, r, z, s);
+      double beta;
+      if (flexible) {
+        const double *a[2] = {r, r}, *bb[2] = {z, zo};
+        double d2[2];
+        dots(c, F, 2, a, bb, d2, s);
+        beta = (d2[0] - d2[1]) / rz;
+        rz = d2[0];
+      } else {
+        const double *a[1] = {r}, *bb[1] = {z};
+        double rzn;
+        dots(c, F, 1, a, bb, &rzn, s);
+        beta = rzn / rz;
+        rz = rzn;
+      }
+      launch_axpby<double>(n, 1.0, z, beta, p, s);
+    }
+    // true residual
+    opA<double>(c, F, x, q, s);
+    launch_sub<double>(n, b, q, r, s);
+    double tr = wnorm(c, F, r, s) / r0;
+    info->rel_res = rel;
+    info->true_rel_res = tr;
+    if (tr <= rtol) {
+      info->converged = 1;
+      return it;
+    }
+  }
+  info->converged = 0;
+  return it;
+}
+
+static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int maxit,
+                        sem_solve_info *info, hipStream_t s) {
+  Level &F = c.lev[0];
+  const int64_t n = F.nloc;
+  const int m = c.opts.gmres_restart;
+  double *r = c.kr, *q = c.kq;
+  double *V = c.gV, *Z = c.gZ;
+  opA<double>(c, F, x, q, s);
+  launch_sub<double>(n, b, q, r, s);
+  const double r0 = wnorm(c, F, r, s);
+  info->r0_norm = r0;
+  if (r0 == 0.0) {
+    info->rel_res = info->true_rel_res = 0.0;
+    info->converged = 1;
+    return 0;
+  }
+  int it = 0;
+  double rel = 1.0;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (it < maxit) {
+    double beta = wnorm(c, F, r, s);
+    launch_axpby<double>(n, 1.0 / beta, r, 0.0, V, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0, jused = 0;
+    for (j = 0; j < m; ++j) {
+      double *vj = V + j * n, *w = V + (j + 1) * n, *zj = Z + j * n;
+      precondition(c, vj, zj, s);
+      opA<double>(c, F, zj, w, s);
+      std::vector<double> h(j + 1, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_mdot(c, n, F.w64, j + 1, V, n, w, c.dres, s);
+        launch_mupdate(n, j + 1, V, n, c.dres, w, -1.0, s);
+        host_scalars(c, c.dres, (j + 1) * sizeof(double), s);
+        for (int i = 0; i <= j; ++i) h[i] += c.hres[i];
+      }
+      double hn = wnorm(c, F, w, s);
+      // apply previous rotations to the new column, then a new one
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      double den = std::sqrt(h[j] * h[j] + hn * hn);
+      cs[j] = den > 0 ? h[j] / den : 1.0;
+      sn[j] = den > 0 ? hn / den : 0.0;
+      h[j] = den;
+      for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jused = j + 1;
+      rel = std::fabs(g[j + 1]) / r0;
+      if (!std::isfinite(rel)) fail(SEM_ENAN, "NaN in FGMRES");
+      if (rel <= rtol || it >= maxit || hn == 0.0) break;
+      launch_axpby<double>(n, 1.0 / hn, w, 0.0, w, s);
+    }
+    // y = R^{-1} g, x += Z y
+    for (int i = jused - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < jused; ++k) acc -= H[i * m + k] * y[k];
+      y[i] = acc / H[i * m + i];
+    }
+    SEM_HIP(hipMemcpyAsync(c.dres, y.data(), jused * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_mupdate(n, jused, Z, n, c.dres, x, 1.0, s);
+    opA<double>(c, F, x, q, s);
+    launch_sub<double>(n, b, q, r, s);
+    double tr = wnorm(c, F, r, s) / r0;
+    info->rel_res = rel;
+    info->true_rel_res = tr;
+    if (tr <= rtol) {
+      info->converged = 1;
+      return it;
+    }
+  }
+  info->converged = 0;
+  return it;
+}
+
+static Level &level_of(sem_ctx *ctx, int level) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) fail(SEM_EINVAL, "null context");
+  if (level < 0 || level >= c->nlev) fail(SEM_EINVAL, "level out of range");
+  return c->lev[level];
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+struct sem_ctx : public sem::Ctx {};
+
+extern "C" {
+
+void sem_default_opts(sem_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nlevels = 3;
+  o->p_levels[0] = 7;
+  o->p_levels[1] = 3;
+  o->p_levels[2] = 1;
+  o->precond = SEM_PRECOND_PMG;
+  o->smoother = SEM_SMOOTH_JACOBI;
+  o->cheb_order = 2;
+  o->lmin_fac = 0.1;
+  o->lmax_fac = 1.1;
+  o->arnoldi_steps = 10;
+  o->seed = 0;
+  o->smoother_prec = SEM_F64;
+  o->fdm_prec = SEM_F64;
+  o->krylov = SEM_KRYLOV_FCG;
+  o->gmres_restart = 20;
+  o->coarse_tol = 1e-10;
+  o->coarse_maxit = 2000;
+}
+
+const char *sem_last_error(void) { return g_last_error.c_str(); }
+
+sem_status sem_plan(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const sem_opts *opts,
+                    size_t *bytes) {
+  return guarded([&] {
+    if (!bytes) fail(SEM_EINVAL, "null size pointer");
+    validate(mesh, p, bc, opts);
+    Ctx c;
+    init_ctx(c, mesh, p, bc, opts);
+    Arena A;
+    SetupScratch sc;
+    layout(c, mesh, A, sc);
+    *bytes = A.off + 256;
+  });
+}
+
+sem_status sem_setup(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const sem_opts *opts,
+                     void *ws, size_t bytes, void *stream, sem_ctx **out) {
+  sem_ctx *c = nullptr;
+  sem_status st = guarded([&] {
+    if (!out || !ws) fail(SEM_EINVAL, "null workspace or output pointer");
+    *out = nullptr;
+    validate(mesh, p, bc, opts);
+    if (!mesh->xyz) fail(SEM_EINVAL, "null coordinates");
+    c = new sem_ctx();
+    init_ctx(*c, mesh, p, bc, opts);
+    setup(*c, mesh, ws, bytes, as_stream(stream));
+    *out = c;
+  });
+  if (st != SEM_OK && c) {
+    if (c->hres) (void)hipHostFree(c->hres);
+    delete c;
+  }
+  return st;
+}
+
+sem_status sem_destroy(sem_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    if (ctx->hres) SEM_HIP(hipHostFree(ctx->hres));
+    delete ctx->prof;
+    delete ctx;
+  });
+}
+
+sem_status sem_profile(sem_ctx *ctx, int32_t enable) {
+  return guarded([&] {
+    if (!ctx) fail(SEM_EINVAL, "null context");
+    if (!ctx->prof) ctx->prof = new Profiler();
+    ctx->prof->reset();
+    ctx->prof->on = enable != 0;
+  });
+}
+
+sem_status sem_profile_read(sem_ctx *ctx, double *total_ms, int64_t *launches) {
+  return guarded([&] {
+    if (!ctx || !total_ms || !launches) fail(SEM_EINVAL, "null argument");
+    for (int k = 0; k < SEM_PROF_COUNT; ++k) {
+      total_ms[k] = 0.0;
+      launches[k] = 0;
+    }
+    if (!ctx->prof) return;
+    for (auto &r : ctx->prof->recs) {
+      SEM_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      SEM_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      total_ms[r.kind] += ms;
+      launches[r.kind] += 1;
+    }
+  });
+}
+
+sem_status sem_level_info(const sem_ctx *ctx, int32_t level, sem_level_desc *out) {
+  return guarded([&] {
+    if (!out) fail(SEM_EINVAL, "null output");
+    const Level &L = level_of(const_cast<sem_ctx *>(ctx), level);
+    out->p = L.p;
+    out->N = L.N;
+    out->E = L.E;
+    out->nlocal = L.nloc;
+    out->nglobal = L.nglob;
+    out->nshared = L.nseg;
+    out->lmin = L.lmin;
+    out->lmax = L.lmax;
+  });
+}
+
+sem_status sem_gll(int32_t p, double *nodes, double *weights, void *stream) {
+  return guarded([&] {
+    if (p < 1 || p > 15) fail(SEM_EINVAL, "p must be in [1, 15]");
+    if (!nodes) fail(SEM_EINVAL, "null nodes");
+    launch_gll(p, nodes, weights, as_stream(stream));
+  });
+}
+
+sem_status sem_coords(const sem_ctx *ctx, int32_t level, double *xyz, void *stream) {
+  return guarded([&] {
+    const Level &L = level_of(const_cast<sem_ctx *>(ctx), level);
+    if (!xyz) fail(SEM_EINVAL, "null output");
+    SEM_HIP(hipMemcpyAsync(xyz, L.X, 3 * L.nloc * sizeof(double), hipMemcpyDeviceToDevice,
+                           as_stream(stream)));
+  });
+}
+
+sem_status sem_gather(const sem_ctx *ctx, int32_t level, const double *ug, double *ul,
+                      void *stream) {
+  return guarded([&] {
+    const Level &L = level_of(const_cast<sem_ctx *>(ctx), level);
+    if (!ug || !ul) fail(SEM_EINVAL, "null vector");
+    launch_gather(*ctx, L, ug, ul, as_stream(stream));
+  });
+}
+
+sem_status sem_rhs(sem_ctx *ctx, const double *f, double *b, void *stream) {
+  return guarded([&] {
+    Level &L = level_of(ctx, 0);
+    if (!f || !b) fail(SEM_EINVAL, "null vector");
+    launch_rhs(L, f, b, as_stream(stream));
+    launch_gs<double>(L, b, as_stream(stream));
+  });
+}
+
+sem_status sem_apply_A(sem_ctx *ctx, int32_t level, int32_t prec, const void *u, void *Au,
+                       void *stream) {
+  return guarded([&] {
+    Level &L = level_of(ctx, level);
+    if (!u || !Au || u == Au) fail(SEM_EINVAL, "null or aliased vectors");
+    hipStream_t s = as_stream(stream);
+    if (prec == SEM_F64)
+      opA<double>(*ctx, L, (const double *)u, (double *)Au, s);
+    else if (prec == SEM_F32)
+      opA<float>(*ctx, L, (const float *)u, (float *)Au, s);
+    else
+      fail(SEM_EINVAL, "prec must be SEM_F64 or SEM_F32");
+  });
+}
+
+sem_status sem_apply_S(sem_ctx *ctx, int32_t level, int32_t prec, const void *r, void *z,
+                       void *stream) {
+  return guarded([&] {
+    Level &L = level_of(ctx, level);
+    if (!r || !z || r == z) fail(SEM_EINVAL, "null or aliased vectors");
+    hipStream_t s = as_stream(stream);
+    if (prec == SEM_F64)
+      opS<double>(*ctx, L, (const double *)r, (double *)z, s);
+    else if (prec == SEM_F32)
+      opS<float>(*ctx, L, (const float *)r, (float *)z, s);
+    else
+      fail(SEM_EINVAL, "prec must be SEM_F64 or SEM_F32");
+  });
+}
+
+sem_status sem_smooth(sem_ctx *ctx, int32_t level, int32_t prec, const void *b, void *x,
+                      void *stream) {
+  return guarded([&] {
+    Level &L = level_of(ctx, level);
+    if (L.coarse || ctx->opts.precond != SEM_PRECOND_PMG)
+      fail(SEM_EINVAL, "level has no smoother (coarsest level or Jacobi preconditioner)");
+    if (!b || !x) fail(SEM_EINVAL, "null vector");
+    hipStream_t s = as_stream(stream);
+    if (prec == SEM_F64)
+      chebyshev<double>(*ctx, L, (const double *)b, (double *)x, false, s);
+    else if (prec == SEM_F32)
+      chebyshev<float>(*ctx, L, (const float *)b, (float *)x, false, s);
+    else
+      fail(SEM_EINVAL, "prec must be SEM_F64 or SEM_F32");
+  });
+}
+
+sem_status sem_prolong(sem_ctx *ctx, int32_t level, int32_t prec, const void *xc, void *xf,
+                       void *stream) {
+  return guarded([&] {
+    Level &F = level_of(ctx, level);
+    Level &C = level_of(ctx, level + 1);
+    if (!xc || !xf) fail(SEM_EINVAL, "null vector");
+    hipStream_t s = as_stream(stream);
+    if (prec == SEM_F64)
+      launch_prolong<double>(F, C, (const double *)xc, (double *)xf, s);
+    else if (prec == SEM_F32)
+      launch_prolong<float>(F, C, (const float *)xc, (float *)xf, s);
+    else
+      fail(SEM_EINVAL, "prec must be SEM_F64 or SEM_F32");
+  });
+}
+
+sem_status sem_restrict(sem_ctx *ctx, int32_t level, int32_t prec, const void *rf, void *rc,
+                        void *stream) {
+  return guarded([&] {
+    Level &F = level_of(ctx, level);
+    Level &C = level_of(ctx, level + 1);
+    if (!rf || !rc) fail(SEM_EINVAL, "null vector");
+    hipStream_t s = as_stream(stream);
+    if (prec == SEM_F64) {
+      launch_restrict<double>(F, C, (const double *)rf, (double *)rc, s);
+      launch_gs<double>(C, (double *)rc, s);
+    } else if (prec == SEM_F32) {
+      if (!F.w32) fail(SEM_EINVAL, "FP32 weights were not built");
+      launch_restrict<float>(F, C, (const float *)rf, (float *)rc, s);
+      launch_gs<float>(C, (float *)rc, s);
+    } else {
+      fail(SEM_EINVAL, "prec must be SEM_F64 or SEM_F32");
+    }
+  });
+}
+
+sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(SEM_EINVAL, "null context");
+    if (!r || !z) fail(SEM_EINVAL, "null vector");
+    precondition(*ctx, r, z, as_stream(stream));
+  });
+}
+
+sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
+                     sem_solve_info *info, void *stream) {
+  sem_solve_info local{};
+  sem_solve_info *inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  bool noconv = false;
+  sem_status st = guarded([&] {
+    if (!ctx) fail(SEM_EINVAL, "null context");
+    if (!b || !x) fail(SEM_EINVAL, "null vector");
+    if (!(rtol > 0) || maxit < 0) fail(SEM_EINVAL, "rtol must be > 0 and maxit >= 0");
+    hipStream_t s = as_stream(stream);
+    for (int l = 0; l < ctx->nlev; ++l) inf->lambda_tilde[l] = ctx->lev[l].lam_tilde;
+    int it;
+    if (ctx->opts.krylov == SEM_KRYLOV_FGMRES)
+      it = solve_fgmres(*ctx, b, x, rtol, maxit, inf, s);
+    else
+      it = solve_cg(*ctx, b, x, rtol, maxit, ctx->opts.krylov == SEM_KRYLOV_FCG, inf, s);
+    inf->iters = it;
+    inf->coarse_iters = ctx->last_coarse_iters;
+    SEM_HIP(hipStreamSynchronize(s));
+    noconv = !inf->converged;
+  });
+  if (st == SEM_OK && noconv) {
+    g_last_error = "no convergence within maxit iterations";
+    return SEM_ENOCONV;
+  }
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// p-multigrid transfers (Sec. 2.2.2, Algorithm 1, "coarsen" and "prolongate").
+//
+// P interpolates the coarse cardinal basis to the fine GLL nodes element by
+// element, P = J (x) J (x) J with J[i][j] = h^c_j(xi^f_i); a continuous coarse
+// field stays continuous, so the fine E-vector comes out consistent.
+// P^T (on global vectors) = assemble_c o (J^T (x) J^T (x) J^T) o (1/mult_f):
+// the consistent fine residual is split among its copies, contracted, then
+// summed over shared coarse nodes (QQ^T) and masked by the caller.
+#include "sem_internal.h"
+
+namespace sem {
+
+constexpr int kTN = 11;  // largest N handled (p <= 10)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__restrict__ J,
+                                                 const T *__restrict__ xc, T *__restrict__ xf) {
+  __shared__ T sJ[kTN * kTN];
+  __shared__ T a[kTN * kTN * kTN];
+  __shared__ T b[kTN * kTN * kTN];
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+  for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
+  for (int t = tid; t < Nc3; t += bs) a[t] = xc[e * Nc3 + t];
+  __syncthreads();
+  // b[c][bb][i] = sum_a J[i][a] x[c][bb][a]
+  for (int t = tid; t < Nc * Nc * Nf; t += bs) {
+    int i = t % Nf, cb = t / Nf;
+    T s = 0;
+    for (int q = 0; q < Nc; ++q) s += sJ[i * Nc + q] * a[cb * Nc + q];
+    b[t] = s;
+  }
+  __syncthreads();
+  // a[c][j][i] = sum_bb J[j][bb] b[c][bb][i]
+  for (int t = tid; t < Nc * Nf * Nf; t += bs) {
+    int i = t % Nf, j = (t / Nf) % Nf, c = t / (Nf * Nf);
+    T s = 0;
+    for (int q = 0; q < Nc; ++q) s += sJ[j * Nc + q] * b[(c * Nc + q) * Nf + i];
+    a[t] = s;
+  }
+  __syncthreads();
+  // xf[k][j][i] += sum_c J[k][c] a[c][j][i]
+  for (int t = tid; t < Nf3; t += bs) {
+    int ji = t % (Nf * Nf), k = t / (Nf * Nf);
+    T s = 0;
+    for (int q = 0; q < Nc; ++q) s += sJ[k * Nc + q] * a[q * Nf * Nf + ji];
+    xf[e * Nf3 + t] += s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__restrict__ J,
+                                                  const T *__restrict__ w, const T *__restrict__ rf,
+                                                  T *__restrict__ rc) {
+  __shared__ T sJ[kTN * kTN];
+  __shared__ T a[kTN * kTN * kTN];
+  __shared__ T b[kTN * kTN * kTN];
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+  for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
+  for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * rf[e * Nf3 + t];
+  __syncthreads();
+  // b[k][j][aa] = sum_i J[i][aa] r[k][j][i]
+  for (int t = tid; t < Nf * Nf * Nc; t += bs) {
+    int aa = t % Nc, kj = t / Nc;
+    T s = 0;
+    for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + aa] * a[kj * Nf + q];
+    b[t] = s;
+  }
+  __syncthreads();
+  // a[k][bb][aa] = sum_j J[j][bb] b[k][j][aa]
+  for (int t = tid; t < Nf * Nc * Nc; t += bs) {
+    int aa = t % Nc, bb = (t / Nc) % Nc, k = t / (Nc * Nc);
+    T s = 0;
+    for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + bb] * b[(k * Nf + q) * Nc + aa];
+    a[t] = s;
+  }
+  __syncthreads();
+  // rc[c][bb][aa] = sum_k J[k][c] a[k][bb][aa]
+  for (int t = tid; t < Nc3; t += bs) {
+    int ba = t % (Nc * Nc), c = t / (Nc * Nc);
+    T s = 0;
+    for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + c] * a[q * Nc * Nc + ba];
+    rc[e * Nc3 + t] = s;
+  }
+}
+
+static int transfer_threads(int Nf) {
+  int n = Nf * Nf * Nf;
+  int t = ((n + 63) / 64) * 64;
+  return t > 256 ? 256 : t;
+}
+
+template <typename T>
+void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s) {
+  const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
+  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)F.E), dim3(transfer_threads(F.N)), 0, s, F.N,
+                     C.N, J, xc, xf);
+  SEM_LAUNCH("k_prolong");
+}
+
+template <typename T>
+void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s) {
+  const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
+  const T *w = sizeof(T) == 8 ? (const T *)F.w64 : (const T *)F.w32;
+  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)F.E), dim3(transfer_threads(F.N)), 0, s, F.N,
+                     C.N, J, w, rf, rc);
+  SEM_LAUNCH("k_restrict");
+}
+
+template void launch_prolong<double>(const Level &, const Level &, const double *, double *,
+                                     hipStream_t);
+template void launch_prolong<float>(const Level &, const Level &, const float *, float *,
+                                    hipStream_t);
+template void launch_restrict<double>(const Level &, const Level &, const double *, double *,
+                                      hipStream_t);
+template void launch_restrict<float>(const Level &, const Level &, const float *, float *,
+                                     hipStream_t);
+
+}  // namespace sem

@@ -1,0 +1,168 @@
+"""GPU parity of the setup and operator entry points against the oracle.
+
+FP64 results must match the oracle to 1e-12 relative (2-norm over E-vector
+entries); FP32 results to 1e-5.
+"""
+import numpy as np
+import pytest
+
+from oracle import gll as ogll
+from oracle.operator import apply_A as o_apply_A
+from pairs import Pair, dev, global_mask, host, rel_err
+from paper_2110_07663_amd import sem
+from paper_2110_07663_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 8, 9, 10, 13])
+def test_gll_nodes_and_weights(p):
+    xg, wg = sem.gll_nodes(p)
+    xo, wo = ogll.gll_nodes_weights(p)
+    np.testing.assert_allclose(xg, xo, atol=2e-16 * p * p, rtol=0)
+    np.testing.assert_allclose(wg, wo, rtol=1e-14)
+
+
+@pytest.mark.parametrize("shape,p,mesh,bc", [
+    ((3, 2, 5), 3, "sin", (1, 1, 1, 1, 1, 1)),
+    ((2, 3, 2), 7, "sin", (1, 0, 0, 1, 1, 0)),
+    ((3, 3, 3), 5, "shift", (1, 1, 1, 1, 1, 1)),
+    ((1, 1, 1), 4, "box", (0, 0, 0, 0, 0, 0)),
+])
+def test_numbering_and_coordinates(shape, p, mesh, bc):
+    P = Pair(shape if mesh != "shift" else shape[0], p, mesh=mesh, bc=bc)
+    info = P.gpu.levels[0]
+    num = P.ora.levels[0].num
+    assert info.nglobal == num.n and info.nlocal == num.E * (p + 1) ** 3
+    shared_or_dir = (num.mult > 1) | (num.mask_global == 0)
+    assert info.nshared == int(shared_or_dir.sum())
+    X = host(P.gpu.coords(0))
+    assert rel_err(X, P.oracle_nodes(0)) < 1e-14
+    g, o = P.random_local(11, masked=False)
+    np.testing.assert_array_equal(host(g), o.reshape(-1))
+
+
+@pytest.mark.parametrize("shape,p,mesh", [
+    ((3, 2, 5), 1, "sin"), ((3, 2, 5), 2, "sin"), ((3, 2, 5), 3, "sin"), ((2, 3, 2), 5, "sin"),
+    ((3, 2, 3), 7, "sin"), ((2, 2, 3), 8, "sin"), ((2, 2, 2), 9, "sin"), ((2, 1, 2), 10, "sin"),
+    (4, 7, "shift"), ((5, 3, 2), 6, "box"),
+])
+def test_apply_A_fp64(shape, p, mesh):
+    P = Pair(shape if mesh != "shift" else shape, p, mesh=mesh, bc=(1, 1, 0, 1, 1, 0))
+    g, o = P.random_local(3, masked=False)
+    Ag = host(P.gpu.apply_A(g))
+    Ao = P.ora.levels[0].apply_A(o)
+    assert rel_err(Ag, Ao) < 1e-12
+
+
+@pytest.mark.parametrize("p", [3, 7])
+def test_apply_A_fp32(p):
+    t = __import__("torch")
+    P = Pair((3, 2, 3), p, mesh="sin", smoother_prec=sem.F32)
+    g, o = P.random_local(5, masked=True)
+    Ag = host(P.gpu.apply_A(g.to(t.float32)))
+    Ao = P.ora.levels[0].apply_A(o)
+    assert rel_err(Ag, Ao) < 1e-5
+
+
+def test_apply_A_neumann_annihilates_constants():
+    t = __import__("torch")
+    P = Pair(3, 6, mesh="sin", bc=(0,) * 6, oracle=False)
+    one = t.ones(P.gpu.levels[0].nlocal, dtype=t.float64, device="cuda")
+    A1 = host(P.gpu.apply_A(one))
+    g, _ = P.random_local(1, masked=False)
+    Ag = host(P.gpu.apply_A(g))
+    assert np.abs(A1).max() < 1e-12 * np.abs(Ag).max()
+
+
+def test_apply_A_bitwise_repeatable():
+    P = Pair(3, 7, mesh="sin", oracle=False)
+    g, _ = P.random_local(2)
+    a = host(P.gpu.apply_A(g))
+    b = host(P.gpu.apply_A(g))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_rhs_matches_oracle():
+    P = Pair((3, 2, 2), 5, mesh="sin")
+    f, _ = wl.sinusoid(1, 2, 1)
+    X = host(P.gpu.coords(0))
+    fl = f(X[0], X[1], X[2])
+    bg = host(P.gpu.rhs(dev(fl)))
+    Xo = P.ora.fine.X
+    bo = P.ora.rhs(f(Xo[0], Xo[1], Xo[2]))
+    assert rel_err(bg, bo) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [sem.F64, sem.F32])
+def test_jacobi_surrogate(prec):
+    t = __import__("torch")
+    P = Pair((2, 3, 2), 5, mesh="sin", schedule=(5, 3, 1),
+             smoother_prec=sem.F32 if prec == sem.F32 else sem.F64, lambda_override=[1.0, 1.0])
+    g, o = P.random_local(9)
+    if prec == sem.F32:
+        g = g.to(t.float32)
+    for level in range(3):
+        gl, ol = P.random_local(20 + level, level=level)
+        if prec == sem.F32:
+            gl = gl.to(t.float32)
+        zg = host(P.gpu.apply_S(gl, level=level))
+        zo = P.ora.levels[level].apply_S(ol)
+        assert rel_err(zg, zo) < (1e-12 if prec == sem.F64 else 1e-6)
+
+
+@pytest.mark.parametrize("sched", [(7, 3, 1), (5, 3, 1), (9, 5, 1), (4, 2, 1)])
+def test_transfers(sched):
+    P = Pair((3, 2, 2), sched[0], mesh="sin", schedule=sched, lambda_override=[1.0] * 3)
+    for l in range(len(sched) - 1):
+        gc, oc = P.random_local(30 + l, level=l + 1)
+        gf, of = P.random_local(40 + l, level=l)
+        xf = gf.clone()
+        P.gpu.prolong(gc, xf, level=l)
+        from oracle import mg
+        ref = of + mg.prolong(P.ora.levels[l].J_to_coarse, oc)
+        assert rel_err(host(xf), ref) < 1e-12
+        rc = host(P.gpu.restrict(gf, level=l))
+        refc = mg.restrict(P.ora.levels[l].num, P.ora.levels[l + 1].num, P.ora.levels[l].J_to_coarse, of)
+        assert rel_err(rc, refc) < 1e-12
+
+
+def _subgrid_apply(xyz_all, n, p, e_center, u_global, bc):
+    """Oracle A u at the nodes of one element from the 3x3x3 element block around it."""
+    from oracle.geom import geometric_factors
+    from oracle.mesh import Numbering, level_coordinates
+    ex, ey, ez = e_center % n, (e_center // n) % n, e_center // (n * n)
+    lo = [max(0, c - 1) for c in (ex, ey, ez)]
+    hi = [min(n - 1, c + 1) for c in (ex, ey, ez)]
+    sx, sy, sz = hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1
+    els = [((z * n) + y) * n + x for z in range(lo[2], hi[2] + 1) for y in range(lo[1], hi[1] + 1)
+           for x in range(lo[0], hi[0] + 1)]
+    sub = Numbering(sx, sy, sz, p, (0,) * 6)
+    X = level_coordinates(xyz_all[els], 1, p)
+    G, _, _ = geometric_factors(X, p)
+    nx = n * p + 1
+    gx = sub.gx + lo[0] * p
+    gy = sub.gy + lo[1] * p
+    gz = sub.gz + lo[2] * p
+    u = u_global[(gz * nx + gy) * nx + gx]
+    Au = o_apply_A(sub, G, u)
+    c = els.index(e_center)
+    m = global_mask(n, n, n, p, bc)[((gz * nx + gy) * nx + gx)[c]]
+    return (Au[c] * m).reshape(-1)
+
+
+@pytest.mark.parametrize("n,p", [(32, 7), (16, 7)])
+def test_apply_A_full_size_sampled(n, p):
+    """Full-size layer-shift mesh: sampled elements against the oracle's 3x3x3 sub-mesh."""
+    P = Pair(n, p, mesh="shift", oracle=False)
+    L = P.gpu.levels[0]
+    ug = wl.random_global(L.nglobal, 7) * global_mask(n, n, n, p, (1,) * 6)
+    Ag = P.gpu.apply_A(P.gpu.gather(dev(ug)))
+    xyz = wl.layer_shift_vertices(n, seed=3)
+    N3 = (p + 1) ** 3
+    rng = np.random.default_rng(0)
+    sample = [0, n ** 3 - 1, n // 2 * (1 + n + n * n)] + list(rng.integers(0, n ** 3, 9))
+    for e in sample:
+        got = host(Ag[e * N3:(e + 1) * N3])
+        ref = _subgrid_apply(xyz, n, p, int(e), ug, (1,) * 6)
+        assert rel_err(got, ref) < 1e-12, e

@@ -1,0 +1,162 @@
+"""GPU parity of the smoother, V-cycle and Krylov entry points against the oracle."""
+import numpy as np
+import pytest
+
+from pairs import Pair, dev, host, rel_err
+from paper_2110_07663_amd import sem
+from paper_2110_07663_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@pytest.mark.parametrize("smoother,p,shape", [("jacobi", 5, (3, 2, 2)), ("ras", 5, (3, 2, 2)),
+                                              ("ras", 7, (2, 3, 2)), ("ras", 3, 3)])
+def test_schwarz_and_jacobi_surrogate_fp64(smoother, p, shape):
+    P = Pair(shape, p, mesh="sin", schedule=(p, 1), smoother=smoother, lambda_override=[2.0])
+    g, o = P.random_local(4)
+    assert rel_err(host(P.gpu.apply_S(g)), P.ora.levels[0].apply_S(o)) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1, 1, 1), (1, 0, 0, 1, 0, 1), (0, 0, 0, 0, 0, 1)])
+def test_ras_boundary_conditions(bc):
+    P = Pair((3, 2, 2), 4, mesh="sin", schedule=(4, 1), smoother="ras", bc=bc, lambda_override=[2.0])
+    g, o = P.random_local(6)
+    assert rel_err(host(P.gpu.apply_S(g)), P.ora.levels[0].apply_S(o)) < 1e-12
+
+
+def test_ras_fp32():
+    t = _torch()
+    P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
+             lambda_override=[2.0, 2.0])
+    g, o = P.random_local(8)
+    zg = host(P.gpu.apply_S(g.to(t.float32)))
+    assert rel_err(zg, P.ora.levels[0].apply_S(o)) < 1e-5
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ras"])
+def test_chebyshev_smooth(smoother):
+    P = Pair((2, 3, 2), 5, mesh="sin", schedule=(5, 3, 1), smoother=smoother, cheb_order=3,
+             lambda_override=[1.7, 1.9])
+    b, bo = P.random_local(12)
+    x, xo = P.random_local(13)
+    P.gpu.smooth(b, x, level=0)
+    ref = P.ora.smooth(bo, xo, level=0)
+    assert rel_err(host(x), ref) < 1e-12
+    # level 1 as well
+    b1, bo1 = P.random_local(14, level=1)
+    x1, xo1 = P.random_local(15, level=1)
+    P.gpu.smooth(b1, x1, level=1)
+    assert rel_err(host(x1), P.ora.smooth(bo1, xo1, level=1)) < 1e-12
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ras"])
+def test_arnoldi_lambda_tilde(smoother):
+    P = Pair((3, 2, 2), 6, mesh="sin", schedule=(6, 3, 1), smoother=smoother, seed=77)
+    for l in range(2):
+        got = P.gpu.levels[l].lmax / 1.1
+        ref = P.ora.levels[l].lam_tilde
+        assert abs(got - ref) < 1e-9 * ref, (l, got, ref)
+
+
+@pytest.mark.parametrize("smoother,sched", [("jacobi", (7, 3, 1)), ("ras", (7, 3, 1)),
+                                            ("ras", (5, 1)), ("jacobi", (4, 2, 1))])
+def test_vcycle_fixed_coarse_iterations(smoother, sched):
+    P = Pair((3, 2, 2), sched[0], mesh="sin", schedule=sched, smoother=smoother,
+             coarse_tol=0.0, coarse_maxit=25, lambda_override=[1.5] * (len(sched) - 1))
+    g, o = P.random_local(21)
+    zg = host(P.gpu.vcycle(g))
+    zo = P.ora.vcycle(o)
+    assert rel_err(zg, zo) < 1e-12
+
+
+def test_vcycle_converged_coarse_matches_to_coarse_tolerance():
+    P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", coarse_tol=1e-10)
+    g, o = P.random_local(22)
+    assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-8
+
+
+def _rhs(P, a=1, b=1, c=1):
+    f, u = wl.sinusoid(a, b, c)
+    X = host(P.gpu.coords(0))
+    bg = P.gpu.rhs(dev(f(X[0], X[1], X[2])))
+    Xo = P.ora.fine.X
+    bo = P.ora.rhs(f(Xo[0], Xo[1], Xo[2]))
+    return bg, bo
+
+
+@pytest.mark.parametrize("krylov,smoother", [(sem.KRYLOV_FCG, "jacobi"), (sem.KRYLOV_FCG, "ras"),
+                                             (sem.KRYLOV_PCG, "jacobi"), (sem.KRYLOV_FGMRES, "ras")])
+def test_solve_fixed_iterations(krylov, smoother):
+    """Same number of outer iterations on both sides: iterates agree to rounding."""
+    kname = {sem.KRYLOV_FCG: "fcg", sem.KRYLOV_PCG: "pcg", sem.KRYLOV_FGMRES: "fgmres"}[krylov]
+    P = Pair((3, 2, 2), 5, mesh="sin", schedule=(5, 3, 1), smoother=smoother, krylov=krylov,
+             coarse_tol=0.0, coarse_maxit=30, lambda_override=[1.6, 1.8], gmres_restart=4)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-30, maxit=6, allow_noconv=True)
+    res = P.ora.solve(bo, tol=1e-30, maxit=6, krylov=kname, restart=4)
+    assert info.iters == res.iters == 6
+    assert rel_err(host(xg), res.x) < 1e-11
+
+
+@pytest.mark.parametrize("krylov", [sem.KRYLOV_FCG, sem.KRYLOV_FGMRES])
+def test_solve_to_tolerance(krylov):
+    P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", krylov=krylov)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
+    assert info.converged and info.true_rel_res <= 1e-8
+    L = P.ora.fine
+    x = host(xg)
+    r = bo - L.apply_A(x)
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+    res = P.ora.solve(bo, tol=1e-8, maxit=100)
+    assert abs(info.iters - res.iters) <= 1
+    assert rel_err(x, res.x) < 1e-6
+
+
+def test_jacobi_pcg_config1_small():
+    """Plain Jacobi-PCG on the undeformed cube, p = 3 (the oracle-size workload)."""
+    P = Pair(4, 3, mesh="box", krylov=sem.KRYLOV_PCG, precond=sem.PRECOND_JACOBI)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-10, maxit=500)
+    res = P.ora.jacobi_pcg(bo, 1e-10, 500)
+    assert abs(info.iters - res.iters) <= 1
+    assert rel_err(host(xg), res.x) < 1e-9
+    # discretisation error against the manufactured solution
+    _, u = wl.sinusoid(1, 1, 1)
+    X = host(P.gpu.coords(0))
+    assert np.abs(host(xg) - u(X[0], X[1], X[2])).max() < 2e-4
+
+
+def test_mixed_precision_solve():
+    P = Pair(4, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
+    assert info.converged
+    L = P.ora.fine
+    r = bo - L.apply_A(host(xg))
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+    res = P.ora.solve(bo, tol=1e-8, maxit=100)
+    assert info.iters <= res.iters + 2
+
+
+def test_error_paths():
+    t = _torch()
+    P = Pair(2, 3, mesh="box", schedule=(3, 1), oracle=False)
+    bg = t.full((P.gpu.levels[0].nlocal,), float("nan"), dtype=t.float64, device="cuda")
+    with pytest.raises(sem.SemError) as ei:
+        P.gpu.solve(bg, rtol=1e-8, maxit=10)
+    assert ei.value.status == sem.SEM_ENAN
+    b, _ = P.random_local(1)
+    x, info = P.gpu.solve(b, rtol=1e-12, maxit=1, allow_noconv=True)
+    assert info.converged == 0 and info.iters == 1
+    # inverted element is rejected at setup
+    xyz = wl.box_vertices(2, 2, 2)
+    xyz[0, [0, 1]] = xyz[0, [1, 0]]
+    with pytest.raises(sem.SemError) as ei:
+        sem.Solver(2, 2, 2, xyz, 1, 3, opts=sem.make_opts(schedule=(3, 1)))
+    assert ei.value.status == sem.SEM_EGEOM

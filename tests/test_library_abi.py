@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every function include/sem.h declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2110_07663_amd import sem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:sem_status|void|const char \*)\s*(sem_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_paper_calls():
+    names = declared_functions()
+    for required in ("sem_setup", "sem_apply_A", "sem_smooth", "sem_vcycle", "sem_solve"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(sem.LIB_PATH), reason="libsem.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(sem.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(declared_functions()) == sorted(sem.EXPORTS)
+
+
+@pytest.mark.skipif(not os.path.exists(sem.LIB_PATH), reason="libsem.so not built")
+def test_host_side_validation_without_gpu():
+    """Planning is host-only: bad inputs are rejected with status codes, no GPU needed."""
+    import numpy as np
+    from paper_2110_07663_amd import workloads as wl
+    L = sem.lib()
+    xyz = np.ascontiguousarray(wl.box_vertices(2, 2, 2))
+    mesh = sem.Mesh(2, 2, 2, 1, xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    bc = (ctypes.c_int8 * 6)(1, 1, 1, 1, 1, 1)
+    n = ctypes.c_size_t(0)
+    o = sem.make_opts(schedule=(7, 3, 1))
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o), ctypes.byref(n)) == sem.SEM_OK
+    assert n.value > 0
+    o_bad = sem.make_opts(schedule=(7, 5, 6))
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_bad), ctypes.byref(n)) == sem.SEM_EINVAL
+    assert b"decreasing" in L.sem_last_error()
+    o_hi = sem.make_opts(schedule=(12, 3, 1))
+    assert L.sem_plan(ctypes.byref(mesh), 12, bc, ctypes.byref(o_hi), ctypes.byref(n)) == sem.SEM_EUNSUPPORTED
+    o_p0 = sem.make_opts(schedule=(5, 3, 1))
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_p0), ctypes.byref(n)) == sem.SEM_EINVAL
+    bad_bc = (ctypes.c_int8 * 6)(1, 1, 2, 1, 1, 1)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bad_bc, ctypes.byref(o), ctypes.byref(n)) == sem.SEM_EINVAL
+    # plan grows with the problem
+    n2 = ctypes.c_size_t(0)
+    xyz3 = np.ascontiguousarray(wl.box_vertices(4, 4, 4))
+    mesh3 = sem.Mesh(4, 4, 4, 1, xyz3.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert L.sem_plan(ctypes.byref(mesh3), 7, bc, ctypes.byref(o), ctypes.byref(n2)) == sem.SEM_OK
+    assert n2.value > n.value
