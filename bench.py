@@ -36,7 +36,38 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
+    ap.add_argument("--mode", choices=("solve", "kernels"), default="solve",
+                    help="kernels: repeat single finest-level kernels (for counter runs)")
+    ap.add_argument("--reps", type=int, default=5, help="repetitions per kernel in --mode kernels")
     return ap.parse_args()
+
+
+def kernels_mode(a):
+    """Repeats each finest-level kernel class `reps` times on the benchmark mesh,
+    plus a plain 1 GiB device copy (torch) that calibrates the HBM counters."""
+    import torch
+    from paper_2110_07663_amd import sem
+    from paper_2110_07663_amd import workloads as wl
+    torch.cuda.set_device(0)
+    n, p = a.n, a.p
+    sched = (p, 3, 1) if p > 3 else (p, 1)
+    opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
+                         lambda_override=[2.0, 2.0])
+    s = sem.Solver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, opts=opts)
+    L = s.levels[0]
+    u = s.gather(torch.as_tensor(wl.random_global(L.nglobal, 0)).cuda())
+    u32 = u.float()
+    v, v32 = torch.empty_like(u), torch.empty_like(u32)
+    for _ in range(a.reps):
+        s.apply_A(u, out=v)
+        s.apply_A(u32, out=v32)
+        s.apply_S(u32, out=v32)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(a.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels", "reps": a.reps, "copy_bytes": 2 * src.numel() * 8}))
 
 
 def algorithmic_bytes(kind, p, E):
@@ -58,6 +89,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    if a.mode == "kernels":
+        kernels_mode(a)
+        return
     import numpy as np
     import torch
 

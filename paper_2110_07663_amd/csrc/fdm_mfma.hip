@@ -1,13 +1,262 @@
-// FDM local solves with the six tensor contractions on MFMA (BF16 / FP16 inputs,
-// FP32 accumulation).  Placeholder until the matrix-core path lands.
+// FDM local solves (Sec. 2.2.2, eqs. 8-9) with the six 1D contractions on the
+// matrix cores: BF16 or FP16 operands, FP32 accumulation.
+//
+// Each contraction of the (p+3)^3 box with a (p+3)x(p+3) factor is one GEMM
+// whose rows are the pairs of the two untouched indices (pbar^2 <= 169 rows,
+// tiles of 16) and whose inner dimension is the contracted index (pbar <= 16,
+// zero-padded): D[m][n] = sum_k A[m][k] B[k][n] with v_mfma_f32_16x16x16
+// (one wave per element).  Operand fragments (64 lanes):
+//   A: lane l holds A[l % 16][4 (l / 16) + j], j < 4
+//   B: lane l holds B[4 (l / 16) + j][l % 16]
+//   D: lane l holds D[4 (l / 16) + j][l % 16]
+// The box stays in LDS in FP32 between contractions.  Narrow formats need
+// bounded magnitudes, so every element's box is divided by its largest entry
+// before the forward pass, the factors S_d are stored divided by their largest
+// entry s_d (in [-1, 1]), and the diagonally scaled tensor is renormalised
+// before the backward pass; the scalars are restored on output.
 #include "sem_internal.h"
 
 namespace sem {
 
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline uint16_t f32_to_f16_bits(float x) {
+  _Float16 h = (_Float16)x;
+  return *reinterpret_cast<uint16_t *>(&h);
+}
+
+template <bool BF>
+struct Mma;
+template <>
+struct Mma<true> {  // BF16
+  using frag = short4_t;
+  static __device__ inline short enc(float x) { return (short)f32_to_bf16_rne(x); }
+  static __device__ inline short from_bits(uint16_t b) { return (short)b; }
+  static __device__ inline float4_t mma(frag a, frag b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<false> {  // FP16
+  using frag = half4_t;
+  static __device__ inline _Float16 enc(float x) { return (_Float16)x; }
+  static __device__ inline _Float16 from_bits(uint16_t b) {
+    return *reinterpret_cast<_Float16 *>(&b);
+  }
+  static __device__ inline float4_t mma(frag a, frag b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ inline float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// setup: S16[e][d][q][a] = S[e][d][q][a] / s_d (16-bit pattern), sscale[e][d] = s_d
+__global__ void k_fdm_pack16(int64_t E, int pb, const float *__restrict__ S32,
+                             uint16_t *__restrict__ S16, float *__restrict__ sscale, int bf) {
+  int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (task >= 3 * E) return;
+  const float *Sd = S32 + task * pb * pb;
+  float m = 0.f;
+  for (int q = 0; q < pb * pb; ++q) m = fmaxf(m, fabsf(Sd[q]));
+  float inv = m > 0.f ? 1.f / m : 0.f;
+  uint16_t *o = S16 + task * pb * pb;
+  for (int q = 0; q < pb * pb; ++q) {
+    float v = Sd[q] * inv;
+    o[q] = bf ? f32_to_bf16_rne(v) : f32_to_f16_bits(v);
+  }
+  sscale[task] = m;
+}
+
+// Operand view of the box in LDS for a contraction along direction `dir`:
+// rows m = (u, v) pairs of the other two indices, k = contracted index.
+template <int PB, int RS, int PS>
+__device__ inline int box_index(int dir, int m, int k) {
+  int hi = m / PB, lo = m - hi * PB;
+  // dir 0 (x): m = (c, b), k = a;  dir 1 (y): m = (c, a), k = b;  dir 2 (z): m = (b, a), k = c
+  if (dir == 0) return hi * PS + lo * RS + k;
+  if (dir == 1) return hi * PS + k * RS + lo;
+  return k * PS + hi * RS + lo;
+}
+
+template <int P, bool BF>
+__global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, int nez,
+                                                  const float *__restrict__ r,
+                                                  const uint16_t *__restrict__ S16,
+                                                  const float *__restrict__ sscale,
+                                                  const float *__restrict__ lam,
+                                                  const float *__restrict__ W,
+                                                  float *__restrict__ z) {
+  using M = Mma<BF>;
+  using frag = typename M::frag;
+  constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
+  constexpr int RS = PB + 1, PS = PB * RS, BOX = PB * PS;
+  constexpr int MROWS = PB * PB;
+  constexpr int TILES = (MROWS + 15) / 16;
+  constexpr int WAVES = 4;
+  static_assert(PB <= 16, "pbar must fit one 16-wide tile");
+  __shared__ float buf[WAVES][2][BOX];
+  __shared__ float sl[WAVES][3][PB];
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t e = (int64_t)blockIdx.x * WAVES + wave;
+  if (e >= E) return;  // whole wave leaves; no block-wide barriers below
+  float *X = buf[wave][0];
+  float *Y = buf[wave][1];
+
+  // B fragments: forward B[k][n] = Shat_d[k][n], backward B[k][n] = Shat_d[n][k]
+  const int col = lane % 16, kb = 4 * (lane / 16);
+  frag Bf[3], Bb[3];
+  const uint16_t *Se = S16 + e * 3 * PB * PB;
+  for (int d = 0; d < 3; ++d) {
+    for (int j = 0; j < 4; ++j) {
+      int k = kb + j;
+      bool ok = k < PB && col < PB;
+      uint16_t f = ok ? Se[(d * PB + k) * PB + col] : (uint16_t)0;
+      uint16_t b = ok ? Se[(d * PB + col) * PB + k] : (uint16_t)0;
+      Bf[d][j] = M::from_bits(f);
+      Bb[d][j] = M::from_bits(b);
+    }
+  }
+  for (int t = lane; t < 3 * PB; t += 64) sl[wave][t / PB][t % PB] = lam[e * 3 * PB + t];
+  const float sxyz = sscale[e * 3 + 0] * sscale[e * 3 + 1] * sscale[e * 3 + 2];
+
+  // gather the extended box (consistent E-vector; outside the domain 0)
+  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  float mr = 0.f;
+  for (int t = lane; t < PB * PB * PB; t += 64) {
+    int a = t % PB, b = (t / PB) % PB, c = t / (PB * PB);
+    int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0), li = a == 0 ? P - 1 : (a == PB - 1 ? 1 : a - 1);
+    int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0), lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+    int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0), lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
+    bool ok = ex + dx >= 0 && ex + dx < nex && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 &&
+              ez + dz < nez;
+    float v = 0.f;
+    if (ok) {
+      int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
+      v = r[en * N3 + (lk * N + lj) * N + li];
+    }
+    X[c * PS + b * RS + a] = v;
+    mr = fmaxf(mr, fabsf(v));
+  }
+  mr = wave_max(mr);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  const float inv_r = mr > 0.f ? 1.f / mr : 0.f;
+
+  // one contraction: src (FP32 box) -> dst, along `dir`, with fragment B;
+  // `post` receives each accumulator value with its (m, n) before it is stored
+  auto contract = [&](const float *src, float *dst, int dir, frag B, float scale, auto &&post) {
+    for (int tile = 0; tile < TILES; ++tile) {
+      frag A;
+      const int m = tile * 16 + col;
+      for (int j = 0; j < 4; ++j) {
+        int k = kb + j;
+        float v = (m < MROWS && k < PB) ? src[box_index<PB, RS, PS>(dir, m, k)] * scale : 0.f;
+        A[j] = M::enc(v);
+      }
+      float4_t acc = {0.f, 0.f, 0.f, 0.f};
+      acc = M::mma(A, B, acc);
+      // src and dst are distinct buffers, so the stores cannot clobber operands
+      for (int j = 0; j < 4; ++j) {
+        int mm = tile * 16 + kb + j;
+        if (mm < MROWS && col < PB) dst[box_index<PB, RS, PS>(dir, mm, col)] = post(acc[j], mm, col);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  };
+  auto id = [](float v, int, int) { return v; };
+
+  contract(X, Y, 0, Bf[0], inv_r, id);   // along x
+  contract(Y, X, 1, Bf[1], 1.f, id);     // along y
+  // along z, then the diagonal of eq. 9 (rows m = (b, a), column n = c)
+  float mt = 0.f;
+  auto diag = [&](float v, int m, int n) {
+    int b = m / PB, a = m - b * PB;
+    float dl = sl[wave][0][a] + sl[wave][1][b] + sl[wave][2][n];
+    float s = dl > 0.f ? sxyz * v / dl : 0.f;  // +inf -> 0 (decoupled node)
+    mt = fmaxf(mt, fabsf(s));
+    return s;
+  };
+  contract(X, Y, 2, Bf[2], 1.f, diag);
+  mt = wave_max(mt);
+  const float inv_t = mt > 0.f ? 1.f / mt : 0.f;
+  contract(Y, X, 2, Bb[2], inv_t, id);   // back along z
+  contract(X, Y, 1, Bb[1], 1.f, id);     // back along y
+  // back along x, fused with the RAS restriction to the element's own nodes
+  const float fin = sxyz * mr * mt;
+  for (int tile = 0; tile < TILES; ++tile) {
+    frag A;
+    const int m = tile * 16 + col;
+    for (int j = 0; j < 4; ++j) {
+      int k = kb + j;
+      float v = (m < MROWS && k < PB) ? Y[box_index<PB, RS, PS>(0, m, k)] : 0.f;
+      A[j] = M::enc(v);
+    }
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+    acc = M::mma(A, Bb[0], acc);
+    for (int j = 0; j < 4; ++j) {
+      int mm = tile * 16 + kb + j;  // (c, b)
+      int c = mm / PB, b = mm - c * PB, a = col;
+      if (mm < MROWS && a >= 1 && a <= P + 1 && b >= 1 && b <= P + 1 && c >= 1 && c <= P + 1) {
+        int64_t o = e * N3 + ((c - 1) * N + (b - 1)) * N + (a - 1);
+        z[o] = W[o] * (acc[j] * fin);
+      }
+    }
+  }
+}
+
+template <int P>
+static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, bool bf,
+                       hipStream_t s) {
+  const float *sscale = L.sscale;
+  unsigned grid = (unsigned)((L.E + 3) / 4);
+  if (bf)
+    hipLaunchKernelGGL((k_fdm_mfma<P, true>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney,
+                       c.nez, r, L.S16, sscale, L.lam32, L.w32, z);
+  else
+    hipLaunchKernelGGL((k_fdm_mfma<P, false>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney,
+                       c.nez, r, L.S16, sscale, L.lam32, L.w32, z);
+  SEM_LAUNCH("k_fdm_mfma");
+}
+
+// prec < 0: pack the 16-bit factors at setup; otherwise apply (RAS only)
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
                      int prec, hipStream_t s) {
-  (void)c; (void)L; (void)r; (void)z; (void)asm_mode; (void)prec; (void)s;
-  fail(SEM_EUNSUPPORTED, "BF16/FP16 MFMA FDM is not available in this build");
+  if (!L.S16 || !L.S32) fail(SEM_EINVAL, "16-bit FDM data were not built");
+  const bool bf = (prec < 0 ? c.fdm_prec : prec) == SEM_BF16;
+  if (prec < 0) {
+    float *sscale = L.sscale;
+    int64_t tasks = 3 * L.E;
+    hipLaunchKernelGGL(k_fdm_pack16, dim3((unsigned)((tasks + 63) / 64)), dim3(64), 0, s, L.E,
+                       L.pb, L.S32, L.S16, sscale, bf ? 1 : 0);
+    SEM_LAUNCH("k_fdm_pack16");
+    return;
+  }
+  if (asm_mode) fail(SEM_EUNSUPPORTED, "ASM weights are not implemented");
+  switch (L.p) {
+    case 2: fdm_mfma_p<2>(c, L, r, z, bf, s); break;
+    case 3: fdm_mfma_p<3>(c, L, r, z, bf, s); break;
+    case 4: fdm_mfma_p<4>(c, L, r, z, bf, s); break;
+    case 5: fdm_mfma_p<5>(c, L, r, z, bf, s); break;
+    case 6: fdm_mfma_p<6>(c, L, r, z, bf, s); break;
+    case 7: fdm_mfma_p<7>(c, L, r, z, bf, s); break;
+    case 8: fdm_mfma_p<8>(c, L, r, z, bf, s); break;
+    case 9: fdm_mfma_p<9>(c, L, r, z, bf, s); break;
+    case 10: fdm_mfma_p<10>(c, L, r, z, bf, s); break;
+    default: fail(SEM_EUNSUPPORTED, "MFMA FDM: unsupported degree");
+  }
 }
 
 }  // namespace sem

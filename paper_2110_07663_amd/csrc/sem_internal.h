@@ -81,7 +81,8 @@ struct Level {
   // lam[E][3][pb] (+inf marks a decoupled node)
   double *S64 = nullptr, *lam64 = nullptr;
   float *S32 = nullptr, *lam32 = nullptr;
-  uint16_t *S16 = nullptr;  // S in BF16 or FP16 bit patterns for the MFMA path
+  uint16_t *S16 = nullptr;  // S / s_d in BF16 or FP16 bit patterns (MFMA path)
+  float *sscale = nullptr;  // [E][3] s_d = max |S_d|
   double *boxlen = nullptr; // [E][3]
   double *wasm64 = nullptr; // [nloc] ASM weight 1/#boxes (0 on Dirichlet)
   float *wasm32 = nullptr;

@@ -130,8 +130,10 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
       if (lowp) {
         L.S32 = A.take<float>(3 * L.E * pb * pb);
         L.lam32 = A.take<float>(3 * L.E * pb);
-        if (o.fdm_prec == SEM_BF16 || o.fdm_prec == SEM_F16)
-          L.S16 = A.take<uint16_t>(3 * L.E * 16 * 16);
+        if (o.fdm_prec == SEM_BF16 || o.fdm_prec == SEM_F16) {
+          L.S16 = A.take<uint16_t>(3 * L.E * pb * pb);
+          L.sscale = A.take<float>(3 * L.E);
+        }
       }
     }
     L.d_b = A.take<double>(L.nloc);

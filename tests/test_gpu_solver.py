@@ -160,3 +160,28 @@ def test_error_paths():
     with pytest.raises(sem.SemError) as ei:
         sem.Solver(2, 2, 2, xyz, 1, 3, opts=sem.make_opts(schedule=(3, 1)))
     assert ei.value.status == sem.SEM_EGEOM
+
+
+@pytest.mark.parametrize("fdm_prec,tol", [(sem.F16, 5e-3), (sem.BF16, 4e-2)])
+@pytest.mark.parametrize("p", [3, 7, 9])
+def test_ras_mfma_low_precision(fdm_prec, tol, p):
+    """FDM contractions on MFMA (16-bit operands, FP32 accumulation) against the FP64 oracle."""
+    t = _torch()
+    P = Pair(3, p, mesh="shift", schedule=(p, 1), smoother="ras", smoother_prec=sem.F32,
+             fdm_prec=fdm_prec, lambda_override=[2.0])
+    g, o = P.random_local(8)
+    zg = host(P.gpu.apply_S(g.to(t.float32)))
+    err = rel_err(zg, P.ora.levels[0].apply_S(o))
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("fdm_prec", [sem.F16, sem.BF16])
+def test_mixed_mfma_solve_converges(fdm_prec):
+    P = Pair(4, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
+             fdm_prec=fdm_prec)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=200)
+    assert info.converged
+    L = P.ora.fine
+    r = bo - L.apply_A(host(xg))
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
