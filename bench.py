@@ -62,6 +62,14 @@ def kernels_mode(a):
         s.apply_A(u, out=v)
         s.apply_A(u32, out=v32)
         s.apply_S(u32, out=v32)
+    # the matrix-core FDM in both 16-bit formats
+    for fp in (sem.F16, sem.BF16):
+        o16 = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
+                            fdm_prec=fp, lambda_override=[2.0, 2.0])
+        s16 = sem.Solver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, opts=o16)
+        for _ in range(a.reps):
+            s16.apply_S(u32, out=v32)
+        s16.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(a.reps):
@@ -149,7 +157,7 @@ def main():
         byt = algorithmic_bytes(k, p, L0.E)
         kern[k] = {"avg_us": 1e3 * avg, "launches": cnt, "total_ms": ms,
                    "bytes_per_launch": byt, "GBs": byt / (avg * 1e-3) / 1e9}
-    for k in ("gs64", "gs32"):
+    for k in ("gs64", "gs32", "coarse", "vcycle"):
         ms, cnt = prof[k]
         if cnt:
             kern[k] = {"avg_us": 1e3 * ms / cnt, "launches": cnt, "total_ms": ms}

@@ -95,6 +95,8 @@ typedef struct {
   int32_t gmres_restart;      /* m of FGMRES(m), <= 64                                    */
   double coarse_tol;          /* relative residual of the coarse Jacobi-PCG; 0 = run      */
   int32_t coarse_maxit;       /*   exactly coarse_maxit iterations                        */
+  int32_t ax_variant;         /* Ax kernel shape at p = 7: 0 generic slab kernel, 1 one   */
+                              /* wavefront per element, -1 library default                */
 } sem_opts;
 
 typedef struct {
@@ -196,8 +198,8 @@ sem_status sem_solve(sem_ctx *ctx, const double *b, double *x_inout, double rtol
 
 /* Kernel timing of the finest level, for roofline reporting.  While enabled, the
  * library records a pair of HIP events on the call's stream around every launch
- * of the instrumented kernels below (finest level only), so durations are those
- * of the kernels themselves.  Enabling clears the counters.  sem_profile_read
+ * of the instrumented kernels below (finest level only; the last two classes
+ * bracket whole phases), so durations are those of the kernels themselves.  Enabling clears the counters.  sem_profile_read
  * synchronises on the recorded events and returns, per class, the summed
  * duration in ms (total_ms[SEM_PROF_COUNT]) and the launch count. */
 typedef enum {
@@ -206,10 +208,48 @@ typedef enum {
   SEM_PROF_FDM = 2,    /* Schwarz FDM local solves (any precision)                  */
   SEM_PROF_GS64 = 3,   /* QQ^T gather-scatter + mask, FP64                          */
   SEM_PROF_GS32 = 4,   /* QQ^T gather-scatter + mask, FP32                          */
-  SEM_PROF_COUNT = 5
+  SEM_PROF_COARSE = 5, /* whole coarse-grid solve of one V-cycle (all its launches)  */
+  SEM_PROF_VCYCLE = 6, /* whole preconditioner application z = M r                   */
+  SEM_PROF_COUNT = 7
 } sem_prof_kernel;
 sem_status sem_profile(sem_ctx *ctx, int32_t enable);
 sem_status sem_profile_read(sem_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* Auto-tuner (Sec. 5: exhaustive search over a small parameter space on the first
+ * solve, at the problem the user runs).  Every candidate option set is set up in
+ * turn in the same workspace, solved `repeats` times from x = 0 on the caller's
+ * right side b (an E-vector of the finest level, which all candidates share: same
+ * mesh and p), and timed with HIP events; the fastest candidate that converges to
+ * rtol within maxit wins (ties: lower Chebyshev order, then fewer levels).  b and x
+ * are caller-owned device FP64 E-vectors; x is overwritten.  Candidates that are
+ * rejected or do not converge are reported with their status and skipped. */
+#define SEM_TUNE_MAX 96
+typedef struct {
+  int32_t ncand;
+  sem_opts cand[SEM_TUNE_MAX];
+  int32_t repeats;            /* timed solves per candidate (the median is kept)         */
+  double rtol;
+  int32_t maxit;
+} sem_tune_request;
+
+typedef struct {
+  int32_t best;               /* index into cand[], -1 if none converged                */
+  double ms[SEM_TUNE_MAX];    /* median solve time (setup excluded)                     */
+  double setup_ms[SEM_TUNE_MAX];
+  int32_t iters[SEM_TUNE_MAX];
+  int32_t status[SEM_TUNE_MAX];
+} sem_tune_result;
+
+/* Fills req with the paper's pMG search space for degree p (Sec. 5 table: Cheby-ASM,
+ * Cheby-RAS and Cheby-Jacobi with their schedules), crossed with Chebyshev orders
+ * 1..3, smoother precisions (FP64; FP32; FP32 with FP16 MFMA FDM) and, at p = 7,
+ * the two Ax kernel shapes.  Fields of `base` not searched are copied. */
+sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req);
+sem_status sem_tune_plan(const sem_mesh *mesh, int32_t p, const int8_t bc[6],
+                         const sem_tune_request *req, size_t *workspace_bytes);
+sem_status sem_tune(const sem_mesh *mesh, int32_t p, const int8_t bc[6],
+                    const sem_tune_request *req, const double *b, double *x, void *workspace,
+                    size_t workspace_bytes, void *stream, sem_tune_result *out);
 
 #ifdef __cplusplus
 }

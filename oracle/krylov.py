@@ -7,7 +7,8 @@ Sec. 2.2: preconditioners are applied inside restarted GMRES or flexible CG
     beta_k = r_{k+1}.(z_{k+1} - z_k) / (r_k.z_k);
   * fgmres: right-preconditioned flexible GMRES(m); here the small
     least-squares problem is solved directly with lstsq at every step.
-All stop when ||r_k|| / ||r_0|| <= tol (2-norm over unique free nodes, i.e.
+CG variants also stop on exact breakdown (p.Ap = 0, so p = 0 and the iterate
+is final).  All stop when ||r_k|| / ||r_0|| <= tol (2-norm over unique free nodes, i.e.
 E-vector dots weighted by mask/mult).  On exit the true residual b - A x is
 recomputed; if it fails the test the iteration restarts from it.
 """
@@ -27,13 +28,19 @@ def pcg(apply_A, apply_M, b, wdot, tol, maxit, x0=None):
     if r0 == 0.0:
         return Result(x, 0, 0.0, hist, True)
     it = 0
+    rel = 1.0
     while it < maxit:
         z = apply_M(r)
         p = z.copy()
         rz = wdot(r, z)
         while it < maxit:
             q = apply_A(p)
-            alpha = rz / wdot(p, q)
+            pq = wdot(p, q)
+            if not pq > 0.0:  # exact breakdown (p = 0): the iterate is final
+                r = b - apply_A(x)
+                rel = np.sqrt(wdot(r, r)) / r0
+                return Result(x, it, rel, hist, rel <= tol)
+            alpha = rz / pq
             x = x + alpha * p
             r = r - alpha * q
             it += 1
@@ -67,7 +74,12 @@ def fcg(apply_A, apply_M, b, wdot, tol, maxit, x0=None):
         rz = wdot(r, z)
         while it < maxit:
             q = apply_A(p)
-            alpha = rz / wdot(p, q)
+            pq = wdot(p, q)
+            if not pq > 0.0:  # exact breakdown (p = 0): the iterate is final
+                r = b - apply_A(x)
+                rel = np.sqrt(wdot(r, r)) / r0
+                return Result(x, it, rel, hist, rel <= tol)
+            alpha = rz / pq
             x = x + alpha * p
             r = r - alpha * q
             it += 1

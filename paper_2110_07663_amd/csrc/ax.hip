@@ -116,8 +116,102 @@ __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__res
   }
 }
 
+// p = 7 (N = 8): one element per wavefront, lane (i, j) of the 8x8 slab.  The
+// element is swept plane by plane; each k-plane of u, h_r and h_s lives in LDS
+// only while it is used, and the transposed r/s contractions of plane k run as
+// soon as that plane's h is known, so the only whole-element state is the
+// t-line of u and of the output (registers).  Plane exchanges are within one
+// wavefront: LDS operations of a wavefront complete in issue order, and the
+// wave barriers keep the compiler from moving LDS accesses across phases.
+template <typename T>
+__device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
+                                         const T *__restrict__ G, const T *__restrict__ Dg,
+                                         T *__restrict__ v, T *sD, T (*sU)[72], T (*sR)[72],
+                                         T (*sS)[72]) {
+  constexpr int N = 8, NN = 64, N3 = 512, RS = 9;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 7, j = lane >> 3;
+  if (threadIdx.x < NN) sD[threadIdx.x] = Dg[threadIdx.x];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 4 + w;
+  if (e >= E) return;
+
+  T Di[N], Dj[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    Di[l] = sD[i * N + l];
+    Dj[l] = sD[j * N + l];
+  }
+  const T *ue = u + e * N3 + lane;
+  const T *Ge = G + e * 6 * N3 + lane;
+  T uk[N], acc[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    uk[k] = ue[k * NN];
+    acc[k] = T(0);
+  }
+  T *su = sU[w], *sr = sR[w], *ss = sS[w];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const T g0 = Ge[0 * N3 + k * NN], g1 = Ge[1 * N3 + k * NN], g2 = Ge[2 * N3 + k * NN];
+    const T g3 = Ge[3 * N3 + k * NN], g4 = Ge[4 * N3 + k * NN], g5 = Ge[5 * N3 + k * NN];
+    su[j * RS + i] = uk[k];
+    __builtin_amdgcn_wave_barrier();
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      ur += Di[l] * su[j * RS + l];
+      us += Dj[l] * su[l * RS + i];
+      ut += Dg[k * N + l] * uk[l];
+    }
+    const T hr = g0 * ur + g1 * us + g2 * ut;
+    const T hs = g1 * ur + g3 * us + g4 * ut;
+    const T ht = g2 * ur + g4 * us + g5 * ut;
+    __builtin_amdgcn_wave_barrier();
+    sr[j * RS + i] = hr;
+    ss[j * RS + i] = hs;
+    __builtin_amdgcn_wave_barrier();
+    T a = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      a += sD[l * N + i] * sr[j * RS + l];
+      a += sD[l * N + j] * ss[l * RS + i];
+      acc[l] += Dg[k * N + l] * ht;  // D_t^T: v[l] += D[k][l] h_t[k]
+    }
+    acc[k] += a;
+    __builtin_amdgcn_wave_barrier();
+  }
+  T *ve = v + e * N3 + lane;
+#pragma unroll
+  for (int k = 0; k < N; ++k) ve[k * NN] = acc[k];
+}
+
+// register budgets: FP64 at 4 waves/SIMD, FP32 at 6
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ax8_f64(
+    int64_t E, const double *__restrict__ u, const double *__restrict__ G,
+    const double *__restrict__ Dg, double *__restrict__ v) {
+  __shared__ double sD[64], sU[4][72], sR[4][72], sS[4][72];
+  ax8_body<double>(E, u, G, Dg, v, sD, sU, sR, sS);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32(
+    int64_t E, const float *__restrict__ u, const float *__restrict__ G,
+    const float *__restrict__ Dg, float *__restrict__ v) {
+  __shared__ float sD[64], sU[4][72], sR[4][72], sS[4][72];
+  ax8_body<float>(E, u, G, Dg, v, sD, sU, sR, sS);
+}
+
 template <typename T, int N>
 static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, hipStream_t s) {
+  if constexpr (N == 8) {
+    if (L.ax_variant == 1) {
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_ax8_f64, dim3((unsigned)((L.E + 3) / 4)), dim3(256), 0, s, L.E, u, G, D, v);
+      else
+        hipLaunchKernelGGL(k_ax8_f32, dim3((unsigned)((L.E + 3) / 4)), dim3(256), 0, s, L.E, u, G, D, v);
+      SEM_LAUNCH("k_ax8");
+      return;
+    }
+  }
   using S = AxShape<N>;
   unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB);
   hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v);

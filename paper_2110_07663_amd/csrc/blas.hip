@@ -351,7 +351,8 @@ __global__ __launch_bounds__(256) void k_cpcg_pq(int64_t n, const double *__rest
     acc[0] += w[t] * p[t] * q[t];
   if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) {
     sc->pq = acc[0];
-    sc->alpha = sc->rz / acc[0];
+    sc->alpha = acc[0] > 0.0 ? sc->rz / acc[0] : 0.0;
+    if (!(acc[0] > 0.0)) sc->done = 1;  // exact breakdown: the iterate is exact
   }
 }
 
@@ -376,8 +377,9 @@ __global__ __launch_bounds__(256) void k_cpcg_update(int64_t n, const double *__
     acc[1] += w[t] * rv * rv;
   }
   if (last_block_sum<2>(acc, partials, counter) && threadIdx.x == 0) {
-    sc->beta = acc[0] / sc->rz;
+    sc->beta = sc->rz != 0.0 ? acc[0] / sc->rz : 0.0;
     sc->rz = acc[0];
+    if (!(acc[0] > 0.0)) sc->done = 1;
     sc->rr = acc[1];
     sc->iters += 1;
     bool conv = sc->tol2 > 0.0 && acc[1] <= sc->tol2 * sc->rr0;

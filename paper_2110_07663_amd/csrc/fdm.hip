@@ -189,7 +189,7 @@ __device__ inline T fdm_inv(T d) {
   return d > T(0) ? T(1) / d : T(0);  // +inf -> 0 (decoupled), 0 -> dropped mode
 }
 
-template <int P, typename T>
+template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
     const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
@@ -284,7 +284,21 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     }
   }
   __syncthreads();
-  // back along x and the RAS output on own nodes: out[c][j][i] = sum_aa Sx[i][aa] y[c][j][aa]
+  // back along x: out[c][j][i] = sum_aa Sx[i][aa] y[c][j][aa]
+  if constexpr (ASM) {  // whole box to z[E][pb^3]; the overlap sum follows
+    if (act) {
+      T *zb = z + e * PB * PB * PB + b * PB + a;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int aa = 0; aa < PB; ++aa) s += sS[0][a * PB + aa] * buf1[c * PS + b * RS + aa];
+        zb[c * PB * PB] = s;
+      }
+    }
+    return;
+  }
+  // RAS output on own nodes, times 1/multiplicity
   if (act && a >= 1 && a <= P + 1 && b >= 1 && b <= P + 1) {
     const int64_t obase = e * N3 + (b - 1) * N + (a - 1);
 #pragma unroll
@@ -298,30 +312,91 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
   }
 }
 
+// ASM (eq. 4): sum of every extended box that contains the node, times
+// 1/#boxes, masked.  Each local copy of a node sums the same boxes, so the
+// result is a consistent E-vector without a separate assembly.
+template <typename T>
+__global__ void k_asm_sum(int64_t E, int p, int nex, int ney, int nez, const T *__restrict__ box,
+                          const T *__restrict__ w, T *__restrict__ z) {
+  const int N = p + 1, N3 = N * N * N, PB = p + 3, PB3 = PB * PB * PB;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= E * N3) return;
+  if (w[t] == T(0)) {  // Dirichlet node
+    z[t] = T(0);
+    return;
+  }
+  int64_t e = t / N3;
+  int q = (int)(t - e * N3);
+  int i = q % N, j = (q / N) % N, k = q / (N * N);
+  int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  int64_t gx = ex * p + i, gy = ey * p + j, gz = ez * p + k;
+  T sum = T(0);
+  int cnt = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int64_t cz = ez + dz;
+    int64_t lz = gz - cz * p + 1;
+    if (cz < 0 || cz >= nez || lz < 0 || lz >= PB) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int64_t cy = ey + dy;
+      int64_t ly = gy - cy * p + 1;
+      if (cy < 0 || cy >= ney || ly < 0 || ly >= PB) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        int64_t cx = ex + dx;
+        int64_t lx = gx - cx * p + 1;
+        if (cx < 0 || cx >= nex || lx < 0 || lx >= PB) continue;
+        int64_t en = (cz * ney + cy) * nex + cx;
+        sum += box[en * PB3 + (lz * PB + ly) * PB + lx];
+        ++cnt;
+      }
+    }
+  }
+  z[t] = sum / T(cnt);
+}
+
+template <typename T>
+void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_t s) {
+  const T *w = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
+  hipLaunchKernelGGL(k_asm_sum<T>, dim3((unsigned)((L.nloc + 255) / 256)), dim3(256), 0, s, L.E,
+                     L.p, c.nex, c.ney, c.nez, box, w, z);
+  SEM_LAUNCH("k_asm_sum");
+}
+template void launch_asm_sum<double>(const Ctx &, const Level &, const double *, double *,
+                                     hipStream_t);
+template void launch_asm_sum<float>(const Ctx &, const Level &, const float *, float *,
+                                    hipStream_t);
+
 template <typename T, int P>
-static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
+static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
   const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
   const T *lam = sizeof(T) == 8 ? (const T *)L.lam64 : (const T *)L.lam32;
   const T *W = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
   if (!S || !lam || !W) fail(SEM_EINVAL, "FDM data of this precision were not built");
-  hipLaunchKernelGGL((k_fdm<P, T>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E, c.nex,
-                     c.ney, c.nez, r, S, lam, W, z);
+  if (asm_mode) {
+    T *box = sizeof(T) == 8 ? (T *)L.box64 : (T *)L.box32;
+    if (!box) fail(SEM_EINVAL, "ASM box buffer was not built");
+    hipLaunchKernelGGL((k_fdm<P, T, true>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
+                       c.nex, c.ney, c.nez, r, S, lam, W, box);
+    SEM_LAUNCH("k_fdm");
+    launch_asm_sum<T>(c, L, box, z, s);
+    return;
+  }
+  hipLaunchKernelGGL((k_fdm<P, T, false>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
+                     c.nex, c.ney, c.nez, r, S, lam, W, z);
   SEM_LAUNCH("k_fdm");
 }
 
 template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
-  if (asm_mode) fail(SEM_EUNSUPPORTED, "ASM weights are not implemented");
   switch (L.p) {
-    case 2: fdm_p<T, 2>(c, L, r, z, s); break;
-    case 3: fdm_p<T, 3>(c, L, r, z, s); break;
-    case 4: fdm_p<T, 4>(c, L, r, z, s); break;
-    case 5: fdm_p<T, 5>(c, L, r, z, s); break;
-    case 6: fdm_p<T, 6>(c, L, r, z, s); break;
-    case 7: fdm_p<T, 7>(c, L, r, z, s); break;
-    case 8: fdm_p<T, 8>(c, L, r, z, s); break;
-    case 9: fdm_p<T, 9>(c, L, r, z, s); break;
-    case 10: fdm_p<T, 10>(c, L, r, z, s); break;
+    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s); break;
+    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s); break;
+    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s); break;
+    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s); break;
+    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s); break;
+    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s); break;
+    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s); break;
+    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s); break;
+    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s); break;
     default: fail(SEM_EUNSUPPORTED, "FDM: unsupported degree");
   }
 }

@@ -89,7 +89,7 @@ __device__ inline int box_index(int dir, int m, int k) {
   return k * PS + hi * RS + lo;
 }
 
-template <int P, bool BF>
+template <int P, bool BF, bool ASM>
 __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const uint16_t *__restrict__ S16,
@@ -209,6 +209,10 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
     for (int j = 0; j < 4; ++j) {
       int mm = tile * 16 + kb + j;  // (c, b)
       int c = mm / PB, b = mm - c * PB, a = col;
+      if constexpr (ASM) {  // whole box to z[E][pb^3]; the overlap sum follows
+        if (mm < MROWS && a < PB) z[e * PB * PB * PB + mm * PB + a] = acc[j] * fin;
+        continue;
+      }
       if (mm < MROWS && a >= 1 && a <= P + 1 && b >= 1 && b <= P + 1 && c >= 1 && c <= P + 1) {
         int64_t o = e * N3 + ((c - 1) * N + (b - 1)) * N + (a - 1);
         z[o] = W[o] * (acc[j] * fin);
@@ -219,16 +223,24 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
 
 template <int P>
 static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, bool bf,
-                       hipStream_t s) {
+                       bool asm_mode, hipStream_t s) {
   const float *sscale = L.sscale;
   unsigned grid = (unsigned)((L.E + 3) / 4);
-  if (bf)
-    hipLaunchKernelGGL((k_fdm_mfma<P, true>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, L.S16, sscale, L.lam32, L.w32, z);
-  else
-    hipLaunchKernelGGL((k_fdm_mfma<P, false>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, L.S16, sscale, L.lam32, L.w32, z);
+  float *out = z;
+  if (asm_mode) {
+    if (!L.box32) fail(SEM_EINVAL, "ASM box buffer was not built");
+    out = L.box32;
+  }
+#define SEM_MFMA_LAUNCH(BFV, ASMV)                                                              \
+  hipLaunchKernelGGL((k_fdm_mfma<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney, \
+                     c.nez, r, L.S16, sscale, L.lam32, L.w32, out)
+  if (bf && asm_mode) SEM_MFMA_LAUNCH(true, true);
+  else if (bf) SEM_MFMA_LAUNCH(true, false);
+  else if (asm_mode) SEM_MFMA_LAUNCH(false, true);
+  else SEM_MFMA_LAUNCH(false, false);
+#undef SEM_MFMA_LAUNCH
   SEM_LAUNCH("k_fdm_mfma");
+  if (asm_mode) launch_asm_sum<float>(c, L, L.box32, z, s);
 }
 
 // prec < 0: pack the 16-bit factors at setup; otherwise apply (RAS only)
@@ -244,17 +256,16 @@ void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, boo
     SEM_LAUNCH("k_fdm_pack16");
     return;
   }
-  if (asm_mode) fail(SEM_EUNSUPPORTED, "ASM weights are not implemented");
   switch (L.p) {
-    case 2: fdm_mfma_p<2>(c, L, r, z, bf, s); break;
-    case 3: fdm_mfma_p<3>(c, L, r, z, bf, s); break;
-    case 4: fdm_mfma_p<4>(c, L, r, z, bf, s); break;
-    case 5: fdm_mfma_p<5>(c, L, r, z, bf, s); break;
-    case 6: fdm_mfma_p<6>(c, L, r, z, bf, s); break;
-    case 7: fdm_mfma_p<7>(c, L, r, z, bf, s); break;
-    case 8: fdm_mfma_p<8>(c, L, r, z, bf, s); break;
-    case 9: fdm_mfma_p<9>(c, L, r, z, bf, s); break;
-    case 10: fdm_mfma_p<10>(c, L, r, z, bf, s); break;
+    case 2: fdm_mfma_p<2>(c, L, r, z, bf, asm_mode, s); break;
+    case 3: fdm_mfma_p<3>(c, L, r, z, bf, asm_mode, s); break;
+    case 4: fdm_mfma_p<4>(c, L, r, z, bf, asm_mode, s); break;
+    case 5: fdm_mfma_p<5>(c, L, r, z, bf, asm_mode, s); break;
+    case 6: fdm_mfma_p<6>(c, L, r, z, bf, asm_mode, s); break;
+    case 7: fdm_mfma_p<7>(c, L, r, z, bf, asm_mode, s); break;
+    case 8: fdm_mfma_p<8>(c, L, r, z, bf, asm_mode, s); break;
+    case 9: fdm_mfma_p<9>(c, L, r, z, bf, asm_mode, s); break;
+    case 10: fdm_mfma_p<10>(c, L, r, z, bf, asm_mode, s); break;
     default: fail(SEM_EUNSUPPORTED, "MFMA FDM: unsupported degree");
   }
 }

@@ -55,6 +55,7 @@ struct Level {
   int nseg = 0, nperm = 0;           // gather-scatter segments and member count
   bool fine = false, coarse = false;
   bool lowp = false;                 // level kept in FP32 for the smoother
+  int ax_variant = 1;                // Ax kernel shape at p = 7 (0 generic, 1 one wave/element)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
   double *xi = nullptr, *wq = nullptr, *D64 = nullptr;
@@ -84,8 +85,8 @@ struct Level {
   uint16_t *S16 = nullptr;  // S / s_d in BF16 or FP16 bit patterns (MFMA path)
   float *sscale = nullptr;  // [E][3] s_d = max |S_d|
   double *boxlen = nullptr; // [E][3]
-  double *wasm64 = nullptr; // [nloc] ASM weight 1/#boxes (0 on Dirichlet)
-  float *wasm32 = nullptr;
+  double *box64 = nullptr;  // [E][pb^3] ASM local-solve outputs before the overlap sum
+  float *box32 = nullptr;
 
   // Chebyshev parameters
   double lam_tilde = 0, lmin = 0, lmax = 0;
@@ -102,6 +103,30 @@ struct Level {
 struct DevScalars {
   double rz, pq, alpha, beta, rr, rr0, tol2;
   int done, iters, maxit, pad;
+};
+
+// scalars of the coarse-grid CG (device resident)
+struct CoarseScalars {
+  double gamma, gamma_old, delta, alpha, beta, rr, rr0, tol2;
+  int done, iters, maxit, pad;
+};
+
+// assembled p = 1 coarse operator and its CG state (buffers in the workspace)
+struct CoarseSolver {
+  int64_t n = 0;                   // global nodes of the coarsest level
+  double *St = nullptr;            // [27][n] stencil values
+  double *dinv = nullptr;          // [n]
+  double *Ae = nullptr;            // [E][8][8] element matrices (setup only)
+  double *b = nullptr, *x = nullptr, *r = nullptr, *u = nullptr, *w = nullptr, *p = nullptr,
+         *s = nullptr;
+  double *partials = nullptr;      // [blocks][4]
+  unsigned *counter = nullptr;
+  CoarseScalars *sc = nullptr;
+  int chunk = 16;                  // iterations per recorded graph
+  bool use_graph = true;
+  hipStream_t cap = nullptr;       // private capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 // HIP-event timing of finest-level kernels (sem_profile)
@@ -143,6 +168,8 @@ struct Ctx {
   // coarse PCG vectors (FP64, coarsest level)
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
   int last_coarse_iters = 0;
+  CoarseSolver coarse_store;
+  CoarseSolver *cs = nullptr;      // set when the coarsest level is p = 1 (assembled solve)
   // Arnoldi basis (FP64, largest level)
   double *av = nullptr;
   int fdm_prec = SEM_F32;
@@ -222,7 +249,14 @@ template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s);
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
                      int prec, hipStream_t s);
-void launch_asm_weights(const Ctx &c, Level &L, hipStream_t s);
+template <typename T>
+void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_t s);
+
+// coarse.hip
+bool coarse_assembled_ok(const Ctx &c, const Level &C);
+void coarse_setup(Ctx &c, Level &C, hipStream_t s);
+void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s);
+void coarse_release(CoarseSolver &S);
 
 // hessenberg.cpp
 double hessenberg_max_abs_eig(const double *H, int ldh, int k);

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -69,9 +70,10 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
     for (int l = 1; l < o->nlevels; ++l)
       if (o->p_levels[l] >= o->p_levels[l - 1] || o->p_levels[l] < 1)
         fail(SEM_EINVAL, "p_levels must be strictly decreasing and >= 1");
-    if (o->smoother != SEM_SMOOTH_JACOBI && o->smoother != SEM_SMOOTH_RAS)
-      fail(o->smoother == SEM_SMOOTH_ASM ? SEM_EUNSUPPORTED : SEM_EINVAL, "unsupported smoother");
-    if (o->smoother == SEM_SMOOTH_RAS)
+    if (o->smoother != SEM_SMOOTH_JACOBI && o->smoother != SEM_SMOOTH_RAS &&
+        o->smoother != SEM_SMOOTH_ASM)
+      fail(SEM_EINVAL, "unknown smoother");
+    if (o->smoother != SEM_SMOOTH_JACOBI)
       for (int l = 0; l + 1 < o->nlevels; ++l)
         if (o->p_levels[l] < 2) fail(SEM_EINVAL, "Schwarz smoothing needs p >= 2 on smoothed levels");
     if (o->cheb_order < 0 || o->cheb_order > 32) fail(SEM_EINVAL, "cheb_order out of range");
@@ -89,6 +91,7 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
   if (o->krylov == SEM_KRYLOV_FGMRES && (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart))
     fail(SEM_EINVAL, "gmres_restart in [1, 64]");
   if (o->coarse_maxit < 1) fail(SEM_EINVAL, "coarse_maxit must be >= 1");
+  if (o->ax_variant < -1 || o->ax_variant > 1) fail(SEM_EINVAL, "ax_variant must be -1, 0 or 1");
   for (int f = 0; f < 6; ++f)
     if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
   int64_t E = (int64_t)m->nex * m->ney * m->nez;
@@ -100,7 +103,8 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
 static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   const sem_opts &o = c.opts;
   const bool lowp = c.lowp;
-  const bool schwarz = o.precond == SEM_PRECOND_PMG && o.smoother == SEM_SMOOTH_RAS;
+  const bool schwarz = o.precond == SEM_PRECOND_PMG && o.smoother != SEM_SMOOTH_JACOBI;
+  const bool asm_on = schwarz && o.smoother == SEM_SMOOTH_ASM;
   for (int l = 0; l < c.nlev; ++l) {
     Level &L = c.lev[l];
     const bool smoothed = !L.coarse;
@@ -134,6 +138,10 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
           L.S16 = A.take<uint16_t>(3 * L.E * pb * pb);
           L.sscale = A.take<float>(3 * L.E);
         }
+      }
+      if (asm_on) {
+        L.box64 = A.take<double>(L.E * pb * pb * pb);
+        if (lowp) L.box32 = A.take<float>(L.E * pb * pb * pb);
       }
     }
     L.d_b = A.take<double>(L.nloc);
@@ -174,6 +182,28 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   c.cq = A.take<double>(C.nloc);
   if (o.precond == SEM_PRECOND_PMG && c.nlev > 1)
     c.av = A.take<double>((size_t)(o.arnoldi_steps + 1) * F.nloc);
+  // assembled coarse solve when the coarsest level is p = 1
+  c.cs = nullptr;
+  if (o.precond == SEM_PRECOND_PMG && C.p == 1) {
+    CoarseSolver &S = c.coarse_store;
+    S.n = C.nglob;
+    S.St = A.take<double>(27 * S.n);
+    S.dinv = A.take<double>(S.n);
+    S.Ae = A.take<double>(64 * C.E);
+    S.b = A.take<double>(S.n);
+    S.x = A.take<double>(S.n);
+    S.r = A.take<double>(S.n);
+    S.u = A.take<double>(S.n);
+    S.w = A.take<double>(S.n);
+    S.p = A.take<double>(S.n);
+    S.s = A.take<double>(S.n);
+    S.partials = A.take<double>(4 * ((S.n + 255) / 256));
+    S.counter = A.take<unsigned>(64);
+    S.sc = A.take<CoarseScalars>(1);
+    const char *g = getenv("SEM_COARSE_GRAPH");
+    S.use_graph = !(g && g[0] == '0');
+    c.cs = &S;
+  }
   // setup-only scratch
   int Ng = m->p_geom + 1;
   int64_t E = F.E;
@@ -216,6 +246,9 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
     L.fine = l == 0;
     L.coarse = l == c.nlev - 1;
     L.lowp = c.lowp;
+    // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element)
+    const char *av = getenv("SEM_AX_VARIANT");
+    L.ax_variant = o->ax_variant >= 0 ? o->ax_variant : (av ? atoi(av) : 1);
   }
 }
 
@@ -273,7 +306,8 @@ struct ProfScope {
   Profiler *p;
   hipStream_t s;
   ProfScope(const Ctx &c, const Level &L, int kind, hipStream_t st)
-      : p((c.prof && c.prof->on && L.fine) ? c.prof : nullptr), s(st) {
+      : p((c.prof && c.prof->on && (L.fine || kind >= SEM_PROF_COARSE)) ? c.prof : nullptr),
+        s(st) {
     if (p) p->begin(kind, s);
   }
   ~ProfScope() {
@@ -293,8 +327,9 @@ static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s) 
 
 template <typename T>
 static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
-  const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother == SEM_SMOOTH_RAS &&
+  const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
+  const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
   if (!schwarz) {
     const T *dinv = Vec<T>::dinv(L);
     if (!dinv) fail(SEM_EINVAL, "Jacobi data of this precision were not built");
@@ -306,12 +341,13 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
     bool mma = false;
     if constexpr (sizeof(T) == 4) {
       if (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16) {
-        launch_fdm_mfma(c, L, (const float *)r, (float *)z, false, c.fdm_prec, s);
+        launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s);
         mma = true;
       }
     }
-    if (!mma) launch_fdm<T>(c, L, r, z, false, s);
+    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s);
   }
+  if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
   launch_gs<T>(L, z, s);
 }
@@ -350,6 +386,11 @@ static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
 static void coarse_solve(Ctx &c, Level &C, hipStream_t s) {
   const double tol = c.opts.coarse_tol;
   const int maxit = c.opts.coarse_maxit;
+  ProfScope ps(c, C, SEM_PROF_COARSE, s);
+  if (coarse_assembled_ok(c, C)) {
+    coarse_solve_assembled(c, C, tol, maxit, s);
+    return;
+  }
   DevScalars init{};
   init.tol2 = tol * tol;
   init.maxit = maxit;
@@ -411,6 +452,7 @@ static void vcycle_level(Ctx &c, int l, hipStream_t s) {
 // z = M r on the finest level, FP64 in and out
 static void precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
   Level &F = c.lev[0];
+  ProfScope ps(c, F, SEM_PROF_VCYCLE, s);
   if (c.opts.precond == SEM_PRECOND_JACOBI) {
     launch_scale<double>(F.nloc, F.dinv64, r, z, s);
     return;
@@ -531,6 +573,10 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
     Level &F = c.lev[l], &C = c.lev[l + 1];
     launch_interp(C.p, F.p, C.xi, F.xi, F.J64, F.J32, s);
   }
+  if (c.cs) {
+    SEM_HIP(hipMemsetAsync(c.cs->counter, 0, 64 * sizeof(unsigned), s));
+    coarse_setup(c, c.lev[c.nlev - 1], s);
+  }
   int bad = 0;
   SEM_HIP(hipMemcpyAsync(&bad, sc.bad, sizeof(int), hipMemcpyDeviceToHost, s));
   SEM_HIP(hipStreamSynchronize(s));
@@ -572,6 +618,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
   }
   int it = 0;
   double rel = 1.0;
+  bool breakdown = false;
   while (it < maxit) {
     precondition(c, r, z, s);
     SEM_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -586,6 +633,10 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
       {
         const double *a[1] = {p}, *bb[1] = {q};
         dots(c, F, 1, a, bb, &pq, s);
+      }
+      if (!(pq > 0.0)) {  // exact breakdown: p = 0, the iterate is final
+        breakdown = true;
+        break;
       }
       const double alpha = rz / pq;
       launch_axpby<double>(n, alpha, p, 1.0, x, s);
@@ -621,6 +672,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
       info->converged = 1;
       return it;
     }
+    if (breakdown) break;
   }
   info->converged = 0;
   return it;
@@ -740,6 +792,7 @@ void sem_default_opts(sem_opts *o) {
   o->gmres_restart = 20;
   o->coarse_tol = 1e-10;
   o->coarse_maxit = 2000;
+  o->ax_variant = -1;
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }
@@ -772,7 +825,9 @@ sem_status sem_setup(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const 
     *out = c;
   });
   if (st != SEM_OK && c) {
+    if (c->cs) coarse_release(*c->cs);
     if (c->hres) (void)hipHostFree(c->hres);
+    delete c->prof;
     delete c;
   }
   return st;
@@ -781,6 +836,7 @@ sem_status sem_setup(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const 
 sem_status sem_destroy(sem_ctx *ctx) {
   return guarded([&] {
     if (!ctx) return;
+    if (ctx->cs) coarse_release(*ctx->cs);
     if (ctx->hres) SEM_HIP(hipHostFree(ctx->hres));
     delete ctx->prof;
     delete ctx;

@@ -26,8 +26,9 @@ _STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EWORKSPACE", -3: "SEM_E
 EXPORTS = ("sem_default_opts", "sem_last_error", "sem_plan", "sem_setup", "sem_destroy",
            "sem_level_info", "sem_gll", "sem_coords", "sem_gather", "sem_rhs", "sem_apply_A",
            "sem_apply_S", "sem_smooth", "sem_prolong", "sem_restrict", "sem_vcycle", "sem_solve",
-           "sem_profile", "sem_profile_read")
-PROF_NAMES = ("ax64", "ax32", "fdm", "gs64", "gs32")
+           "sem_profile", "sem_profile_read", "sem_tune_space", "sem_tune_plan", "sem_tune")
+TUNE_MAX = 96
+PROF_NAMES = ("ax64", "ax32", "fdm", "gs64", "gs32", "coarse", "vcycle")
 
 
 class Mesh(ctypes.Structure):
@@ -43,7 +44,8 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("lambda_override", ctypes.c_double * 8),
                 ("smoother_prec", ctypes.c_int32), ("fdm_prec", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
-                ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32)]
+                ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32),
+                ("ax_variant", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -57,6 +59,17 @@ class LevelDesc(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("N", ctypes.c_int32), ("E", ctypes.c_int64),
                 ("nlocal", ctypes.c_int64), ("nglobal", ctypes.c_int64),
                 ("nshared", ctypes.c_int64), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double)]
+
+
+class TuneRequest(ctypes.Structure):
+    _fields_ = [("ncand", ctypes.c_int32), ("cand", Opts * TUNE_MAX), ("repeats", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_int32), ("ms", ctypes.c_double * TUNE_MAX),
+                ("setup_ms", ctypes.c_double * TUNE_MAX), ("iters", ctypes.c_int32 * TUNE_MAX),
+                ("status", ctypes.c_int32 * TUNE_MAX)]
 
 
 class SemError(RuntimeError):
@@ -94,6 +107,12 @@ def lib():
             getattr(L, name).argtypes = [vp, i32, i32, vp, vp, vp]
         L.sem_vcycle.argtypes = [vp, vp, vp, vp]
         L.sem_solve.argtypes = [vp, vp, vp, dp, i32, ctypes.POINTER(SolveInfo), vp]
+        L.sem_tune_space.argtypes = [i32, ctypes.POINTER(Opts), ctypes.POINTER(TuneRequest)]
+        L.sem_tune_plan.argtypes = [ctypes.POINTER(Mesh), i32, ctypes.POINTER(ctypes.c_int8),
+                                    ctypes.POINTER(TuneRequest), ctypes.POINTER(ctypes.c_size_t)]
+        L.sem_tune.argtypes = [ctypes.POINTER(Mesh), i32, ctypes.POINTER(ctypes.c_int8),
+                               ctypes.POINTER(TuneRequest), vp, vp, vp, ctypes.c_size_t, vp,
+                               ctypes.POINTER(TuneResult)]
         L.sem_profile.argtypes = [vp, i32]
         L.sem_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -134,10 +153,38 @@ def gll_nodes(p):
     return h[:p + 1].copy(), h[p + 1:].copy()
 
 
+def tune(nex, ney, nez, xyz, p_geom, p, b, bc=(1, 1, 1, 1, 1, 1), base=None, request=None,
+         repeats=3, rtol=1e-8, maxit=200):
+    """Exhaustive search (library side) over the pMG space; returns (best Opts, result, request).
+
+    b is the FP64 right side on the finest level (an E-vector shared by all candidates).
+    """
+    import torch
+    L = lib()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    mesh = Mesh(nex, ney, nez, p_geom, xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    bcs = (ctypes.c_int8 * 6)(*[int(v) for v in bc])
+    if request is None:
+        request = TuneRequest()
+        base = base if base is not None else make_opts(schedule=(p,))
+        check(L.sem_tune_space(p, ctypes.byref(base), ctypes.byref(request)))
+    request.repeats, request.rtol, request.maxit = repeats, rtol, maxit
+    nbytes = ctypes.c_size_t(0)
+    check(L.sem_tune_plan(ctypes.byref(mesh), p, bcs, ctypes.byref(request), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+    x = torch.empty_like(b)
+    res = TuneResult()
+    check(L.sem_tune(ctypes.byref(mesh), p, bcs, ctypes.byref(request), _ptr(b), _ptr(x), _ptr(ws),
+                     nbytes, _stream(), ctypes.byref(res)))
+    best = Opts()
+    ctypes.pointer(best)[0] = request.cand[res.best]
+    return best, res, request
+
+
 def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac=0.1,
               lmax_fac=1.1, arnoldi_steps=10, seed=0, lambda_override=None, smoother_prec=F64,
               fdm_prec=F64, krylov=KRYLOV_FCG, gmres_restart=20, coarse_tol=1e-10,
-              coarse_maxit=2000, precond=PRECOND_PMG):
+              coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1):
     o = default_opts()
     o.nlevels = len(schedule)
     for l, p in enumerate(schedule):
@@ -151,6 +198,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
             o.lambda_override[l] = float(v)
     o.smoother_prec, o.fdm_prec, o.krylov = smoother_prec, fdm_prec, krylov
     o.gmres_restart, o.coarse_tol, o.coarse_maxit = gmres_restart, coarse_tol, coarse_maxit
+    o.ax_variant = ax_variant
     return o
 
 

@@ -50,7 +50,7 @@ class Pair:
             xyz_o = wl.sampled_mesh(nex, ney, nez, ogll.gll_nodes_weights(p)[0], wl.sin_map(0.05))
         else:
             raise ValueError(mesh)
-        sm = {"jacobi": sem.SMOOTH_JACOBI, "ras": sem.SMOOTH_RAS}[smoother]
+        sm = {"jacobi": sem.SMOOTH_JACOBI, "ras": sem.SMOOTH_RAS, "asm": sem.SMOOTH_ASM}[smoother]
         opts = sem.make_opts(schedule=schedule, smoother=sm, cheb_order=cheb_order,
                              lambda_override=lambda_override, smoother_prec=smoother_prec,
                              fdm_prec=fdm_prec, krylov=krylov, coarse_tol=coarse_tol,

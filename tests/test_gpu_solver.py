@@ -66,8 +66,9 @@ def test_arnoldi_lambda_tilde(smoother):
 @pytest.mark.parametrize("smoother,sched", [("jacobi", (7, 3, 1)), ("ras", (7, 3, 1)),
                                             ("ras", (5, 1)), ("jacobi", (4, 2, 1))])
 def test_vcycle_fixed_coarse_iterations(smoother, sched):
-    P = Pair((3, 2, 2), sched[0], mesh="sin", schedule=sched, smoother=smoother,
-             coarse_tol=0.0, coarse_maxit=25, lambda_override=[1.5] * (len(sched) - 1))
+    # 18 free coarse unknowns, 12 coarse iterations: no exact convergence inside
+    P = Pair((4, 4, 3), sched[0], mesh="sin", schedule=sched, smoother=smoother,
+             coarse_tol=0.0, coarse_maxit=12, lambda_override=[1.5] * (len(sched) - 1))
     g, o = P.random_local(21)
     zg = host(P.gpu.vcycle(g))
     zo = P.ora.vcycle(o)
@@ -78,6 +79,19 @@ def test_vcycle_converged_coarse_matches_to_coarse_tolerance():
     P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", coarse_tol=1e-10)
     g, o = P.random_local(22)
     assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-8
+
+
+def test_vcycle_graph_replays_match_every_time():
+    """The coarse CG chunk is a replayed HIP graph: check several replays, with
+    eager work and synchronisation in between, against the oracle."""
+    t = _torch()
+    P = Pair(4, 5, mesh="shift", schedule=(5, 3, 1), smoother="ras", coarse_tol=1e-10)
+    for seed in (31, 32, 33):
+        g, o = P.random_local(seed)
+        z = P.gpu.vcycle(g)
+        _ = P.gpu.apply_A(g)  # unrelated eager work between replays
+        t.cuda.synchronize()
+        assert rel_err(host(z), P.ora.vcycle(o)) < 1e-8
 
 
 def _rhs(P, a=1, b=1, c=1):
@@ -94,8 +108,8 @@ def _rhs(P, a=1, b=1, c=1):
 def test_solve_fixed_iterations(krylov, smoother):
     """Same number of outer iterations on both sides: iterates agree to rounding."""
     kname = {sem.KRYLOV_FCG: "fcg", sem.KRYLOV_PCG: "pcg", sem.KRYLOV_FGMRES: "fgmres"}[krylov]
-    P = Pair((3, 2, 2), 5, mesh="sin", schedule=(5, 3, 1), smoother=smoother, krylov=krylov,
-             coarse_tol=0.0, coarse_maxit=30, lambda_override=[1.6, 1.8], gmres_restart=4)
+    P = Pair((4, 4, 3), 5, mesh="sin", schedule=(5, 3, 1), smoother=smoother, krylov=krylov,
+             coarse_tol=0.0, coarse_maxit=12, lambda_override=[1.6, 1.8], gmres_restart=4)
     bg, bo = _rhs(P)
     xg, info = P.gpu.solve(bg, rtol=1e-30, maxit=6, allow_noconv=True)
     res = P.ora.solve(bo, tol=1e-30, maxit=6, krylov=kname, restart=4)
@@ -110,7 +124,7 @@ def test_solve_to_tolerance(krylov):
     xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
     assert info.converged and info.true_rel_res <= 1e-8
     L = P.ora.fine
-    x = host(xg)
+    x = host(xg).reshape(bo.shape)
     r = bo - L.apply_A(x)
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
     res = P.ora.solve(bo, tol=1e-8, maxit=100)
@@ -138,7 +152,7 @@ def test_mixed_precision_solve():
     xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
     assert info.converged
     L = P.ora.fine
-    r = bo - L.apply_A(host(xg))
+    r = bo - L.apply_A(host(xg).reshape(bo.shape))
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
     res = P.ora.solve(bo, tol=1e-8, maxit=100)
     assert info.iters <= res.iters + 2
@@ -183,5 +197,28 @@ def test_mixed_mfma_solve_converges(fdm_prec):
     xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=200)
     assert info.converged
     L = P.ora.fine
-    r = bo - L.apply_A(host(xg))
+    r = bo - L.apply_A(host(xg).reshape(bo.shape))
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+
+
+@pytest.mark.parametrize("p,prec", [(4, sem.F64), (7, sem.F64), (5, sem.F32)])
+def test_asm_surrogate(p, prec):
+    """Additive Schwarz (eq. 4) with 1/#boxes weights against the oracle."""
+    t = _torch()
+    P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="asm", lambda_override=[2.0],
+             smoother_prec=sem.F32 if prec == sem.F32 else sem.F64, bc=(1, 0, 1, 1, 0, 1))
+    g, o = P.random_local(10)
+    if prec == sem.F32:
+        g = g.to(t.float32)
+    err = rel_err(host(P.gpu.apply_S(g)), P.ora.levels[0].apply_S(o))
+    assert err < (1e-12 if prec == sem.F64 else 1e-5), err
+
+
+def test_asm_vcycle_and_solve():
+    P = Pair(3, 5, mesh="shift", schedule=(5, 3, 1), smoother="asm", coarse_tol=0.0,
+             coarse_maxit=6, lambda_override=[1.5, 1.5])
+    g, o = P.random_local(23)
+    assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-12
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=200)
+    assert info.converged and info.true_rel_res <= 1e-8

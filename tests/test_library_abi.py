@@ -59,3 +59,43 @@ def test_host_side_validation_without_gpu():
     mesh3 = sem.Mesh(4, 4, 4, 1, xyz3.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     assert L.sem_plan(ctypes.byref(mesh3), 7, bc, ctypes.byref(o), ctypes.byref(n2)) == sem.SEM_OK
     assert n2.value > n.value
+
+
+@pytest.mark.skipif(not os.path.exists(sem.LIB_PATH), reason="libsem.so not built")
+def test_tune_space_follows_the_papers_table():
+    """Sec. 5 table: p=7 -> Cheby-ASM/RAS (7,3,1), Cheby-Jac (7,5,3,1); p=9 -> (9,5,1), (9,7,5,1)."""
+    L = sem.lib()
+    for p, short, long_ in ((7, [7, 3, 1], [7, 5, 3, 1]), (9, [9, 5, 1], [9, 7, 5, 1])):
+        req = sem.TuneRequest()
+        base = sem.make_opts(schedule=(p,))
+        assert L.sem_tune_space(p, ctypes.byref(base), ctypes.byref(req)) == sem.SEM_OK
+        seen = set()
+        for k in range(req.ncand):
+            o = req.cand[k]
+            sched = [o.p_levels[l] for l in range(o.nlevels)]
+            if o.smoother == sem.SMOOTH_JACOBI:
+                assert sched == long_
+                assert o.fdm_prec != sem.F16
+            else:
+                assert sched == short
+            seen.add((o.smoother, o.cheb_order, o.smoother_prec, o.fdm_prec, o.ax_variant))
+        assert len(seen) == req.ncand  # no duplicates
+        orders = {s[1] for s in seen}
+        assert orders == {1, 2, 3}
+        assert {s[0] for s in seen} == {sem.SMOOTH_ASM, sem.SMOOTH_RAS, sem.SMOOTH_JACOBI}
+        assert req.ncand == (48 if p == 7 else 24)
+    # plan covers the largest candidate
+    import numpy as np
+    from paper_2110_07663_amd import workloads as wl
+    xyz = np.ascontiguousarray(wl.box_vertices(2, 2, 2))
+    mesh = sem.Mesh(2, 2, 2, 1, xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    bc = (ctypes.c_int8 * 6)(1, 1, 1, 1, 1, 1)
+    req = sem.TuneRequest()
+    base = sem.make_opts(schedule=(7,))
+    L.sem_tune_space(7, ctypes.byref(base), ctypes.byref(req))
+    big = ctypes.c_size_t(0)
+    assert L.sem_tune_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(req), ctypes.byref(big)) == 0
+    for k in range(req.ncand):
+        n = ctypes.c_size_t(0)
+        assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(req.cand[k]), ctypes.byref(n)) == 0
+        assert n.value <= big.value
