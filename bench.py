@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32, help="elements per direction")
     ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--coarse-tol", type=float, default=1e-10,
+                    help="relative tolerance of the coarse Jacobi-PCG")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
@@ -62,6 +64,15 @@ def kernels_mode(a):
         s.apply_A(u, out=v)
         s.apply_A(u32, out=v32)
         s.apply_S(u32, out=v32)
+    # the other Ax kernel shapes at p = 7
+    for av in (0, 2):
+        oa = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
+                           lambda_override=[2.0, 2.0], ax_variant=av)
+        sa = sem.Solver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, opts=oa)
+        for _ in range(a.reps):
+            sa.apply_A(u, out=v)
+            sa.apply_A(u32, out=v32)
+        sa.close()
     # the matrix-core FDM in both 16-bit formats
     for fp in (sem.F16, sem.BF16):
         o16 = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
@@ -114,7 +125,7 @@ def main():
 
     def make(prec):
         opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
-                             smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=1e-10)
+                             smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=a.coarse_tol)
         t0 = time.perf_counter()
         s = sem.Solver(n, n, n, xyz, 1, p, opts=opts)
         torch.cuda.synchronize()
@@ -205,7 +216,8 @@ def main():
         "dtype": "f64 outer / f32 smoother",
         "data": "synthetic",
         "config": {"workload": f"layer-shift box {n}^3 hex, p={p}, Dirichlet, sin RHS; "
-                               f"FCG + pMG{sched} Cheby-RAS(2) FP32, coarse Jacobi-PCG 1e-10, tol 1e-8",
+                               f"FCG + pMG{sched} Cheby-RAS(2) FP32, coarse Jacobi-PCG "
+                               f"{a.coarse_tol:g}, tol 1e-8",
                    "elements": int(L0.E), "p": p, "n_unique": int(L0.nglobal),
                    "n_local": int(L0.nlocal), "parallelism": "single GPU"},
         "roofline": roofline,

@@ -96,7 +96,9 @@ typedef struct {
   double coarse_tol;          /* relative residual of the coarse Jacobi-PCG; 0 = run      */
   int32_t coarse_maxit;       /*   exactly coarse_maxit iterations                        */
   int32_t ax_variant;         /* Ax kernel shape at p = 7: 0 generic slab kernel, 1 one   */
-                              /* wavefront per element, -1 library default                */
+                              /* wavefront per element, 2 same with non-temporal streams, */
+                              /* -1 library default                                       */
+  int32_t batch_rhs;          /* right sides this context can take in sem_batch_solve     */
 } sem_opts;
 
 typedef struct {
@@ -214,6 +216,21 @@ typedef enum {
 } sem_prof_kernel;
 sem_status sem_profile(sem_ctx *ctx, int32_t enable);
 sem_status sem_profile_read(sem_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* Batched solves: nctx independent problems (contexts set up with batch_rhs >=
+ * nrhs), nrhs right sides each, advanced together by flexible CG whose scalars
+ * stay on the device.  One outer iteration of every unconverged (problem, right
+ * side) pair is recorded as one HIP graph (a branch per problem, branches on
+ * several streams) and replayed iters_per_launch times between host checks of
+ * the convergence flags; the graph is recorded again when pairs finish.  The
+ * coarse solve inside a recorded V-cycle runs a fixed iteration count (the count
+ * the first, eager V-cycle of that problem needed, plus 4, at most coarse_maxit).
+ * b[i*nrhs + k], x[i*nrhs + k]: device FP64 E-vectors of problem i, right side k
+ * (x is the initial guess and the result).  infos (may be NULL) has nctx*nrhs
+ * entries.  Returns SEM_ENOCONV if some pair misses rtol within maxit. */
+sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctx, int32_t nrhs, const double *const *b,
+                           double *const *x, double rtol, int32_t maxit, int32_t iters_per_launch,
+                           sem_solve_info *infos, void *stream);
 
 /* Auto-tuner (Sec. 5: exhaustive search over a small parameter space on the first
  * solve, at the problem the user runs).  Every candidate option set is set up in

@@ -123,7 +123,19 @@ __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__res
 // t-line of u and of the output (registers).  Plane exchanges are within one
 // wavefront: LDS operations of a wavefront complete in issue order, and the
 // wave barriers keep the compiler from moving LDS accesses across phases.
-template <typename T>
+// streaming loads/stores: NT = true marks them non-temporal (no reuse)
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T *p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename T, bool NT>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
                                          const T *__restrict__ G, const T *__restrict__ Dg,
                                          T *__restrict__ v, T *sD, T (*sU)[72], T (*sR)[72],
@@ -147,14 +159,15 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
   T uk[N], acc[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    uk[k] = ue[k * NN];
+    uk[k] = ld<NT>(ue + k * NN);
     acc[k] = T(0);
   }
   T *su = sU[w], *sr = sR[w], *ss = sS[w];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const T g0 = Ge[0 * N3 + k * NN], g1 = Ge[1 * N3 + k * NN], g2 = Ge[2 * N3 + k * NN];
-    const T g3 = Ge[3 * N3 + k * NN], g4 = Ge[4 * N3 + k * NN], g5 = Ge[5 * N3 + k * NN];
+    const T g0 = ld<NT>(Ge + 0 * N3 + k * NN), g1 = ld<NT>(Ge + 1 * N3 + k * NN);
+    const T g2 = ld<NT>(Ge + 2 * N3 + k * NN), g3 = ld<NT>(Ge + 3 * N3 + k * NN);
+    const T g4 = ld<NT>(Ge + 4 * N3 + k * NN), g5 = ld<NT>(Ge + 5 * N3 + k * NN);
     su[j * RS + i] = uk[k];
     __builtin_amdgcn_wave_barrier();
     T ur = 0, us = 0, ut = 0;
@@ -183,31 +196,41 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
   }
   T *ve = v + e * N3 + lane;
 #pragma unroll
-  for (int k = 0; k < N; ++k) ve[k * NN] = acc[k];
+  for (int k = 0; k < N; ++k) st<NT>(ve + k * NN, acc[k]);
 }
 
 // register budgets: FP64 at 4 waves/SIMD, FP32 at 6
+template <bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ax8_f64(
     int64_t E, const double *__restrict__ u, const double *__restrict__ G,
     const double *__restrict__ Dg, double *__restrict__ v) {
   __shared__ double sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<double>(E, u, G, Dg, v, sD, sU, sR, sS);
+  ax8_body<double, NT>(E, u, G, Dg, v, sD, sU, sR, sS);
 }
+template <bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32(
     int64_t E, const float *__restrict__ u, const float *__restrict__ G,
     const float *__restrict__ Dg, float *__restrict__ v) {
   __shared__ float sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<float>(E, u, G, Dg, v, sD, sU, sR, sS);
+  ax8_body<float, NT>(E, u, G, Dg, v, sD, sU, sR, sS);
 }
 
 template <typename T, int N>
 static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, hipStream_t s) {
   if constexpr (N == 8) {
-    if (L.ax_variant == 1) {
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_ax8_f64, dim3((unsigned)((L.E + 3) / 4)), dim3(256), 0, s, L.E, u, G, D, v);
-      else
-        hipLaunchKernelGGL(k_ax8_f32, dim3((unsigned)((L.E + 3) / 4)), dim3(256), 0, s, L.E, u, G, D, v);
+    if (L.ax_variant >= 1) {
+      const dim3 grid((unsigned)((L.E + 3) / 4));
+      if constexpr (sizeof(T) == 8) {
+        if (L.ax_variant == 2)
+          hipLaunchKernelGGL(k_ax8_f64<true>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+        else
+          hipLaunchKernelGGL(k_ax8_f64<false>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+      } else {
+        if (L.ax_variant == 2)
+          hipLaunchKernelGGL(k_ax8_f32<true>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+        else
+          hipLaunchKernelGGL(k_ax8_f32<false>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+      }
       SEM_LAUNCH("k_ax8");
       return;
     }

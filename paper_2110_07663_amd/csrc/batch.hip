@@ -1,0 +1,396 @@
+// Batched solves: many independent problems and right-hand sides advanced
+// together, one recorded HIP graph per outer iteration of the whole batch.
+//
+// Each (problem, right side) pair is a lane running flexible CG (the same
+// recurrence as sem_solve) with every scalar on the device: the inner product
+// kernels close with a last-block reduction that also forms alpha, beta and the
+// convergence flag, and every lane kernel is a no-op once its lane is done.
+// One outer iteration of all active lanes is recorded as a single graph: one
+// branch per problem (lanes of a problem share its V-cycle work vectors and run
+// in sequence inside the branch), branches spread over a few streams so that
+// small problems run concurrently.  The graph is replayed a few times between
+// host checks of the lane flags, and recorded again when lanes finish.  The
+// coarse solve inside a recorded V-cycle runs a fixed number of iterations
+// (the count the eager first V-cycle needed, plus a margin, capped by
+// coarse_maxit); flexible CG absorbs the variation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+struct LaneScalars {
+  double rz, pq, alpha, beta, rr, rr0, tol2, pad;
+  int done, iters, maxit, breakdown;
+};
+
+template <int ND>
+__device__ inline bool lane_last_block(double (&acc)[ND], double *partials, unsigned *counter) {
+  __shared__ double sh[ND][256];
+  __shared__ bool is_last;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = sh[j][0];
+    __threadfence();
+    is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += 256)
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      acc[j] += __hip_atomic_load(&partials[b * 8 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = sh[j][0];
+  if (tid == 0) *counter = 0u;
+  return true;
+}
+
+__global__ void k_lane_init(LaneScalars *L, double rz, double rr0, double tol2, int maxit) {
+  L->rz = rz;
+  L->rr0 = rr0;
+  L->rr = rr0;
+  L->tol2 = tol2;
+  L->maxit = maxit;
+  L->iters = 0;
+  L->breakdown = 0;
+  L->alpha = L->beta = L->pq = 0.0;
+  L->done = (rr0 == 0.0 || maxit <= 0) ? 1 : 0;
+}
+
+// pq = (p, q)_w; alpha = rz / pq
+__global__ __launch_bounds__(256) void k_lane_pq(int64_t n, const double *__restrict__ w,
+                                                 const double *__restrict__ p,
+                                                 const double *__restrict__ q, double *partials,
+                                                 unsigned *counter, LaneScalars *L) {
+  if (L->done) return;
+  double acc[1] = {0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    acc[0] += w[t] * p[t] * q[t];
+  if (lane_last_block<1>(acc, partials, counter) && threadIdx.x == 0) {
+    L->pq = acc[0];
+    if (acc[0] > 0.0) {
+      L->alpha = L->rz / acc[0];
+    } else {
+      L->alpha = 0.0;
+      L->breakdown = 1;
+      L->done = 1;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; (r, r) and the stopping test
+__global__ __launch_bounds__(256) void k_lane_update(int64_t n, const double *__restrict__ w,
+                                                     double *__restrict__ x, double *__restrict__ r,
+                                                     const double *__restrict__ p,
+                                                     const double *__restrict__ q,
+                                                     double *partials, unsigned *counter,
+                                                     LaneScalars *L) {
+  if (L->done) return;
+  const double alpha = L->alpha;
+  double acc[1] = {0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    x[t] += alpha * p[t];
+    double rv = r[t] - alpha * q[t];
+    r[t] = rv;
+    acc[0] += w[t] * rv * rv;
+  }
+  if (lane_last_block<1>(acc, partials, counter) && threadIdx.x == 0) {
+    L->rr = acc[0];
+    L->iters += 1;
+    if (acc[0] <= L->tol2 * L->rr0 || L->iters >= L->maxit || !(acc[0] == acc[0])) L->done = 1;
+  }
+}
+
+// beta = (r.z - r.z_old) / rz (flexible CG, Polak-Ribiere)
+__global__ __launch_bounds__(256) void k_lane_beta(int64_t n, const double *__restrict__ w,
+                                                   const double *__restrict__ r,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ zo, double *partials,
+                                                   unsigned *counter, LaneScalars *L) {
+  if (L->done) return;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double wr = w[t] * r[t];
+    acc[0] += wr * z[t];
+    acc[1] += wr * zo[t];
+  }
+  if (lane_last_block<2>(acc, partials, counter) && threadIdx.x == 0) {
+    L->beta = (acc[0] - acc[1]) / L->rz;
+    L->rz = acc[0];
+  }
+}
+
+// p = z + beta p; z_old = z
+__global__ void k_lane_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                         double *__restrict__ zo, const LaneScalars *L) {
+  if (L->done) return;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double zv = z[t];
+  p[t] = zv + L->beta * p[t];
+  zo[t] = zv;
+}
+
+static inline unsigned rgrid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > kRedBlocks) g = kRedBlocks;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+static inline unsigned egrid(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// eager helpers from solver.hip
+void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s);
+void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s);
+double batch_wnorm2(Ctx &c, const double *a, const double *b, hipStream_t s);
+
+struct Lane {
+  Ctx *c;
+  int k;  // right side index inside its problem
+  const double *b;
+  double *x;
+  double *r, *z, *zo, *p, *q;
+  LaneScalars *sc;
+  bool active;
+};
+
+static void lane_iteration(Lane &ln, hipStream_t s) {
+  Ctx &c = *ln.c;
+  const Level &F = c.lev[0];
+  const int64_t n = F.nloc;
+  batch_opA(c, F, ln.p, ln.q, s);
+  hipLaunchKernelGGL(k_lane_pq, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.p, ln.q, c.partials,
+                     c.counter, ln.sc);
+  SEM_LAUNCH("k_lane_pq");
+  hipLaunchKernelGGL(k_lane_update, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.x, ln.r, ln.p,
+                     ln.q, c.partials, c.counter, ln.sc);
+  SEM_LAUNCH("k_lane_update");
+  batch_precondition(c, ln.r, ln.z, s);
+  hipLaunchKernelGGL(k_lane_beta, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.r, ln.z, ln.zo,
+                     c.partials, c.counter, ln.sc);
+  SEM_LAUNCH("k_lane_beta");
+  hipLaunchKernelGGL(k_lane_p, dim3(egrid(n)), dim3(256), 0, s, n, ln.z, ln.p, ln.zo, ln.sc);
+  SEM_LAUNCH("k_lane_p");
+}
+
+struct BatchStreams {
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t fork = nullptr;
+  ~BatchStreams() {
+    for (auto s : st) (void)hipStreamDestroy(s);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
+
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_t nrhs,
+                                      const double *const *b, double *const *x, double rtol,
+                                      int32_t maxit, int32_t iters_per_launch,
+                                      sem_solve_info *infos, void *stream) {
+  sem_status status = SEM_OK;
+  std::vector<Ctx *> cs;
+  try {
+    if (nctx < 1 || nrhs < 1 || !ctxs || !b || !x || !(rtol > 0) || maxit < 0)
+      fail(SEM_EINVAL, "bad batch arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int ipl = std::max(1, iters_per_launch);
+    for (int i = 0; i < nctx; ++i) {
+      Ctx *c = reinterpret_cast<Ctx *>(ctxs[i]);
+      if (!c) fail(SEM_EINVAL, "null context in batch");
+      if (c->nlanes < nrhs) fail(SEM_EINVAL, "context was set up with fewer batch lanes than nrhs");
+      if (c->opts.krylov != SEM_KRYLOV_FCG && c->opts.krylov != SEM_KRYLOV_PCG)
+        fail(SEM_EUNSUPPORTED, "batched solves use flexible CG");
+      cs.push_back(c);
+    }
+    // lanes and their eager start: r = b - A x, z = M r, p = z_old = z
+    std::vector<Lane> lanes;
+    for (int i = 0; i < nctx; ++i) {
+      Ctx &c = *cs[i];
+      const Level &F = c.lev[0];
+      for (int k = 0; k < nrhs; ++k) {
+        Lane ln;
+        ln.c = &c;
+        ln.k = k;
+        ln.b = b[i * nrhs + k];
+        ln.x = x[i * nrhs + k];
+        if (!ln.b || !ln.x) fail(SEM_EINVAL, "null vector in batch");
+        const size_t off = (size_t)k * 5 * F.nloc;
+        ln.r = c.lanev + off;
+        ln.z = ln.r + F.nloc;
+        ln.zo = ln.z + F.nloc;
+        ln.p = ln.zo + F.nloc;
+        ln.q = ln.p + F.nloc;
+        ln.sc = reinterpret_cast<LaneScalars *>(c.lanes) + k;
+        batch_opA(c, F, ln.x, ln.q, s);
+        launch_sub<double>(F.nloc, ln.b, ln.q, ln.r, s);
+        double rr0 = batch_wnorm2(c, ln.r, ln.r, s);
+        batch_precondition(c, ln.r, ln.z, s);
+        launch_copy<double>(F.nloc, ln.z, ln.p, s);
+        launch_copy<double>(F.nloc, ln.z, ln.zo, s);
+        double rz = batch_wnorm2(c, ln.r, ln.z, s);
+        hipLaunchKernelGGL(k_lane_init, dim3(1), dim3(1), 0, s, ln.sc, rz, rr0, rtol * rtol, maxit);
+        SEM_LAUNCH("k_lane_init");
+        ln.active = rr0 > 0.0 && maxit > 0;
+        lanes.push_back(ln);
+      }
+      c.capture_coarse_iters = std::min(c.opts.coarse_maxit, c.last_coarse_iters + 4);
+    }
+    // streams for concurrent branches
+    BatchStreams bs;
+    const int nbs = std::min(nctx, 8);
+    for (int q = 0; q < nbs; ++q) {
+      hipStream_t t;
+      SEM_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+      bs.st.push_back(t);
+      hipEvent_t e;
+      SEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      bs.ev.push_back(e);
+    }
+    SEM_HIP(hipEventCreateWithFlags(&bs.fork, hipEventDisableTiming));
+    hipStream_t cap;
+    SEM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    bs.st.push_back(cap);
+
+    std::vector<LaneScalars> host(nrhs);
+    int iterations = 0;
+    while (true) {
+      bool any = false;
+      for (auto &ln : lanes) any = any || ln.active;
+      if (!any || iterations >= maxit) break;
+      // record one outer iteration of every active lane
+      for (auto *c : cs) c->capturing = true;
+      SEM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      hipGraph_t graph = nullptr;
+      try {
+        SEM_HIP(hipEventRecord(bs.fork, cap));
+        for (int i = 0; i < nctx; ++i) {
+          hipStream_t br = bs.st[i % nbs];
+          SEM_HIP(hipStreamWaitEvent(br, bs.fork, 0));
+          for (auto &ln : lanes)
+            if (ln.c == cs[i] && ln.active) lane_iteration(ln, br);
+        }
+        for (int q = 0; q < nbs; ++q) {
+          SEM_HIP(hipEventRecord(bs.ev[q], bs.st[q]));
+          SEM_HIP(hipStreamWaitEvent(cap, bs.ev[q], 0));
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto *c : cs) c->capturing = false;
+        throw;
+      }
+      SEM_HIP(hipStreamEndCapture(cap, &graph));
+      for (auto *c : cs) c->capturing = false;
+      hipGraphExec_t exec = nullptr;
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        SEM_HIP(ie);
+      }
+      // replay until some lane finishes
+      bool changed = false;
+      while (!changed && iterations < maxit) {
+        const int k = std::min(ipl, maxit - iterations);
+        for (int q = 0; q < k; ++q) SEM_HIP(hipGraphLaunch(exec, s));
+        iterations += k;
+        for (int i = 0; i < nctx; ++i) {
+          SEM_HIP(hipMemcpyAsync(host.data(), cs[i]->lanes, nrhs * sizeof(LaneScalars),
+                                 hipMemcpyDeviceToHost, s));
+          SEM_HIP(hipStreamSynchronize(s));
+          for (auto &ln : lanes)
+            if (ln.c == cs[i] && ln.active) {
+              const LaneScalars &h = host[ln.k];
+              if (!(h.rr == h.rr)) fail(SEM_ENAN, "NaN in a batched solve");
+              if (h.done) {
+                ln.active = false;
+                changed = true;
+              }
+            }
+        }
+      }
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+    }
+    // true residuals and per-lane results
+    bool all = true;
+    for (size_t li = 0; li < lanes.size(); ++li) {
+      Lane &ln = lanes[li];
+      Ctx &c = *ln.c;
+      const Level &F = c.lev[0];
+      SEM_HIP(hipMemcpyAsync(host.data(), c.lanes, nrhs * sizeof(LaneScalars),
+                             hipMemcpyDeviceToHost, s));
+      SEM_HIP(hipStreamSynchronize(s));
+      const LaneScalars &h = host[ln.k];
+      batch_opA(c, F, ln.x, ln.q, s);
+      launch_sub<double>(F.nloc, ln.b, ln.q, ln.r, s);
+      double tr = batch_wnorm2(c, ln.r, ln.r, s);
+      sem_solve_info *inf = infos ? &infos[li] : nullptr;
+      double rel = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
+      double trel = h.rr0 > 0 ? std::sqrt(tr / h.rr0) : 0.0;
+      bool conv = trel <= rtol;
+      all = all && conv;
+      if (inf) {
+        std::memset(inf, 0, sizeof(*inf));
+        inf->iters = h.iters;
+        inf->converged = conv ? 1 : 0;
+        inf->rel_res = rel;
+        inf->true_rel_res = trel;
+        inf->r0_norm = std::sqrt(h.rr0);
+        inf->coarse_iters = c.capture_coarse_iters;
+        for (int l = 0; l < c.nlev; ++l) inf->lambda_tilde[l] = c.lev[l].lam_tilde;
+      }
+    }
+    SEM_HIP(hipStreamSynchronize(s));
+    if (!all) {
+      set_last_error("a batched lane did not reach rtol within maxit");
+      status = SEM_ENOCONV;
+    }
+  } catch (const Error &e) {
+    for (auto *c : cs) c->capturing = false;
+    set_last_error(e.msg);
+    status = e.status;
+  } catch (...) {
+    for (auto *c : cs) c->capturing = false;
+    set_last_error("unexpected exception in a batched solve");
+    status = SEM_EHIP;
+  }
+  return status;
+}

@@ -132,6 +132,19 @@ void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *d
   SEM_LAUNCH("k_jacobi_inv");
 }
 
+template <typename T>
+__global__ void k_copy(int64_t n, const T *__restrict__ x, T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = x[t];
+}
+template <typename T>
+void launch_copy(int64_t n, const T *x, T *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
+  SEM_LAUNCH("k_copy");
+}
+template void launch_copy<double>(int64_t, const double *, double *, hipStream_t);
+template void launch_copy<float>(int64_t, const float *, float *, hipStream_t);
+
 __global__ void k_fill(int64_t n, double v, double *x) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < n) x[t] = v;

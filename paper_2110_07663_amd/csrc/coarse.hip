@@ -194,16 +194,16 @@ __device__ inline bool cg_last_block(double (&acc)[ND], double *partials, unsign
 // start from x = 0: r = b, z = D^{-1} r, p = s = 0; (r,z), (r,r)
 __global__ __launch_bounds__(256) void k_cg_start(int64_t n, CgPtrs P, double tol2, int maxit) {
   double acc[2] = {0.0, 0.0};
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
     double rv = P.b[t], zv = P.dinv[t] * rv;
     P.x[t] = 0.0;
     P.r[t] = rv;
     P.u[t] = zv;
     P.p[t] = 0.0;
     P.s[t] = 0.0;
-    acc[0] = rv * zv;
-    acc[1] = rv * rv;
+    acc[0] += rv * zv;
+    acc[1] += rv * rv;
   }
   if (cg_last_block<2>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     CoarseScalars *c = P.sc;
@@ -223,11 +223,11 @@ __global__ __launch_bounds__(256) void k_cg_start(int64_t n, CgPtrs P, double to
 __global__ __launch_bounds__(256) void k_cg_spmv(int64_t n, CoarseGrid g, CgPtrs P, int first) {
   if (P.sc->done) return;
   double acc[1] = {0.0};
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
     double wv = stencil_apply(g, P.St, P.u, t, n);
     P.w[t] = wv;
-    acc[0] = wv * P.u[t];
+    acc[0] += wv * P.u[t];
   }
   if (cg_last_block<1>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     CoarseScalars *c = P.sc;
@@ -253,8 +253,8 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, CgPtrs P) {
   if (c->done) return;
   const double alpha = c->alpha, beta = c->beta;
   double acc[2] = {0.0, 0.0};
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
     double pv = P.u[t] + beta * P.p[t];
     double sv = P.w[t] + beta * P.s[t];
     P.p[t] = pv;
@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, CgPtrs P) {
     double zv = P.dinv[t] * rv;
     P.r[t] = rv;
     P.u[t] = zv;
-    acc[0] = rv * zv;
-    acc[1] = rv * rv;
+    acc[0] += rv * zv;
+    acc[1] += rv * rv;
   }
   if (cg_last_block<2>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     c->gamma_old = c->gamma;
@@ -278,6 +278,12 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, CgPtrs P) {
 }
 
 static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+// CG kernels: each thread handles `rows_per_thread` rows (fewer blocks close
+// each reduction); the grid is fixed per solver so the summation order is too
+static inline unsigned cg_grid(const CoarseSolver &S) {
+  int64_t per = 256 * (int64_t)S.rows_per_thread;
+  return (unsigned)((S.n + per - 1) / per);
+}
 
 static CgPtrs ptrs(const Ctx &c) {
   const CoarseSolver &S = *c.cs;
@@ -304,9 +310,9 @@ static void enqueue_iterations(const Ctx &c, int k, hipStream_t s) {
   CoarseGrid g = cgrid(c);
   const int64_t n = c.cs->n;
   for (int it = 0; it < k; ++it) {
-    hipLaunchKernelGGL(k_cg_update, dim3(nb(n)), dim3(256), 0, s, n, P);
+    hipLaunchKernelGGL(k_cg_update, dim3(cg_grid(*c.cs)), dim3(256), 0, s, n, P);
     SEM_LAUNCH("k_cg_update");
-    hipLaunchKernelGGL(k_cg_spmv, dim3(nb(n)), dim3(256), 0, s, n, g, P, 0);
+    hipLaunchKernelGGL(k_cg_spmv, dim3(cg_grid(*c.cs)), dim3(256), 0, s, n, g, P, 0);
     SEM_LAUNCH("k_cg_spmv");
   }
 }
@@ -334,11 +340,18 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
   CgPtrs P = ptrs(c);
   hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, C.d_b, S.b);
   SEM_LAUNCH("k_coarse_to_global");
-  hipLaunchKernelGGL(k_cg_start, dim3(nb(S.n)), dim3(256), 0, s, S.n, P, tol > 0 ? tol * tol : 0.0,
-                     maxit);
+  hipLaunchKernelGGL(k_cg_start, dim3(cg_grid(S)), dim3(256), 0, s, S.n, P,
+                     tol > 0 ? tol * tol : 0.0, maxit);
   SEM_LAUNCH("k_cg_start");
-  hipLaunchKernelGGL(k_cg_spmv, dim3(nb(S.n)), dim3(256), 0, s, S.n, g, P, 1);
+  hipLaunchKernelGGL(k_cg_spmv, dim3(cg_grid(S)), dim3(256), 0, s, S.n, g, P, 1);
   SEM_LAUNCH("k_cg_spmv");
+  if (c.capturing) {
+    // inside a recorded batch iteration: a fixed count, no readback
+    const int k = tol > 0.0 ? std::min(maxit, c.capture_coarse_iters) : maxit;
+    enqueue_iterations(c, k, s);
+    launch_gather(c, C, S.x, c.cx, s);
+    return;
+  }
   if (tol <= 0.0 || !S.use_graph) {
     // fixed iteration count (or graphs off): plain launches, one readback at most
     if (tol <= 0.0) {

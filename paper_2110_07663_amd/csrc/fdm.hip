@@ -180,7 +180,7 @@ struct FdmShape {
   static constexpr int PB = P + 3;
   static constexpr int N = P + 1;
   static constexpr int BS = ((PB * PB + 63) / 64) * 64;
-  static constexpr int RS = PB + 1;
+  static constexpr int RS = PB;
   static constexpr int PS = PB * RS;
 };
 
@@ -195,18 +195,32 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
   using F = FdmShape<P>;
   constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
-  constexpr int N3 = N * N * N;
-  __shared__ T sS[3][PB * PB];
-  __shared__ T sL[3][PB];
+  constexpr int N3 = N * N * N, PB2 = PB * PB;
   __shared__ T buf0[PB * PS];
   __shared__ T buf1[PB * PS];
 
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
   const int a = tid % PB, b = tid / PB;
-  const bool act = tid < PB * PB;
-  for (int t = tid; t < 3 * PB * PB; t += F::BS) sS[t / (PB * PB)][t % (PB * PB)] = Sg[e * 3 * PB * PB + t];
-  for (int t = tid; t < 3 * PB; t += F::BS) sL[t / PB][t % PB] = lamg[e * 3 * PB + t];
+  const bool act = tid < PB2;
+  // the thread's rows and columns of S_x (index a) and S_y (index b) live in
+  // registers; S_z and lambda_z are the same for the whole block (scalar loads)
+  const T *Se = Sg + e * 3 * PB2;
+  const T *le = lamg + e * 3 * PB;
+  const T *__restrict__ Sz = Se + 2 * PB2;
+  const T *__restrict__ lz = le + 2 * PB;
+  T Sxc[PB], Sxr[PB], Syc[PB], Syr[PB];
+  T lxy = T(0);
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      Sxc[q] = Se[q * PB + a];
+      Sxr[q] = Se[a * PB + q];
+      Syc[q] = Se[PB2 + q * PB + b];
+      Syr[q] = Se[PB2 + b * PB + q];
+    }
+    lxy = le[a] + le[PB + b];
+  }
 
   const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
   T col[PB];
@@ -239,7 +253,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     for (int c = 0; c < PB; ++c) {
       T s = 0;
 #pragma unroll
-      for (int i = 0; i < PB; ++i) s += sS[0][i * PB + a] * buf0[c * PS + b * RS + i];
+      for (int i = 0; i < PB; ++i) s += Sxc[i] * buf0[c * PS + b * RS + i];
       buf1[c * PS + b * RS + a] = s;
     }
   }
@@ -250,7 +264,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     for (int c = 0; c < PB; ++c) {
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < PB; ++j) s += sS[1][j * PB + b] * buf1[c * PS + j * RS + a];
+      for (int j = 0; j < PB; ++j) s += Syc[j] * buf1[c * PS + j * RS + a];
       col[c] = s;
     }
     T h[PB];
@@ -258,15 +272,15 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     for (int cc = 0; cc < PB; ++cc) {
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < PB; ++k) s += sS[2][k * PB + cc] * col[k];
-      h[cc] = s * fdm_inv<T>(sL[0][a] + sL[1][b] + sL[2][cc]);
+      for (int k = 0; k < PB; ++k) s += Sz[k * PB + cc] * col[k];
+      h[cc] = s * fdm_inv<T>(lxy + lz[cc]);
     }
     // back along z
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
       T s = 0;
 #pragma unroll
-      for (int cc = 0; cc < PB; ++cc) s += sS[2][k * PB + cc] * h[cc];
+      for (int cc = 0; cc < PB; ++cc) s += Sz[k * PB + cc] * h[cc];
       col[k] = s;
     }
 #pragma unroll
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     for (int c = 0; c < PB; ++c) {
       T s = 0;
 #pragma unroll
-      for (int bb = 0; bb < PB; ++bb) s += sS[1][b * PB + bb] * buf0[c * PS + bb * RS + a];
+      for (int bb = 0; bb < PB; ++bb) s += Syr[bb] * buf0[c * PS + bb * RS + a];
       buf1[c * PS + b * RS + a] = s;
     }
   }
@@ -292,7 +306,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
       for (int c = 0; c < PB; ++c) {
         T s = 0;
 #pragma unroll
-        for (int aa = 0; aa < PB; ++aa) s += sS[0][a * PB + aa] * buf1[c * PS + b * RS + aa];
+        for (int aa = 0; aa < PB; ++aa) s += Sxr[aa] * buf1[c * PS + b * RS + aa];
         zb[c * PB * PB] = s;
       }
     }
@@ -305,7 +319,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     for (int c = 1; c <= P + 1; ++c) {
       T s = 0;
 #pragma unroll
-      for (int aa = 0; aa < PB; ++aa) s += sS[0][a * PB + aa] * buf1[c * PS + b * RS + aa];
+      for (int aa = 0; aa < PB; ++aa) s += Sxr[aa] * buf1[c * PS + b * RS + aa];
       const int64_t o = obase + (int64_t)(c - 1) * N * N;
       z[o] = W[o] * s;
     }

@@ -5,7 +5,9 @@
 // local indices of every shared node (and of every Dirichlet node, which the
 // same pass zeroes) by global id, stably, so each global node becomes one
 // contiguous segment of `perm`; `off[s]` is the segment start with bit 31 set
-// for Dirichlet segments.  The summation then visits each segment once, adds
+// for Dirichlet segments.  The segments are then reordered by their first
+// (smallest) local index, so that consecutive threads work on neighbouring
+// nodes of the same few elements.  The summation then visits each segment once, adds
 // its copies in ascending local index (a fixed order: results are bitwise
 // repeatable, no floating-point atomics) and writes the sum to every copy.
 #include <hipcub/hipcub.hpp>
@@ -91,6 +93,33 @@ __global__ void k_gs_offsets(GridInfo g, int64_t nloc, const int32_t *skeys, con
 
 __global__ void k_gs_close(int32_t *off, const int32_t *counts) {
   off[counts[1]] = counts[0];
+}
+
+// element-major segment order: key = first (smallest) member local index
+__global__ void k_seg_first(int nseg, const int32_t *perm, const int32_t *off, int32_t *key,
+                            int32_t *val) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  key[s] = perm[off[s] & 0x7fffffff];
+  val[s] = s;
+}
+__global__ void k_seg_count(int nseg, const int32_t *off, const int32_t *order, int32_t *cnt) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nseg) return;
+  int s = order[t];
+  cnt[t] = (off[s + 1] & 0x7fffffff) - (off[s] & 0x7fffffff);
+}
+__global__ void k_seg_move(int nseg, int nperm, const int32_t *perm, const int32_t *off,
+                           const int32_t *order, const int32_t *start, int32_t *perm2,
+                           int32_t *off2) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nseg) return;
+  int s = order[t];
+  int32_t a = off[s] & 0x7fffffff, b = off[s + 1] & 0x7fffffff;
+  int32_t flag = off[s] & (int32_t)0x80000000u;
+  for (int m = a; m < b; ++m) perm2[start[t] + (m - a)] = perm[m];
+  off2[t] = start[t] | flag;
+  if (t == nseg - 1) off2[nseg] = nperm;
 }
 
 template <typename T>
@@ -221,6 +250,30 @@ void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s)
   SEM_HIP(hipStreamSynchronize(s));
   L.nperm = h[0];
   L.nseg = h[1];
+  if (L.nseg == 0) return;
+  // reorder the segments element-major (by their first copy) so that a
+  // wavefront's segments touch neighbouring memory; members stay sorted
+  const int ns = L.nseg;
+  int32_t *order = head, *cnt = segid, *start = keys;
+  int32_t *perm2 = scratch.take<int32_t>(n);
+  int32_t *off2 = scratch.take<int32_t>(n + 1);
+  int32_t *k2 = scratch.take<int32_t>(n);
+  hipLaunchKernelGGL(k_seg_first, dim3(nb(ns, 256)), dim3(256), 0, s, ns, L.perm, L.off, k2, vals);
+  SEM_LAUNCH("k_seg_first");
+  tb2 = tb;
+  SEM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb2, k2, skeys, vals, order, ns, 0, 32, s));
+  hipLaunchKernelGGL(k_seg_count, dim3(nb(ns, 256)), dim3(256), 0, s, ns, L.off, order, cnt);
+  SEM_LAUNCH("k_seg_count");
+  tb2 = tb;
+  SEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb2, cnt, start, ns, s));
+  hipLaunchKernelGGL(k_seg_move, dim3(nb(ns, 256)), dim3(256), 0, s, ns, L.nperm, L.perm, L.off,
+                     order, start, perm2, off2);
+  SEM_LAUNCH("k_seg_move");
+  SEM_HIP(hipMemcpyAsync(L.perm, perm2, (size_t)L.nperm * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s));
+  SEM_HIP(hipMemcpyAsync(L.off, off2, (size_t)(ns + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s));
+  SEM_HIP(hipStreamSynchronize(s));
 }
 
 template <typename T>

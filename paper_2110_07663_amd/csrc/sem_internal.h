@@ -21,6 +21,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(sem_status st, const std::string &msg);
+void set_last_error(const std::string &msg);
 void check_hip(hipError_t e, const char *what, const char *file, int line);
 #define SEM_HIP(call) ::sem::check_hip((call), #call, __FILE__, __LINE__)
 #define SEM_LAUNCH(what) ::sem::check_hip(hipGetLastError(), what, __FILE__, __LINE__)
@@ -123,6 +124,7 @@ struct CoarseSolver {
   unsigned *counter = nullptr;
   CoarseScalars *sc = nullptr;
   int chunk = 16;                  // iterations per recorded graph
+  int rows_per_thread = 1;
   bool use_graph = true;
   hipStream_t cap = nullptr;       // private capture stream
   hipGraph_t graph = nullptr;
@@ -139,8 +141,8 @@ struct Profiler {
   std::vector<Rec> recs;  // events of the current session
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   size_t used = 0;
-  void begin(int kind, hipStream_t s);
-  void end(hipStream_t s);
+  size_t begin(int kind, hipStream_t s);
+  void end(size_t rec, hipStream_t s);
   void reset();
   ~Profiler();
 };
@@ -168,6 +170,14 @@ struct Ctx {
   // coarse PCG vectors (FP64, coarsest level)
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
   int last_coarse_iters = 0;
+  // graph capture of whole iterations (batched solves): no host synchronisation
+  // may be enqueued, so the coarse solve runs a fixed number of iterations
+  bool capturing = false;
+  int capture_coarse_iters = 0;
+  // batched-solve lanes: per right side r, z, z_old, p, q (FP64) and scalars
+  int nlanes = 0;
+  double *lanev = nullptr;
+  void *lanes = nullptr;
   CoarseSolver coarse_store;
   CoarseSolver *cs = nullptr;      // set when the coarsest level is p = 1 (assembled solve)
   // Arnoldi basis (FP64, largest level)
@@ -231,6 +241,8 @@ void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *
 void launch_mupdate(int64_t n, int k, const double *V, int64_t ld, const double *h, double *x,
                     double sign, hipStream_t s);
 void launch_fill(int64_t n, double v, double *x, hipStream_t s);
+template <typename T>
+void launch_copy(int64_t n, const T *x, T *y, hipStream_t s);
 void launch_fillf(int64_t n, float v, float *x, hipStream_t s);
 
 // coarse PCG kernels with device scalars (blas.hip)

@@ -22,6 +22,7 @@ namespace sem {
 static thread_local std::string g_last_error;
 
 void fail(sem_status st, const std::string &msg) { throw Error{st, msg}; }
+void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 void check_hip(hipError_t e, const char *what, const char *file, int line) {
   if (e != hipSuccess) {
@@ -91,7 +92,8 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
   if (o->krylov == SEM_KRYLOV_FGMRES && (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart))
     fail(SEM_EINVAL, "gmres_restart in [1, 64]");
   if (o->coarse_maxit < 1) fail(SEM_EINVAL, "coarse_maxit must be >= 1");
-  if (o->ax_variant < -1 || o->ax_variant > 1) fail(SEM_EINVAL, "ax_variant must be -1, 0 or 1");
+  if (o->ax_variant < -1 || o->ax_variant > 2) fail(SEM_EINVAL, "ax_variant must be in [-1, 2]");
+  if (o->batch_rhs < 0 || o->batch_rhs > 64) fail(SEM_EINVAL, "batch_rhs must be in [0, 64]");
   for (int f = 0; f < 6; ++f)
     if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
   int64_t E = (int64_t)m->nex * m->ney * m->nez;
@@ -182,6 +184,12 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   c.cq = A.take<double>(C.nloc);
   if (o.precond == SEM_PRECOND_PMG && c.nlev > 1)
     c.av = A.take<double>((size_t)(o.arnoldi_steps + 1) * F.nloc);
+  // batched-solve lanes
+  c.nlanes = std::max(0, o.batch_rhs);
+  if (c.nlanes > 0) {
+    c.lanev = A.take<double>((size_t)c.nlanes * 5 * F.nloc);
+    c.lanes = A.take<char>((size_t)c.nlanes * 128);
+  }
   // assembled coarse solve when the coarsest level is p = 1
   c.cs = nullptr;
   if (o.precond == SEM_PRECOND_PMG && C.p == 1) {
@@ -202,6 +210,8 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     S.sc = A.take<CoarseScalars>(1);
     const char *g = getenv("SEM_COARSE_GRAPH");
     S.use_graph = !(g && g[0] == '0');
+    const char *rp = getenv("SEM_COARSE_RPT");
+    S.rows_per_thread = rp ? std::max(1, std::min(16, atoi(rp))) : 4;
     c.cs = &S;
   }
   // setup-only scratch
@@ -211,7 +221,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   sc.xig = A.take<double>(Ng);
   sc.Jg = A.take<double>(Ng * (kMaxP + 1));
   sc.bad = A.take<int>(64);
-  size_t gsb = 5 * F.nloc * sizeof(int32_t) + 16 + gs_sort_temp_bytes(F.nloc) + 8 * 256;
+  size_t gsb = 8 * (F.nloc + 1) * sizeof(int32_t) + 16 + gs_sort_temp_bytes(F.nloc) + 12 * 256;
   char *g = A.take<char>(gsb);
   sc.gs.base = g;
   sc.gs.cap = gsb;
@@ -277,7 +287,7 @@ struct Vec<float> {
   static const float *dinv(const Level &L) { return L.dinv32; }
 };
 
-void Profiler::begin(int kind, hipStream_t s) {
+size_t Profiler::begin(int kind, hipStream_t s) {
   if (used == pool.size()) {
     hipEvent_t a, b;
     SEM_HIP(hipEventCreate(&a));
@@ -288,8 +298,9 @@ void Profiler::begin(int kind, hipStream_t s) {
   ++used;
   SEM_HIP(hipEventRecord(r.a, s));
   recs.push_back(r);
+  return recs.size() - 1;
 }
-void Profiler::end(hipStream_t s) { (void)hipEventRecord(recs.back().b, s); }
+void Profiler::end(size_t rec, hipStream_t s) { (void)hipEventRecord(recs[rec].b, s); }
 void Profiler::reset() {
   recs.clear();
   used = 0;
@@ -302,16 +313,19 @@ Profiler::~Profiler() {
 }
 
 // records the enclosed launches when profiling a finest-level kernel
+// (scopes nest: each closes its own record)
 struct ProfScope {
   Profiler *p;
   hipStream_t s;
+  size_t rec = 0;
   ProfScope(const Ctx &c, const Level &L, int kind, hipStream_t st)
-      : p((c.prof && c.prof->on && (L.fine || kind >= SEM_PROF_COARSE)) ? c.prof : nullptr),
+      : p((c.prof && c.prof->on && !c.capturing && (L.fine || kind >= SEM_PROF_COARSE)) ? c.prof
+                                                                                        : nullptr),
         s(st) {
-    if (p) p->begin(kind, s);
+    if (p) rec = p->begin(kind, s);
   }
   ~ProfScope() {
-    if (p) p->end(s);
+    if (p) p->end(rec, s);
   }
 };
 
@@ -397,12 +411,13 @@ static void coarse_solve(Ctx &c, Level &C, hipStream_t s) {
   launch_cpcg_init(c, C, init.tol2, maxit, s);
   int done_iters = 0;
   bool first = true;
-  if (tol <= 0.0) {
-    for (int it = 0; it < maxit; ++it) {
+  if (tol <= 0.0 || c.capturing) {
+    const int n = c.capturing && tol > 0.0 ? std::min(maxit, c.capture_coarse_iters) : maxit;
+    for (int it = 0; it < n; ++it) {
       launch_cpcg_iteration(c, C, first, s);
       first = false;
     }
-    c.last_coarse_iters = maxit;
+    if (!c.capturing) c.last_coarse_iters = maxit;
     return;
   }
   int chunk = std::max(8, c.last_coarse_iters + 2);
@@ -434,7 +449,7 @@ static void vcycle_level(Ctx &c, int l, hipStream_t s) {
     if constexpr (sizeof(T) == 4)
       launch_copy_cvt_d2f(L.nloc, c.cx, L.f_x, s);
     else
-      SEM_HIP(hipMemcpyAsync(L.d_x, c.cx, L.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_copy<double>(L.nloc, c.cx, L.d_x, s);
     return;
   }
   Level &C = c.lev[l + 1];
@@ -458,9 +473,9 @@ static void precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
     return;
   }
   if (F.coarse) {  // single-level schedule: the coarse solve itself, in FP64
-    SEM_HIP(hipMemcpyAsync(F.d_b, r, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_copy<double>(F.nloc, r, F.d_b, s);
     coarse_solve(c, F, s);
-    SEM_HIP(hipMemcpyAsync(z, c.cx, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_copy<double>(F.nloc, c.cx, z, s);
     return;
   }
   if (c.lowp) {
@@ -468,9 +483,9 @@ static void precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
     vcycle_level<float>(c, 0, s);
     launch_copy_cvt_f2d(F.nloc, F.f_x, z, s);
   } else {
-    SEM_HIP(hipMemcpyAsync(F.d_b, r, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_copy<double>(F.nloc, r, F.d_b, s);
     vcycle_level<double>(c, 0, s);
-    SEM_HIP(hipMemcpyAsync(z, F.d_x, F.nloc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_copy<double>(F.nloc, F.d_x, z, s);
   }
 }
 
@@ -757,6 +772,20 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
   return it;
 }
 
+// entry points used by the batched driver (batch.hip)
+void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s) {
+  opA<double>(c, L, u, Au, s);
+}
+void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
+  precondition(c, r, z, s);
+}
+double batch_wnorm2(Ctx &c, const double *a, const double *b, hipStream_t s) {
+  const double *pa[1] = {a}, *pb[1] = {b};
+  double v;
+  dots(c, c.lev[0], 1, pa, pb, &v, s);
+  return v;
+}
+
 static Level &level_of(sem_ctx *ctx, int level) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) fail(SEM_EINVAL, "null context");
@@ -793,6 +822,7 @@ void sem_default_opts(sem_opts *o) {
   o->coarse_tol = 1e-10;
   o->coarse_maxit = 2000;
   o->ax_variant = -1;
+  o->batch_rhs = 0;
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }

@@ -26,7 +26,8 @@ _STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EWORKSPACE", -3: "SEM_E
 EXPORTS = ("sem_default_opts", "sem_last_error", "sem_plan", "sem_setup", "sem_destroy",
            "sem_level_info", "sem_gll", "sem_coords", "sem_gather", "sem_rhs", "sem_apply_A",
            "sem_apply_S", "sem_smooth", "sem_prolong", "sem_restrict", "sem_vcycle", "sem_solve",
-           "sem_profile", "sem_profile_read", "sem_tune_space", "sem_tune_plan", "sem_tune")
+           "sem_profile", "sem_profile_read", "sem_tune_space", "sem_tune_plan", "sem_tune",
+           "sem_batch_solve")
 TUNE_MAX = 96
 PROF_NAMES = ("ax64", "ax32", "fdm", "gs64", "gs32", "coarse", "vcycle")
 
@@ -45,7 +46,7 @@ class Opts(ctypes.Structure):
                 ("smoother_prec", ctypes.c_int32), ("fdm_prec", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32),
-                ("ax_variant", ctypes.c_int32)]
+                ("ax_variant", ctypes.c_int32), ("batch_rhs", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -113,6 +114,8 @@ def lib():
         L.sem_tune.argtypes = [ctypes.POINTER(Mesh), i32, ctypes.POINTER(ctypes.c_int8),
                                ctypes.POINTER(TuneRequest), vp, vp, vp, ctypes.c_size_t, vp,
                                ctypes.POINTER(TuneResult)]
+        L.sem_batch_solve.argtypes = [i32, ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), dp, i32, i32, ctypes.POINTER(SolveInfo), vp]
         L.sem_profile.argtypes = [vp, i32]
         L.sem_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -181,10 +184,28 @@ def tune(nex, ney, nez, xyz, p_geom, p, b, bc=(1, 1, 1, 1, 1, 1), base=None, req
     return best, res, request
 
 
+def batch_solve(solvers, bs, xs, rtol=1e-8, maxit=200, iters_per_launch=4, allow_noconv=False):
+    """Solve every (solver i, right side k) pair together: bs[i][k] -> xs[i][k] (in place).
+
+    Returns the list of SolveInfo (problem-major).  Each solver must have been
+    set up with batch_rhs >= the number of right sides.
+    """
+    nctx = len(solvers)
+    nrhs = len(bs[0])
+    ctxs = (ctypes.c_void_p * nctx)(*[s.ctx for s in solvers])
+    bp = (ctypes.c_void_p * (nctx * nrhs))(*[b.data_ptr() for row in bs for b in row])
+    xp = (ctypes.c_void_p * (nctx * nrhs))(*[x.data_ptr() for row in xs for x in row])
+    infos = (SolveInfo * (nctx * nrhs))()
+    st = lib().sem_batch_solve(nctx, ctxs, nrhs, bp, xp, rtol, maxit, iters_per_launch, infos,
+                               _stream())
+    check(st, allow=(SEM_ENOCONV,) if allow_noconv else ())
+    return list(infos)
+
+
 def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac=0.1,
               lmax_fac=1.1, arnoldi_steps=10, seed=0, lambda_override=None, smoother_prec=F64,
               fdm_prec=F64, krylov=KRYLOV_FCG, gmres_restart=20, coarse_tol=1e-10,
-              coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1):
+              coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1, batch_rhs=0):
     o = default_opts()
     o.nlevels = len(schedule)
     for l, p in enumerate(schedule):
@@ -199,6 +220,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
     o.smoother_prec, o.fdm_prec, o.krylov = smoother_prec, fdm_prec, krylov
     o.gmres_restart, o.coarse_tol, o.coarse_maxit = gmres_restart, coarse_tol, coarse_maxit
     o.ax_variant = ax_variant
+    o.batch_rhs = batch_rhs
     return o
 
 

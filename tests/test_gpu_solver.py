@@ -219,6 +219,11 @@ def test_asm_vcycle_and_solve():
              coarse_maxit=6, lambda_override=[1.5, 1.5])
     g, o = P.random_local(23)
     assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-12
-    bg, bo = _rhs(P)
-    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=200)
+    # the solve uses Arnoldi bounds (the fixed 1.5 above underestimates ASM's spectrum)
+    Q = Pair(3, 5, mesh="shift", schedule=(5, 3, 1), smoother="asm")
+    bg, bo = _rhs(Q)
+    xg, info = Q.gpu.solve(bg, rtol=1e-8, maxit=200)
     assert info.converged and info.true_rel_res <= 1e-8
+    L = Q.ora.fine
+    r = bo - L.apply_A(host(xg).reshape(bo.shape))
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
