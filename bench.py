@@ -38,8 +38,11 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
-    ap.add_argument("--mode", choices=("solve", "kernels"), default="solve",
-                    help="kernels: repeat single finest-level kernels (for counter runs)")
+    ap.add_argument("--mode", choices=("solve", "kernels", "batch"), default="solve",
+                    help="kernels: repeat single finest-level kernels (for counter runs); "
+                         "batch: the 64-problem x 4-RHS batched workload")
+    ap.add_argument("--nprob", type=int, default=64, help="problems in --mode batch")
+    ap.add_argument("--no-tune", action="store_true", help="--mode batch: skip the auto-tuner")
     ap.add_argument("--reps", type=int, default=5, help="repetitions per kernel in --mode kernels")
     return ap.parse_args()
 
@@ -89,6 +92,93 @@ def kernels_mode(a):
     print(json.dumps({"mode": "kernels", "reps": a.reps, "copy_bytes": 2 * src.numel() * 8}))
 
 
+def batch_mode(a):
+    """Batched workload: `nprob` independent Poisson solves on the smooth
+    sinusoidal map, E = side^3 with side in {8, 12, 16, 24} and p in {5, 7, 9}
+    drawn by seed 5, each with 4 sinusoidal right sides of random frequencies
+    1..4; mixed precision Cheby-RAS pMG, tol 1e-8.  The auto-tuner picks the
+    Chebyshev order and the Ax kernel shape per (p, side) bucket on its first
+    problem.  Reports the time of the batched solve (one recorded graph per
+    outer iteration of all 4*nprob lanes) against solving every lane in turn."""
+    import torch
+    from paper_2110_07663_amd import sem
+    from paper_2110_07663_amd import workloads as wl
+    torch.cuda.set_device(0)
+    spec = wl.batch_spec(nprob=a.nprob, seed=5)
+    sched_of = {5: (5, 3, 1), 7: (7, 3, 1), 9: (9, 5, 1)}
+    tuned = {}
+    solvers, bs, t_tune = [], [], 0.0
+    total_dof = 0
+    for side, p, freqs in spec:
+        xyz = wl.sampled_mesh(side, side, side, sem.gll_nodes(p)[0], wl.sin_map(0.05))
+        base = sem.make_opts(schedule=sched_of[p], smoother=sem.SMOOTH_RAS, cheb_order=2,
+                             smoother_prec=sem.F32, batch_rhs=4)
+        key = (p, side)
+        if key not in tuned and not a.no_tune:
+            probe = sem.Solver(side, side, side, xyz, p, p, opts=base)
+            X = probe.coords(0).cpu().numpy()
+            f, _ = wl.sinusoid(*freqs[0])
+            b0 = probe.rhs(torch.as_tensor(f(X[0], X[1], X[2])).cuda())
+            req = sem.TuneRequest()
+            req.ncand = 0
+            for order in (1, 2, 3):
+                for av in ((0, 1) if p == 7 else (-1,)):
+                    o = sem.make_opts(schedule=sched_of[p], smoother=sem.SMOOTH_RAS,
+                                      cheb_order=order, smoother_prec=sem.F32, batch_rhs=4,
+                                      ax_variant=av)
+                    req.cand[req.ncand] = o
+                    req.ncand += 1
+            t0 = time.perf_counter()
+            best, res, _ = sem.tune(side, side, side, xyz, p, p, b0, request=req, repeats=1)
+            t_tune += time.perf_counter() - t0
+            probe.close()
+            best.batch_rhs = 4
+            tuned[key] = best
+        opts = tuned.get(key, base)
+        s = sem.Solver(side, side, side, xyz, p, p, opts=opts)
+        X = s.coords(0).cpu().numpy()
+        row = []
+        for fr in freqs:
+            f, _ = wl.sinusoid(*fr)
+            row.append(s.rhs(torch.as_tensor(f(X[0], X[1], X[2])).cuda()))
+        solvers.append(s)
+        bs.append(row)
+        total_dof += s.levels[0].nglobal * len(freqs)
+    torch.cuda.synchronize()
+    # sequential: every lane through sem_solve
+    xs_seq = [[torch.zeros_like(b) for b in row] for row in bs]
+    for s_, row, xrow in zip(solvers, bs, xs_seq):   # warm-up of every context
+        s_.solve(row[0], x=torch.zeros_like(row[0]), rtol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_seq = []
+    for s_, row, xrow in zip(solvers, bs, xs_seq):
+        for b, x in zip(row, xrow):
+            _, info = s_.solve(b, x=x, rtol=1e-8, maxit=300)
+            iters_seq.append(info.iters)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    # batched
+    xs = [[torch.zeros_like(b) for b in row] for row in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=4)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    worst = max(i.true_rel_res for i in infos)
+    out = {"mode": "batch", "problems": len(solvers), "rhs_per_problem": 4,
+           "lanes": len(infos), "unique_dof_total": int(total_dof),
+           "sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
+           "speedup_batched_vs_sequential": round(t_seq / t_bat, 3),
+           "batched_gdof_s": round(total_dof / t_bat / 1e9, 4),
+           "worst_true_rel_res": worst, "all_converged": all(i.converged for i in infos),
+           "iters_batched_max": max(i.iters for i in infos),
+           "iters_sequential_max": max(iters_seq), "tune_s": round(t_tune, 2),
+           "tuned": {f"p{k[0]}_side{k[1]}": {"cheb_order": v.cheb_order, "ax_variant": v.ax_variant}
+                     for k, v in tuned.items()}}
+    print(json.dumps(out), flush=True)
+
+
 def algorithmic_bytes(kind, p, E):
     """HBM bytes one launch must move (each operand read or written once)."""
     N3 = (p + 1) ** 3
@@ -110,6 +200,9 @@ def main():
         sys.exit(2)
     if a.mode == "kernels":
         kernels_mode(a)
+        return
+    if a.mode == "batch":
+        batch_mode(a)
         return
     import numpy as np
     import torch

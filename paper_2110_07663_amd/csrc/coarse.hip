@@ -9,12 +9,22 @@
 // unknowns for a 32^3 mesh, all L2/MALL resident).
 //
 // The iteration is the Chronopoulos-Gear form of PCG (the same iterates as the
-// textbook recurrence in exact arithmetic): one pointwise kernel (update of
-// p, s = A p, x, r, z = D^{-1} r and the products (r,z), (r,r)) and one stencil
-// kernel (w = A z and (w,z), then alpha and beta) per iteration, both closing
-// with a fixed-order last-block reduction.  All scalars stay on the device; a
-// finished or broken-down iteration turns every later kernel into a no-op, so a
-// chunk of iterations is recorded once as a HIP graph and replayed.
+// textbook recurrence in exact arithmetic): update p, s = A p, x, r and
+// z = D^{-1} r, then w = A z, and one reduction of (r,z), (r,r), (w,z) gives
+// the next alpha and beta.  Both halves run in ONE kernel per iteration: the
+// stencil needs the new z of neighbouring rows, and each row recomputes those
+// from the neighbours' previous r, s, w (kept in two alternating copies), so
+// no grid-wide synchronisation separates the update from the product.  The
+// kernel closes with a fixed-order last-block reduction.  All scalars stay on
+// the device; a finished or broken-down iteration turns every later kernel
+// into a no-op, so a chunk of iterations is recorded once as a HIP graph and
+// replayed.
+//
+// Optionally (SEM_COARSE_PERSIST=1) the whole solve runs as one persistent
+// cooperative launch (k_cg_persistent): each thread keeps its stencil row and
+// its entries of the CG vectors in registers and the phases are separated by
+// grid barriers that carry the partial sums.  On an 8-XCD device a grid
+// barrier costs more than a kernel boundary, so this is not the default.
 #include "sem_internal.h"
 
 namespace sem {
@@ -105,11 +115,16 @@ __global__ void k_coarse_assemble(CoarseGrid g, const double *__restrict__ Ae,
   dinv[t] = dir ? 0.0 : 1.0 / row[13];
 }
 
-// b_g[node] = b_L at the node's owner copy (the element with the smallest index)
+// b_g[node] = b_L at the node's owner copy (the element with the smallest index);
+// also clears the grid-barrier state of the persistent solve that follows
 __global__ void k_coarse_to_global(CoarseGrid g, const double *__restrict__ bl,
-                                   double *__restrict__ bg) {
+                                   double *__restrict__ bg, unsigned *bar, int *aborted) {
   int64_t n = g.nx * g.ny * g.nz;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *bar = 0u;
+    *aborted = 0;
+  }
   if (t >= n) return;
   int64_t x = t % g.nx, y = (t / g.nx) % g.ny, z = t / (g.nx * g.ny);
   int64_t ex = x < g.nex ? x : g.nex - 1, ey = y < g.ney ? y : g.ney - 1,
@@ -139,6 +154,7 @@ __device__ inline double stencil_apply(const CoarseGrid &g, const double *__rest
 struct CgPtrs {
   const double *St, *dinv, *b;
   double *x, *r, *u, *w, *p, *s;
+  double *r2, *w2, *s2;  // second copies of r, w, s (alternating iterations)
   double *partials;
   unsigned *counter;
   CoarseScalars *sc;
@@ -219,8 +235,8 @@ __global__ __launch_bounds__(256) void k_cg_start(int64_t n, CgPtrs P, double to
   }
 }
 
-// w = A z, delta = (w, z); then alpha, beta for the next update
-__global__ __launch_bounds__(256) void k_cg_spmv(int64_t n, CoarseGrid g, CgPtrs P, int first) {
+// first product: w = A z, delta = (w, z), alpha = gamma / delta, beta = 0
+__global__ __launch_bounds__(256) void k_cg_first(int64_t n, CoarseGrid g, CgPtrs P) {
   if (P.sc->done) return;
   double acc[1] = {0.0};
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
@@ -232,57 +248,355 @@ __global__ __launch_bounds__(256) void k_cg_spmv(int64_t n, CoarseGrid g, CgPtrs
   if (cg_last_block<1>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     CoarseScalars *c = P.sc;
     const double delta = acc[0];
-    double alpha, beta;
-    if (first) {
-      beta = 0.0;
-      alpha = c->gamma / delta;
-    } else {
-      beta = c->gamma / c->gamma_old;
-      alpha = c->gamma / (delta - beta * c->gamma / c->alpha);
-    }
+    const double alpha = c->gamma / delta;
     c->delta = delta;
-    c->beta = beta;
+    c->beta = 0.0;
     c->alpha = alpha;
     if (!(alpha > 0.0) || !(delta > 0.0)) c->done = 1;  // exact breakdown (or NaN)
   }
 }
 
-// p = z + beta p; s = w + beta s; x += alpha p; r -= alpha s; z = D^{-1} r; (r,z), (r,r)
-__global__ __launch_bounds__(256) void k_cg_update(int64_t n, CgPtrs P) {
+// new z of a row from its previous r, s, w: s' = w + beta s, r' = r - alpha s',
+// z' = D^{-1} r' (the same expression for the row itself and for its neighbours)
+__device__ inline double cg_next_z(double dinv, double r, double w, double s, double alpha,
+                                   double beta, double &s_new, double &r_new) {
+  s_new = w + beta * s;
+  r_new = r - alpha * s_new;
+  return dinv * r_new;
+}
+
+// Sum over a wavefront by an xor butterfly: every lane ends with the same bits
+// (each step adds the same two values, in either order).
+template <int ND>
+__device__ inline void wave_sum(double (&acc)[ND]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += __shfl_xor(acc[j], o, 64);
+}
+
+// cg_last_block for 1024-thread blocks: wave sums, then the 16 wave sums in
+// order; the last block sums the block partials the same way.
+template <int ND>
+__device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, unsigned *counter) {
+  __shared__ double sh[ND][16];
+  __shared__ bool is_last;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  wave_sum<ND>(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) sh[j][wv] = acc[j];
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += sh[j][w];
+      partials[blockIdx.x * 4 + j] = t;
+    }
+    __threadfence();
+    is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += 1024)
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      acc[j] += __hip_atomic_load(&partials[b * 4 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wave_sum<ND>(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) sh[j][wv] = acc[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sh[j][w];
+    acc[j] = t;
+  }
+  if (tid == 0) *counter = 0u;
+  return true;
+}
+
+// One iteration: p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+// z = D^{-1} r, w = A z, then (r,z), (r,r), (w,z) -> gamma, rr, delta and the
+// next alpha, beta.  Reads r, s, w from copy `par`, writes them to copy 1-par.
+// Four lanes share a row (lane q takes stencil entries q, q+4, ...), 256 rows
+// per 1024-thread block; every load is issued before the scalars are known, so
+// the kernel waits on memory about once.
+constexpr int kCgRows = 256;
+__global__ __launch_bounds__(1024) void k_cg_iter(int64_t n, CoarseGrid g, CgPtrs P, int par) {
   CoarseScalars *c = P.sc;
+  const double *__restrict__ R = par ? P.r2 : P.r;
+  const double *__restrict__ Wv = par ? P.w2 : P.w;
+  const double *__restrict__ Sv = par ? P.s2 : P.s;
+  const int q = threadIdx.x & 3;
+  const int64_t t = blockIdx.x * (int64_t)kCgRows + (threadIdx.x >> 2);
+  const bool row = t < n;
+  const int64_t tt = row ? t : 0;
+  const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+  // (n < 2^31 for any coarse grid this solver takes: 32-bit index arithmetic)
+  const unsigned ut = (unsigned)tt, uxy = ut / (unsigned)nx;
+  const int x = (int)(ut - uxy * (unsigned)nx), y = (int)(uxy % (unsigned)ny),
+            z = (int)(uxy / (unsigned)ny);
+  // this lane's stencil entries m = q + 4k and the neighbours' previous r, s, w
+  // (unconditional loads at clamped indices, so that they all issue at once;
+  // entries outside the grid get coefficient 0)
+  double a[7], dj[7], rj[7], wj[7], sj[7];
+  bool in[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int m = q + 4 * k;
+    const int dx = m % 3 - 1, dy = (m / 3) % 3 - 1, dz = m / 9 - 1;
+    in[k] = row && m < 27 && x + dx >= 0 && x + dx < nx && y + dy >= 0 && y + dy < ny &&
+            z + dz >= 0 && z + dz < nz;
+    const int64_t j = in[k] ? tt + dx + (int64_t)dy * nx + (int64_t)dz * nx * ny : tt;
+    a[k] = P.St[(m < 27 ? m : 26) * n + tt];
+    dj[k] = P.dinv[j];
+    rj[k] = R[j];
+    wj[k] = Wv[j];
+    sj[k] = Sv[j];
+  }
+  const double di = P.dinv[tt], r0 = R[tt], w0 = Wv[tt], s0 = Sv[tt], p0 = P.p[tt];
+  const double x0 = P.x[tt];
   if (c->done) return;
   const double alpha = c->alpha, beta = c->beta;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    double pv = P.u[t] + beta * P.p[t];
-    double sv = P.w[t] + beta * P.s[t];
-    P.p[t] = pv;
-    P.s[t] = sv;
-    P.x[t] += alpha * pv;
-    double rv = P.r[t] - alpha * sv;
-    double zv = P.dinv[t] * rv;
-    P.r[t] = rv;
-    P.u[t] = zv;
-    acc[0] += rv * zv;
-    acc[1] += rv * rv;
+  const double pv = di * r0 + beta * p0;
+  double sv, rv;
+  const double zv = cg_next_z(di, r0, w0, s0, alpha, beta, sv, rv);
+  double wq = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    double s1, r1;
+    const double zj = cg_next_z(dj[k], rj[k], wj[k], sj[k], alpha, beta, s1, r1);
+    if (in[k]) wq += a[k] * zj;
   }
-  if (cg_last_block<2>(acc, P.partials, P.counter) && threadIdx.x == 0) {
+  wq += __shfl_xor(wq, 1, 64);
+  wq += __shfl_xor(wq, 2, 64);
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (row && q == 0) {
+    double *__restrict__ Rn = par ? P.r : P.r2;
+    double *__restrict__ Wn = par ? P.w : P.w2;
+    double *__restrict__ Sn = par ? P.s : P.s2;
+    P.p[t] = pv;
+    P.x[t] = x0 + alpha * pv;
+    Rn[t] = rv;
+    Sn[t] = sv;
+    Wn[t] = wq;
+    acc[0] = rv * zv;
+    acc[1] = rv * rv;
+    acc[2] = wq * zv;
+  }
+  if (cg_last_block_1k<3>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     c->gamma_old = c->gamma;
     c->gamma = acc[0];
     c->rr = acc[1];
     c->iters += 1;
-    bool conv = c->tol2 > 0.0 && acc[1] <= c->tol2 * c->rr0;
-    if (conv || c->iters >= c->maxit || !(acc[0] > 0.0) || !(acc[1] == acc[1])) c->done = 1;
+    const bool conv = c->tol2 > 0.0 && acc[1] <= c->tol2 * c->rr0;
+    if (conv || c->iters >= c->maxit || !(acc[0] > 0.0) || !(acc[1] == acc[1])) {
+      c->done = 1;
+    } else {
+      const double delta = acc[2];
+      const double b2 = c->gamma / c->gamma_old;
+      const double a2 = c->gamma / (delta - b2 * c->gamma / alpha);
+      c->delta = delta;
+      c->beta = b2;
+      c->alpha = a2;
+      if (!(a2 > 0.0) || !(delta > 0.0)) c->done = 1;  // exact breakdown (or NaN)
+    }
+  }
+}
+
+// ---- persistent form ------------------------------------------------------
+
+struct GridSync {
+  unsigned *count;    // arrivals, monotone within one launch (cleared before it)
+  int *aborted;       // raised by a block whose wait exceeded spin_limit
+  double *partials;   // [2][gridDim.x][4], alternating between barriers
+  unsigned epoch;     // barriers passed so far (same in every block)
+  int spin_limit;
+};
+
+// Grid barrier that also reduces: every block publishes its block sum of acc,
+// waits until all blocks have arrived, then sums the gridDim.x partials in the
+// order of cg_last_block, so every block ends with the same totals.  Returns
+// false (in every thread of the block) if the wait was abandoned.
+template <int ND>
+__device__ bool grid_reduce(double (&acc)[ND], GridSync &gs) {
+  __shared__ double sh[ND][256];
+  __shared__ int ok;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
+    }
+    __syncthreads();
+  }
+  double *part = gs.partials + (size_t)(gs.epoch & 1u) * gridDim.x * 4;
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) part[blockIdx.x * 4 + j] = sh[j][0];
+  }
+  __threadfence();  // every wave: its stores (z and the partials) reach agent scope
+  __syncthreads();
+  gs.epoch += 1u;
+  if (tid == 0) {
+    int good = 1;
+    __hip_atomic_fetch_add(gs.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = gs.epoch * gridDim.x;
+    int spins = 0;
+    while (__hip_atomic_load(gs.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 63) == 0 &&
+          (spins > gs.spin_limit ||
+           __hip_atomic_load(gs.aborted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(gs.aborted, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+    }
+    ok = good;
+  }
+  __syncthreads();
+  if (!ok) return false;
+  __threadfence();  // acquire: later loads see the other blocks' stores
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += 256)
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      acc[j] += __hip_atomic_load(&part[b * 4 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = sh[j][0];
+  __syncthreads();  // sh is reused by the next call
+  return true;
+}
+
+// The whole Chronopoulos-Gear PCG of k_cg_start / k_cg_first / k_cg_iter in
+// one launch of ceil(n/256) blocks, thread = row.  The scalar recurrences and
+// the stopping and breakdown tests are those of the two-kernel form, evaluated
+// redundantly (and identically) in every block, so all blocks leave the loop
+// at the same iteration.
+__global__ __launch_bounds__(256) void k_cg_persistent(CoarseGrid g, CgPtrs P, double tol2,
+                                                       int maxit, GridSync gs) {
+  const int64_t n = g.nx * g.ny * g.nz;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool act = t < n;
+  double a[27];
+  unsigned valid = 0u;
+  if (act) {
+    const int64_t x = t % g.nx, y = (t / g.nx) % g.ny, z = t / (g.nx * g.ny);
+#pragma unroll
+    for (int m = 0; m < 27; ++m) {
+      const int dx = m % 3 - 1, dy = (m / 3) % 3 - 1, dz = m / 9 - 1;
+      const bool in = x + dx >= 0 && y + dy >= 0 && z + dz >= 0 && x + dx < g.nx &&
+                      y + dy < g.ny && z + dz < g.nz;
+      a[m] = P.St[m * n + t];
+      if (in) valid |= 1u << m;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 27; ++m) a[m] = 0.0;
+  }
+  const int64_t sy = g.nx, sz = g.nx * g.ny;
+  const double *__restrict__ U = P.u;
+  auto spmv = [&]() {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 27; ++m) {
+      const int64_t off = (int64_t)(m / 9 - 1) * sz + (int64_t)((m / 3) % 3 - 1) * sy + (m % 3 - 1);
+      if (valid & (1u << m)) acc += a[m] * U[t + off];
+    }
+    return acc;
+  };
+  const double di = act ? P.dinv[t] : 0.0;
+  double rv = act ? P.b[t] : 0.0;
+  double uv = di * rv, xv = 0.0, pv = 0.0, sv = 0.0, wv = 0.0;
+  if (act) P.u[t] = uv;
+  double acc2[2] = {rv * uv, rv * rv};
+  if (!grid_reduce<2>(acc2, gs)) return;
+  double gamma = acc2[0], rr = acc2[1];
+  const double rr0 = rr;
+  double gamma_old = 0.0, alpha = 0.0, beta = 0.0, delta = 0.0;
+  int iters = 0;
+  bool done = rr == 0.0 || maxit <= 0 || !(gamma > 0.0);
+  if (!done) {
+    wv = spmv();
+    double acc1[1] = {wv * uv};
+    if (!grid_reduce<1>(acc1, gs)) return;
+    delta = acc1[0];
+    beta = 0.0;
+    alpha = gamma / delta;
+    if (!(alpha > 0.0) || !(delta > 0.0)) done = true;
+  }
+  while (!done) {
+    pv = uv + beta * pv;
+    sv = wv + beta * sv;
+    xv += alpha * pv;
+    rv = rv - alpha * sv;
+    uv = di * rv;
+    if (act) P.u[t] = uv;
+    acc2[0] = rv * uv;
+    acc2[1] = rv * rv;
+    if (!grid_reduce<2>(acc2, gs)) return;
+    gamma_old = gamma;
+    gamma = acc2[0];
+    rr = acc2[1];
+    iters += 1;
+    const bool conv = tol2 > 0.0 && rr <= tol2 * rr0;
+    if (conv || iters >= maxit || !(gamma > 0.0) || !(rr == rr)) break;
+    wv = spmv();
+    double acc1[1] = {wv * uv};
+    if (!grid_reduce<1>(acc1, gs)) return;
+    delta = acc1[0];
+    beta = gamma / gamma_old;
+    alpha = gamma / (delta - beta * gamma / alpha);
+    if (!(alpha > 0.0) || !(delta > 0.0)) done = true;
+  }
+  if (act) {
+    P.x[t] = xv;
+    P.r[t] = rv;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CoarseScalars *c = P.sc;
+    c->gamma = gamma;
+    c->gamma_old = gamma_old;
+    c->delta = delta;
+    c->alpha = alpha;
+    c->beta = beta;
+    c->rr = rr;
+    c->rr0 = rr0;
+    c->tol2 = tol2;
+    c->iters = iters;
+    c->maxit = maxit;
+    c->done = 1;
   }
 }
 
 static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
-// CG kernels: each thread handles `rows_per_thread` rows (fewer blocks close
-// each reduction); the grid is fixed per solver so the summation order is too
+// CG kernels: one block per 256 rows (256 threads for the start kernels, 1024
+// for the iteration); the grid is fixed per solver, so is the summation order
 static inline unsigned cg_grid(const CoarseSolver &S) {
-  int64_t per = 256 * (int64_t)S.rows_per_thread;
-  return (unsigned)((S.n + per - 1) / per);
+  return (unsigned)((S.n + kCgRows - 1) / kCgRows);
 }
 
 static CgPtrs ptrs(const Ctx &c) {
@@ -290,6 +604,7 @@ static CgPtrs ptrs(const Ctx &c) {
   CgPtrs P;
   P.St = S.St; P.dinv = S.dinv; P.b = S.b;
   P.x = S.x; P.r = S.r; P.u = S.u; P.w = S.w; P.p = S.p; P.s = S.s;
+  P.r2 = S.r2; P.w2 = S.w2; P.s2 = S.s2;
   P.partials = S.partials; P.counter = S.counter; P.sc = S.sc;
   return P;
 }
@@ -299,21 +614,33 @@ bool coarse_assembled_ok(const Ctx &c, const Level &C) { return C.p == 1 && c.cs
 void coarse_setup(Ctx &c, Level &C, hipStream_t s) {
   CoarseSolver &S = *c.cs;
   CoarseGrid g = cgrid(c);
+  // the persistent solve needs all ceil(n/256) blocks resident at once
+  {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    SEM_HIP(hipGetDevice(&dev));
+    SEM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    SEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_persistent, 256, 0));
+    const char *env = getenv("SEM_COARSE_PERSIST");
+    const int64_t blocks = (S.n + 255) / 256;
+    const int64_t barriers = 4 + 2 * (int64_t)c.opts.coarse_maxit;
+    S.persistent = coop != 0 && blocks <= (int64_t)per_cu * cus && blocks * barriers < (1ll << 31) &&
+                   env && env[0] == '1';
+  }
   hipLaunchKernelGGL(k_coarse_elem, dim3(nb(C.E)), dim3(256), 0, s, C.E, C.G64, C.D64, S.Ae);
   SEM_LAUNCH("k_coarse_elem");
   hipLaunchKernelGGL(k_coarse_assemble, dim3(nb(S.n)), dim3(256), 0, s, g, S.Ae, S.St, S.dinv);
   SEM_LAUNCH("k_coarse_assemble");
 }
 
-static void enqueue_iterations(const Ctx &c, int k, hipStream_t s) {
+// k iterations after `done` earlier ones (which fixes the copy of r, s, w read first)
+static void enqueue_iterations(const Ctx &c, int k, int done, hipStream_t s) {
   CgPtrs P = ptrs(c);
   CoarseGrid g = cgrid(c);
   const int64_t n = c.cs->n;
   for (int it = 0; it < k; ++it) {
-    hipLaunchKernelGGL(k_cg_update, dim3(cg_grid(*c.cs)), dim3(256), 0, s, n, P);
-    SEM_LAUNCH("k_cg_update");
-    hipLaunchKernelGGL(k_cg_spmv, dim3(cg_grid(*c.cs)), dim3(256), 0, s, n, g, P, 0);
-    SEM_LAUNCH("k_cg_spmv");
+    hipLaunchKernelGGL(k_cg_iter, dim3(cg_grid(*c.cs)), dim3(1024), 0, s, n, g, P, (done + it) & 1);
+    SEM_LAUNCH("k_cg_iter");
   }
 }
 
@@ -323,7 +650,7 @@ static void ensure_graph(Ctx &c) {
   if (!S.cap) SEM_HIP(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
   SEM_HIP(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
   try {
-    enqueue_iterations(c, S.chunk, S.cap);
+    enqueue_iterations(c, S.chunk, 0, S.cap);  // chunk is even: every replay starts on copy 0
   } catch (...) {
     hipGraph_t dummy;
     (void)hipStreamEndCapture(S.cap, &dummy);
@@ -338,30 +665,51 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
   CoarseSolver &S = *c.cs;
   CoarseGrid g = cgrid(c);
   CgPtrs P = ptrs(c);
-  hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, C.d_b, S.b);
+  hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, C.d_b, S.b,
+                     S.counter + 32, &S.sc->aborted);
   SEM_LAUNCH("k_coarse_to_global");
+  if (!c.capturing && S.persistent) {
+    GridSync gs;
+    gs.count = S.counter + 32;
+    gs.aborted = &S.sc->aborted;
+    gs.partials = S.partials;
+    gs.epoch = 0u;
+    gs.spin_limit = 1 << 20;
+    double tol2 = tol > 0 ? tol * tol : 0.0;
+    void *args[] = {&g, &P, &tol2, &maxit, &gs};
+    SEM_HIP(hipLaunchCooperativeKernel((const void *)k_cg_persistent, dim3(nb(S.n)), dim3(256), args,
+                                       0, s));
+    SEM_HIP(hipMemcpyAsync(c.hres, S.sc, sizeof(CoarseScalars), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    const CoarseScalars *h = reinterpret_cast<const CoarseScalars *>(c.hres);
+    if (h->aborted) fail(SEM_EHIP, "coarse-grid solve: a grid barrier timed out");
+    c.last_coarse_iters = tol > 0.0 ? h->iters : maxit;
+    if (!(h->rr == h->rr)) fail(SEM_ENAN, "NaN in the coarse-grid solve");
+    launch_gather(c, C, S.x, c.cx, s);
+    return;
+  }
   hipLaunchKernelGGL(k_cg_start, dim3(cg_grid(S)), dim3(256), 0, s, S.n, P,
                      tol > 0 ? tol * tol : 0.0, maxit);
   SEM_LAUNCH("k_cg_start");
-  hipLaunchKernelGGL(k_cg_spmv, dim3(cg_grid(S)), dim3(256), 0, s, S.n, g, P, 1);
-  SEM_LAUNCH("k_cg_spmv");
+  hipLaunchKernelGGL(k_cg_first, dim3(cg_grid(S)), dim3(256), 0, s, S.n, g, P);
+  SEM_LAUNCH("k_cg_first");
   if (c.capturing) {
     // inside a recorded batch iteration: a fixed count, no readback
     const int k = tol > 0.0 ? std::min(maxit, c.capture_coarse_iters) : maxit;
-    enqueue_iterations(c, k, s);
+    enqueue_iterations(c, k, 0, s);
     launch_gather(c, C, S.x, c.cx, s);
     return;
   }
   if (tol <= 0.0 || !S.use_graph) {
     // fixed iteration count (or graphs off): plain launches, one readback at most
     if (tol <= 0.0) {
-      enqueue_iterations(c, maxit, s);
+      enqueue_iterations(c, maxit, 0, s);
     } else {
       int done_it = 0;
       int chunk = std::max(8, c.last_coarse_iters + 2);
       while (true) {
         int k = std::min(chunk, maxit - done_it);
-        enqueue_iterations(c, k, s);
+        enqueue_iterations(c, k, done_it, s);
         done_it += k;
         SEM_HIP(hipMemcpyAsync(c.hres, S.sc, sizeof(CoarseScalars), hipMemcpyDeviceToHost, s));
         SEM_HIP(hipStreamSynchronize(s));

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
   __shared__ T buf0[PB * PS];
   __shared__ T buf1[PB * PS];
 
-  const int64_t e = blockIdx.x;
+  const int64_t e = xcd_block();
   const int tid = threadIdx.x;
   const int a = tid % PB, b = tid / PB;
   const bool act = tid < PB2;
@@ -326,6 +326,173 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
   }
 }
 
+// Same local solve, organised by lines: in each contraction a thread owns one
+// line of the box along the contracted direction, reads its pbar values from
+// LDS once and forms all pbar outputs, with the entries of S taken as
+// block-uniform (scalar-loaded) operands.  That is one LDS read per pbar
+// multiply-adds instead of one per multiply-add.  The RAS write-out has the
+// thread (b, c) own the row of pbar-2 = p+1 consecutive output values, so the
+// element's (p+1)^3 outputs leave as contiguous rows.  Used for pbar^2 > 64.
+template <int P>
+struct FdmLines {
+  static constexpr int PB = P + 3;
+  static constexpr int N = P + 1;
+  static constexpr int BS = ((PB * PB + 63) / 64) * 64;
+  static constexpr int RS = PB | 1;
+  static constexpr int PS = (PB * RS) | 1;
+};
+
+template <int P, typename T, bool ASM>
+__global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
+    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
+    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
+  using F = FdmLines<P>;
+  constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
+  constexpr int N3 = N * N * N, PB2 = PB * PB;
+  __shared__ T buf0[PB * PS];
+  __shared__ T buf1[PB * PS];
+
+  const int64_t e = xcd_block();
+  const int tid = threadIdx.x;
+  const bool act = tid < PB2;
+  const int lo = tid % PB, hi = tid / PB;  // the two free box indices of this thread's line
+  const T *__restrict__ Sx = Sg + e * 3 * PB2;
+  const T *__restrict__ Sy = Sx + PB2;
+  const T *__restrict__ Sz = Sx + 2 * PB2;
+  const T *__restrict__ le = lamg + e * 3 * PB;
+  T v[PB], o[PB];
+
+  // gather the box: thread (a, b) = (lo, hi) reads the line along c
+  {
+    const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+    if (act) {
+      const int a = lo, b = hi;
+      const int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0);
+      const int li = a == 0 ? P - 1 : (a == PB - 1 ? 1 : a - 1);
+      const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
+      const int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+      const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
+        const int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
+        const bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
+        T val = T(0);
+        if (ok) {
+          const int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
+          val = r[en * N3 + (lk * N + lj) * N + li];
+        }
+        v[c] = val;
+      }
+#pragma unroll
+      for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = v[c];
+    }
+  }
+  __syncthreads();
+  // x: t[c][b][m] = sum_i Sx[i][m] box[c][b][i]      line (b, c) = (lo, hi)
+  if (act) {
+    const int b = lo, c = hi;
+#pragma unroll
+    for (int i = 0; i < PB; ++i) v[i] = buf0[c * PS + b * RS + i];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) o[m] = T(0);
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int m = 0; m < PB; ++m) o[m] += Sx[i * PB + m] * v[i];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) buf1[c * PS + b * RS + m] = o[m];
+  }
+  __syncthreads();
+  // y: t[c][m][a] = sum_j Sy[j][m] t[c][j][a]         line (a, c) = (lo, hi)
+  if (act) {
+    const int a = lo, c = hi;
+#pragma unroll
+    for (int j = 0; j < PB; ++j) v[j] = buf1[c * PS + j * RS + a];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) o[m] = T(0);
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+#pragma unroll
+      for (int m = 0; m < PB; ++m) o[m] += Sy[j * PB + m] * v[j];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) buf0[c * PS + m * RS + a] = o[m];
+  }
+  __syncthreads();
+  // z forward, divide by lambda_x + lambda_y + lambda_z, z back   line (a, b)
+  if (act) {
+    const int a = lo, b = hi;
+    const T lxy = le[a] + le[PB + b];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) v[k] = buf0[k * PS + b * RS + a];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) o[m] = T(0);
+#pragma unroll
+    for (int k = 0; k < PB; ++k)
+#pragma unroll
+      for (int m = 0; m < PB; ++m) o[m] += Sz[k * PB + m] * v[k];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) o[m] *= fdm_inv<T>(lxy + le[2 * PB + m]);
+#pragma unroll
+    for (int k = 0; k < PB; ++k) v[k] = T(0);
+#pragma unroll
+    for (int m = 0; m < PB; ++m)
+#pragma unroll
+      for (int k = 0; k < PB; ++k) v[k] += Sz[k * PB + m] * o[m];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) buf1[k * PS + b * RS + a] = v[k];
+  }
+  __syncthreads();
+  // y back: t[c][j][a] = sum_m Sy[j][m] t[c][m][a]    line (a, c)
+  if (act) {
+    const int a = lo, c = hi;
+#pragma unroll
+    for (int m = 0; m < PB; ++m) v[m] = buf1[c * PS + m * RS + a];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) o[j] = T(0);
+#pragma unroll
+    for (int m = 0; m < PB; ++m)
+#pragma unroll
+      for (int j = 0; j < PB; ++j) o[j] += Sy[j * PB + m] * v[m];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) buf0[c * PS + j * RS + a] = o[j];
+  }
+  __syncthreads();
+  // x back: out[c][b][i] = sum_m Sx[i][m] t[c][b][m]
+  if constexpr (ASM) {  // whole box to z[E][pb^3]; the overlap sum follows
+    if (act) {
+      const int b = lo, c = hi;
+#pragma unroll
+      for (int m = 0; m < PB; ++m) v[m] = buf0[c * PS + b * RS + m];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) o[i] = T(0);
+#pragma unroll
+      for (int m = 0; m < PB; ++m)
+#pragma unroll
+        for (int i = 0; i < PB; ++i) o[i] += Sx[i * PB + m] * v[m];
+      T *zb = z + e * PB * PB2 + c * PB2 + b * PB;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) zb[i] = o[i];
+    }
+    return;
+  }
+  // RAS: own rows (b, c) in 1..p+1, outputs i in 1..p+1, times 1/multiplicity
+  if (tid < N * N) {
+    const int b = 1 + tid % N, c = 1 + tid / N;
+#pragma unroll
+    for (int m = 0; m < PB; ++m) v[m] = buf0[c * PS + b * RS + m];
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = T(0);
+#pragma unroll
+    for (int m = 0; m < PB; ++m)
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] += Sx[(i + 1) * PB + m] * v[m];
+    const int64_t row = e * N3 + (int64_t)(c - 1) * N * N + (b - 1) * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[row + i] = W[row + i] * o[i];
+  }
+}
+
 // ASM (eq. 4): sum of every extended box that contains the node, times
 // 1/#boxes, masked.  Each local copy of a node sums the same boxes, so the
 // result is a consistent E-vector without a separate assembly.
@@ -333,7 +500,7 @@ template <typename T>
 __global__ void k_asm_sum(int64_t E, int p, int nex, int ney, int nez, const T *__restrict__ box,
                           const T *__restrict__ w, T *__restrict__ z) {
   const int N = p + 1, N3 = N * N * N, PB = p + 3, PB3 = PB * PB * PB;
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= E * N3) return;
   if (w[t] == T(0)) {  // Dirichlet node
     z[t] = T(0);
@@ -379,6 +546,18 @@ template void launch_asm_sum<double>(const Ctx &, const Level &, const double *,
 template void launch_asm_sum<float>(const Ctx &, const Level &, const float *, float *,
                                     hipStream_t);
 
+template <int P, typename T, bool ASM>
+static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *S, const T *lam,
+                       const T *W, T *out, hipStream_t s) {
+  if (FdmLines<P>::PB * FdmLines<P>::PB > 64 && c.fdm_lines)
+    hipLaunchKernelGGL((k_fdm_lines<P, T, ASM>), dim3((unsigned)L.E), dim3(FdmLines<P>::BS), 0, s,
+                       L.E, c.nex, c.ney, c.nez, r, S, lam, W, out);
+  else
+    hipLaunchKernelGGL((k_fdm<P, T, ASM>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
+                       c.nex, c.ney, c.nez, r, S, lam, W, out);
+  SEM_LAUNCH("k_fdm");
+}
+
 template <typename T, int P>
 static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
   const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
@@ -388,15 +567,11 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
   if (asm_mode) {
     T *box = sizeof(T) == 8 ? (T *)L.box64 : (T *)L.box32;
     if (!box) fail(SEM_EINVAL, "ASM box buffer was not built");
-    hipLaunchKernelGGL((k_fdm<P, T, true>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
-                       c.nex, c.ney, c.nez, r, S, lam, W, box);
-    SEM_LAUNCH("k_fdm");
+    fdm_launch<P, T, true>(c, L, r, S, lam, W, box, s);
     launch_asm_sum<T>(c, L, box, z, s);
     return;
   }
-  hipLaunchKernelGGL((k_fdm<P, T, false>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
-                     c.nex, c.ney, c.nez, r, S, lam, W, z);
-  SEM_LAUNCH("k_fdm");
+  fdm_launch<P, T, false>(c, L, r, S, lam, W, z, s);
 }
 
 template <typename T>

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
   __shared__ float sl[WAVES][3][PB];
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t e = (int64_t)blockIdx.x * WAVES + wave;
+  const int64_t e = (int64_t)xcd_block() * WAVES + wave;
   if (e >= E) return;  // whole wave leaves; no block-wide barriers below
   float *X = buf[wave][0];
   float *Y = buf[wave][1];

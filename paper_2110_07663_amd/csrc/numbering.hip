@@ -125,7 +125,7 @@ __global__ void k_seg_move(int nseg, int nperm, const int32_t *perm, const int32
 template <typename T>
 __global__ void k_gs(T *__restrict__ v, const int32_t *__restrict__ perm,
                      const int32_t *__restrict__ off, int nseg) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
   int32_t a = off[s];
   int32_t b = off[s + 1] & 0x7fffffff;

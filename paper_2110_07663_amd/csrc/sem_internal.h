@@ -29,6 +29,17 @@ void check_hip(hipError_t e, const char *what, const char *file, int line);
 constexpr int kMaxP = 10;      // highest supported polynomial degree
 constexpr int kMaxLevels = 8;
 constexpr int kMaxArnoldi = 16;
+
+// Workgroups are dispatched to the device's 8 XCDs round-robin (block b runs on
+// XCD b % 8), and each XCD has its own L2.  Kernels whose blocks read their
+// neighbours' data (gather-scatter segments, Schwarz boxes) renumber their
+// blocks so that each XCD walks one contiguous range of logical blocks; the
+// neighbours of a block then live in the same L2.  A bijection of [0, gridDim.x).
+__device__ inline unsigned xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned x = b & 7u, q = b >> 3, per = nb >> 3, rem = nb & 7u;
+  return x * per + (x < rem ? x : rem) + q;
+}
 constexpr int kMaxRestart = 64;
 
 // ---------------------------------------------------------------------------
@@ -56,7 +67,7 @@ struct Level {
   int nseg = 0, nperm = 0;           // gather-scatter segments and member count
   bool fine = false, coarse = false;
   bool lowp = false;                 // level kept in FP32 for the smoother
-  int ax_variant = 1;                // Ax kernel shape at p = 7 (0 generic, 1 one wave/element)
+  int ax_variant = 2;                // Ax kernel shape at p = 7 (0 generic, 1 one wave/element, 2 non-temporal)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
   double *xi = nullptr, *wq = nullptr, *D64 = nullptr;
@@ -103,13 +114,15 @@ struct Level {
 // device-resident scalars of the coarse PCG and of reductions
 struct DevScalars {
   double rz, pq, alpha, beta, rr, rr0, tol2;
-  int done, iters, maxit, pad;
+  int done, iters, maxit;
+  int aborted;  // set when a grid barrier of the persistent solve timed out
 };
 
 // scalars of the coarse-grid CG (device resident)
 struct CoarseScalars {
   double gamma, gamma_old, delta, alpha, beta, rr, rr0, tol2;
-  int done, iters, maxit, pad;
+  int done, iters, maxit;
+  int aborted;  // set when a grid barrier of the persistent solve timed out
 };
 
 // assembled p = 1 coarse operator and its CG state (buffers in the workspace)
@@ -120,12 +133,13 @@ struct CoarseSolver {
   double *Ae = nullptr;            // [E][8][8] element matrices (setup only)
   double *b = nullptr, *x = nullptr, *r = nullptr, *u = nullptr, *w = nullptr, *p = nullptr,
          *s = nullptr;
-  double *partials = nullptr;      // [blocks][4]
-  unsigned *counter = nullptr;
+  double *r2 = nullptr, *w2 = nullptr, *s2 = nullptr;  // alternate copies of r, w, s
+  double *partials = nullptr;      // [2][blocks][4]
+  unsigned *counter = nullptr;     // [64]: [0] last-block counter, [32] grid-barrier arrivals
   CoarseScalars *sc = nullptr;
-  int chunk = 16;                  // iterations per recorded graph
-  int rows_per_thread = 1;
+  int chunk = 16;                  // iterations per recorded graph (even)
   bool use_graph = true;
+  bool persistent = false;         // whole solve in one cooperative launch
   hipStream_t cap = nullptr;       // private capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -183,6 +197,7 @@ struct Ctx {
   // Arnoldi basis (FP64, largest level)
   double *av = nullptr;
   int fdm_prec = SEM_F32;
+  bool fdm_lines = true;  // line-organised VALU FDM kernel for pbar^2 > 64
 };
 
 // ---------------------------------------------------------------------------

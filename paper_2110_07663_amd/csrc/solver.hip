@@ -205,13 +205,14 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     S.w = A.take<double>(S.n);
     S.p = A.take<double>(S.n);
     S.s = A.take<double>(S.n);
-    S.partials = A.take<double>(4 * ((S.n + 255) / 256));
+    S.r2 = A.take<double>(S.n);
+    S.w2 = A.take<double>(S.n);
+    S.s2 = A.take<double>(S.n);
+    S.partials = A.take<double>(8 * ((S.n + 255) / 256));
     S.counter = A.take<unsigned>(64);
     S.sc = A.take<CoarseScalars>(1);
     const char *g = getenv("SEM_COARSE_GRAPH");
     S.use_graph = !(g && g[0] == '0');
-    const char *rp = getenv("SEM_COARSE_RPT");
-    S.rows_per_thread = rp ? std::max(1, std::min(16, atoi(rp))) : 4;
     c.cs = &S;
   }
   // setup-only scratch
@@ -256,10 +257,13 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
     L.fine = l == 0;
     L.coarse = l == c.nlev - 1;
     L.lowp = c.lowp;
-    // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element)
+    // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element,
+    // non-temporal streams)
     const char *av = getenv("SEM_AX_VARIANT");
-    L.ax_variant = o->ax_variant >= 0 ? o->ax_variant : (av ? atoi(av) : 1);
+    L.ax_variant = o->ax_variant >= 0 ? o->ax_variant : (av ? atoi(av) : 2);
   }
+  const char *fl = getenv("SEM_FDM_LINES");
+  c.fdm_lines = !(fl && fl[0] == '0');
 }
 
 // ---------------------------------------------------------------------------

@@ -63,7 +63,7 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
   req->maxit = 200;
   const int smoothers[3] = {SEM_SMOOTH_ASM, SEM_SMOOTH_RAS, SEM_SMOOTH_JACOBI};
   const int precs[3][2] = {{SEM_F64, SEM_F64}, {SEM_F32, SEM_F32}, {SEM_F32, SEM_F16}};
-  const int nax = p == 7 ? 2 : 1;
+  const int nax = p == 7 ? 3 : 1;
   for (int sm = 0; sm < 3; ++sm) {
     const TuneSched &t = smoothers[sm] == SEM_SMOOTH_JACOBI ? jac : sch;
     if (smoothers[sm] != SEM_SMOOTH_JACOBI && t.n > 1 && t.p[t.n - 2] < 2) continue;
@@ -80,7 +80,7 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
           o.cheb_order = order;
           o.smoother_prec = precs[pr][0];
           o.fdm_prec = precs[pr][1];
-          o.ax_variant = nax == 2 ? ax : -1;
+          o.ax_variant = nax > 1 ? ax : -1;
           for (int l = 0; l < 8; ++l) o.lambda_override[l] = 0.0;
           req->cand[req->ncand++] = o;
         }

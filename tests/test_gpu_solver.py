@@ -15,7 +15,9 @@ def _torch():
 
 
 @pytest.mark.parametrize("smoother,p,shape", [("jacobi", 5, (3, 2, 2)), ("ras", 5, (3, 2, 2)),
-                                              ("ras", 7, (2, 3, 2)), ("ras", 3, 3)])
+                                              ("ras", 7, (2, 3, 2)), ("ras", 3, 3),
+                                              ("ras", 6, (3, 2, 2)), ("ras", 8, (2, 2, 3)),
+                                              ("ras", 9, (2, 3, 2)), ("ras", 10, (2, 2, 2))])
 def test_schwarz_and_jacobi_surrogate_fp64(smoother, p, shape):
     P = Pair(shape, p, mesh="sin", schedule=(p, 1), smoother=smoother, lambda_override=[2.0])
     g, o = P.random_local(4)
@@ -29,9 +31,10 @@ def test_ras_boundary_conditions(bc):
     assert rel_err(host(P.gpu.apply_S(g)), P.ora.levels[0].apply_S(o)) < 1e-12
 
 
-def test_ras_fp32():
+@pytest.mark.parametrize("p", [7, 9])
+def test_ras_fp32(p):
     t = _torch()
-    P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
+    P = Pair(3, p, mesh="shift", schedule=(p, 3, 1), smoother="ras", smoother_prec=sem.F32,
              lambda_override=[2.0, 2.0])
     g, o = P.random_local(8)
     zg = host(P.gpu.apply_S(g.to(t.float32)))
@@ -92,6 +95,23 @@ def test_vcycle_graph_replays_match_every_time():
         _ = P.gpu.apply_A(g)  # unrelated eager work between replays
         t.cuda.synchronize()
         assert rel_err(host(z), P.ora.vcycle(o)) < 1e-8
+
+
+@pytest.mark.parametrize("env", [("SEM_COARSE_GRAPH", "0"), ("SEM_COARSE_PERSIST", "1")])
+def test_coarse_solve_paths_agree(monkeypatch, env):
+    """The coarse CG runs as replayed graph chunks (default), as eager chunks of
+    varying length (both alternating copies of r, s, w get used first), or as
+    one persistent cooperative launch; all take the same steps."""
+    base = Pair(6, 3, mesh="shift", schedule=(3, 1), smoother="jacobi", coarse_tol=1e-10,
+                oracle=False, lambda_override=[1.8])
+    monkeypatch.setenv(*env)
+    other = Pair(6, 3, mesh="shift", schedule=(3, 1), smoother="jacobi", coarse_tol=1e-10,
+                 oracle=False, lambda_override=[1.8])
+    for seed in (41, 42, 43):
+        g, _ = base.random_local(seed)
+        za = host(base.gpu.vcycle(g))
+        zb = host(other.gpu.vcycle(g))
+        assert rel_err(zb, za) < 1e-13, (env, seed)
 
 
 def _rhs(P, a=1, b=1, c=1):
@@ -201,7 +221,7 @@ def test_mixed_mfma_solve_converges(fdm_prec):
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
 
 
-@pytest.mark.parametrize("p,prec", [(4, sem.F64), (7, sem.F64), (5, sem.F32)])
+@pytest.mark.parametrize("p,prec", [(4, sem.F64), (7, sem.F64), (5, sem.F32), (9, sem.F32)])
 def test_asm_surrogate(p, prec):
     """Additive Schwarz (eq. 4) with 1/#boxes weights against the oracle."""
     t = _torch()

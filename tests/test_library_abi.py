@@ -83,7 +83,7 @@ def test_tune_space_follows_the_papers_table():
         orders = {s[1] for s in seen}
         assert orders == {1, 2, 3}
         assert {s[0] for s in seen} == {sem.SMOOTH_ASM, sem.SMOOTH_RAS, sem.SMOOTH_JACOBI}
-        assert req.ncand == (48 if p == 7 else 24)
+        assert req.ncand == (72 if p == 7 else 24)
     # plan covers the largest candidate
     import numpy as np
     from paper_2110_07663_amd import workloads as wl
