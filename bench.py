@@ -4,7 +4,9 @@ Workload (default): the anisotropic "layer-shift" box, 32^3 = 32768 hexahedra,
 p = 7 (11,390,625 unique nodes, 16,777,216 local points), homogeneous
 Dirichlet, f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z); preconditioner Cheby-RAS(2)
 p-multigrid (7,3,1) with the smoother in FP32 and FDM local solves, coarse
-p = 1 Jacobi-PCG to 1e-10, outer FP64 flexible CG to relative residual 1e-8.
+p = 1 level solved exactly by block-tridiagonal elimination over z-planes
+(--coarse pcg: Jacobi-PCG to 1e-10 instead), outer FP64 flexible CG to
+relative residual 1e-8.
 
 One step = one full solve from x = 0 (inputs resident in HBM, setup excluded).
 value = unique DOF solved per second (GDOF/s) over the timed steps.  Kernel
@@ -35,6 +37,9 @@ def parse():
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--coarse-tol", type=float, default=1e-10,
                     help="relative tolerance of the coarse Jacobi-PCG")
+    ap.add_argument("--coarse", choices=("auto", "pcg", "direct"), default="auto",
+                    help="coarse p=1 solve: Jacobi-PCG, exact block-tridiagonal elimination, "
+                         "or the library default (direct when its storage fits 4 GiB)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
@@ -216,9 +221,12 @@ def main():
     xyz = wl.layer_shift_vertices(n, seed=3)
     f, _ = wl.sinusoid(1, 1, 1)
 
+    coarse = {"auto": sem.COARSE_AUTO, "pcg": sem.COARSE_PCG, "direct": sem.COARSE_DIRECT}[a.coarse]
+
     def make(prec):
         opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
-                             smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=a.coarse_tol)
+                             smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=a.coarse_tol,
+                             coarse_solver=coarse)
         t0 = time.perf_counter()
         s = sem.Solver(n, n, n, xyz, 1, p, opts=opts)
         torch.cuda.synchronize()
@@ -248,6 +256,7 @@ def main():
     ms_step = 1e3 * t_total / a.steps
     value = L0.nglobal / (t_total / a.steps) / 1e9
     iters = [i.iters for i in infos]
+    coarse_used = "direct" if infos[-1].coarse_iters == 0 else "pcg"
     print(f"[bench] mixed solve {ms_step:.2f} ms/step iters={iters} "
           f"true_rel_res={infos[-1].true_rel_res:.2e}", file=sys.stderr, flush=True)
 
@@ -309,14 +318,17 @@ def main():
         "dtype": "f64 outer / f32 smoother",
         "data": "synthetic",
         "config": {"workload": f"layer-shift box {n}^3 hex, p={p}, Dirichlet, sin RHS; "
-                               f"FCG + pMG{sched} Cheby-RAS(2) FP32, coarse Jacobi-PCG "
-                               f"{a.coarse_tol:g}, tol 1e-8",
+                               f"FCG + pMG{sched} Cheby-RAS(2) FP32, coarse p=1 "
+                               + ("exact block-tridiagonal solve" if coarse_used == "direct"
+                                  else f"Jacobi-PCG {a.coarse_tol:g}") + ", tol 1e-8",
+                   "coarse_solver": coarse_used,
                    "elements": int(L0.E), "p": p, "n_unique": int(L0.nglobal),
                    "n_local": int(L0.nlocal), "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "iters": iters,
         "true_rel_res": infos[-1].true_rel_res,
+        "lambda_tilde": [round(infos[-1].lambda_tilde[l], 4) for l in range(len(sched) - 1)],
         "setup_s": round(t_setup, 3),
         "ax64_gdof_s": round(ax_gdofs, 3) if ax_gdofs else None,
         "ax64_hbm_frac": round(ax["GBs"] / HBM_PEAK_GBS, 4) if ax else None,

@@ -99,6 +99,11 @@ typedef struct {
                               /* wavefront per element, 2 same with non-temporal streams, */
                               /* -1 library default                                       */
   int32_t batch_rhs;          /* right sides this context can take in sem_batch_solve     */
+  int32_t coarse_solver;      /* p = 1 coarsest level: 0 Jacobi-PCG (coarse_tol,          */
+                              /* coarse_maxit), 1 exact block-tridiagonal elimination     */
+                              /* over z-planes (3 nz (nx ny)^2 doubles of workspace;      */
+                              /* falls back to the PCG if the level is singular), -1      */
+                              /* library default: 1 when that storage is <= 4 GiB         */
 } sem_opts;
 
 typedef struct {

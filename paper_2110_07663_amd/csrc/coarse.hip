@@ -631,6 +631,7 @@ void coarse_setup(Ctx &c, Level &C, hipStream_t s) {
   SEM_LAUNCH("k_coarse_elem");
   hipLaunchKernelGGL(k_coarse_assemble, dim3(nb(S.n)), dim3(256), 0, s, g, S.Ae, S.St, S.dinv);
   SEM_LAUNCH("k_coarse_assemble");
+  if (S.direct) coarse_direct_setup(S, g.nx, g.ny, g.nz, s);
 }
 
 // k iterations after `done` earlier ones (which fixes the copy of r, s, w read first)
@@ -668,6 +669,12 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
   hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, C.d_b, S.b,
                      S.counter + 32, &S.sc->aborted);
   SEM_LAUNCH("k_coarse_to_global");
+  if (S.direct) {  // exact: no iteration, no host interaction (also inside a recorded graph)
+    coarse_direct_apply(S, g.nx, g.ny, g.nz, S.b, S.x, s);
+    if (!c.capturing) c.last_coarse_iters = 0;
+    launch_gather(c, C, S.x, c.cx, s);
+    return;
+  }
   if (!c.capturing && S.persistent) {
     GridSync gs;
     gs.count = S.counter + 32;

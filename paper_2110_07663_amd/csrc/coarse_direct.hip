@@ -1,0 +1,323 @@
+// Exact coarse-grid solve of the V-cycle (Algorithm 1, "solve" on the
+// coarsest level) for the assembled p = 1 operator.
+//
+// With nodes numbered plane by plane along z, the 27-point operator is block
+// tridiagonal: D_k couples the nodes of plane k among themselves, C_k couples
+// plane k to plane k-1 (and C_k^T the other way).  Block elimination gives
+//   T_0 = D_0,  T_k = D_k - C_k T_{k-1}^{-1} C_k^T,   G_k = T_k^{-1},
+//   H_k = C_k G_{k-1},  J_k = G_k C_{k+1}^T = H_{k+1}^T,
+// and the solve is two sweeps of dense products:
+//   y_0 = b_0,  y_k = b_k - H_k y_{k-1};
+//   x_{K-1} = G_{K-1} y_{K-1},  x_k = G_k y_k - J_k x_{k+1}.
+// Each T_k is symmetric positive definite (a Schur complement of an SPD
+// matrix), so it is inverted in place by blocked Gauss-Jordan elimination
+// without pivoting (32x32 blocks: invert the pivot block, scale its block row,
+// update the rest, scale its block column).  Dirichlet rows of the stencil are
+// identity rows, so they need no special case.  A pivot below 1e-12 of its
+// row's diagonal (a numerically singular level, e.g. all-Neumann) is reported
+// and the caller keeps the CG.
+//
+// Storage: G, H, J as K dense [Mp][Mp] FP64 blocks, Mp = nx*ny rounded up to
+// 32 (identity / zero padding).  A solve reads each block once: 3 K Mp^2 * 8
+// bytes, in 2K dependent matrix-vector products with no host interaction, so
+// it can be recorded into a graph.
+#include "sem_internal.h"
+
+namespace sem {
+
+constexpr int kGB = 32;  // Gauss-Jordan block
+
+static inline int64_t padded(int64_t m) { return (m + kGB - 1) / kGB * kGB; }
+
+size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz) {
+  const int64_t Mp = padded(nx * ny);
+  return (size_t)(3 * nz * Mp * Mp + nx * ny * nz) * sizeof(double);
+}
+
+// ---- setup kernels ----------------------------------------------------------
+
+// stencil entry of row t for the node offset (dx, dy, dz)
+__device__ inline double st_at(const double *St, int64_t n, int64_t t, int dx, int dy, int dz) {
+  return St[(int64_t)((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)) * n + t];
+}
+
+// H[i][l] = sum_a C_k[i][a] G_{k-1}[a][l], C_k[i][a] = stencil of row (k, i) at dz = -1
+__global__ void k_bt_H(int nx, int ny, int64_t n, int k, int Mp, const double *__restrict__ St,
+                       const double *__restrict__ Gp, double *__restrict__ H) {
+  const int m = nx * ny;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)Mp * Mp) return;
+  const int i = (int)(e / Mp), l = (int)(e - (int64_t)i * Mp);
+  double h = 0.0;
+  if (i < m && l < m) {
+    const int xi = i % nx, yi = i / nx;
+    const int64_t row = (int64_t)k * m + i;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xa = xi + dx, ya = yi + dy;
+        if (xa < 0 || xa >= nx || ya < 0 || ya >= ny) continue;
+        h += st_at(St, n, row, dx, dy, -1) * Gp[(int64_t)(ya * nx + xa) * Mp + l];
+      }
+  }
+  H[e] = h;
+}
+
+// T[i][j] = D_k[i][j] - sum_l H[i][l] C_k[j][l]   (padding: identity)
+// (the diagonal is also kept in `diag` for the pivot test of the inversion)
+__global__ void k_bt_T(int nx, int ny, int64_t n, int k, int Mp, const double *__restrict__ St,
+                       const double *__restrict__ H, double *__restrict__ T,
+                       double *__restrict__ diag) {
+  const int m = nx * ny;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)Mp * Mp) return;
+  const int i = (int)(e / Mp), j = (int)(e - (int64_t)i * Mp);
+  if (i >= m || j >= m) {
+    T[e] = i == j ? 1.0 : 0.0;
+    if (i == j) diag[i] = 1.0;
+    return;
+  }
+  const int xi = i % nx, yi = i / nx, xj = j % nx, yj = j / nx;
+  const int dx = xj - xi, dy = yj - yi;
+  double v = 0.0;
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = st_at(St, n, (int64_t)k * m + i, dx, dy, 0);
+  if (H) {
+    const int64_t rowj = (int64_t)k * m + j;
+    for (int ey = -1; ey <= 1; ++ey)
+      for (int ex = -1; ex <= 1; ++ex) {
+        const int xl = xj + ex, yl = yj + ey;
+        if (xl < 0 || xl >= nx || yl < 0 || yl >= ny) continue;
+        v -= H[(int64_t)i * Mp + yl * nx + xl] * st_at(St, n, rowj, ex, ey, -1);
+      }
+  }
+  T[e] = v;
+  if (i == j) diag[i] = v;
+}
+
+// in-place inverse of the pivot block (Kb, Kb) in LDS.  For an SPD matrix
+// every pivot lies in (0, original diagonal]; a pivot below 1e-12 of its row's
+// original diagonal marks a (numerically) singular level.
+__global__ __launch_bounds__(256) void k_gj_diag(double *A, int Mp, int Kb,
+                                                 const double *__restrict__ diag, int *flag) {
+  __shared__ double P[kGB][kGB + 1];
+  const int tid = threadIdx.x;
+  double *blk = A + (int64_t)Kb * kGB * Mp + (int64_t)Kb * kGB;
+  for (int e = tid; e < kGB * kGB; e += 256) P[e / kGB][e % kGB] = blk[(int64_t)(e / kGB) * Mp + e % kGB];
+  __syncthreads();
+  for (int p = 0; p < kGB; ++p) {
+    const double piv = P[p][p];
+    const double d = 1.0 / piv;
+    __syncthreads();
+    if (tid < kGB && tid != p) P[p][tid] *= d;
+    __syncthreads();
+    for (int e = tid; e < kGB * kGB; e += 256) {
+      const int i = e / kGB, j = e % kGB;
+      if (i != p && j != p) P[i][j] -= P[i][p] * P[p][j];
+    }
+    __syncthreads();
+    if (tid < kGB && tid != p) P[tid][p] = -P[tid][p] * d;
+    if (tid == 0) {
+      P[p][p] = d;
+      if (!(piv > 1e-12 * diag[Kb * kGB + p])) atomicOr(flag, 1);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kGB * kGB; e += 256) blk[(int64_t)(e / kGB) * Mp + e % kGB] = P[e / kGB][e % kGB];
+}
+
+// block row: A[Kb][J] <- P A[Kb][J] for J != Kb (P = inverted pivot block)
+__global__ __launch_bounds__(256) void k_gj_row(double *A, int Mp, int Kb) {
+  __shared__ double P[kGB][kGB + 1], B[kGB][kGB + 1];
+  const int tid = threadIdx.x;
+  const int J = (int)blockIdx.x < Kb ? (int)blockIdx.x : (int)blockIdx.x + 1;
+  const double *pb = A + (int64_t)Kb * kGB * Mp + (int64_t)Kb * kGB;
+  double *tb = A + (int64_t)Kb * kGB * Mp + (int64_t)J * kGB;
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    P[i][j] = pb[(int64_t)i * Mp + j];
+    B[i][j] = tb[(int64_t)i * Mp + j];
+  }
+  __syncthreads();
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGB; ++q) s += P[i][q] * B[q][j];
+    tb[(int64_t)i * Mp + j] = s;
+  }
+}
+
+// rest: A[I][J] -= A[I][Kb] A[Kb][J] for I, J != Kb (block row already scaled)
+__global__ __launch_bounds__(256) void k_gj_trail(double *A, int Mp, int Kb, int nbk) {
+  __shared__ double L[kGB][kGB + 1], R[kGB][kGB + 1];
+  const int tid = threadIdx.x;
+  const int ti = (int)blockIdx.x / (nbk - 1), tj = (int)blockIdx.x % (nbk - 1);
+  const int I = ti < Kb ? ti : ti + 1, J = tj < Kb ? tj : tj + 1;
+  const double *lb = A + (int64_t)I * kGB * Mp + (int64_t)Kb * kGB;
+  const double *rb = A + (int64_t)Kb * kGB * Mp + (int64_t)J * kGB;
+  double *ob = A + (int64_t)I * kGB * Mp + (int64_t)J * kGB;
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    L[i][j] = lb[(int64_t)i * Mp + j];
+    R[i][j] = rb[(int64_t)i * Mp + j];
+  }
+  __syncthreads();
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGB; ++q) s += L[i][q] * R[q][j];
+    ob[(int64_t)i * Mp + j] -= s;
+  }
+}
+
+// block column: A[I][Kb] <- -A[I][Kb] P for I != Kb
+__global__ __launch_bounds__(256) void k_gj_col(double *A, int Mp, int Kb) {
+  __shared__ double P[kGB][kGB + 1], B[kGB][kGB + 1];
+  const int tid = threadIdx.x;
+  const int I = (int)blockIdx.x < Kb ? (int)blockIdx.x : (int)blockIdx.x + 1;
+  const double *pb = A + (int64_t)Kb * kGB * Mp + (int64_t)Kb * kGB;
+  double *tb = A + (int64_t)I * kGB * Mp + (int64_t)Kb * kGB;
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    P[i][j] = pb[(int64_t)i * Mp + j];
+    B[i][j] = tb[(int64_t)i * Mp + j];
+  }
+  __syncthreads();
+  for (int e = tid; e < kGB * kGB; e += 256) {
+    const int i = e / kGB, j = e % kGB;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGB; ++q) s += B[i][q] * P[q][j];
+    tb[(int64_t)i * Mp + j] = -s;
+  }
+}
+
+// J[i][a] = H[a][i]
+__global__ void k_bt_transpose(int Mp, const double *__restrict__ H, double *__restrict__ J) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 256 threads: 8 rows per pass
+  for (int r = ty; r < 32; r += 8) t[r][tx] = H[(int64_t)(by + r) * Mp + bx + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) J[(int64_t)(bx + r) * Mp + by + tx] = t[tx][r];
+}
+
+// ---- solve kernel -------------------------------------------------------------
+
+// out = c + s1 * (M1 v1) - (M2 v2), one wavefront per row (rows < m)
+__global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, const double *__restrict__ M1,
+                                               const double *__restrict__ v1, double s1,
+                                               const double *__restrict__ M2,
+                                               const double *__restrict__ v2,
+                                               const double *__restrict__ c,
+                                               double *__restrict__ out) {
+  const int row = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= m) return;  // whole wave
+  // four independent partial sums per lane keep 8 loads in flight
+  const double *r1 = M1 + (int64_t)row * Mp;
+  double a1 = 0.0, a2 = 0.0;
+  {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int j = lane;
+    for (; j + 192 < m; j += 256) {
+      t0 += r1[j] * v1[j];
+      t1 += r1[j + 64] * v1[j + 64];
+      t2 += r1[j + 128] * v1[j + 128];
+      t3 += r1[j + 192] * v1[j + 192];
+    }
+    for (; j < m; j += 64) t0 += r1[j] * v1[j];
+    a1 = (t0 + t1) + (t2 + t3);
+  }
+  if (M2) {
+    const double *r2 = M2 + (int64_t)row * Mp;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int j = lane;
+    for (; j + 192 < m; j += 256) {
+      t0 += r2[j] * v2[j];
+      t1 += r2[j + 64] * v2[j + 64];
+      t2 += r2[j + 128] * v2[j + 128];
+      t3 += r2[j + 192] * v2[j + 192];
+    }
+    for (; j < m; j += 64) t0 += r2[j] * v2[j];
+    a2 = (t0 + t1) + (t2 + t3);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  if (lane == 0) out[row] = (c ? c[row] : 0.0) + s1 * a1 - a2;
+}
+
+// ---- host side -------------------------------------------------------------------
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s) {
+  const int m = (int)(nx * ny), K = (int)nz;
+  const int Mp = (int)padded(m), nbk = Mp / kGB;
+  const int64_t M2 = (int64_t)Mp * Mp;
+  SEM_HIP(hipMemsetAsync(S.dflag, 0, sizeof(int), s));
+  for (int k = 0; k < K; ++k) {
+    double *Gk = S.dG + k * M2;
+    double *Hk = S.dH + k * M2;
+    if (k > 0) {
+      hipLaunchKernelGGL(k_bt_H, dim3(nblk(M2)), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp,
+                         S.St, Gk - M2, Hk);
+      SEM_LAUNCH("k_bt_H");
+    }
+    hipLaunchKernelGGL(k_bt_T, dim3(nblk(M2)), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
+                       k > 0 ? (const double *)Hk : nullptr, Gk, S.dy);
+    SEM_LAUNCH("k_bt_T");
+    for (int b = 0; b < nbk; ++b) {
+      hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, Gk, Mp, b, (const double *)S.dy,
+                         S.dflag);
+      SEM_LAUNCH("k_gj_diag");
+      if (nbk == 1) continue;
+      hipLaunchKernelGGL(k_gj_row, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
+      SEM_LAUNCH("k_gj_row");
+      hipLaunchKernelGGL(k_gj_trail, dim3((nbk - 1) * (nbk - 1)), dim3(256), 0, s, Gk, Mp, b, nbk);
+      SEM_LAUNCH("k_gj_trail");
+      hipLaunchKernelGGL(k_gj_col, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
+      SEM_LAUNCH("k_gj_col");
+    }
+  }
+  for (int k = 0; k + 1 < K; ++k) {
+    hipLaunchKernelGGL(k_bt_transpose, dim3(nbk, nbk), dim3(256), 0, s, Mp, S.dH + (k + 1) * M2,
+                       S.dJ + k * M2);
+    SEM_LAUNCH("k_bt_transpose");
+  }
+  int flag = 0;
+  SEM_HIP(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  S.direct = flag == 0;
+}
+
+void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
+                         double *x, hipStream_t s) {
+  const int m = (int)(nx * ny), K = (int)nz;
+  const int Mp = (int)padded(m);
+  const int64_t M2 = (int64_t)Mp * Mp;
+  const unsigned grid = (unsigned)((m + 3) / 4);
+  double *y = S.dy;
+  launch_copy<double>(m, b, y, s);
+  for (int k = 1; k < K; ++k) {
+    hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dH + k * M2,
+                       (const double *)(y + (int64_t)(k - 1) * m), -1.0, (const double *)nullptr,
+                       (const double *)nullptr, b + (int64_t)k * m, y + (int64_t)k * m);
+    SEM_LAUNCH("k_bt_mv");
+  }
+  hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + (K - 1) * M2,
+                     (const double *)(y + (int64_t)(K - 1) * m), 1.0, (const double *)nullptr,
+                     (const double *)nullptr, (const double *)nullptr, x + (int64_t)(K - 1) * m);
+  SEM_LAUNCH("k_bt_mv");
+  for (int k = K - 2; k >= 0; --k) {
+    hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + k * M2,
+                       (const double *)(y + (int64_t)k * m), 1.0, (const double *)(S.dJ + k * M2),
+                       (const double *)(x + (int64_t)(k + 1) * m), (const double *)nullptr,
+                       x + (int64_t)k * m);
+    SEM_LAUNCH("k_bt_mv");
+  }
+}
+
+}  // namespace sem

@@ -140,6 +140,10 @@ struct CoarseSolver {
   int chunk = 16;                  // iterations per recorded graph (even)
   bool use_graph = true;
   bool persistent = false;         // whole solve in one cooperative launch
+  // exact block-tridiagonal solve (coarse_direct.hip): G, H, J blocks, work vector
+  bool direct = false;
+  double *dG = nullptr, *dH = nullptr, *dJ = nullptr, *dy = nullptr;
+  int *dflag = nullptr;
   hipStream_t cap = nullptr;       // private capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -284,6 +288,10 @@ bool coarse_assembled_ok(const Ctx &c, const Level &C);
 void coarse_setup(Ctx &c, Level &C, hipStream_t s);
 void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s);
 void coarse_release(CoarseSolver &S);
+size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz);
+void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s);
+void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
+                         double *x, hipStream_t s);
 
 // hessenberg.cpp
 double hessenberg_max_abs_eig(const double *H, int ldh, int k);

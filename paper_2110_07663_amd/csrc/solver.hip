@@ -94,6 +94,7 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
   if (o->coarse_maxit < 1) fail(SEM_EINVAL, "coarse_maxit must be >= 1");
   if (o->ax_variant < -1 || o->ax_variant > 2) fail(SEM_EINVAL, "ax_variant must be in [-1, 2]");
   if (o->batch_rhs < 0 || o->batch_rhs > 64) fail(SEM_EINVAL, "batch_rhs must be in [0, 64]");
+  if (o->coarse_solver < -1 || o->coarse_solver > 1) fail(SEM_EINVAL, "coarse_solver must be in [-1, 1]");
   for (int f = 0; f < 6; ++f)
     if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
   int64_t E = (int64_t)m->nex * m->ney * m->nez;
@@ -209,6 +210,24 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     S.w2 = A.take<double>(S.n);
     S.s2 = A.take<double>(S.n);
     S.partials = A.take<double>(8 * ((S.n + 255) / 256));
+    // exact block-tridiagonal solve of the p = 1 level (chosen, or by size)
+    {
+      const int64_t nx = m->nex + 1, ny = m->ney + 1, nz = m->nez + 1;
+      const size_t db = coarse_direct_bytes(nx, ny, nz);
+      const bool want = o.coarse_solver == 1 || (o.coarse_solver < 0 && db <= ((size_t)4 << 30));
+      S.direct = false;
+      S.dG = S.dH = S.dJ = S.dy = nullptr;
+      S.dflag = nullptr;
+      if (want) {
+        const int64_t Mp = (nx * ny + 31) / 32 * 32;
+        S.dG = A.take<double>((size_t)(nz * Mp * Mp));
+        S.dH = A.take<double>((size_t)(nz * Mp * Mp));
+        S.dJ = A.take<double>((size_t)(nz * Mp * Mp));
+        S.dy = A.take<double>((size_t)std::max<int64_t>(S.n, Mp));  // also the pivot-test diagonal
+        S.dflag = A.take<int>(64);
+        S.direct = true;  // until the setup finds the level singular
+      }
+    }
     S.counter = A.take<unsigned>(64);
     S.sc = A.take<CoarseScalars>(1);
     const char *g = getenv("SEM_COARSE_GRAPH");
@@ -827,6 +846,7 @@ void sem_default_opts(sem_opts *o) {
   o->coarse_maxit = 2000;
   o->ax_variant = -1;
   o->batch_rhs = 0;
+  o->coarse_solver = -1;
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }

@@ -19,6 +19,7 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 SMOOTH_JACOBI, SMOOTH_RAS, SMOOTH_ASM = 0, 1, 2
 KRYLOV_PCG, KRYLOV_FCG, KRYLOV_FGMRES = 0, 1, 2
 PRECOND_PMG, PRECOND_JACOBI = 0, 1
+COARSE_AUTO, COARSE_PCG, COARSE_DIRECT = -1, 0, 1
 
 _STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EWORKSPACE", -3: "SEM_EHIP",
                  -4: "SEM_ENOCONV", -5: "SEM_ENAN", -6: "SEM_EUNSUPPORTED", -7: "SEM_EGEOM"}
@@ -46,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("smoother_prec", ctypes.c_int32), ("fdm_prec", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32),
-                ("ax_variant", ctypes.c_int32), ("batch_rhs", ctypes.c_int32)]
+                ("ax_variant", ctypes.c_int32), ("batch_rhs", ctypes.c_int32),
+                ("coarse_solver", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -205,7 +207,8 @@ def batch_solve(solvers, bs, xs, rtol=1e-8, maxit=200, iters_per_launch=4, allow
 def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac=0.1,
               lmax_fac=1.1, arnoldi_steps=10, seed=0, lambda_override=None, smoother_prec=F64,
               fdm_prec=F64, krylov=KRYLOV_FCG, gmres_restart=20, coarse_tol=1e-10,
-              coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1, batch_rhs=0):
+              coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1, batch_rhs=0,
+              coarse_solver=-1):
     o = default_opts()
     o.nlevels = len(schedule)
     for l, p in enumerate(schedule):
@@ -221,6 +224,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
     o.gmres_restart, o.coarse_tol, o.coarse_maxit = gmres_restart, coarse_tol, coarse_maxit
     o.ax_variant = ax_variant
     o.batch_rhs = batch_rhs
+    o.coarse_solver = coarse_solver
     return o
 
 

@@ -33,7 +33,7 @@ class Pair:
                  cheb_order=2, lambda_override=None, smoother_prec=sem.F64, fdm_prec=sem.F64,
                  krylov=sem.KRYLOV_FCG, coarse_tol=1e-10, coarse_maxit=2000, seed=0,
                  precond=sem.PRECOND_PMG, oracle=True, lmin_fac=0.1, lmax_fac=1.1,
-                 gmres_restart=20):
+                 gmres_restart=20, coarse="pcg"):
         nex, ney, nez = (n, n, n) if np.isscalar(n) else n
         self.shape = (nex, ney, nez)
         schedule = tuple(schedule) if schedule else (p,)
@@ -55,7 +55,8 @@ class Pair:
                              lambda_override=lambda_override, smoother_prec=smoother_prec,
                              fdm_prec=fdm_prec, krylov=krylov, coarse_tol=coarse_tol,
                              coarse_maxit=coarse_maxit, seed=seed, precond=precond,
-                             lmin_fac=lmin_fac, lmax_fac=lmax_fac, gmres_restart=gmres_restart)
+                             lmin_fac=lmin_fac, lmax_fac=lmax_fac, gmres_restart=gmres_restart,
+                             coarse_solver={"pcg": sem.COARSE_PCG, "dense": sem.COARSE_DIRECT}[coarse])
         self.gpu = sem.Solver(nex, ney, nez, xyz_g, pg, p, bc=bc, opts=opts)
         self.ora = None
         if oracle:
@@ -66,7 +67,7 @@ class Pair:
             self.ora = OSolver(nex, ney, nez, xyz_o, pg, osched, bc=bc, smoother=smoother,
                                cheb_order=cheb_order, lmin_fac=lmin_fac, lmax_fac=lmax_fac,
                                seed=seed, lambda_override=lam, coarse_tol=coarse_tol,
-                               coarse_maxit=coarse_maxit)
+                               coarse_maxit=coarse_maxit, coarse=coarse)
 
     def random_local(self, seed, level=0, masked=True):
         """The same consistent random E-vector on both sides: (gpu tensor, oracle array)."""

@@ -152,6 +152,48 @@ def test_solve_to_tolerance(krylov):
     assert rel_err(x, res.x) < 1e-6
 
 
+@pytest.mark.parametrize("shape,p,sched,smoother,bc,mesh,lam", [
+    ((3, 3, 3), 5, (5, 3, 1), "ras", (1,) * 6, "sin", [1.7, 1.9]),
+    ((7, 6, 3), 3, (3, 1), "jacobi", (1,) * 6, "sin", [1.9]),             # 8x7 plane: two 32-blocks
+    ((9, 8, 3), 2, (2, 1), "jacobi", (1, 0, 0, 1, 0, 1), "sin", [1.9]),   # 10x9 plane: three blocks
+    # 4^3 layer-shift: one element per slab, strongly skewed; the oracle's
+    # Arnoldi gives lambda~ = 41.9 and 14.6 for RAS here
+    (4, 7, (7, 3, 1), "ras", (1,) * 6, "shift", [42.0, 14.6]),
+])
+def test_vcycle_direct_coarse_matches_oracle(shape, p, sched, smoother, bc, mesh, lam):
+    """Exact block-tridiagonal coarse solve against the oracle's dense solve."""
+    P = Pair(shape, p, mesh=mesh, schedule=sched, smoother=smoother, bc=bc, coarse="dense",
+             lambda_override=lam)
+    for seed in (51, 52):
+        g, o = P.random_local(seed)
+        assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-12
+
+
+def test_direct_coarse_falls_back_when_singular():
+    """All-Neumann: the p = 1 level is singular, the setup keeps the CG."""
+    kw = dict(mesh="sin", schedule=(4, 1), smoother="jacobi", bc=(0,) * 6, coarse_tol=0.0,
+              coarse_maxit=5, lambda_override=[1.8], oracle=False)
+    a = Pair(3, 4, coarse="dense", **kw)
+    b = Pair(3, 4, coarse="pcg", **kw)
+    g, _ = a.random_local(53, masked=False)
+    za, zb = host(a.gpu.vcycle(g)), host(b.gpu.vcycle(g))
+    assert np.all(np.isfinite(za))
+    assert rel_err(za, zb) < 1e-14
+
+
+def test_solve_with_direct_coarse():
+    P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", coarse="dense")
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
+    assert info.converged and info.true_rel_res <= 1e-8 and info.coarse_iters == 0
+    L = P.ora.fine
+    x = host(xg).reshape(bo.shape)
+    r = bo - L.apply_A(x)
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+    res = P.ora.solve(bo, tol=1e-8, maxit=100)
+    assert abs(info.iters - res.iters) <= 1
+
+
 def test_jacobi_pcg_config1_small():
     """Plain Jacobi-PCG on the undeformed cube, p = 3 (the oracle-size workload)."""
     P = Pair(4, 3, mesh="box", krylov=sem.KRYLOV_PCG, precond=sem.PRECOND_JACOBI)
