@@ -72,8 +72,8 @@ def kernels_mode(a):
         s.apply_A(u, out=v)
         s.apply_A(u32, out=v32)
         s.apply_S(u32, out=v32)
-    # the other Ax kernel shapes at p = 7
-    for av in (0, 2):
+    # the other Ax kernel shapes at p = 7 (the default is variant 2)
+    for av in (0, 1):
         oa = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
                            lambda_override=[2.0, 2.0], ax_variant=av)
         sa = sem.Solver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, opts=oa)
@@ -184,8 +184,9 @@ def batch_mode(a):
     print(json.dumps(out), flush=True)
 
 
-def algorithmic_bytes(kind, p, E):
+def algorithmic_bytes(kind, L):
     """HBM bytes one launch must move (each operand read or written once)."""
+    p, E = L.p, L.E
     N3 = (p + 1) ** 3
     pb = p + 3
     if kind == "ax64":   # u, v and 6 geometric factors, FP64
@@ -194,7 +195,30 @@ def algorithmic_bytes(kind, p, E):
         return E * N3 * 8 * 4
     if kind == "fdm":    # FP32: input, RAS weight, output E-vectors; S (3 pb^2); lambda (3 pb)
         return E * (3 * N3 * 4 + 3 * pb * pb * 4 + 3 * pb * 4)
+    if kind in ("gs32", "gs64"):  # value read + write and index per member, offset per segment
+        w = 4 if kind == "gs32" else 8
+        return L.nmembers * (2 * w + 4) + (L.nshared + 1) * 4
     raise ValueError(kind)
+
+
+def fdm_flops(L):
+    """Multiply-adds x 2 of the six 1D contractions plus the diagonal scaling, per launch."""
+    pb = L.p + 3
+    return L.E * (12 * pb ** 4 + pb ** 3)
+
+
+# HBM bytes per launch measured on this workload (2 x FETCH_SIZE + WRITE_SIZE,
+# KiB x 1024, calibrated on a 1 GiB device copy; commands and raw counter
+# values in profiles/kernels_layer_shift_32cube_p7.md).  A kernel whose code
+# changed after its counters were taken is left out (traffic null).
+TRAFFIC_32CUBE_P7 = {
+    "ax64": 1073867626,   # k_ax8_f64<true>
+    "ax32": 536987200,    # k_ax8_f32<true>
+    "fdm": 300657578,     # k_fdm_lines<7,float,false>
+    "gs32": 190531528,    # k_gs<float>
+    "gs64": 334522573,    # k_gs<double>
+}
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def main():
@@ -262,22 +286,33 @@ def main():
 
     # per-kernel rooflines from the event timings of the timed steps
     kern = {}
-    for k in ("ax64", "ax32", "fdm"):
+    for k in ("ax64", "ax32", "fdm", "gs32", "gs64"):
         ms, cnt = prof[k]
         if cnt == 0:
             continue
         avg = ms / cnt
-        byt = algorithmic_bytes(k, p, L0.E)
+        byt = algorithmic_bytes(k, L0)
         kern[k] = {"avg_us": 1e3 * avg, "launches": cnt, "total_ms": ms,
                    "bytes_per_launch": byt, "GBs": byt / (avg * 1e-3) / 1e9}
-    for k in ("gs64", "gs32", "coarse", "vcycle"):
+        if k == "fdm":
+            kern[k]["TFLOPs"] = fdm_flops(L0) / (avg * 1e-3) / 1e12
+    for k in ("coarse", "vcycle"):
         ms, cnt = prof[k]
         if cnt:
             kern[k] = {"avg_us": 1e3 * ms / cnt, "launches": cnt, "total_ms": ms}
-    dom = max((k for k in kern if k in ("ax64", "ax32", "fdm")), key=lambda k: kern[k]["total_ms"])
+    # dominant finest-level kernel of the timed solves (by total time)
+    dom = max((k for k in kern if "bytes_per_launch" in kern[k]), key=lambda k: kern[k]["total_ms"])
     d = kern[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": None}
+    traffic = TRAFFIC_32CUBE_P7.get(dom) if (n, p) == (32, 7) else None
+    if dom == "fdm":   # FP32 VALU contractions: arithmetic bound
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(d["TFLOPs"], 2),
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(d["TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": traffic, "hbm_GBs": round(d["GBs"], 1)}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": traffic}
     ax = kern.get("ax64")
     ax_gdofs = L0.nglobal / (ax["avg_us"] * 1e-6) / 1e9 if ax else None
 

@@ -123,6 +123,7 @@ typedef struct {
   int64_t nglobal;            /* unique nodes (nex*p+1)(ney*p+1)(nez*p+1)                 */
   int64_t nshared;            /* gather-scatter segments (shared or Dirichlet nodes)      */
   double lmin, lmax;          /* Chebyshev bounds of this level (0 on the coarsest)       */
+  int64_t nmembers;           /* E-vector entries in those segments                       */
 } sem_level_desc;
 
 void sem_default_opts(sem_opts *opts);

@@ -188,6 +188,11 @@ template <typename T>
 __device__ inline T fdm_inv(T d) {
   return d > T(0) ? T(1) / d : T(0);  // +inf -> 0 (decoupled), 0 -> dropped mode
 }
+// FP32: the hardware reciprocal (about 1 ulp) instead of the IEEE division
+template <>
+__device__ inline float fdm_inv<float>(float d) {
+  return d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
+}
 
 template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
@@ -222,7 +227,8 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     lxy = le[a] + le[PB + b];
   }
 
-  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  int64_t ex, ey, ez;
+  elem_coords(e, nex, ney, ex, ey, ez);
   T col[PB];
   if (act) {
     // box node (a, b, c): direction offsets and local indices
@@ -232,16 +238,13 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
     bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
 #pragma unroll
-    for (int c = 0; c < PB; ++c) {
+    for (int c = 0; c < PB; ++c) {  // unconditional loads, as in k_fdm_lines
       int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
       int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
       bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
-      T v = T(0);
-      if (ok) {
-        int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
-        v = r[en * N3 + (lk * N + lj) * N + li];
-      }
-      col[c] = v;
+      int64_t en = ok ? e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
+      T v = r[en * N3 + (lk * N + lj) * N + li];
+      col[c] = ok ? v : T(0);
     }
 #pragma unroll
     for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
@@ -364,7 +367,8 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
 
   // gather the box: thread (a, b) = (lo, hi) reads the line along c
   {
-    const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+    int64_t ex, ey, ez;
+    elem_coords(e, nex, ney, ex, ey, ez);
     if (act) {
       const int a = lo, b = hi;
       const int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0);
@@ -372,17 +376,16 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
       const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
       const int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
       const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
+      // unconditional loads (an outside neighbour reads the element itself and
+      // is replaced by 0), so that all PB loads are in flight together
 #pragma unroll
       for (int c = 0; c < PB; ++c) {
         const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
         const int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
         const bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
-        T val = T(0);
-        if (ok) {
-          const int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
-          val = r[en * N3 + (lk * N + lj) * N + li];
-        }
-        v[c] = val;
+        const int64_t en = ok ? e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
+        const T val = r[en * N3 + (lk * N + lj) * N + li];
+        v[c] = ok ? val : T(0);
       }
 #pragma unroll
       for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = v[c];

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
   const float sxyz = sscale[e * 3 + 0] * sscale[e * 3 + 1] * sscale[e * 3 + 2];
 
   // gather the extended box (consistent E-vector; outside the domain 0)
-  const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
+  int64_t ex, ey, ez;
+  elem_coords(e, nex, ney, ex, ey, ez);
   float mr = 0.f;
   for (int t = lane; t < PB * PB * PB; t += 64) {
     int a = t % PB, b = (t / PB) % PB, c = t / (PB * PB);
@@ -141,11 +142,10 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
     int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0), lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
     bool ok = ex + dx >= 0 && ex + dx < nex && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 &&
               ez + dz < nez;
-    float v = 0.f;
-    if (ok) {
-      int64_t en = e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney;
-      v = r[en * N3 + (lk * N + lj) * N + li];
-    }
+    // unconditional load (an outside neighbour reads the element itself, then 0)
+    int64_t en = ok ? e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
+    float v = r[en * N3 + (lk * N + lj) * N + li];
+    v = ok ? v : 0.f;
     X[c * PS + b * RS + a] = v;
     mr = fmaxf(mr, fabsf(v));
   }

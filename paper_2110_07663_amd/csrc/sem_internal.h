@@ -30,6 +30,16 @@ constexpr int kMaxP = 10;      // highest supported polynomial degree
 constexpr int kMaxLevels = 8;
 constexpr int kMaxArnoldi = 16;
 
+// Element coordinates in the structured element grid (element counts stay
+// below 2^31, so 32-bit unsigned division suffices)
+__device__ inline void elem_coords(int64_t e, int nex, int ney, int64_t &ex, int64_t &ey,
+                                   int64_t &ez) {
+  const unsigned ue = (unsigned)e, q = ue / (unsigned)nex;
+  ex = ue - q * (unsigned)nex;
+  ey = q % (unsigned)ney;
+  ez = q / (unsigned)ney;
+}
+
 // Workgroups are dispatched to the device's 8 XCDs round-robin (block b runs on
 // XCD b % 8), and each XCD has its own L2.  Kernels whose blocks read their
 // neighbours' data (gather-scatter segments, Schwarz boxes) renumber their

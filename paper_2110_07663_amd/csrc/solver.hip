@@ -934,6 +934,7 @@ sem_status sem_level_info(const sem_ctx *ctx, int32_t level, sem_level_desc *out
     out->nlocal = L.nloc;
     out->nglobal = L.nglob;
     out->nshared = L.nseg;
+    out->nmembers = L.nperm;
     out->lmin = L.lmin;
     out->lmax = L.lmax;
   });

@@ -61,7 +61,8 @@ class SolveInfo(ctypes.Structure):
 class LevelDesc(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("N", ctypes.c_int32), ("E", ctypes.c_int64),
                 ("nlocal", ctypes.c_int64), ("nglobal", ctypes.c_int64),
-                ("nshared", ctypes.c_int64), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double)]
+                ("nshared", ctypes.c_int64), ("lmin", ctypes.c_double), ("lmax", ctypes.c_double),
+                ("nmembers", ctypes.c_int64)]
 
 
 class TuneRequest(ctypes.Structure):
