@@ -110,6 +110,9 @@ def batch_mode(a):
     from paper_2110_07663_amd import workloads as wl
     torch.cuda.set_device(0)
     spec = wl.batch_spec(nprob=a.nprob, seed=5)
+
+    def note(msg):
+        print(f"[batch] {msg}", file=sys.stderr, flush=True)
     sched_of = {5: (5, 3, 1), 7: (7, 3, 1), 9: (9, 5, 1)}
     tuned = {}
     solvers, bs, t_tune = [], [], 0.0
@@ -136,6 +139,8 @@ def batch_mode(a):
             t0 = time.perf_counter()
             best, res, _ = sem.tune(side, side, side, xyz, p, p, b0, request=req, repeats=1)
             t_tune += time.perf_counter() - t0
+            note(f"tuned p={p} side={side}: order {best.cheb_order} ax {best.ax_variant} "
+                 f"({time.perf_counter() - t0:.1f} s)")
             probe.close()
             best.batch_rhs = 4
             tuned[key] = best
@@ -149,6 +154,7 @@ def batch_mode(a):
         solvers.append(s)
         bs.append(row)
         total_dof += s.levels[0].nglobal * len(freqs)
+        note(f"set up problem {len(solvers)}/{len(spec)} (side {side}, p {p})")
     torch.cuda.synchronize()
     # sequential: every lane through sem_solve
     xs_seq = [[torch.zeros_like(b) for b in row] for row in bs]
@@ -157,24 +163,50 @@ def batch_mode(a):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters_seq = []
-    for s_, row, xrow in zip(solvers, bs, xs_seq):
+    for i, (s_, row, xrow) in enumerate(zip(solvers, bs, xs_seq)):
         for b, x in zip(row, xrow):
             _, info = s_.solve(b, x=x, rtol=1e-8, maxit=300)
             iters_seq.append(info.iters)
+        if i % 8 == 7:
+            note(f"sequential: {i + 1} problems solved")
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    note(f"sequential {t_seq:.2f} s; batched solve starts")
     # batched
     xs = [[torch.zeros_like(b) for b in row] for row in bs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=4)
+    infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=2)
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
+    note(f"batched {t_bat:.2f} s")
+    # plain FP64 sequential baseline: one context at a time (set up, 4 solves timed, freed)
+    t_seq64, iters64 = 0.0, []
+    for i, ((side, p, freqs), row) in enumerate(zip(spec, bs)):
+        xyz = wl.sampled_mesh(side, side, side, sem.gll_nodes(p)[0], wl.sin_map(0.05))
+        o64 = sem.make_opts(schedule=sched_of[p], smoother=sem.SMOOTH_RAS, cheb_order=2,
+                            smoother_prec=sem.F64)
+        s64 = sem.Solver(side, side, side, xyz, p, p, opts=o64)
+        s64.solve(row[0], x=torch.zeros_like(row[0]), rtol=1e-8, maxit=300)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in row:
+            _, info = s64.solve(b, x=torch.zeros_like(b), rtol=1e-8, maxit=300)
+            iters64.append(info.iters)
+        torch.cuda.synchronize()
+        t_seq64 += time.perf_counter() - t0
+        s64.close()
+        del s64
+        if i % 8 == 7:
+            note(f"fp64 sequential: {i + 1} problems")
     worst = max(i.true_rel_res for i in infos)
     out = {"mode": "batch", "problems": len(solvers), "rhs_per_problem": 4,
            "lanes": len(infos), "unique_dof_total": int(total_dof),
            "sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
            "speedup_batched_vs_sequential": round(t_seq / t_bat, 3),
+           "sequential_fp64_s": round(t_seq64, 3),
+           "speedup_batched_vs_sequential_fp64": round(t_seq64 / t_bat, 3),
+           "iters_sequential_fp64_max": max(iters64),
            "batched_gdof_s": round(total_dof / t_bat / 1e9, 4),
            "worst_true_rel_res": worst, "all_converged": all(i.converged for i in infos),
            "iters_batched_max": max(i.iters for i in infos),

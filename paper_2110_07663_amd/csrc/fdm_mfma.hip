@@ -221,6 +221,212 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
   }
 }
 
+// Second form: the 16-bit box stays in LDS between contractions, every
+// operand fragment is one 8-byte LDS read, and S is the A operand so that a
+// contraction's D fragment (lane: 4 consecutive rows, one column) is the B
+// fragment of a contraction over those rows.  Tiles are slices of the box
+// (16x16, zero padded), one wavefront per element.  Order:
+//   x: Y1_c = Sx^T X_c      (slices c,  rows a', cols b)  -> LDS [c][a'][b]
+//   y: Y2_c = Sy^T Y1_c^T   (slices c,  rows b', cols a') -> LDS [a'][b'][c]
+//   z: Y3_a = Sz^T (...)    (slices a', rows c', cols b'), divide by lambda sums
+//   back z from registers: Y4_a = Sz Y3_a (rows c, cols b') -> LDS [a'][c][b']
+//   back y: Y5_a = Sy (...) (rows b, cols c)              -> LDS [b][c][a']
+//   back x: Y6_b = Sx (...) (rows a, cols c) -> own nodes times the RAS weight
+// Each step keeps its PB tiles of accumulators in registers until all reads
+// of the previous layout are done, so one LDS buffer per wave suffices.
+template <int P, bool BF, bool ASM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fdm_mfma2(int64_t E, int nex, int ney, int nez,
+                                                   const float *__restrict__ r,
+                                                   const uint16_t *__restrict__ S16,
+                                                   const float *__restrict__ sscale,
+                                                   const float *__restrict__ lam,
+                                                   const float *__restrict__ W,
+                                                   float *__restrict__ z) {
+  using M = Mma<BF>;
+  using frag = typename M::frag;
+  constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
+  constexpr int RS = 20, SS = 324;  // LDS strides in 16-bit units (8-byte aligned rows)
+  // PB slices, and room for the FP32 output staging
+  constexpr int OUT = 2 * (ASM ? PB * PB * PB : N3);
+  constexpr int BUF = ((PB * SS > OUT ? PB * SS : OUT) + 3) / 4 * 4;
+  constexpr int WAVES = 4;
+  static_assert(PB <= 16, "pbar must fit one 16-wide tile");
+  __shared__ uint16_t lds[WAVES * BUF];
+  
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)xcd_block() * WAVES + wave;
+  if (e >= E) return;  // whole wave leaves; no block-wide barriers below
+  uint16_t *buf = lds + wave * BUF;
+  const int g = lane >> 4, t = lane & 15;
+
+  auto bits = [](float x) -> uint16_t {
+    auto h = M::enc(x);
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+  };
+  // (at is a multiple of 4: one 8-byte LDS read)
+  auto load_frag = [&](int at) -> frag { return *reinterpret_cast<const frag *>(buf + at); };
+  auto sync = []() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  };
+
+  // A fragments of S: forward A[mode][node] = S[node][mode], backward A[node][mode]
+  const uint16_t *Se = S16 + e * 3 * PB * PB;
+  frag Af[3], Ab[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * g + j;
+      const bool ok = k < PB && t < PB;
+      Af[d][j] = M::from_bits(ok ? Se[(d * PB + k) * PB + t] : (uint16_t)0);
+      Ab[d][j] = M::from_bits(ok ? Se[(d * PB + t) * PB + k] : (uint16_t)0);
+    }
+  // eigenvalues for eq. 9: lambda_y at this lane's column t, lambda_z at its
+  // rows 4g+j (padding: +inf, so that the mode is dropped); lambda_x per tile
+  const float *le = lam + e * 3 * PB;
+  const float inf = __builtin_huge_valf();
+  const float ly = t < PB ? le[PB + t] : inf;
+  float lz[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) lz[j] = 4 * g + j < PB ? le[2 * PB + 4 * g + j] : inf;
+  const float sxyz = sscale[e * 3 + 0] * sscale[e * 3 + 1] * sscale[e * 3 + 2];
+
+  // zero the buffer (padding rows and columns are read as operands)
+  for (int q = lane * 4; q < BUF; q += 256) *reinterpret_cast<uint2 *>(buf + q) = make_uint2(0u, 0u);
+  // gather the extended box row by row (row (b, c): the x-neighbours' nodes
+  // p-1 and 1 around the element's own N nodes; outside the domain 0), scaled
+  // by its largest entry
+  int64_t ex, ey, ez;
+  elem_coords(e, nex, ney, ex, ey, ez);
+  constexpr int NR = (PB * PB + 63) / 64;
+  float v[NR][PB];
+  float mr = 0.f;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int row = lane + 64 * u;
+    const int rr = row < PB * PB ? row : 0;
+    const int b = rr % PB, c = rr / PB;
+    const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0), lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+    const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0), lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
+    const bool okyz = row < PB * PB && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 && ez + dz < nez;
+    const int64_t em = okyz ? e + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
+    const float *src = r + em * N3 + (lk * N + lj) * N;
+    const bool okl = okyz && ex > 0, okr = okyz && ex < nex - 1;
+    const float left = src[okl ? -N3 + P - 1 : 0], right = src[okr ? N3 + 1 : 0];
+    v[u][0] = okl ? left : 0.f;
+    v[u][PB - 1] = okr ? right : 0.f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[u][a + 1] = okyz ? src[a] : 0.f;
+#pragma unroll
+    for (int a = 0; a < PB; ++a) mr = fmaxf(mr, fabsf(v[u][a]));
+  }
+  mr = wave_max(mr);
+  const float inv_r = mr > 0.f ? 1.f / mr : 0.f;
+  sync();
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int row = lane + 64 * u;
+    if (row < PB * PB) {
+      const int b = row % PB, c = row / PB;
+#pragma unroll
+      for (int a = 0; a < PB; ++a) buf[c * SS + b * RS + a] = bits(v[u][a] * inv_r);
+    }
+  }
+  sync();
+
+  float4_t acc[PB];
+  const float4_t zero4 = {0.f, 0.f, 0.f, 0.f};
+  // x: tile c, B[a][b] = X[c][b][a]
+#pragma unroll
+  for (int c = 0; c < PB; ++c) acc[c] = M::mma(Af[0], load_frag(c * SS + t * RS + 4 * g), zero4);
+  sync();
+#pragma unroll
+  for (int c = 0; c < PB; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) buf[c * SS + (4 * g + j) * RS + t] = bits(acc[c][j]);
+  sync();
+  // y: tile c, B[b][a'] from [c][a'][b]
+#pragma unroll
+  for (int c = 0; c < PB; ++c) acc[c] = M::mma(Af[1], load_frag(c * SS + t * RS + 4 * g), zero4);
+  sync();
+  if (t < PB) {  // slice a' = t
+#pragma unroll
+    for (int c = 0; c < PB; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) buf[t * SS + (4 * g + j) * RS + c] = bits(acc[c][j]);
+  }
+  sync();
+  // z: tile a', B[c][b'] from [a'][b'][c]; then the diagonal of eq. 9
+  float mt = 0.f;
+#pragma unroll
+  for (int a = 0; a < PB; ++a) {
+    acc[a] = M::mma(Af[2], load_frag(a * SS + t * RS + 4 * g), zero4);
+    const float lxy = le[a] + ly;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float dl = lxy + lz[j];
+      const float val = dl > 0.f ? sxyz * acc[a][j] * __builtin_amdgcn_rcpf(dl) : 0.f;  // +inf -> 0
+      acc[a][j] = val;
+      mt = fmaxf(mt, fabsf(val));
+    }
+  }
+  mt = wave_max(mt);
+  const float inv_t = mt > 0.f ? 1.f / mt : 0.f;
+  sync();
+  // back along z from registers: B[c'][b'] = scaled tile; result [a'][c][b']
+#pragma unroll
+  for (int a = 0; a < PB; ++a) {
+    frag B;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) B[j] = M::enc(acc[a][j] * inv_t);
+    acc[a] = M::mma(Ab[2], B, zero4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) buf[a * SS + (4 * g + j) * RS + t] = bits(acc[a][j]);
+  }
+  sync();
+  // back along y: tile a', B[b'][c] from [a'][c][b']; result [b][c][a']
+#pragma unroll
+  for (int a = 0; a < PB; ++a) acc[a] = M::mma(Ab[1], load_frag(a * SS + t * RS + 4 * g), zero4);
+  sync();
+#pragma unroll
+  for (int a = 0; a < PB; ++a)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * g + j < PB) buf[(4 * g + j) * SS + t * RS + a] = bits(acc[a][j]);  // slice b = 4g+j
+  sync();
+  // back along x: tile b, B[a'][c] from [b][c][a']; rows a, columns c
+#pragma unroll
+  for (int b = 0; b < PB; ++b) acc[b] = M::mma(Ab[0], load_frag(b * SS + t * RS + 4 * g), zero4);
+  sync();
+  // stage the result in LDS (FP32, node order) and write it out in contiguous runs
+  const float fin = sxyz * mr * mt;
+  float *st = reinterpret_cast<float *>(buf);
+  const int c = t;
+#pragma unroll
+  for (int b = 0; b < PB; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = 4 * g + j;
+      if constexpr (ASM) {
+        if (a < PB && c < PB) st[(c * PB + b) * PB + a] = acc[b][j] * fin;
+      } else {
+        if (a >= 1 && a <= P + 1 && b >= 1 && b <= P + 1 && c >= 1 && c <= P + 1)
+          st[((c - 1) * N + (b - 1)) * N + (a - 1)] = acc[b][j] * fin;
+      }
+    }
+  sync();
+  if constexpr (ASM) {
+    float *zb = z + e * PB * PB * PB;
+    for (int q = lane; q < PB * PB * PB; q += 64) zb[q] = st[q];
+  } else {
+    const int64_t o = e * N3;
+    for (int q = lane; q < N3; q += 64) z[o + q] = W[o + q] * st[q];
+  }
+}
+
 template <int P>
 static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, bool bf,
                        bool asm_mode, hipStream_t s) {
@@ -231,9 +437,15 @@ static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, b
     if (!L.box32) fail(SEM_EINVAL, "ASM box buffer was not built");
     out = L.box32;
   }
-#define SEM_MFMA_LAUNCH(BFV, ASMV)                                                              \
-  hipLaunchKernelGGL((k_fdm_mfma<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex, c.ney, \
-                     c.nez, r, L.S16, sscale, L.lam32, L.w32, out)
+#define SEM_MFMA_LAUNCH(BFV, ASMV)                                                                \
+  do {                                                                                            \
+    if (c.fdm_mfma1)                                                                              \
+      hipLaunchKernelGGL((k_fdm_mfma<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex,      \
+                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out);                     \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_fdm_mfma2<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex,     \
+                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out);                     \
+  } while (0)
   if (bf && asm_mode) SEM_MFMA_LAUNCH(true, true);
   else if (bf) SEM_MFMA_LAUNCH(true, false);
   else if (asm_mode) SEM_MFMA_LAUNCH(false, true);

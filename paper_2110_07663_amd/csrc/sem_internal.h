@@ -212,6 +212,7 @@ struct Ctx {
   double *av = nullptr;
   int fdm_prec = SEM_F32;
   bool fdm_lines = true;  // line-organised VALU FDM kernel for pbar^2 > 64
+  bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
 };
 
 // ---------------------------------------------------------------------------
