@@ -279,10 +279,10 @@ def main():
 
     coarse = {"auto": sem.COARSE_AUTO, "pcg": sem.COARSE_PCG, "direct": sem.COARSE_DIRECT}[a.coarse]
 
-    def make(prec):
+    def make(prec, fdm_prec=None):
         opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
                              smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=a.coarse_tol,
-                             coarse_solver=coarse)
+                             coarse_solver=coarse, fdm_prec=fdm_prec if fdm_prec else prec)
         t0 = time.perf_counter()
         s = sem.Solver(n, n, n, xyz, 1, p, opts=opts)
         torch.cuda.synchronize()
@@ -364,7 +364,27 @@ def main():
         print(f"[bench] fp64 solve {1e3 * t_fp64:.2f} ms iters={ip.iters}", file=sys.stderr,
               flush=True)
         plain.close()
-        del plain, xp
+        del plain
+        # FDM contractions on the matrix cores (16-bit operands, FP32 accumulation)
+        mfma = {}
+        for name, fp in (("fp16", sem.F16), ("bf16", sem.BF16)):
+            sm, _ = make(sem.F32, fp)
+            sm.solve(b, rtol=1e-8, maxit=200)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            xm, im = sm.solve(b, rtol=1e-8, maxit=200)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t1
+            mfma[name] = {"ms": round(1e3 * tm, 2), "iters": im.iters,
+                          "true_rel_res": im.true_rel_res,
+                          "rel_diff_vs_fp64": float((xm - xp).norm() / xp.norm()),
+                          "speedup_vs_fp64": round(t_fp64 / tm, 3)}
+            print(f"[bench] {name}-FDM solve {1e3 * tm:.2f} ms iters={im.iters}", file=sys.stderr,
+                  flush=True)
+            sm.close()
+            del sm, xm
+        fp64["mfma_fdm"] = mfma
+        del xp
 
     cpu = None
     if not a.no_cpu_baseline:
