@@ -5,11 +5,14 @@
 // fixed launch shape and a fixed summation tree (per-thread strided partial
 // sums, an LDS tree per block, then the last block to finish sums the block
 // partials in block order), so results are bitwise repeatable.
+#include <type_traits>
+
 #include "sem_internal.h"
 
 namespace sem {
 
 static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 static inline unsigned red_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > kRedBlocks) g = kRedBlocks;
@@ -215,23 +218,95 @@ struct Ptr4 {
   const double *p[4];
 };
 
-template <int ND>
+// per-thread strided pairs (16-byte loads when every operand is 16-byte
+// aligned), two partial sums per product; an odd last entry goes to the
+// first thread
+template <typename V>
+__device__ inline double2 ld2(const double *p, int64_t t) {
+  if constexpr (V::value) return reinterpret_cast<const double2 *>(p)[t];
+  return make_double2(p[2 * t], p[2 * t + 1]);
+}
+template <int ND, typename V>
 __global__ __launch_bounds__(256) void k_wdots(int64_t n, const double *__restrict__ w, Ptr4 a,
                                                Ptr4 b, double *partials, unsigned *counter,
                                                double *out) {
-  double acc[ND];
+  double acc[ND], acc2[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    double wt = w[t];
+  for (int j = 0; j < ND; ++j) acc[j] = acc2[j] = 0.0;
+  const int64_t n2 = n / 2;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wt = ld2<V>(w, t);
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc[j] += wt * a.p[j][t] * b.p[j][t];
+    for (int j = 0; j < ND; ++j) {
+      const double2 x = ld2<V>(a.p[j], t);
+      const double2 y = ld2<V>(b.p[j], t);
+      acc[j] += wt.x * x.x * y.x;
+      acc2[j] += wt.y * x.y * y.y;
+    }
   }
+  if (t0 == 0 && (n & 1)) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += w[n - 1] * a.p[j][n - 1] * b.p[j][n - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
   if (last_block_sum<ND>(acc, partials, counter) && threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < ND; ++j) out[j] = acc[j];
   }
+}
+
+// FCG step: x += alpha p, r -= alpha q, and (r, r)_w of the new r
+template <typename V>
+__device__ inline void st2(double *p, int64_t t, double2 v) {
+  if constexpr (V::value) {
+    reinterpret_cast<double2 *>(p)[t] = v;
+  } else {
+    p[2 * t] = v.x;
+    p[2 * t + 1] = v.y;
+  }
+}
+template <typename V>
+__global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
+                                                const double *__restrict__ w,
+                                                const double *__restrict__ p,
+                                                const double *__restrict__ q, double *__restrict__ x,
+                                                double *__restrict__ r, double *partials,
+                                                unsigned *counter, double *out) {
+  double acc[1] = {0.0}, acc2 = 0.0;
+  const int64_t n2 = n / 2;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
+    const double2 pv = ld2<V>(p, t), qv = ld2<V>(q, t), wt = ld2<V>(w, t);
+    double2 xv = ld2<V>(x, t), rv = ld2<V>(r, t);
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    st2<V>(x, t, xv);
+    st2<V>(r, t, rv);
+    acc[0] += wt.x * rv.x * rv.x;
+    acc2 += wt.y * rv.y * rv.y;
+  }
+  if (t0 == 0 && (n & 1)) {
+    x[n - 1] += alpha * p[n - 1];
+    r[n - 1] -= alpha * q[n - 1];
+    acc[0] += w[n - 1] * r[n - 1] * r[n - 1];
+  }
+  acc[0] += acc2;
+  if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) out[0] = acc[0];
+}
+
+void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
+                   const double *q, double *x, double *r, double *out, hipStream_t s) {
+  if (aligned16(w) && aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r))
+    hipLaunchKernelGGL(k_fcg_xr<std::true_type>, dim3(red_grid(n)), dim3(256), 0, s, n, alpha, w,
+                       p, q, x, r, c.partials, c.counter, out);
+  else
+    hipLaunchKernelGGL(k_fcg_xr<std::false_type>, dim3(red_grid(n)), dim3(256), 0, s, n, alpha, w,
+                       p, q, x, r, c.partials, c.counter, out);
+  SEM_LAUNCH("k_fcg_xr");
 }
 
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
@@ -242,13 +317,18 @@ void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double
     pb.p[j] = b[j];
   }
   unsigned g = red_grid(n);
-  switch (nd) {
-    case 1: hipLaunchKernelGGL(k_wdots<1>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
-    case 2: hipLaunchKernelGGL(k_wdots<2>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
-    case 3: hipLaunchKernelGGL(k_wdots<3>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
-    case 4: hipLaunchKernelGGL(k_wdots<4>, dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out); break;
-    default: fail(SEM_EINVAL, "wdots: at most 4 products");
+  bool al = aligned16(w);
+  for (int j = 0; j < nd; ++j) al = al && aligned16(a[j]) && aligned16(b[j]);
+#define WD(ND, V) hipLaunchKernelGGL((k_wdots<ND, V>), dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out)
+  if (nd < 1 || nd > 4) fail(SEM_EINVAL, "wdots: at most 4 products");
+  if (al) {
+    if (nd == 1) WD(1, std::true_type); else if (nd == 2) WD(2, std::true_type);
+    else if (nd == 3) WD(3, std::true_type); else WD(4, std::true_type);
+  } else {
+    if (nd == 1) WD(1, std::false_type); else if (nd == 2) WD(2, std::false_type);
+    else if (nd == 3) WD(3, std::false_type); else WD(4, std::false_type);
   }
+#undef WD
   SEM_LAUNCH("k_wdots");
 }
 

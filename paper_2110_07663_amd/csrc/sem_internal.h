@@ -262,6 +262,8 @@ void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zer
 void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
                        hipStream_t s);
 // weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)
+void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
+                   const double *q, double *x, double *r, double *out, hipStream_t s);
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
                   const double *const *b, double *out, hipStream_t s);
 // block dots for Gram-Schmidt: out[j] = sum_i w_i V_j(i) x(i), j < k

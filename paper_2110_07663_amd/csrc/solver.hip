@@ -679,10 +679,11 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
         break;
       }
       const double alpha = rz / pq;
-      launch_axpby<double>(n, alpha, p, 1.0, x, s);
-      launch_axpby<double>(n, -alpha, q, 1.0, r, s);
+      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s);  // x, r and (r, r) in one pass
+      host_scalars(c, c.dres, sizeof(double), s);
+      if (!std::isfinite(c.hres[0])) fail(SEM_ENAN, "NaN/Inf in an inner product");
       ++it;
-      rel = wnorm(c, F, r, s) / r0;
+      rel = std::sqrt(c.hres[0]) / r0;
       if (rel <= rtol) break;
       std::swap(z, zo);
       precondition(c, r, z, s);
