@@ -227,9 +227,11 @@ def algorithmic_bytes(kind, L):
         return E * N3 * 8 * 4
     if kind == "fdm":    # FP32: input, RAS weight, output E-vectors; S (3 pb^2); lambda (3 pb)
         return E * (3 * N3 * 4 + 3 * pb * pb * 4 + 3 * pb * 4)
-    if kind in ("gs32", "gs64"):  # value read + write and index per member, offset per segment
+    if kind in ("gs32", "gs64"):
         w = 4 if kind == "gs32" else 8
-        return L.nmembers * (2 * w + 4) + (L.nshared + 1) * 4
+        if os.environ.get("SEM_GS_SORTED") == "1":  # + index per member, offset per segment
+            return L.nmembers * (2 * w + 4) + (L.nshared + 1) * 4
+        return L.nmembers * 2 * w  # value read + write per member of a shared or Dirichlet node
     raise ValueError(kind)
 
 
@@ -247,8 +249,6 @@ TRAFFIC_32CUBE_P7 = {
     "ax64": 1073867626,   # k_ax8_f64<true>
     "ax32": 536987200,    # k_ax8_f32<true>
     "fdm": 300657578,     # k_fdm_lines<7,float,false>
-    "gs32": 190531528,    # k_gs<float>
-    "gs64": 334522573,    # k_gs<double>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 

@@ -276,8 +276,73 @@ void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s)
   SEM_HIP(hipStreamSynchronize(s));
 }
 
+// The same summation on the structured element grid, one direction per pass:
+// the copies of a node on the faces normal to direction D of two neighbouring
+// elements are summed pairwise, and the Dirichlet faces of that direction are
+// zeroed.  After the x, y and z passes every copy holds the sum of all copies
+// (2, 4 or 8) and Dirichlet nodes are 0; each pairwise sum is symmetric, so
+// the copies agree bit for bit.  No index arrays: thread (e, line) touches the
+// line's two face nodes and the neighbour's facing node.
+struct GsGrid {
+  int nex, ney, nez, p, N;
+  int bc[6];
+};
+
+template <typename T, int D>
+__global__ void k_gs_dir(T *__restrict__ v, GsGrid g, int64_t E) {
+  const int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
+  const int N = g.N, N2 = N * N;
+  if (t >= E * N2) return;
+  const unsigned ut = (unsigned)t;  // E * N^2 < 2^31
+  const int64_t e = ut / (unsigned)N2;
+  const int rem = (int)(ut - (unsigned)e * (unsigned)N2);
+  int64_t ex, ey, ez;
+  elem_coords(e, g.nex, g.ney, ex, ey, ez);
+  const int64_t N3 = (int64_t)N2 * N;
+  int64_t lo, hi, step;
+  int64_t pos, cnt;
+  int blo, bhi;
+  if (D == 0) {  // line along i through (j, k) = rem
+    lo = e * N3 + (int64_t)rem * N;
+    hi = lo + g.p;
+    step = N3;
+    pos = ex; cnt = g.nex; blo = g.bc[0]; bhi = g.bc[1];
+  } else if (D == 1) {  // line along j through (i, k)
+    const int k = rem / N, i = rem - k * N;
+    lo = e * N3 + (int64_t)k * N2 + i;
+    hi = lo + (int64_t)g.p * N;
+    step = (int64_t)g.nex * N3;
+    pos = ey; cnt = g.ney; blo = g.bc[2]; bhi = g.bc[3];
+  } else {  // line along k through (i, j)
+    lo = e * N3 + rem;
+    hi = lo + (int64_t)g.p * N2;
+    step = (int64_t)g.nex * g.ney * N3;
+    pos = ez; cnt = g.nez; blo = g.bc[4]; bhi = g.bc[5];
+  }
+  if (pos + 1 < cnt) {
+    const T sum = v[hi] + v[lo + step];
+    v[hi] = sum;
+    v[lo + step] = sum;
+  }
+  if (pos == 0 && blo) v[lo] = T(0);
+  if (pos == cnt - 1 && bhi) v[hi] = T(0);
+}
+
 template <typename T>
 void launch_gs(const Level &L, T *v, hipStream_t s) {
+  if (L.gs_struct) {
+    GsGrid g;
+    g.nex = L.nex; g.ney = L.ney; g.nez = L.nez; g.p = L.p; g.N = L.N;
+    for (int f = 0; f < 6; ++f) g.bc[f] = L.bc[f];
+    const unsigned grid = nb(L.E * L.N * L.N, 256);
+    hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
+    SEM_LAUNCH("k_gs_dir");
+    hipLaunchKernelGGL((k_gs_dir<T, 1>), dim3(grid), dim3(256), 0, s, v, g, L.E);
+    SEM_LAUNCH("k_gs_dir");
+    hipLaunchKernelGGL((k_gs_dir<T, 2>), dim3(grid), dim3(256), 0, s, v, g, L.E);
+    SEM_LAUNCH("k_gs_dir");
+    return;
+  }
   if (L.nseg == 0) return;
   hipLaunchKernelGGL(k_gs<T>, dim3(nb(L.nseg, 256)), dim3(256), 0, s, v, L.perm, L.off, L.nseg);
   SEM_LAUNCH("k_gs");

@@ -78,6 +78,11 @@ struct Level {
   bool fine = false, coarse = false;
   bool lowp = false;                 // level kept in FP32 for the smoother
   int ax_variant = 2;                // Ax kernel shape at p = 7 (0 generic, 1 one wave/element, 2 non-temporal)
+  // structured element grid (x fastest) and boundary conditions, for the
+  // direction-by-direction gather-scatter
+  int nex = 0, ney = 0, nez = 0;
+  int bc[6] = {0, 0, 0, 0, 0, 0};
+  bool gs_struct = true;             // false: the sorted-numbering segments (perm/off)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
   double *xi = nullptr, *wq = nullptr, *D64 = nullptr;

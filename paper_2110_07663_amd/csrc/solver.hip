@@ -275,6 +275,14 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
     L.nglob = ((int64_t)m->nex * L.p + 1) * ((int64_t)m->ney * L.p + 1) * ((int64_t)m->nez * L.p + 1);
     L.fine = l == 0;
     L.coarse = l == c.nlev - 1;
+    L.nex = m->nex;
+    L.ney = m->ney;
+    L.nez = m->nez;
+    for (int f = 0; f < 6; ++f) L.bc[f] = bc[f];
+    {
+      const char *gsv = getenv("SEM_GS_SORTED");
+      L.gs_struct = !(gsv && gsv[0] == '1');
+    }
     L.lowp = c.lowp;
     // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element,
     // non-temporal streams)
