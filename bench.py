@@ -172,14 +172,25 @@ def batch_mode(a):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     note(f"sequential {t_seq:.2f} s; batched solve starts")
-    # batched
-    xs = [[torch.zeros_like(b) for b in row] for row in bs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=2)
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
+    # batched: the 4 right sides of a problem share each operator application and
+    # V-cycle (one launch per kernel for all 4); first an untimed warm-up call
+    def batched(joint):
+        os.environ["SEM_BATCH_JOINT"] = "1" if joint else "0"
+        try:
+            xs = [[torch.zeros_like(b) for b in row] for row in bs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=2)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, infos
+        finally:
+            del os.environ["SEM_BATCH_JOINT"]
+
+    batched(True)
+    t_bat, infos = batched(True)
     note(f"batched {t_bat:.2f} s")
+    t_turn, infos_turn = batched(False)
+    note(f"batched, lanes of a problem in turn {t_turn:.2f} s")
     # plain FP64 sequential baseline: one context at a time (set up, 4 solves timed, freed)
     t_seq64, iters64 = 0.0, []
     for i, ((side, p, freqs), row) in enumerate(zip(spec, bs)):
@@ -204,6 +215,9 @@ def batch_mode(a):
            "lanes": len(infos), "unique_dof_total": int(total_dof),
            "sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
            "speedup_batched_vs_sequential": round(t_seq / t_bat, 3),
+           "batched_lanes_in_turn_s": round(t_turn, 3),
+           "speedup_shared_vs_lanes_in_turn": round(t_turn / t_bat, 3),
+           "iters_in_turn_equal": [i.iters for i in infos_turn] == [i.iters for i in infos],
            "sequential_fp64_s": round(t_seq64, 3),
            "speedup_batched_vs_sequential_fp64": round(t_seq64 / t_bat, 3),
            "iters_sequential_fp64_max": max(iters64),

@@ -24,11 +24,22 @@ struct AxShape {
   static constexpr int PS = N * RS;                        // LDS plane stride
 };
 
+// Several right sides (nv > 1): the nv workgroups of one element group run on
+// one XCD back to back, so the group's G comes from HBM once and from L2 for
+// the other right sides.
+__device__ inline unsigned rhs_block(int nv, int &vec) {
+  if (nv == 1) {
+    vec = 0;
+    return blockIdx.x;
+  }
+  return split_rhs(xcd_block(), nv, vec);
+}
+
 template <int N, typename T>
 __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__restrict__ u,
                                                        const T *__restrict__ G,
                                                        const T *__restrict__ Dg,
-                                                       T *__restrict__ v) {
+                                                       T *__restrict__ v, int nv) {
   using S = AxShape<N>;
   constexpr int NN = S::NN, N3 = S::N3, EPB = S::EPB, RS = S::RS, PS = S::PS;
   __shared__ T sD[NN];
@@ -39,7 +50,10 @@ __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__res
   const int le = tid / NN;
   const int ij = tid - le * NN;
   const int i = ij % N, j = ij / N;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  int vec;
+  const int64_t e = (int64_t)rhs_block(nv, vec) * EPB + le;
+  u += (int64_t)vec * E * N3;
+  v += (int64_t)vec * E * N3;
   const bool active = le < EPB && e < E;
 
   for (int t = tid; t < NN; t += S::BS) sD[t] = Dg[t];
@@ -138,15 +152,18 @@ __device__ __forceinline__ void st(T *p, T v) {
 template <typename T, bool NT>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
                                          const T *__restrict__ G, const T *__restrict__ Dg,
-                                         T *__restrict__ v, T *sD, T (*sU)[72], T (*sR)[72],
-                                         T (*sS)[72]) {
+                                         T *__restrict__ v, int nv, T *sD, T (*sU)[72],
+                                         T (*sR)[72], T (*sS)[72]) {
   constexpr int N = 8, NN = 64, N3 = 512, RS = 9;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 7, j = lane >> 3;
   if (threadIdx.x < NN) sD[threadIdx.x] = Dg[threadIdx.x];
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 4 + w;
+  int vec;
+  const int64_t e = (int64_t)rhs_block(nv, vec) * 4 + w;
   if (e >= E) return;
+  u += (int64_t)vec * E * N3;
+  v += (int64_t)vec * E * N3;
 
   T Di[N], Dj[N];
 #pragma unroll
@@ -203,46 +220,49 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
 template <bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ax8_f64(
     int64_t E, const double *__restrict__ u, const double *__restrict__ G,
-    const double *__restrict__ Dg, double *__restrict__ v) {
+    const double *__restrict__ Dg, double *__restrict__ v, int nv) {
   __shared__ double sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<double, NT>(E, u, G, Dg, v, sD, sU, sR, sS);
+  ax8_body<double, NT>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
 }
 template <bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32(
     int64_t E, const float *__restrict__ u, const float *__restrict__ G,
-    const float *__restrict__ Dg, float *__restrict__ v) {
+    const float *__restrict__ Dg, float *__restrict__ v, int nv) {
   __shared__ float sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<float, NT>(E, u, G, Dg, v, sD, sU, sR, sS);
+  ax8_body<float, NT>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
 }
 
 template <typename T, int N>
-static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, hipStream_t s) {
+static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, int nv, hipStream_t s) {
   if constexpr (N == 8) {
+    // several right sides share G through L2: plain loads (non-temporal ones would bypass it)
     if (L.ax_variant >= 1) {
-      const dim3 grid((unsigned)((L.E + 3) / 4));
+      const dim3 grid((unsigned)((L.E + 3) / 4 * nv));
+      const bool nt = L.ax_variant == 2 && nv == 1;
       if constexpr (sizeof(T) == 8) {
-        if (L.ax_variant == 2)
-          hipLaunchKernelGGL(k_ax8_f64<true>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+        if (nt)
+          hipLaunchKernelGGL(k_ax8_f64<true>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
         else
-          hipLaunchKernelGGL(k_ax8_f64<false>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+          hipLaunchKernelGGL(k_ax8_f64<false>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
       } else {
-        if (L.ax_variant == 2)
-          hipLaunchKernelGGL(k_ax8_f32<true>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+        if (nt)
+          hipLaunchKernelGGL(k_ax8_f32<true>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
         else
-          hipLaunchKernelGGL(k_ax8_f32<false>, grid, dim3(256), 0, s, L.E, u, G, D, v);
+          hipLaunchKernelGGL(k_ax8_f32<false>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
       }
       SEM_LAUNCH("k_ax8");
       return;
     }
   }
   using S = AxShape<N>;
-  unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB);
-  hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v);
+  unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB * nv);
+  hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v, nv);
   SEM_LAUNCH("k_ax");
 }
 
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s) {
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv) {
+  if (nv < 1) fail(SEM_EINVAL, "Ax: no right side");
   const T *G;
   const T *D;
   if constexpr (sizeof(T) == 8) {
@@ -254,21 +274,21 @@ void launch_ax(const Level &L, const T *u, T *v, hipStream_t s) {
   }
   if (!G || !D) fail(SEM_EINVAL, "geometric factors of this precision were not built");
   switch (L.N) {
-    case 2: ax_n<T, 2>(L, u, v, G, D, s); break;
-    case 3: ax_n<T, 3>(L, u, v, G, D, s); break;
-    case 4: ax_n<T, 4>(L, u, v, G, D, s); break;
-    case 5: ax_n<T, 5>(L, u, v, G, D, s); break;
-    case 6: ax_n<T, 6>(L, u, v, G, D, s); break;
-    case 7: ax_n<T, 7>(L, u, v, G, D, s); break;
-    case 8: ax_n<T, 8>(L, u, v, G, D, s); break;
-    case 9: ax_n<T, 9>(L, u, v, G, D, s); break;
-    case 10: ax_n<T, 10>(L, u, v, G, D, s); break;
-    case 11: ax_n<T, 11>(L, u, v, G, D, s); break;
+    case 2: ax_n<T, 2>(L, u, v, G, D, nv, s); break;
+    case 3: ax_n<T, 3>(L, u, v, G, D, nv, s); break;
+    case 4: ax_n<T, 4>(L, u, v, G, D, nv, s); break;
+    case 5: ax_n<T, 5>(L, u, v, G, D, nv, s); break;
+    case 6: ax_n<T, 6>(L, u, v, G, D, nv, s); break;
+    case 7: ax_n<T, 7>(L, u, v, G, D, nv, s); break;
+    case 8: ax_n<T, 8>(L, u, v, G, D, nv, s); break;
+    case 9: ax_n<T, 9>(L, u, v, G, D, nv, s); break;
+    case 10: ax_n<T, 10>(L, u, v, G, D, nv, s); break;
+    case 11: ax_n<T, 11>(L, u, v, G, D, nv, s); break;
     default: fail(SEM_EUNSUPPORTED, "Ax: unsupported degree");
   }
 }
-template void launch_ax<double>(const Level &, const double *, double *, hipStream_t);
-template void launch_ax<float>(const Level &, const float *, float *, hipStream_t);
+template void launch_ax<double>(const Level &, const double *, double *, hipStream_t, int);
+template void launch_ax<float>(const Level &, const float *, float *, hipStream_t, int);
 
 // diag(A^e) per point: only q' on the r-, s- or t-line through q contribute, and
 // the cross terms only at q' = q.

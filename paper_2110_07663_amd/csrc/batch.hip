@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -88,11 +89,24 @@ __global__ void k_lane_init(LaneScalars *L, double rz, double rr0, double tol2, 
   L->done = (rr0 == 0.0 || maxit <= 0) ? 1 : 0;
 }
 
+// The lane kernels run over blockIdx.y = lanes lane0, lane0 + 1, ... of one
+// problem: vectors n apart, reduction partials kRedBlocks * 8 apart, counters
+// 16 apart, scalars consecutive.  A finished lane's blocks return at once.
+#define SEM_LANE_OFFSETS(...)                        \
+  do {                                               \
+    const int64_t y = blockIdx.y;                    \
+    partials += y * kRedBlocks * 8;                  \
+    counter += y * 16;                               \
+    L += y;                                          \
+    __VA_ARGS__                                      \
+  } while (0)
+
 // pq = (p, q)_w; alpha = rz / pq
 __global__ __launch_bounds__(256) void k_lane_pq(int64_t n, const double *__restrict__ w,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ q, double *partials,
                                                  unsigned *counter, LaneScalars *L) {
+  SEM_LANE_OFFSETS(p += y * n; q += y * n;);
   if (L->done) return;
   double acc[1] = {0.0};
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
@@ -117,6 +131,7 @@ __global__ __launch_bounds__(256) void k_lane_update(int64_t n, const double *__
                                                      const double *__restrict__ q,
                                                      double *partials, unsigned *counter,
                                                      LaneScalars *L) {
+  SEM_LANE_OFFSETS(x += y * n; r += y * n; p += y * n; q += y * n;);
   if (L->done) return;
   const double alpha = L->alpha;
   double acc[1] = {0.0};
@@ -140,6 +155,7 @@ __global__ __launch_bounds__(256) void k_lane_beta(int64_t n, const double *__re
                                                    const double *__restrict__ z,
                                                    const double *__restrict__ zo, double *partials,
                                                    unsigned *counter, LaneScalars *L) {
+  SEM_LANE_OFFSETS(r += y * n; z += y * n; zo += y * n;);
   if (L->done) return;
   double acc[2] = {0.0, 0.0};
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
@@ -157,6 +173,13 @@ __global__ __launch_bounds__(256) void k_lane_beta(int64_t n, const double *__re
 // p = z + beta p; z_old = z
 __global__ void k_lane_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
                          double *__restrict__ zo, const LaneScalars *L) {
+  {
+    const int64_t y = blockIdx.y;
+    z += y * n;
+    p += y * n;
+    zo += y * n;
+    L += y;
+  }
   if (L->done) return;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -172,9 +195,10 @@ static inline unsigned rgrid(int64_t n) {
 }
 static inline unsigned egrid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// eager helpers from solver.hip
-void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s);
-void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s);
+// eager helpers from solver.hip (nv right sides nloc apart)
+void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s,
+               int nv = 1);
+void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s, int nv = 1);
 double batch_wnorm2(Ctx &c, const double *a, const double *b, hipStream_t s);
 
 struct Lane {
@@ -187,22 +211,31 @@ struct Lane {
   bool active;
 };
 
-static void lane_iteration(Lane &ln, hipStream_t s) {
-  Ctx &c = *ln.c;
+// one flexible-CG iteration of nv consecutive lanes starting at ln (nv > 1:
+// the lanes share each operator application and V-cycle; their x vectors, which
+// the caller owns, are updated one lane per launch)
+static void lane_iteration(Lane *ln, int nv, hipStream_t s) {
+  Ctx &c = *ln->c;
   const Level &F = c.lev[0];
   const int64_t n = F.nloc;
-  batch_opA(c, F, ln.p, ln.q, s);
-  hipLaunchKernelGGL(k_lane_pq, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.p, ln.q, c.partials,
-                     c.counter, ln.sc);
+  const int k = ln->k;
+  double *part = c.lpartials + (int64_t)k * kRedBlocks * 8;
+  unsigned *cnt = c.lcounter + k * 16;
+  const dim3 rg(rgrid(n), (unsigned)nv), eg(egrid(n), (unsigned)nv);
+  batch_opA(c, F, ln->p, ln->q, s, nv);
+  hipLaunchKernelGGL(k_lane_pq, rg, dim3(256), 0, s, n, F.w64, ln->p, ln->q, part, cnt, ln->sc);
   SEM_LAUNCH("k_lane_pq");
-  hipLaunchKernelGGL(k_lane_update, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.x, ln.r, ln.p,
-                     ln.q, c.partials, c.counter, ln.sc);
-  SEM_LAUNCH("k_lane_update");
-  batch_precondition(c, ln.r, ln.z, s);
-  hipLaunchKernelGGL(k_lane_beta, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, ln.r, ln.z, ln.zo,
-                     c.partials, c.counter, ln.sc);
+  for (int j = 0; j < nv; ++j) {
+    Lane &lj = ln[j];
+    hipLaunchKernelGGL(k_lane_update, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, lj.x, lj.r, lj.p,
+                       lj.q, part + (int64_t)j * kRedBlocks * 8, cnt + j * 16, lj.sc);
+    SEM_LAUNCH("k_lane_update");
+  }
+  batch_precondition(c, ln->r, ln->z, s, nv);
+  hipLaunchKernelGGL(k_lane_beta, rg, dim3(256), 0, s, n, F.w64, ln->r, ln->z, ln->zo, part, cnt,
+                     ln->sc);
   SEM_LAUNCH("k_lane_beta");
-  hipLaunchKernelGGL(k_lane_p, dim3(egrid(n)), dim3(256), 0, s, n, ln.z, ln.p, ln.zo, ln.sc);
+  hipLaunchKernelGGL(k_lane_p, eg, dim3(256), 0, s, n, ln->z, ln->p, ln->zo, ln->sc);
   SEM_LAUNCH("k_lane_p");
 }
 
@@ -252,12 +285,13 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
         ln.b = b[i * nrhs + k];
         ln.x = x[i * nrhs + k];
         if (!ln.b || !ln.x) fail(SEM_EINVAL, "null vector in batch");
-        const size_t off = (size_t)k * 5 * F.nloc;
-        ln.r = c.lanev + off;
-        ln.z = ln.r + F.nloc;
-        ln.zo = ln.z + F.nloc;
-        ln.p = ln.zo + F.nloc;
-        ln.q = ln.p + F.nloc;
+        // [5][nlanes][nloc]: the r (z, z_old, p, q) of consecutive lanes are adjacent
+        const size_t blk = (size_t)c.nlanes * F.nloc;
+        ln.r = c.lanev + (size_t)k * F.nloc;
+        ln.z = ln.r + blk;
+        ln.zo = ln.z + blk;
+        ln.p = ln.zo + blk;
+        ln.q = ln.p + blk;
         ln.sc = reinterpret_cast<LaneScalars *>(c.lanes) + k;
         batch_opA(c, F, ln.x, ln.q, s);
         launch_sub<double>(F.nloc, ln.b, ln.q, ln.r, s);
@@ -272,6 +306,14 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
         lanes.push_back(ln);
       }
       c.capture_coarse_iters = std::min(c.opts.coarse_maxit, c.last_coarse_iters + 4);
+    }
+    // lanes of one problem share each operator application and V-cycle when the
+    // context holds work vectors for all of them (SEM_BATCH_JOINT=0: one at a time)
+    std::vector<char> joint(nctx, 0);
+    {
+      const char *j = getenv("SEM_BATCH_JOINT");
+      const bool allow = !(j && j[0] == '0');
+      for (int i = 0; i < nctx; ++i) joint[i] = allow && nrhs > 1 && cs[i]->nvmax >= nrhs;
     }
     // streams for concurrent branches
     BatchStreams bs;
@@ -304,8 +346,16 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
         for (int i = 0; i < nctx; ++i) {
           hipStream_t br = bs.st[i % nbs];
           SEM_HIP(hipStreamWaitEvent(br, bs.fork, 0));
-          for (auto &ln : lanes)
-            if (ln.c == cs[i] && ln.active) lane_iteration(ln, br);
+          Lane *first = &lanes[(size_t)i * nrhs];
+          bool any_active = false;
+          for (int k = 0; k < nrhs; ++k) any_active = any_active || first[k].active;
+          if (!any_active) continue;
+          if (joint[i]) {
+            lane_iteration(first, nrhs, br);  // finished lanes' own kernels return at once
+          } else {
+            for (int k = 0; k < nrhs; ++k)
+              if (first[k].active) lane_iteration(first + k, 1, br);
+          }
         }
         for (int q = 0; q < nbs; ++q) {
           SEM_HIP(hipEventRecord(bs.ev[q], bs.st[q]));

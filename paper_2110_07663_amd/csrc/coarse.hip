@@ -121,11 +121,13 @@ __global__ void k_coarse_to_global(CoarseGrid g, const double *__restrict__ bl,
                                    double *__restrict__ bg, unsigned *bar, int *aborted) {
   int64_t n = g.nx * g.ny * g.nz;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t == 0) {
+  if (t == 0 && blockIdx.y == 0) {
     *bar = 0u;
     *aborted = 0;
   }
   if (t >= n) return;
+  bl += blockIdx.y * (int64_t)g.nex * g.ney * g.nez * 8;  // right side blockIdx.y
+  bg += blockIdx.y * n;
   int64_t x = t % g.nx, y = (t / g.nx) % g.ny, z = t / (g.nx * g.ny);
   int64_t ex = x < g.nex ? x : g.nex - 1, ey = y < g.ney ? y : g.ney - 1,
           ez = z < g.nez ? z : g.nez - 1;
@@ -661,20 +663,15 @@ static void ensure_graph(Ctx &c) {
   SEM_HIP(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
 }
 
-// solve on the coarsest level: C.d_b (consistent, masked E-vector) -> c.cx
-void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s) {
+// one right side: bl (consistent, masked E-vector of the coarsest level) -> xl
+static void coarse_solve_one(Ctx &c, Level &C, double tol, int maxit, hipStream_t s,
+                             const double *bl, double *xl) {
   CoarseSolver &S = *c.cs;
   CoarseGrid g = cgrid(c);
   CgPtrs P = ptrs(c);
-  hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, C.d_b, S.b,
+  hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, bl, S.b,
                      S.counter + 32, &S.sc->aborted);
   SEM_LAUNCH("k_coarse_to_global");
-  if (S.direct) {  // exact: no iteration, no host interaction (also inside a recorded graph)
-    coarse_direct_apply(S, g.nx, g.ny, g.nz, S.b, S.x, s);
-    if (!c.capturing) c.last_coarse_iters = 0;
-    launch_gather(c, C, S.x, c.cx, s);
-    return;
-  }
   if (!c.capturing && S.persistent) {
     GridSync gs;
     gs.count = S.counter + 32;
@@ -692,7 +689,7 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
     if (h->aborted) fail(SEM_EHIP, "coarse-grid solve: a grid barrier timed out");
     c.last_coarse_iters = tol > 0.0 ? h->iters : maxit;
     if (!(h->rr == h->rr)) fail(SEM_ENAN, "NaN in the coarse-grid solve");
-    launch_gather(c, C, S.x, c.cx, s);
+    launch_gather(c, C, S.x, xl, s);
     return;
   }
   hipLaunchKernelGGL(k_cg_start, dim3(cg_grid(S)), dim3(256), 0, s, S.n, P,
@@ -704,7 +701,7 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
     // inside a recorded batch iteration: a fixed count, no readback
     const int k = tol > 0.0 ? std::min(maxit, c.capture_coarse_iters) : maxit;
     enqueue_iterations(c, k, 0, s);
-    launch_gather(c, C, S.x, c.cx, s);
+    launch_gather(c, C, S.x, xl, s);
     return;
   }
   if (tol <= 0.0 || !S.use_graph) {
@@ -747,7 +744,27 @@ void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t
   if (tol > 0.0) c.last_coarse_iters = h->iters;
   else c.last_coarse_iters = maxit;
   if (!(h->rr == h->rr)) fail(SEM_ENAN, "NaN in the coarse-grid solve");
-  launch_gather(c, C, S.x, c.cx, s);
+  launch_gather(c, C, S.x, xl, s);
+}
+
+// solve on the coarsest level for nv right sides: C.d_b (consistent, masked
+// E-vectors, nloc apart) -> c.cx.  The exact solve takes all right sides in one
+// pair of sweeps; the iterative one solves them in turn.
+void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv) {
+  CoarseSolver &S = *c.cs;
+  if (nv > c.nvmax) fail(SEM_EINVAL, "coarse solve: more right sides than were set up");
+  if (S.direct) {  // exact: no iteration, no host interaction (also inside a recorded graph)
+    CoarseGrid g = cgrid(c);
+    hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n), (unsigned)nv), dim3(256), 0, s, g, C.d_b,
+                       S.b, S.counter + 32, &S.sc->aborted);
+    SEM_LAUNCH("k_coarse_to_global");
+    coarse_direct_apply(S, g.nx, g.ny, g.nz, S.b, S.x, s, nv);
+    if (!c.capturing) c.last_coarse_iters = 0;
+    launch_gather(c, C, S.x, c.cx, s, nv, S.n);
+    return;
+  }
+  for (int v = 0; v < nv; ++v)
+    coarse_solve_one(c, C, tol, maxit, s, C.d_b + v * C.nloc, c.cx + v * C.nloc);
 }
 
 void coarse_release(CoarseSolver &S) {

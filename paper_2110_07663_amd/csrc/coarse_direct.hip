@@ -21,6 +21,8 @@
 // 32 (identity / zero padding).  A solve reads each block once: 3 K Mp^2 * 8
 // bytes, in 2K dependent matrix-vector products with no host interaction, so
 // it can be recorded into a graph.
+#include <algorithm>
+
 #include "sem_internal.h"
 
 namespace sem {
@@ -204,49 +206,65 @@ __global__ void k_bt_transpose(int Mp, const double *__restrict__ H, double *__r
 
 // ---- solve kernel -------------------------------------------------------------
 
-// out = c + s1 * (M1 v1) - (M2 v2), one wavefront per row (rows < m)
+// out = c + s1 * (M1 v1) - (M2 v2) for NV right sides (vectors vs apart in v1,
+// v2, c and out), one wavefront per row (rows < m): the matrix rows are read
+// once for all right sides.  Each right side is summed in the same order for
+// any NV (four strided partial sums per lane, then the wave reduction).
+template <int NV>
 __global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, const double *__restrict__ M1,
                                                const double *__restrict__ v1, double s1,
                                                const double *__restrict__ M2,
                                                const double *__restrict__ v2,
                                                const double *__restrict__ c,
-                                               double *__restrict__ out) {
+                                               double *__restrict__ out, int64_t vs) {
   const int row = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= m) return;  // whole wave
-  // four independent partial sums per lane keep 8 loads in flight
-  const double *r1 = M1 + (int64_t)row * Mp;
-  double a1 = 0.0, a2 = 0.0;
-  {
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  double a1[NV], a2[NV];
+  // four independent partial sums per lane and right side keep the loads in flight
+  auto rowdot = [&](const double *__restrict__ r, const double *__restrict__ x, double *acc) {
+    double t[NV][4];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v][0] = t[v][1] = t[v][2] = t[v][3] = 0.0;
     int j = lane;
     for (; j + 192 < m; j += 256) {
-      t0 += r1[j] * v1[j];
-      t1 += r1[j + 64] * v1[j + 64];
-      t2 += r1[j + 128] * v1[j + 128];
-      t3 += r1[j + 192] * v1[j + 192];
+      const double r0 = r[j], r1 = r[j + 64], r2 = r[j + 128], r3 = r[j + 192];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double *xv = x + v * vs;
+        t[v][0] += r0 * xv[j];
+        t[v][1] += r1 * xv[j + 64];
+        t[v][2] += r2 * xv[j + 128];
+        t[v][3] += r3 * xv[j + 192];
+      }
     }
-    for (; j < m; j += 64) t0 += r1[j] * v1[j];
-    a1 = (t0 + t1) + (t2 + t3);
-  }
+    for (; j < m; j += 64) {
+      const double r0 = r[j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) t[v][0] += r0 * x[v * vs + j];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = (t[v][0] + t[v][1]) + (t[v][2] + t[v][3]);
+  };
+  rowdot(M1 + (int64_t)row * Mp, v1, a1);
   if (M2) {
-    const double *r2 = M2 + (int64_t)row * Mp;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    int j = lane;
-    for (; j + 192 < m; j += 256) {
-      t0 += r2[j] * v2[j];
-      t1 += r2[j + 64] * v2[j + 64];
-      t2 += r2[j + 128] * v2[j + 128];
-      t3 += r2[j + 192] * v2[j + 192];
-    }
-    for (; j < m; j += 64) t0 += r2[j] * v2[j];
-    a2 = (t0 + t1) + (t2 + t3);
+    rowdot(M2 + (int64_t)row * Mp, v2, a2);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a2[v] = 0.0;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    a1 += __shfl_xor(a1, o, 64);
-    a2 += __shfl_xor(a2, o, 64);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      a1[v] += __shfl_xor(a1[v], o, 64);
+      a2[v] += __shfl_xor(a2[v], o, 64);
+    }
   }
-  if (lane == 0) out[row] = (c ? c[row] : 0.0) + s1 * a1 - a2;
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      out[v * vs + row] = (c ? c[v * vs + row] : 0.0) + s1 * a1[v] - a2[v];
+  }
 }
 
 // ---- host side -------------------------------------------------------------------
@@ -293,30 +311,45 @@ void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hi
   S.direct = flag == 0;
 }
 
-void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
-                         double *x, hipStream_t s) {
-  const int m = (int)(nx * ny), K = (int)nz;
-  const int Mp = (int)padded(m);
-  const int64_t M2 = (int64_t)Mp * Mp;
+template <int NV>
+static void bt_sweeps(const CoarseSolver &S, int m, int K, int Mp, const double *b, double *x,
+                      double *y, hipStream_t s) {
+  const int64_t M2 = (int64_t)Mp * Mp, vs = S.n;
   const unsigned grid = (unsigned)((m + 3) / 4);
-  double *y = S.dy;
-  launch_copy<double>(m, b, y, s);
-  for (int k = 1; k < K; ++k) {
-    hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dH + k * M2,
+  for (int v = 0; v < NV; ++v) launch_copy<double>(m, b + v * vs, y + v * vs, s);
+  for (int k = 1; k < K; ++k) {  // y_k = b_k - H_k y_{k-1}
+    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dH + k * M2,
                        (const double *)(y + (int64_t)(k - 1) * m), -1.0, (const double *)nullptr,
-                       (const double *)nullptr, b + (int64_t)k * m, y + (int64_t)k * m);
+                       (const double *)nullptr, b + (int64_t)k * m, y + (int64_t)k * m, vs);
     SEM_LAUNCH("k_bt_mv");
   }
-  hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + (K - 1) * M2,
+  // x_{K-1} = G_{K-1} y_{K-1}; x_k = G_k y_k - J_k x_{k+1}
+  hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + (K - 1) * M2,
                      (const double *)(y + (int64_t)(K - 1) * m), 1.0, (const double *)nullptr,
-                     (const double *)nullptr, (const double *)nullptr, x + (int64_t)(K - 1) * m);
+                     (const double *)nullptr, (const double *)nullptr, x + (int64_t)(K - 1) * m,
+                     vs);
   SEM_LAUNCH("k_bt_mv");
   for (int k = K - 2; k >= 0; --k) {
-    hipLaunchKernelGGL(k_bt_mv, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + k * M2,
+    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + k * M2,
                        (const double *)(y + (int64_t)k * m), 1.0, (const double *)(S.dJ + k * M2),
                        (const double *)(x + (int64_t)(k + 1) * m), (const double *)nullptr,
-                       x + (int64_t)k * m);
+                       x + (int64_t)k * m, vs);
     SEM_LAUNCH("k_bt_mv");
+  }
+}
+
+void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
+                         double *x, hipStream_t s, int nv) {
+  const int m = (int)(nx * ny), K = (int)nz;
+  const int Mp = (int)padded(m);
+  for (int v0 = 0; v0 < nv; v0 += 4) {  // up to four right sides per sweep
+    const int64_t o = (int64_t)v0 * S.n;
+    switch (std::min(4, nv - v0)) {
+      case 1: bt_sweeps<1>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      case 2: bt_sweeps<2>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      case 3: bt_sweeps<3>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      default: bt_sweeps<4>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+    }
   }
 }
 

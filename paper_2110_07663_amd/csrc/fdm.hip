@@ -197,14 +197,17 @@ __device__ inline float fdm_inv<float>(float d) {
 template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
-    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
+    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z, int nv) {
   using F = FdmShape<P>;
   constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
   constexpr int N3 = N * N * N, PB2 = PB * PB;
   __shared__ T buf0[PB * PS];
   __shared__ T buf1[PB * PS];
 
-  const int64_t e = xcd_block();
+  int vec;
+  const int64_t e = split_rhs(xcd_block(), nv, vec);
+  r += (int64_t)vec * E * N3;
+  z += (int64_t)vec * E * N3;
   const int tid = threadIdx.x;
   const int a = tid % PB, b = tid / PB;
   const bool act = tid < PB2;
@@ -348,14 +351,17 @@ struct FdmLines {
 template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
     int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
-    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z) {
+    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z, int nv) {
   using F = FdmLines<P>;
   constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
   constexpr int N3 = N * N * N, PB2 = PB * PB;
   __shared__ T buf0[PB * PS];
   __shared__ T buf1[PB * PS];
 
-  const int64_t e = xcd_block();
+  int vec;
+  const int64_t e = split_rhs(xcd_block(), nv, vec);
+  r += (int64_t)vec * E * N3;
+  z += (int64_t)vec * E * N3;
   const int tid = threadIdx.x;
   const bool act = tid < PB2;
   const int lo = tid % PB, hi = tid / PB;  // the two free box indices of this thread's line
@@ -551,18 +557,20 @@ template void launch_asm_sum<float>(const Ctx &, const Level &, const float *, f
 
 template <int P, typename T, bool ASM>
 static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *S, const T *lam,
-                       const T *W, T *out, hipStream_t s) {
+                       const T *W, T *out, hipStream_t s, int nv) {
+  const dim3 grid((unsigned)(L.E * nv));
   if (FdmLines<P>::PB * FdmLines<P>::PB > 64 && c.fdm_lines)
-    hipLaunchKernelGGL((k_fdm_lines<P, T, ASM>), dim3((unsigned)L.E), dim3(FdmLines<P>::BS), 0, s,
-                       L.E, c.nex, c.ney, c.nez, r, S, lam, W, out);
+    hipLaunchKernelGGL((k_fdm_lines<P, T, ASM>), grid, dim3(FdmLines<P>::BS), 0, s, L.E, c.nex,
+                       c.ney, c.nez, r, S, lam, W, out, nv);
   else
-    hipLaunchKernelGGL((k_fdm<P, T, ASM>), dim3((unsigned)L.E), dim3(FdmShape<P>::BS), 0, s, L.E,
-                       c.nex, c.ney, c.nez, r, S, lam, W, out);
+    hipLaunchKernelGGL((k_fdm<P, T, ASM>), grid, dim3(FdmShape<P>::BS), 0, s, L.E, c.nex, c.ney,
+                       c.nez, r, S, lam, W, out, nv);
   SEM_LAUNCH("k_fdm");
 }
 
 template <typename T, int P>
-static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
+static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
+                  int nv) {
   const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
   const T *lam = sizeof(T) == 8 ? (const T *)L.lam64 : (const T *)L.lam32;
   const T *W = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
@@ -570,31 +578,34 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
   if (asm_mode) {
     T *box = sizeof(T) == 8 ? (T *)L.box64 : (T *)L.box32;
     if (!box) fail(SEM_EINVAL, "ASM box buffer was not built");
-    fdm_launch<P, T, true>(c, L, r, S, lam, W, box, s);
-    launch_asm_sum<T>(c, L, box, z, s);
+    for (int k = 0; k < nv; ++k) {  // one box buffer: right sides in turn
+      fdm_launch<P, T, true>(c, L, r + k * L.nloc, S, lam, W, box, s, 1);
+      launch_asm_sum<T>(c, L, box, z + k * L.nloc, s);
+    }
     return;
   }
-  fdm_launch<P, T, false>(c, L, r, S, lam, W, z, s);
+  fdm_launch<P, T, false>(c, L, r, S, lam, W, z, s, nv);
 }
 
 template <typename T>
-void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s) {
+void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
+                int nv) {
   switch (L.p) {
-    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s); break;
-    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s); break;
-    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s); break;
-    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s); break;
-    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s); break;
-    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s); break;
-    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s); break;
-    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s); break;
-    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s); break;
+    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s, nv); break;
+    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s, nv); break;
+    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s, nv); break;
+    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s, nv); break;
+    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s, nv); break;
+    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s, nv); break;
+    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s, nv); break;
+    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s, nv); break;
+    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s, nv); break;
     default: fail(SEM_EUNSUPPORTED, "FDM: unsupported degree");
   }
 }
 template void launch_fdm<double>(const Ctx &, const Level &, const double *, double *, bool,
-                                 hipStream_t);
+                                 hipStream_t, int);
 template void launch_fdm<float>(const Ctx &, const Level &, const float *, float *, bool,
-                                hipStream_t);
+                                hipStream_t, int);
 
 }  // namespace sem

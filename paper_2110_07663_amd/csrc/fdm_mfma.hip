@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
                                                   const float *__restrict__ sscale,
                                                   const float *__restrict__ lam,
                                                   const float *__restrict__ W,
-                                                  float *__restrict__ z) {
+                                                  float *__restrict__ z, int nv) {
   using M = Mma<BF>;
   using frag = typename M::frag;
   constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
@@ -109,8 +109,11 @@ __global__ __launch_bounds__(256) void k_fdm_mfma(int64_t E, int nex, int ney, i
   __shared__ float sl[WAVES][3][PB];
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t e = (int64_t)xcd_block() * WAVES + wave;
+  int vec;
+  const int64_t e = (int64_t)split_rhs(xcd_block(), nv, vec) * WAVES + wave;
   if (e >= E) return;  // whole wave leaves; no block-wide barriers below
+  r += (int64_t)vec * E * N3;  // right side vec (RAS: output E-vectors nloc apart)
+  z += (int64_t)vec * E * N3;
   float *X = buf[wave][0];
   float *Y = buf[wave][1];
 
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                    const float *__restrict__ sscale,
                                                    const float *__restrict__ lam,
                                                    const float *__restrict__ W,
-                                                   float *__restrict__ z) {
+                                                   float *__restrict__ z, int nv) {
   using M = Mma<BF>;
   using frag = typename M::frag;
   constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
@@ -254,8 +257,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   __shared__ uint16_t lds[WAVES * BUF];
   
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)xcd_block() * WAVES + wave;
+  int vec;
+  const int64_t e = (int64_t)split_rhs(xcd_block(), nv, vec) * WAVES + wave;
   if (e >= E) return;  // whole wave leaves; no block-wide barriers below
+  r += (int64_t)vec * E * N3;  // right side vec (RAS: output E-vectors nloc apart)
+  z += (int64_t)vec * E * N3;
   uint16_t *buf = lds + wave * BUF;
   const int g = lane >> 4, t = lane & 15;
 
@@ -429,9 +435,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
 template <int P>
 static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, bool bf,
-                       bool asm_mode, hipStream_t s) {
+                       bool asm_mode, hipStream_t s, int nv) {
   const float *sscale = L.sscale;
-  unsigned grid = (unsigned)((L.E + 3) / 4);
+  if (asm_mode && nv > 1) {  // one box buffer: right sides in turn
+    for (int k = 0; k < nv; ++k) fdm_mfma_p<P>(c, L, r + k * L.nloc, z + k * L.nloc, bf, true, s, 1);
+    return;
+  }
+  unsigned grid = (unsigned)((L.E + 3) / 4 * nv);
   float *out = z;
   if (asm_mode) {
     if (!L.box32) fail(SEM_EINVAL, "ASM box buffer was not built");
@@ -441,10 +451,10 @@ static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, b
   do {                                                                                            \
     if (c.fdm_mfma1)                                                                              \
       hipLaunchKernelGGL((k_fdm_mfma<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex,      \
-                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out);                     \
+                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out, nv);                 \
     else                                                                                          \
       hipLaunchKernelGGL((k_fdm_mfma2<P, BFV, ASMV>), dim3(grid), dim3(256), 0, s, L.E, c.nex,     \
-                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out);                     \
+                         c.ney, c.nez, r, L.S16, sscale, L.lam32, L.w32, out, nv);                 \
   } while (0)
   if (bf && asm_mode) SEM_MFMA_LAUNCH(true, true);
   else if (bf) SEM_MFMA_LAUNCH(true, false);
@@ -457,7 +467,7 @@ static void fdm_mfma_p(const Ctx &c, const Level &L, const float *r, float *z, b
 
 // prec < 0: pack the 16-bit factors at setup; otherwise apply (RAS only)
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
-                     int prec, hipStream_t s) {
+                     int prec, hipStream_t s, int nv) {
   if (!L.S16 || !L.S32) fail(SEM_EINVAL, "16-bit FDM data were not built");
   const bool bf = (prec < 0 ? c.fdm_prec : prec) == SEM_BF16;
   if (prec < 0) {
@@ -469,15 +479,15 @@ void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, boo
     return;
   }
   switch (L.p) {
-    case 2: fdm_mfma_p<2>(c, L, r, z, bf, asm_mode, s); break;
-    case 3: fdm_mfma_p<3>(c, L, r, z, bf, asm_mode, s); break;
-    case 4: fdm_mfma_p<4>(c, L, r, z, bf, asm_mode, s); break;
-    case 5: fdm_mfma_p<5>(c, L, r, z, bf, asm_mode, s); break;
-    case 6: fdm_mfma_p<6>(c, L, r, z, bf, asm_mode, s); break;
-    case 7: fdm_mfma_p<7>(c, L, r, z, bf, asm_mode, s); break;
-    case 8: fdm_mfma_p<8>(c, L, r, z, bf, asm_mode, s); break;
-    case 9: fdm_mfma_p<9>(c, L, r, z, bf, asm_mode, s); break;
-    case 10: fdm_mfma_p<10>(c, L, r, z, bf, asm_mode, s); break;
+    case 2: fdm_mfma_p<2>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 3: fdm_mfma_p<3>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 4: fdm_mfma_p<4>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 5: fdm_mfma_p<5>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 6: fdm_mfma_p<6>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 7: fdm_mfma_p<7>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 8: fdm_mfma_p<8>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 9: fdm_mfma_p<9>(c, L, r, z, bf, asm_mode, s, nv); break;
+    case 10: fdm_mfma_p<10>(c, L, r, z, bf, asm_mode, s, nv); break;
     default: fail(SEM_EUNSUPPORTED, "MFMA FDM: unsupported degree");
   }
 }

@@ -170,9 +170,11 @@ __global__ void k_fill1(int64_t n, double *w64, float *w32) {
 }
 
 __global__ void k_gather(GridInfo g, int64_t nloc, const double *__restrict__ ug,
-                         double *__restrict__ ul) {
+                         double *__restrict__ ul, int64_t ug_stride) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nloc) return;
+  ug += blockIdx.y * ug_stride;  // right side blockIdx.y
+  ul += blockIdx.y * nloc;
   int64_t gx, gy, gz;
   global_coords(g, t, gx, gy, gz);
   ul[t] = ug[(gz * g.ny + gy) * g.nx + gx];
@@ -293,6 +295,7 @@ __global__ void k_gs_dir(T *__restrict__ v, GsGrid g, int64_t E) {
   const int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   const int N = g.N, N2 = N * N;
   if (t >= E * N2) return;
+  v += blockIdx.y * E * N2 * N;  // right side blockIdx.y
   const unsigned ut = (unsigned)t;  // E * N^2 < 2^31
   const int64_t e = ut / (unsigned)N2;
   const int rem = (int)(ut - (unsigned)e * (unsigned)N2);
@@ -329,12 +332,12 @@ __global__ void k_gs_dir(T *__restrict__ v, GsGrid g, int64_t E) {
 }
 
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s) {
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv) {
   if (L.gs_struct) {
     GsGrid g;
     g.nex = L.nex; g.ney = L.ney; g.nez = L.nez; g.p = L.p; g.N = L.N;
     for (int f = 0; f < 6; ++f) g.bc[f] = L.bc[f];
-    const unsigned grid = nb(L.E * L.N * L.N, 256);
+    const dim3 grid(nb(L.E * L.N * L.N, 256), (unsigned)nv);
     hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
     SEM_LAUNCH("k_gs_dir");
     hipLaunchKernelGGL((k_gs_dir<T, 1>), dim3(grid), dim3(256), 0, s, v, g, L.E);
@@ -344,11 +347,14 @@ void launch_gs(const Level &L, T *v, hipStream_t s) {
     return;
   }
   if (L.nseg == 0) return;
-  hipLaunchKernelGGL(k_gs<T>, dim3(nb(L.nseg, 256)), dim3(256), 0, s, v, L.perm, L.off, L.nseg);
-  SEM_LAUNCH("k_gs");
+  for (int k = 0; k < nv; ++k) {
+    hipLaunchKernelGGL(k_gs<T>, dim3(nb(L.nseg, 256)), dim3(256), 0, s, v + k * L.nloc, L.perm,
+                       L.off, L.nseg);
+    SEM_LAUNCH("k_gs");
+  }
 }
-template void launch_gs<double>(const Level &, double *, hipStream_t);
-template void launch_gs<float>(const Level &, float *, hipStream_t);
+template void launch_gs<double>(const Level &, double *, hipStream_t, int);
+template void launch_gs<float>(const Level &, float *, hipStream_t, int);
 
 void launch_weights(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_fill1, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, L.w64, L.w32);
@@ -359,9 +365,11 @@ void launch_weights(const Level &L, hipStream_t s) {
   SEM_LAUNCH("k_weights");
 }
 
-void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s) {
+void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s,
+                   int nv, int64_t ug_stride) {
   GridInfo g = grid_of(c, L);
-  hipLaunchKernelGGL(k_gather, dim3(nb(L.nloc, 256)), dim3(256), 0, s, g, L.nloc, ug, ul);
+  hipLaunchKernelGGL(k_gather, dim3(nb(L.nloc, 256), (unsigned)nv), dim3(256), 0, s, g, L.nloc,
+                     ug, ul, ug_stride);
   SEM_LAUNCH("k_gather");
 }
 

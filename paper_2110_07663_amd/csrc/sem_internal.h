@@ -50,6 +50,17 @@ __device__ inline unsigned xcd_block() {
   const unsigned x = b & 7u, q = b >> 3, per = nb >> 3, rem = nb & 7u;
   return x * per + (x < rem ? x : rem) + q;
 }
+// Launches over nv right sides (vectors nloc apart) run nv logical blocks per
+// element group, consecutive so that they share an XCD and its L2: logical
+// block q is element group q / nv of right side q % nv.
+__device__ inline unsigned split_rhs(unsigned q, int nv, int &vec) {
+  if (nv == 1) {
+    vec = 0;
+    return q;
+  }
+  vec = (int)(q % (unsigned)nv);
+  return q / (unsigned)nv;
+}
 constexpr int kMaxRestart = 64;
 
 // ---------------------------------------------------------------------------
@@ -209,8 +220,13 @@ struct Ctx {
   int capture_coarse_iters = 0;
   // batched-solve lanes: per right side r, z, z_old, p, q (FP64) and scalars
   int nlanes = 0;
-  double *lanev = nullptr;
+  double *lanev = nullptr;           // [5][nlanes][nloc]: r, z, z_old, p, q of every lane
   void *lanes = nullptr;
+  double *lpartials = nullptr;       // [nlanes][kRedBlocks][8] lane reductions
+  unsigned *lcounter = nullptr;      // [nlanes][16] last-block counters
+  // level work vectors (and the coarse solve's vectors) hold nvmax right sides,
+  // so the lanes of a batched solve share one V-cycle (nvmax = nlanes), else 1
+  int nvmax = 1;
   CoarseSolver coarse_store;
   CoarseSolver *cs = nullptr;      // set when the coarsest level is p = 1 (assembled solve)
   // Arnoldi basis (FP64, largest level)
@@ -240,15 +256,17 @@ void launch_rhs(const Level &L, const double *f, double *b, hipStream_t s);
 // numbering.hip
 size_t gs_sort_temp_bytes(int64_t nloc);
 void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s);
-void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s);
+void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s,
+                   int nv = 1, int64_t ug_stride = 0);
+// nv > 1: nv vectors nloc apart (several right sides of one problem)
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s);
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1);
 void launch_weights(const Level &L, hipStream_t s);
 void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s);
 
 // ax.hip
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s);
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv = 1);
 void launch_diag(const Level &L, double *d, hipStream_t s);
 
 // blas.hip
@@ -288,28 +306,31 @@ void launch_cpcg_iteration(const Ctx &c, const Level &L, bool first, hipStream_t
 
 // transfer.hip
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s);
+void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s, int nv = 1);
 template <typename T>
-void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s);
+void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s,
+                     int nv = 1);
 
 // fdm.hip
 void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s);
 template <typename T>
-void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s);
+void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
+                int nv = 1);
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
-                     int prec, hipStream_t s);
+                     int prec, hipStream_t s, int nv = 1);
 template <typename T>
 void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_t s);
 
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);
 void coarse_setup(Ctx &c, Level &C, hipStream_t s);
-void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s);
+void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv = 1);
 void coarse_release(CoarseSolver &S);
 size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz);
 void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s);
+// nv right sides, S.n apart in b, x and the work vector S.dy
 void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
-                         double *x, hipStream_t s);
+                         double *x, hipStream_t s, int nv = 1);
 
 // hessenberg.cpp
 double hessenberg_max_abs_eig(const double *H, int ldh, int k);

@@ -108,6 +108,14 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   const bool lowp = c.lowp;
   const bool schwarz = o.precond == SEM_PRECOND_PMG && o.smoother != SEM_SMOOTH_JACOBI;
   const bool asm_on = schwarz && o.smoother == SEM_SMOOTH_ASM;
+  // batch lanes share one V-cycle when the hierarchy ends in the assembled
+  // p = 1 solve: every level's work vectors then hold all lanes
+  c.nlanes = std::max(0, o.batch_rhs);
+  c.nvmax = (c.nlanes > 1 && o.precond == SEM_PRECOND_PMG && c.nlev > 1 &&
+             c.lev[c.nlev - 1].p == 1)
+                ? c.nlanes
+                : 1;
+  const size_t nv = (size_t)c.nvmax;
   for (int l = 0; l < c.nlev; ++l) {
     Level &L = c.lev[l];
     const bool smoothed = !L.coarse;
@@ -147,19 +155,22 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
         if (lowp) L.box32 = A.take<float>(L.E * pb * pb * pb);
       }
     }
-    L.d_b = A.take<double>(L.nloc);
-    L.d_x = A.take<double>(L.nloc);
-    L.d_r = A.take<double>(L.nloc);
-    L.d_d = A.take<double>(L.nloc);
-    L.d_w = A.take<double>(L.nloc);
-    L.d_t = A.take<double>(L.nloc);
+    // FP64 work vectors: every right side where the V-cycle runs in FP64 (and
+    // on the coarsest level, whose solve is FP64), else one
+    const size_t nd = (!lowp || L.coarse) ? nv : 1;
+    L.d_b = A.take<double>(nd * L.nloc);
+    L.d_x = A.take<double>(nd * L.nloc);
+    L.d_r = A.take<double>(nd * L.nloc);
+    L.d_d = A.take<double>(nd * L.nloc);
+    L.d_w = A.take<double>(nd * L.nloc);
+    L.d_t = A.take<double>(nd * L.nloc);
     if (lowp) {
-      L.f_b = A.take<float>(L.nloc);
-      L.f_x = A.take<float>(L.nloc);
-      L.f_r = A.take<float>(L.nloc);
-      L.f_d = A.take<float>(L.nloc);
-      L.f_w = A.take<float>(L.nloc);
-      L.f_t = A.take<float>(L.nloc);
+      L.f_b = A.take<float>(nv * L.nloc);
+      L.f_x = A.take<float>(nv * L.nloc);
+      L.f_r = A.take<float>(nv * L.nloc);
+      L.f_d = A.take<float>(nv * L.nloc);
+      L.f_w = A.take<float>(nv * L.nloc);
+      L.f_t = A.take<float>(nv * L.nloc);
     }
   }
   c.partials = A.take<double>(kRedBlocks * 8);
@@ -178,7 +189,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     c.gZ = A.take<double>((size_t)o.gmres_restart * F.nloc);
   }
   const Level &C = c.lev[c.nlev - 1];
-  c.cx = A.take<double>(C.nloc);
+  c.cx = A.take<double>(nv * C.nloc);
   c.cr = A.take<double>(C.nloc);
   c.cz = A.take<double>(C.nloc);
   c.cp = A.take<double>(C.nloc);
@@ -186,10 +197,11 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   if (o.precond == SEM_PRECOND_PMG && c.nlev > 1)
     c.av = A.take<double>((size_t)(o.arnoldi_steps + 1) * F.nloc);
   // batched-solve lanes
-  c.nlanes = std::max(0, o.batch_rhs);
   if (c.nlanes > 0) {
     c.lanev = A.take<double>((size_t)c.nlanes * 5 * F.nloc);
     c.lanes = A.take<char>((size_t)c.nlanes * 128);
+    c.lpartials = A.take<double>((size_t)c.nlanes * kRedBlocks * 8);
+    c.lcounter = A.take<unsigned>((size_t)c.nlanes * 16);
   }
   // assembled coarse solve when the coarsest level is p = 1
   c.cs = nullptr;
@@ -199,8 +211,8 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     S.St = A.take<double>(27 * S.n);
     S.dinv = A.take<double>(S.n);
     S.Ae = A.take<double>(64 * C.E);
-    S.b = A.take<double>(S.n);
-    S.x = A.take<double>(S.n);
+    S.b = A.take<double>(nv * S.n);
+    S.x = A.take<double>(nv * S.n);
     S.r = A.take<double>(S.n);
     S.u = A.take<double>(S.n);
     S.w = A.take<double>(S.n);
@@ -223,7 +235,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
         S.dG = A.take<double>((size_t)(nz * Mp * Mp));
         S.dH = A.take<double>((size_t)(nz * Mp * Mp));
         S.dJ = A.take<double>((size_t)(nz * Mp * Mp));
-        S.dy = A.take<double>((size_t)std::max<int64_t>(S.n, Mp));  // also the pivot-test diagonal
+        S.dy = A.take<double>(std::max<size_t>(nv * S.n, Mp));  // also the pivot-test diagonal
         S.dflag = A.take<int>(64);
         S.direct = true;  // until the setup finds the level singular
       }
@@ -362,25 +374,26 @@ struct ProfScope {
   }
 };
 
+// nv right sides, nloc apart (batch lanes sharing a V-cycle); 1 otherwise
 template <typename T>
-static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s) {
+static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv = 1) {
   {
     ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_AX64 : SEM_PROF_AX32, s);
-    launch_ax<T>(L, u, Au, s);
+    launch_ax<T>(L, u, Au, s, nv);
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, Au, s);
+  launch_gs<T>(L, Au, s, nv);
 }
 
 template <typename T>
-static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
+static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1) {
   const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
   const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
   if (!schwarz) {
     const T *dinv = Vec<T>::dinv(L);
     if (!dinv) fail(SEM_EINVAL, "Jacobi data of this precision were not built");
-    launch_scale<T>(L.nloc, dinv, r, z, s);
+    for (int k = 0; k < nv; ++k) launch_scale<T>(L.nloc, dinv, r + k * L.nloc, z + k * L.nloc, s);
     return;
   }
   {
@@ -388,40 +401,42 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s) {
     bool mma = false;
     if constexpr (sizeof(T) == 4) {
       if (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16) {
-        launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s);
+        launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s, nv);
         mma = true;
       }
     }
-    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s);
+    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv);
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, z, s);
+  launch_gs<T>(L, z, s, nv);
 }
 
 // Algorithm 2 read as a correction: x <- x + e (x_zero: x <- e)
 template <typename T>
-static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hipStream_t s) {
+static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hipStream_t s,
+                      int nv = 1) {
   T *r = Vec<T>::r(L), *d = Vec<T>::d(L), *w = Vec<T>::w(L), *t = Vec<T>::t(L);
   const double theta = 0.5 * (L.lmax + L.lmin), delta = 0.5 * (L.lmax - L.lmin);
   const double sigma = theta / delta;
+  const int64_t n = L.nloc * nv;  // the vector updates are pointwise over all right sides
   double rho = 1.0 / sigma;
   if (x_zero) {
-    opS<T>(c, L, b, r, s);
+    opS<T>(c, L, b, r, s, nv);
   } else {
-    opA<T>(c, L, x, w, s);
-    launch_sub<T>(L.nloc, b, w, w, s);
-    opS<T>(c, L, w, r, s);
+    opA<T>(c, L, x, w, s, nv);
+    launch_sub<T>(n, b, w, w, s);
+    opS<T>(c, L, w, r, s, nv);
   }
-  launch_cheb_init<T>(L.nloc, x, r, d, (T)(1.0 / theta), x_zero, s);
+  launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), x_zero, s);
   for (int k = 0; k < L.K; ++k) {
-    opA<T>(c, L, d, w, s);
-    opS<T>(c, L, w, t, s);
+    opA<T>(c, L, d, w, s, nv);
+    opS<T>(c, L, w, t, s, nv);
     double rho_new = 1.0 / (2.0 * sigma - rho);
-    launch_cheb_update<T>(L.nloc, x, r, d, t, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
+    launch_cheb_update<T>(n, x, r, d, t, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
     rho = rho_new;
   }
-  launch_axpby<T>(L.nloc, (T)1, d, (T)1, x, s);
+  launch_axpby<T>(n, (T)1, d, (T)1, x, s);
 }
 
 static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
@@ -430,14 +445,15 @@ static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
 }
 
 // coarse Jacobi-PCG from x = 0: C.d_b -> c.cx (all scalars on the device)
-static void coarse_solve(Ctx &c, Level &C, hipStream_t s) {
+static void coarse_solve(Ctx &c, Level &C, hipStream_t s, int nv = 1) {
   const double tol = c.opts.coarse_tol;
   const int maxit = c.opts.coarse_maxit;
   ProfScope ps(c, C, SEM_PROF_COARSE, s);
   if (coarse_assembled_ok(c, C)) {
-    coarse_solve_assembled(c, C, tol, maxit, s);
+    coarse_solve_assembled(c, C, tol, maxit, s, nv);
     return;
   }
+  if (nv != 1) fail(SEM_EUNSUPPORTED, "several right sides need the assembled p = 1 coarse solve");
   DevScalars init{};
   init.tol2 = tol * tol;
   init.maxit = maxit;
@@ -474,51 +490,55 @@ static void coarse_solve(Ctx &c, Level &C, hipStream_t s) {
 
 // one V-cycle of Algorithm 1 from x = 0 on level l (levels l.. in precision T)
 template <typename T>
-static void vcycle_level(Ctx &c, int l, hipStream_t s) {
+static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1) {
   Level &L = c.lev[l];
+  const int64_t n = L.nloc * nv;
   if (L.coarse) {
-    if constexpr (sizeof(T) == 4) launch_copy_cvt_f2d(L.nloc, L.f_b, L.d_b, s);
-    coarse_solve(c, L, s);
+    if constexpr (sizeof(T) == 4) launch_copy_cvt_f2d(n, L.f_b, L.d_b, s);
+    coarse_solve(c, L, s, nv);
     if constexpr (sizeof(T) == 4)
-      launch_copy_cvt_d2f(L.nloc, c.cx, L.f_x, s);
+      launch_copy_cvt_d2f(n, c.cx, L.f_x, s);
     else
-      launch_copy<double>(L.nloc, c.cx, L.d_x, s);
+      launch_copy<double>(n, c.cx, L.d_x, s);
     return;
   }
   Level &C = c.lev[l + 1];
   T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *r = Vec<T>::r(L), *w = Vec<T>::w(L);
-  chebyshev<T>(c, L, b, x, true, s);                    // x = M b
-  opA<T>(c, L, x, w, s);                                // r = b - A x
-  launch_sub<T>(L.nloc, b, w, r, s);
-  launch_restrict<T>(L, C, r, Vec<T>::b(C), s);         // r_C = P^T r
-  launch_gs<T>(C, Vec<T>::b(C), s);
-  vcycle_level<T>(c, l + 1, s);                         // e_C
-  launch_prolong<T>(L, C, Vec<T>::x(C), x, s);          // x += P e_C
-  chebyshev<T>(c, L, b, x, false, s);                   // post-smoothing
+  chebyshev<T>(c, L, b, x, true, s, nv);                // x = M b
+  opA<T>(c, L, x, w, s, nv);                            // r = b - A x
+  launch_sub<T>(n, b, w, r, s);
+  launch_restrict<T>(L, C, r, Vec<T>::b(C), s, nv);     // r_C = P^T r
+  launch_gs<T>(C, Vec<T>::b(C), s, nv);
+  vcycle_level<T>(c, l + 1, s, nv);                     // e_C
+  launch_prolong<T>(L, C, Vec<T>::x(C), x, s, nv);      // x += P e_C
+  chebyshev<T>(c, L, b, x, false, s, nv);               // post-smoothing
 }
 
-// z = M r on the finest level, FP64 in and out
-static void precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
+// z = M r on the finest level, FP64 in and out; nv right sides nloc apart
+static void precondition(Ctx &c, const double *r, double *z, hipStream_t s, int nv = 1) {
   Level &F = c.lev[0];
   ProfScope ps(c, F, SEM_PROF_VCYCLE, s);
+  if (nv < 1 || nv > c.nvmax) fail(SEM_EINVAL, "preconditioner: more right sides than were set up");
+  const int64_t n = F.nloc * nv;
   if (c.opts.precond == SEM_PRECOND_JACOBI) {
-    launch_scale<double>(F.nloc, F.dinv64, r, z, s);
+    for (int k = 0; k < nv; ++k)
+      launch_scale<double>(F.nloc, F.dinv64, r + k * F.nloc, z + k * F.nloc, s);
     return;
   }
   if (F.coarse) {  // single-level schedule: the coarse solve itself, in FP64
-    launch_copy<double>(F.nloc, r, F.d_b, s);
-    coarse_solve(c, F, s);
-    launch_copy<double>(F.nloc, c.cx, z, s);
+    launch_copy<double>(n, r, F.d_b, s);
+    coarse_solve(c, F, s, nv);
+    launch_copy<double>(n, c.cx, z, s);
     return;
   }
   if (c.lowp) {
-    launch_copy_cvt_d2f(F.nloc, r, F.f_b, s);
-    vcycle_level<float>(c, 0, s);
-    launch_copy_cvt_f2d(F.nloc, F.f_x, z, s);
+    launch_copy_cvt_d2f(n, r, F.f_b, s);
+    vcycle_level<float>(c, 0, s, nv);
+    launch_copy_cvt_f2d(n, F.f_x, z, s);
   } else {
-    launch_copy<double>(F.nloc, r, F.d_b, s);
-    vcycle_level<double>(c, 0, s);
-    launch_copy<double>(F.nloc, F.d_x, z, s);
+    launch_copy<double>(n, r, F.d_b, s);
+    vcycle_level<double>(c, 0, s, nv);
+    launch_copy<double>(n, F.d_x, z, s);
   }
 }
 
@@ -597,6 +617,7 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
                          hipMemcpyHostToDevice, s));
   SEM_HIP(hipMemsetAsync(sc.bad, 0, 64 * sizeof(int), s));
   SEM_HIP(hipMemsetAsync(c.counter, 0, 64 * sizeof(unsigned), s));
+  if (c.lcounter) SEM_HIP(hipMemsetAsync(c.lcounter, 0, c.nlanes * 16 * sizeof(unsigned), s));
   launch_gll(m->p_geom, sc.xig, nullptr, s);
 
   for (int l = 0; l < c.nlev; ++l) {
@@ -807,11 +828,11 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
 }
 
 // entry points used by the batched driver (batch.hip)
-void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s) {
-  opA<double>(c, L, u, Au, s);
+void batch_opA(const Ctx &c, const Level &L, const double *u, double *Au, hipStream_t s, int nv) {
+  opA<double>(c, L, u, Au, s, nv);
 }
-void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s) {
-  precondition(c, r, z, s);
+void batch_precondition(Ctx &c, const double *r, double *z, hipStream_t s, int nv) {
+  precondition(c, r, z, s, nv);
 }
 double batch_wnorm2(Ctx &c, const double *a, const double *b, hipStream_t s) {
   const double *pa[1] = {a}, *pb[1] = {b};

@@ -21,6 +21,8 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__rest
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+  xc += blockIdx.y * (int64_t)gridDim.x * Nc3;  // right side blockIdx.y
+  xf += blockIdx.y * (int64_t)gridDim.x * Nf3;
   for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
   for (int t = tid; t < Nc3; t += bs) a[t] = xc[e * Nc3 + t];
   __syncthreads();
@@ -59,6 +61,8 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__res
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
+  rf += blockIdx.y * (int64_t)gridDim.x * Nf3;  // right side blockIdx.y
+  rc += blockIdx.y * (int64_t)gridDim.x * Nc3;
   for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
   for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * rf[e * Nf3 + t];
   __syncthreads();
@@ -94,29 +98,31 @@ static int transfer_threads(int Nf) {
 }
 
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s) {
+void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s, int nv) {
   const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
-  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)F.E), dim3(transfer_threads(F.N)), 0, s, F.N,
+  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)F.E, (unsigned)nv), dim3(transfer_threads(F.N)),
+                     0, s, F.N,
                      C.N, J, xc, xf);
   SEM_LAUNCH("k_prolong");
 }
 
 template <typename T>
-void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s) {
+void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s, int nv) {
   const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
   const T *w = sizeof(T) == 8 ? (const T *)F.w64 : (const T *)F.w32;
-  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)F.E), dim3(transfer_threads(F.N)), 0, s, F.N,
+  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)F.E, (unsigned)nv), dim3(transfer_threads(F.N)),
+                     0, s, F.N,
                      C.N, J, w, rf, rc);
   SEM_LAUNCH("k_restrict");
 }
 
 template void launch_prolong<double>(const Level &, const Level &, const double *, double *,
-                                     hipStream_t);
+                                     hipStream_t, int);
 template void launch_prolong<float>(const Level &, const Level &, const float *, float *,
-                                    hipStream_t);
+                                    hipStream_t, int);
 template void launch_restrict<double>(const Level &, const Level &, const double *, double *,
-                                      hipStream_t);
+                                      hipStream_t, int);
 template void launch_restrict<float>(const Level &, const Level &, const float *, float *,
-                                     hipStream_t);
+                                     hipStream_t, int);
 
 }  // namespace sem

@@ -100,3 +100,36 @@ def test_autotuner_picks_a_converged_fast_candidate():
     S = sem.Solver(3, 3, 3, xyz, 1, 5, opts=best)
     x, info = S.solve(b, rtol=1e-8, maxit=200)
     assert info.converged
+
+
+@pytest.mark.parametrize("shape,p,sched,sm,prec,fdm,coarse", [
+    ((3, 3, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO),
+    ((2, 3, 3), 5, (5, 3, 1), sem.SMOOTH_RAS, sem.F32, sem.BF16, sem.COARSE_AUTO),
+    ((3, 2, 2), 5, (5, 1), sem.SMOOTH_ASM, sem.F64, None, sem.COARSE_AUTO),
+    ((2, 2, 3), 4, (4, 2, 1), sem.SMOOTH_JACOBI, sem.F32, None, sem.COARSE_PCG),
+])
+def test_joint_lanes_equal_lanes_in_turn(monkeypatch, shape, p, sched, sm, prec, fdm, coarse):
+    """The right sides of one problem sharing each operator application and
+    V-cycle (nv vectors per launch) give bit-for-bit the results of running the
+    lanes one at a time (same iteration counts, same iterates), both converged."""
+    import torch
+    freqs = [(1, 1, 1), (2, 1, 3), (1, 3, 2)]
+    opts = sem.make_opts(schedule=sched, smoother=sm, smoother_prec=prec, batch_rhs=len(freqs),
+                         coarse_solver=coarse, fdm_prec=fdm if fdm else prec)
+    xyz = wl.sampled_mesh(*shape, sem.gll_nodes(p)[0], wl.sin_map(0.05))
+    S = sem.Solver(*shape, xyz, p, p, opts=opts)
+    X = host(S.coords(0))
+    bs = []
+    for fr in freqs:
+        f, _ = wl.sinusoid(*fr)
+        bs.append(S.rhs(dev(f(X[0], X[1], X[2]))))
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("SEM_BATCH_JOINT", mode)
+        xs = [[torch.zeros_like(b) for b in bs]]
+        infos = sem.batch_solve([S], [bs], xs, rtol=1e-8, maxit=200)
+        assert all(i.converged and i.true_rel_res <= 1e-8 for i in infos)
+        out[mode] = ([i.iters for i in infos], [host(x) for x in xs[0]])
+    assert out["1"][0] == out["0"][0]
+    for a, b in zip(out["1"][1], out["0"][1]):
+        np.testing.assert_array_equal(a, b)
