@@ -231,6 +231,12 @@ sem_status sem_profile_read(sem_ctx *ctx, double *total_ms, int64_t *launches);
  * the convergence flags; the graph is recorded again when pairs finish.  The
  * coarse solve inside a recorded V-cycle runs a fixed iteration count (the count
  * the first, eager V-cycle of that problem needed, plus 4, at most coarse_maxit).
+ * When the context's hierarchy ends in the assembled p = 1 level and nrhs > 1,
+ * its work vectors hold batch_rhs right sides and the nrhs right sides of a
+ * problem share every operator application, V-cycle and coarse sweep (one launch
+ * per kernel for all of them; finished right sides are carried along, their CG
+ * kernels do nothing); environment SEM_BATCH_JOINT=0 runs them one at a time.
+ * Both give bit-identical iterates.
  * b[i*nrhs + k], x[i*nrhs + k]: device FP64 E-vectors of problem i, right side k
  * (x is the initial guess and the result).  infos (may be NULL) has nctx*nrhs
  * entries.  Returns SEM_ENOCONV if some pair misses rtol within maxit. */

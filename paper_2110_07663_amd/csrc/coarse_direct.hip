@@ -2,13 +2,17 @@
 // coarsest level) for the assembled p = 1 operator.
 //
 // With nodes numbered plane by plane along z, the 27-point operator is block
-// tridiagonal: D_k couples the nodes of plane k among themselves, C_k couples
-// plane k to plane k-1 (and C_k^T the other way).  Block elimination gives
-//   T_0 = D_0,  T_k = D_k - C_k T_{k-1}^{-1} C_k^T,   G_k = T_k^{-1},
-//   H_k = C_k G_{k-1},  J_k = G_k C_{k+1}^T = H_{k+1}^T,
-// and the solve is two sweeps of dense products:
-//   y_0 = b_0,  y_k = b_k - H_k y_{k-1};
-//   x_{K-1} = G_{K-1} y_{K-1},  x_k = G_k y_k - J_k x_{k+1}.
+// tridiagonal: D_k couples the nodes of plane k among themselves, A_{k,k-1} and
+// A_{k,k+1} couple it to the planes below and above.  Block elimination runs
+// from both ends towards the middle plane c = K/2 (a "twisted" factorisation),
+// so the solve has two independent chains of half the length:
+//   below c:  T_0 = D_0,  H_k = A_{k,k-1} G_{k-1},  T_k = D_k - H_k A_{k-1,k};
+//   above c:  T_{K-1} = D_{K-1},  H_k = A_{k,k+1} G_{k+1},  T_k = D_k - H_k A_{k+1,k};
+//   at c:     T_c = D_c - Hd_c A_{c-1,c} - Hu_c A_{c+1,c}   (both updates);
+//   G_k = T_k^{-1}, and J_k = H_{k+1}^T (below c) or H_{k-1}^T (above c).
+// Solve: y_0 = b_0, y_{K-1} = b_{K-1}, y_k = b_k - H_k y_{k-+1} walking inwards,
+// y_c = b_c - Hd_c y_{c-1} - Hu_c y_{c+1}, x_c = G_c y_c, then outwards
+// x_k = G_k y_k - J_k x_{k+-1}.  One launch advances both chains.
 // Each T_k is symmetric positive definite (a Schur complement of an SPD
 // matrix), so it is inverted in place by blocked Gauss-Jordan elimination
 // without pivoting (32x32 blocks: invert the pivot block, scale its block row,
@@ -18,9 +22,9 @@
 // and the caller keeps the CG.
 //
 // Storage: G, H, J as K dense [Mp][Mp] FP64 blocks, Mp = nx*ny rounded up to
-// 32 (identity / zero padding).  A solve reads each block once: 3 K Mp^2 * 8
-// bytes, in 2K dependent matrix-vector products with no host interaction, so
-// it can be recorded into a graph.
+// 32 (identity / zero padding); Hu_c sits in J's slot c.  A solve reads each
+// block once: 3 K Mp^2 * 8 bytes, in about K dependent matrix-vector launches
+// with no host interaction, so it can be recorded into a graph.
 #include <algorithm>
 
 #include "sem_internal.h"
@@ -43,9 +47,10 @@ __device__ inline double st_at(const double *St, int64_t n, int64_t t, int dx, i
   return St[(int64_t)((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)) * n + t];
 }
 
-// H[i][l] = sum_a C_k[i][a] G_{k-1}[a][l], C_k[i][a] = stencil of row (k, i) at dz = -1
+// H[i][l] = sum_a A_{k,k+dz}[i][a] G_{k+dz}[a][l], A_{k,k+dz}[i][a] = stencil of
+// row (k, i) towards node (k + dz, a), dz = -1 or +1
 __global__ void k_bt_H(int nx, int ny, int64_t n, int k, int Mp, const double *__restrict__ St,
-                       const double *__restrict__ Gp, double *__restrict__ H) {
+                       const double *__restrict__ Gp, double *__restrict__ H, int dz) {
   const int m = nx * ny;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)Mp * Mp) return;
@@ -58,17 +63,31 @@ __global__ void k_bt_H(int nx, int ny, int64_t n, int k, int Mp, const double *_
       for (int dx = -1; dx <= 1; ++dx) {
         const int xa = xi + dx, ya = yi + dy;
         if (xa < 0 || xa >= nx || ya < 0 || ya >= ny) continue;
-        h += st_at(St, n, row, dx, dy, -1) * Gp[(int64_t)(ya * nx + xa) * Mp + l];
+        h += st_at(St, n, row, dx, dy, dz) * Gp[(int64_t)(ya * nx + xa) * Mp + l];
       }
   }
   H[e] = h;
 }
 
-// T[i][j] = D_k[i][j] - sum_l H[i][l] C_k[j][l]   (padding: identity)
-// (the diagonal is also kept in `diag` for the pivot test of the inversion)
+// T[i][j] = D_k[i][j] - sum_l H1[i][l] A_{k,k+dz1}[j][l] - sum_l H2[i][l] A_{k,k+dz2}[j][l]
+// (A_{k+dz,k} = A_{k,k+dz}^T; absent updates are null; padding: identity).  The
+// diagonal is also kept in `diag` for the pivot test of the inversion.
+__device__ inline double bt_update(int nx, int ny, int64_t n, int64_t rowj, int xj, int yj, int Mp,
+                                   const double *__restrict__ St, const double *__restrict__ Hi,
+                                   int dz) {
+  double v = 0.0;
+  for (int ey = -1; ey <= 1; ++ey)
+    for (int ex = -1; ex <= 1; ++ex) {
+      const int xl = xj + ex, yl = yj + ey;
+      if (xl < 0 || xl >= nx || yl < 0 || yl >= ny) continue;
+      v += Hi[yl * nx + xl] * st_at(St, n, rowj, ex, ey, dz);
+    }
+  return v;
+}
+
 __global__ void k_bt_T(int nx, int ny, int64_t n, int k, int Mp, const double *__restrict__ St,
-                       const double *__restrict__ H, double *__restrict__ T,
-                       double *__restrict__ diag) {
+                       const double *__restrict__ H1, int dz1, const double *__restrict__ H2,
+                       int dz2, double *__restrict__ T, double *__restrict__ diag) {
   const int m = nx * ny;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)Mp * Mp) return;
@@ -82,15 +101,9 @@ __global__ void k_bt_T(int nx, int ny, int64_t n, int k, int Mp, const double *_
   const int dx = xj - xi, dy = yj - yi;
   double v = 0.0;
   if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = st_at(St, n, (int64_t)k * m + i, dx, dy, 0);
-  if (H) {
-    const int64_t rowj = (int64_t)k * m + j;
-    for (int ey = -1; ey <= 1; ++ey)
-      for (int ex = -1; ex <= 1; ++ex) {
-        const int xl = xj + ex, yl = yj + ey;
-        if (xl < 0 || xl >= nx || yl < 0 || yl >= ny) continue;
-        v -= H[(int64_t)i * Mp + yl * nx + xl] * st_at(St, n, rowj, ex, ey, -1);
-      }
-  }
+  const int64_t rowj = (int64_t)k * m + j;
+  if (H1) v -= bt_update(nx, ny, n, rowj, xj, yj, Mp, St, H1 + (int64_t)i * Mp, dz1);
+  if (H2) v -= bt_update(nx, ny, n, rowj, xj, yj, Mp, St, H2 + (int64_t)i * Mp, dz2);
   T[e] = v;
   if (i == j) diag[i] = v;
 }
@@ -206,18 +219,25 @@ __global__ void k_bt_transpose(int Mp, const double *__restrict__ H, double *__r
 
 // ---- solve kernel -------------------------------------------------------------
 
-// out = c + s1 * (M1 v1) - (M2 v2) for NV right sides (vectors vs apart in v1,
-// v2, c and out), one wavefront per row (rows < m): the matrix rows are read
-// once for all right sides.  Each right side is summed in the same order for
-// any NV (four strided partial sums per lane, then the wave reduction).
+// One product of a sweep: out = c + s1 * (M1 v1) - (M2 v2) (absent terms null)
+struct BtOp {
+  const double *M1, *v1, *M2, *v2, *c;
+  double *out;
+  double s1;
+};
+
+// Up to two independent products (the two chains of the sweep) for NV right
+// sides (vectors vs apart in v1, v2, c and out); one wavefront per row, the
+// matrix rows are read once for all right sides.  Each right side is summed in
+// the same order for any NV (four strided partial sums per lane, then the wave
+// reduction).
 template <int NV>
-__global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, const double *__restrict__ M1,
-                                               const double *__restrict__ v1, double s1,
-                                               const double *__restrict__ M2,
-                                               const double *__restrict__ v2,
-                                               const double *__restrict__ c,
-                                               double *__restrict__ out, int64_t vs) {
-  const int row = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+__global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, BtOp o0, BtOp o1, int64_t vs) {
+  const int rb = (m + 3) / 4;
+  const int which = (int)blockIdx.x >= rb;
+  const BtOp &o = which ? o1 : o0;
+  const int row = ((int)blockIdx.x - which * rb) * 4 + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (row >= m) return;  // whole wave
   double a1[NV], a2[NV];
   // four independent partial sums per lane and right side keep the loads in flight
@@ -245,25 +265,30 @@ __global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, const double *__re
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = (t[v][0] + t[v][1]) + (t[v][2] + t[v][3]);
   };
-  rowdot(M1 + (int64_t)row * Mp, v1, a1);
-  if (M2) {
-    rowdot(M2 + (int64_t)row * Mp, v2, a2);
+  if (o.M1) {
+    rowdot(o.M1 + (int64_t)row * Mp, o.v1, a1);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a1[v] = 0.0;
+  }
+  if (o.M2) {
+    rowdot(o.M2 + (int64_t)row * Mp, o.v2, a2);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) a2[v] = 0.0;
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int sh = 32; sh > 0; sh >>= 1) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      a1[v] += __shfl_xor(a1[v], o, 64);
-      a2[v] += __shfl_xor(a2[v], o, 64);
+      a1[v] += __shfl_xor(a1[v], sh, 64);
+      a2[v] += __shfl_xor(a2[v], sh, 64);
     }
   }
   if (lane == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      out[v * vs + row] = (c ? c[v * vs + row] : 0.0) + s1 * a1[v] - a2[v];
+      o.out[v * vs + row] = (o.c ? o.c[v * vs + row] : 0.0) + o.s1 * a1[v] - a2[v];
   }
 }
 
@@ -271,38 +296,76 @@ __global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, const double *__re
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+static void bt_invert(double *Gk, int Mp, int nbk, const double *diag, int *flag, hipStream_t s) {
+  for (int b = 0; b < nbk; ++b) {
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, Gk, Mp, b, diag, flag);
+    SEM_LAUNCH("k_gj_diag");
+    if (nbk == 1) continue;
+    hipLaunchKernelGGL(k_gj_row, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
+    SEM_LAUNCH("k_gj_row");
+    hipLaunchKernelGGL(k_gj_trail, dim3((nbk - 1) * (nbk - 1)), dim3(256), 0, s, Gk, Mp, b, nbk);
+    SEM_LAUNCH("k_gj_trail");
+    hipLaunchKernelGGL(k_gj_col, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
+    SEM_LAUNCH("k_gj_col");
+  }
+}
+
 void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s) {
-  const int m = (int)(nx * ny), K = (int)nz;
+  const int m = (int)(nx * ny), K = (int)nz, c = K / 2;
   const int Mp = (int)padded(m), nbk = Mp / kGB;
   const int64_t M2 = (int64_t)Mp * Mp;
+  const unsigned g2 = nblk(M2);
   SEM_HIP(hipMemsetAsync(S.dflag, 0, sizeof(int), s));
-  for (int k = 0; k < K; ++k) {
-    double *Gk = S.dG + k * M2;
-    double *Hk = S.dH + k * M2;
+  auto G = [&](int k) { return S.dG + k * M2; };
+  auto H = [&](int k) { return S.dH + k * M2; };
+  auto J = [&](int k) { return S.dJ + k * M2; };
+  // chain from plane 0 up to c - 1
+  for (int k = 0; k < c; ++k) {
     if (k > 0) {
-      hipLaunchKernelGGL(k_bt_H, dim3(nblk(M2)), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp,
-                         S.St, Gk - M2, Hk);
+      hipLaunchKernelGGL(k_bt_H, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
+                         (const double *)G(k - 1), H(k), -1);
       SEM_LAUNCH("k_bt_H");
     }
-    hipLaunchKernelGGL(k_bt_T, dim3(nblk(M2)), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
-                       k > 0 ? (const double *)Hk : nullptr, Gk, S.dy);
+    hipLaunchKernelGGL(k_bt_T, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
+                       k > 0 ? (const double *)H(k) : nullptr, -1, (const double *)nullptr, 0,
+                       G(k), S.dy);
     SEM_LAUNCH("k_bt_T");
-    for (int b = 0; b < nbk; ++b) {
-      hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, Gk, Mp, b, (const double *)S.dy,
-                         S.dflag);
-      SEM_LAUNCH("k_gj_diag");
-      if (nbk == 1) continue;
-      hipLaunchKernelGGL(k_gj_row, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
-      SEM_LAUNCH("k_gj_row");
-      hipLaunchKernelGGL(k_gj_trail, dim3((nbk - 1) * (nbk - 1)), dim3(256), 0, s, Gk, Mp, b, nbk);
-      SEM_LAUNCH("k_gj_trail");
-      hipLaunchKernelGGL(k_gj_col, dim3(nbk - 1), dim3(256), 0, s, Gk, Mp, b);
-      SEM_LAUNCH("k_gj_col");
-    }
+    bt_invert(G(k), Mp, nbk, S.dy, S.dflag, s);
   }
-  for (int k = 0; k + 1 < K; ++k) {
-    hipLaunchKernelGGL(k_bt_transpose, dim3(nbk, nbk), dim3(256), 0, s, Mp, S.dH + (k + 1) * M2,
-                       S.dJ + k * M2);
+  // chain from plane K - 1 down to c + 1
+  for (int k = K - 1; k > c; --k) {
+    if (k < K - 1) {
+      hipLaunchKernelGGL(k_bt_H, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
+                         (const double *)G(k + 1), H(k), 1);
+      SEM_LAUNCH("k_bt_H");
+    }
+    hipLaunchKernelGGL(k_bt_T, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, k, Mp, S.St,
+                       k < K - 1 ? (const double *)H(k) : nullptr, 1, (const double *)nullptr, 0,
+                       G(k), S.dy);
+    SEM_LAUNCH("k_bt_T");
+    bt_invert(G(k), Mp, nbk, S.dy, S.dflag, s);
+  }
+  // plane c takes both updates: from below in H's slot, from above in J's slot
+  if (c > 0) {
+    hipLaunchKernelGGL(k_bt_H, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, c, Mp, S.St,
+                       (const double *)G(c - 1), H(c), -1);
+    SEM_LAUNCH("k_bt_H");
+  }
+  if (c < K - 1) {
+    hipLaunchKernelGGL(k_bt_H, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, c, Mp, S.St,
+                       (const double *)G(c + 1), J(c), 1);
+    SEM_LAUNCH("k_bt_H");
+  }
+  hipLaunchKernelGGL(k_bt_T, dim3(g2), dim3(256), 0, s, (int)nx, (int)ny, S.n, c, Mp, S.St,
+                     c > 0 ? (const double *)H(c) : nullptr, -1,
+                     c < K - 1 ? (const double *)J(c) : nullptr, 1, G(c), S.dy);
+  SEM_LAUNCH("k_bt_T");
+  bt_invert(G(c), Mp, nbk, S.dy, S.dflag, s);
+  // back-substitution blocks: J_k = H_{k+1}^T below c, H_{k-1}^T above c (Hu_c for c + 1)
+  for (int k = 0; k < K; ++k) {
+    if (k == c) continue;
+    const double *src = k < c ? H(k + 1) : (k - 1 == c ? J(c) : H(k - 1));
+    hipLaunchKernelGGL(k_bt_transpose, dim3(nbk, nbk), dim3(256), 0, s, Mp, src, J(k));
     SEM_LAUNCH("k_bt_transpose");
   }
   int flag = 0;
@@ -315,26 +378,48 @@ template <int NV>
 static void bt_sweeps(const CoarseSolver &S, int m, int K, int Mp, const double *b, double *x,
                       double *y, hipStream_t s) {
   const int64_t M2 = (int64_t)Mp * Mp, vs = S.n;
-  const unsigned grid = (unsigned)((m + 3) / 4);
-  for (int v = 0; v < NV; ++v) launch_copy<double>(m, b + v * vs, y + v * vs, s);
-  for (int k = 1; k < K; ++k) {  // y_k = b_k - H_k y_{k-1}
-    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dH + k * M2,
-                       (const double *)(y + (int64_t)(k - 1) * m), -1.0, (const double *)nullptr,
-                       (const double *)nullptr, b + (int64_t)k * m, y + (int64_t)k * m, vs);
+  const int c = K / 2;
+  const unsigned rb = (unsigned)((m + 3) / 4);
+  auto G = [&](int k) { return (const double *)(S.dG + k * M2); };
+  auto H = [&](int k) { return (const double *)(S.dH + k * M2); };
+  auto J = [&](int k) { return (const double *)(S.dJ + k * M2); };
+  // y_k of the sweep; y_0 and y_{K-1} are b itself
+  auto Y = [&](int k) -> const double * {
+    return (k == 0 || k == K - 1) ? b + (int64_t)k * m : (const double *)(y + (int64_t)k * m);
+  };
+  auto launch = [&](const BtOp &o0, const BtOp *o1) {
+    const BtOp none{};
+    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(o1 ? 2 * rb : rb), dim3(256), 0, s, m, Mp, o0,
+                       o1 ? *o1 : none, vs);
     SEM_LAUNCH("k_bt_mv");
+  };
+  // inwards: y_k = b_k - H_k y_{k-1} (k < c), y_k = b_k - H_k y_{k+1} (k > c)
+  for (int t = 1;; ++t) {
+    const int kd = t, ku = K - 1 - t;
+    const bool dn = kd < c, up = ku > c;
+    if (!dn && !up) break;
+    BtOp od{H(kd), Y(kd - 1), nullptr, nullptr, b + (int64_t)kd * m, y + (int64_t)kd * m, -1.0};
+    BtOp ou{H(ku), Y(ku + 1), nullptr, nullptr, b + (int64_t)ku * m, y + (int64_t)ku * m, -1.0};
+    if (dn && up) launch(od, &ou);
+    else launch(dn ? od : ou, nullptr);
   }
-  // x_{K-1} = G_{K-1} y_{K-1}; x_k = G_k y_k - J_k x_{k+1}
-  hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + (K - 1) * M2,
-                     (const double *)(y + (int64_t)(K - 1) * m), 1.0, (const double *)nullptr,
-                     (const double *)nullptr, (const double *)nullptr, x + (int64_t)(K - 1) * m,
-                     vs);
-  SEM_LAUNCH("k_bt_mv");
-  for (int k = K - 2; k >= 0; --k) {
-    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(grid), dim3(256), 0, s, m, Mp, S.dG + k * M2,
-                       (const double *)(y + (int64_t)k * m), 1.0, (const double *)(S.dJ + k * M2),
-                       (const double *)(x + (int64_t)(k + 1) * m), (const double *)nullptr,
-                       x + (int64_t)k * m, vs);
-    SEM_LAUNCH("k_bt_mv");
+  // plane c: y_c = b_c - Hd_c y_{c-1} - Hu_c y_{c+1}; x_c = G_c y_c
+  {
+    BtOp oy{c > 0 ? H(c) : nullptr, c > 0 ? Y(c - 1) : nullptr, c < K - 1 ? J(c) : nullptr,
+            c < K - 1 ? Y(c + 1) : nullptr, b + (int64_t)c * m, y + (int64_t)c * m, -1.0};
+    launch(oy, nullptr);
+    BtOp ox{G(c), y + (int64_t)c * m, nullptr, nullptr, nullptr, x + (int64_t)c * m, 1.0};
+    launch(ox, nullptr);
+  }
+  // outwards: x_k = G_k y_k - J_k x_{k+1} (k < c), x_k = G_k y_k - J_k x_{k-1} (k > c)
+  for (int t = 1;; ++t) {
+    const int kd = c - t, ku = c + t;
+    const bool dn = kd >= 0, up = ku < K;
+    if (!dn && !up) break;
+    BtOp od{G(kd), Y(kd), J(kd), x + (int64_t)(kd + 1) * m, nullptr, x + (int64_t)kd * m, 1.0};
+    BtOp ou{G(ku), Y(ku), J(ku), x + (int64_t)(ku - 1) * m, nullptr, x + (int64_t)ku * m, 1.0};
+    if (dn && up) launch(od, &ou);
+    else launch(dn ? od : ou, nullptr);
   }
 }
 
