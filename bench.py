@@ -43,9 +43,11 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
-    ap.add_argument("--mode", choices=("solve", "kernels", "batch"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "kernels", "batch", "sensitivity"),
+                    default="solve",
                     help="kernels: repeat single finest-level kernels (for counter runs); "
-                         "batch: the 64-problem x 4-RHS batched workload")
+                         "batch: the 64-problem x 4-RHS batched workload; sensitivity: "
+                         "iteration counts over the Chebyshev bound multipliers")
     ap.add_argument("--nprob", type=int, default=64, help="problems in --mode batch")
     ap.add_argument("--no-tune", action="store_true", help="--mode batch: skip the auto-tuner")
     ap.add_argument("--reps", type=int, default=5, help="repetitions per kernel in --mode kernels")
@@ -230,6 +232,52 @@ def batch_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def sensitivity_mode(a):
+    """The (lambda_min, lambda_max) multiplier grid of the paper's bound study
+    (Sec. 3, Table 1): 24^3 elements, p = 7, Cheby-ASM(2) in the (7, 3, 1)
+    V-cycle, tol 1e-8, at most 1000 iterations, on the layer-shift mesh (seed 3)
+    standing in for Kershaw eps = 0.3.  The Arnoldi estimate of every level is
+    taken once and reused, so only the multipliers change between entries."""
+    import torch
+    from paper_2110_07663_amd import sem
+    from paper_2110_07663_amd import workloads as wl
+    torch.cuda.set_device(0)
+    n, p = 24, 7
+    sched = (7, 3, 1)
+    xyz = wl.layer_shift_vertices(n, seed=3)
+    f, _ = wl.sinusoid(1, 1, 1)
+
+    def opts(lmin, lmax, lam=None):
+        return sem.make_opts(schedule=sched, smoother=sem.SMOOTH_ASM, cheb_order=2,
+                             smoother_prec=sem.F32, lmin_fac=lmin, lmax_fac=lmax,
+                             lambda_override=lam)
+
+    s0 = sem.Solver(n, n, n, xyz, 1, p, opts=opts(0.1, 1.1))
+    X = s0.coords(0)
+    b = s0.rhs(torch.as_tensor(f(*(X.cpu().numpy())), dtype=torch.float64).cuda())
+    _, info = s0.solve(b, rtol=1e-8, maxit=1000, allow_noconv=True)
+    lam = [info.lambda_tilde[l] for l in range(len(sched) - 1)]
+    s0.close()
+    lmins = (0.0, 0.025, 0.05, 0.1, 0.2, 0.25)
+    lmaxs = (0.9, 0.95, 1.0, 1.1, 1.2, 1.3)
+    grid = {}
+    for lmin in lmins:
+        row = {}
+        for lmax in lmaxs:
+            s = sem.Solver(n, n, n, xyz, 1, p, opts=opts(lmin, lmax, lam))
+            _, inf = s.solve(b, rtol=1e-8, maxit=1000, allow_noconv=True)
+            row[str(lmax)] = inf.iters if inf.converged else None
+            s.close()
+            print(f"[sensitivity] lmin {lmin} lmax {lmax}: "
+                  f"{inf.iters if inf.converged else '-'}", file=sys.stderr, flush=True)
+        grid[str(lmin)] = row
+    print(json.dumps({"mode": "sensitivity", "mesh": "layer-shift 24^3 seed 3", "p": p,
+                      "smoother": "Cheby-ASM(2) FP32", "schedule": list(sched), "tol": 1e-8,
+                      "maxit": 1000, "lambda_tilde": lam,
+                      "iters (row lambda_min factor, column lambda_max factor; null = no "
+                      "convergence)": grid}), flush=True)
+
+
 def algorithmic_bytes(kind, L):
     """HBM bytes one launch must move (each operand read or written once)."""
     p, E = L.p, L.E
@@ -278,6 +326,9 @@ def main():
         return
     if a.mode == "batch":
         batch_mode(a)
+        return
+    if a.mode == "sensitivity":
+        sensitivity_mode(a)
         return
     import numpy as np
     import torch

@@ -79,7 +79,8 @@ void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s) {
 template void launch_sub<double>(int64_t, const double *, const double *, double *, hipStream_t);
 template void launch_sub<float>(int64_t, const float *, const float *, float *, hipStream_t);
 
-// Chebyshev (Algorithm 2): d = r / theta, x = 0 when starting from zero
+// Chebyshev (Algorithm 2): d = r / theta, x = 0 when starting from zero (the
+// caller may instead let the first update treat x as zero: x_zero = false here)
 template <typename T>
 __global__ void k_cheb_init(int64_t n, T *__restrict__ x, const T *__restrict__ r,
                             T *__restrict__ d, T inv_theta, int x_zero) {
@@ -100,26 +101,54 @@ template void launch_cheb_init<float>(int64_t, float *, const float *, float *, 
                                       hipStream_t);
 
 // one pass of the loop body: x += d_k; r -= S A d_k (= t); d = a d_k + c r
+// (xz: x is zero on entry and is not read)
 template <typename T>
 __global__ void k_cheb_update(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
-                              const T *__restrict__ tv, T a, T c) {
+                              const T *__restrict__ tv, T a, T c, int xz) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   T dk = d[t];
-  x[t] += dk;
+  x[t] = xz ? dk : x[t] + dk;
   T rn = r[t] - tv[t];
   r[t] = rn;
   d[t] = a * dk + c * rn;
 }
 template <typename T>
-void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c);
+void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s,
+                        bool x_zero) {
+  hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                     (int)x_zero);
   SEM_LAUNCH("k_cheb_update");
 }
 template void launch_cheb_update<double>(int64_t, double *, double *, double *, const double *,
-                                         double, double, hipStream_t);
+                                         double, double, hipStream_t, bool);
 template void launch_cheb_update<float>(int64_t, float *, float *, float *, const float *, float,
-                                        float, hipStream_t);
+                                        float, hipStream_t, bool);
+
+// the last pass of the loop and the closing x += d in one: r and d are not
+// needed afterwards, so only x is written (same roundings as the two passes)
+template <typename T>
+__global__ void k_cheb_last(int64_t n, T *__restrict__ x, const T *__restrict__ r,
+                            const T *__restrict__ d, const T *__restrict__ tv, T a, T c, int xz) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const T dk = d[t];
+  const T x1 = xz ? dk : x[t] + dk;
+  const T rn = r[t] - tv[t];
+  const T dn = a * dk + c * rn;
+  x[t] = dn + x1;
+}
+template <typename T>
+void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c, hipStream_t s,
+                      bool x_zero) {
+  hipLaunchKernelGGL(k_cheb_last<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                     (int)x_zero);
+  SEM_LAUNCH("k_cheb_last");
+}
+template void launch_cheb_last<double>(int64_t, double *, const double *, const double *,
+                                       const double *, double, double, hipStream_t, bool);
+template void launch_cheb_last<float>(int64_t, float *, const float *, const float *,
+                                      const float *, float, float, hipStream_t, bool);
 
 __global__ void k_jacobi_inv(int64_t n, const double *__restrict__ diag, const double *__restrict__ w,
                              double *__restrict__ dinv, float *__restrict__ dinv32) {

@@ -240,24 +240,31 @@ __global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, BtOp o0, BtOp o1, 
   const int lane = threadIdx.x & 63;
   if (row >= m) return;  // whole wave
   double a1[NV], a2[NV];
-  // four independent partial sums per lane and right side keep the loads in flight
+  // The matrix row (16-byte aligned: Mp is a multiple of 32) streams as 16-byte
+  // loads, four per lane per step (512 entries a wave), into four partial sums
+  // per right side; x (L2 resident, any alignment) is read per entry.
   auto rowdot = [&](const double *__restrict__ r, const double *__restrict__ x, double *acc) {
     double t[NV][4];
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v][0] = t[v][1] = t[v][2] = t[v][3] = 0.0;
-    int j = lane;
-    for (; j + 192 < m; j += 256) {
-      const double r0 = r[j], r1 = r[j + 64], r2 = r[j + 128], r3 = r[j + 192];
+    const double2 *__restrict__ r2 = reinterpret_cast<const double2 *>(r);
+    int j0 = 0;
+    for (; j0 + 512 <= m; j0 += 512) {
+      double2 q[4];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double *xv = x + v * vs;
-        t[v][0] += r0 * xv[j];
-        t[v][1] += r1 * xv[j + 64];
-        t[v][2] += r2 * xv[j + 128];
-        t[v][3] += r3 * xv[j + 192];
+      for (int u = 0; u < 4; ++u) q[u] = r2[(j0 >> 1) + 64 * u + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 128 * u + 2 * lane;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double *xv = x + v * vs;
+          t[v][u] += q[u].x * xv[j];
+          t[v][u] += q[u].y * xv[j + 1];
+        }
       }
     }
-    for (; j < m; j += 64) {
+    for (int j = j0 + lane; j < m; j += 64) {
       const double r0 = r[j];
 #pragma unroll
       for (int v = 0; v < NV; ++v) t[v][0] += r0 * x[v * vs + j];

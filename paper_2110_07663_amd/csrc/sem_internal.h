@@ -278,8 +278,13 @@ template <typename T>
 void launch_axpby(int64_t n, T a, const T *x, T b, T *y, hipStream_t s);  // y = a x + b y
 template <typename T>
 void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s);  // y = a - b
+// x_zero: x is zero on entry (not read)
 template <typename T>
-void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s);
+void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s,
+                        bool x_zero = false);
+template <typename T>
+void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c,
+                      hipStream_t s, bool x_zero = false);  // x += d + (a d + c (r - t))
 template <typename T>
 void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zero, hipStream_t s);
 void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
@@ -307,9 +312,10 @@ void launch_cpcg_iteration(const Ctx &c, const Level &L, bool first, hipStream_t
 // transfer.hip
 template <typename T>
 void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s, int nv = 1);
+// bf != null: restrict bf - rf (the residual of a right side bf and a product rf)
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s,
-                     int nv = 1);
+                     int nv = 1, const T *bf = nullptr);
 
 // fdm.hip
 void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s);

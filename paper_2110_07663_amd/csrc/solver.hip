@@ -428,15 +428,25 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
     launch_sub<T>(n, b, w, w, s);
     opS<T>(c, L, w, r, s, nv);
   }
-  launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), x_zero, s);
+  if (L.K == 0) {
+    launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), x_zero, s);
+    launch_axpby<T>(n, (T)1, d, (T)1, x, s);
+    return;
+  }
+  // a zero start is not written: the first update takes x as zero
+  launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), false, s);
   for (int k = 0; k < L.K; ++k) {
     opA<T>(c, L, d, w, s, nv);
     opS<T>(c, L, w, t, s, nv);
     double rho_new = 1.0 / (2.0 * sigma - rho);
-    launch_cheb_update<T>(n, x, r, d, t, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
+    const T a = (T)(rho_new * rho), cc = (T)(2.0 * rho_new / delta);
+    const bool xz = x_zero && k == 0;
+    if (k + 1 < L.K)
+      launch_cheb_update<T>(n, x, r, d, t, a, cc, s, xz);
+    else  // last pass and the closing x += d together
+      launch_cheb_last<T>(n, x, r, d, t, a, cc, s, xz);
     rho = rho_new;
   }
-  launch_axpby<T>(n, (T)1, d, (T)1, x, s);
 }
 
 static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
@@ -503,11 +513,10 @@ static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1) {
     return;
   }
   Level &C = c.lev[l + 1];
-  T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *r = Vec<T>::r(L), *w = Vec<T>::w(L);
+  T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *w = Vec<T>::w(L);
   chebyshev<T>(c, L, b, x, true, s, nv);                // x = M b
-  opA<T>(c, L, x, w, s, nv);                            // r = b - A x
-  launch_sub<T>(n, b, w, r, s);
-  launch_restrict<T>(L, C, r, Vec<T>::b(C), s, nv);     // r_C = P^T r
+  opA<T>(c, L, x, w, s, nv);                            // r_C = P^T (b - A x)
+  launch_restrict<T>(L, C, w, Vec<T>::b(C), s, nv, b);
   launch_gs<T>(C, Vec<T>::b(C), s, nv);
   vcycle_level<T>(c, l + 1, s, nv);                     // e_C
   launch_prolong<T>(L, C, Vec<T>::x(C), x, s, nv);      // x += P e_C

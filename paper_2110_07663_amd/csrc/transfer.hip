@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__rest
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__restrict__ J,
                                                   const T *__restrict__ w, const T *__restrict__ rf,
-                                                  T *__restrict__ rc) {
+                                                  const T *__restrict__ bf, T *__restrict__ rc) {
   __shared__ T sJ[kTN * kTN];
   __shared__ T a[kTN * kTN * kTN];
   __shared__ T b[kTN * kTN * kTN];
@@ -64,7 +64,12 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__res
   rf += blockIdx.y * (int64_t)gridDim.x * Nf3;  // right side blockIdx.y
   rc += blockIdx.y * (int64_t)gridDim.x * Nc3;
   for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
-  for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * rf[e * Nf3 + t];
+  if (bf) {  // residual b - A x formed on the way in
+    bf += blockIdx.y * (int64_t)gridDim.x * Nf3;
+    for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * (bf[e * Nf3 + t] - rf[e * Nf3 + t]);
+  } else {
+    for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * rf[e * Nf3 + t];
+  }
   __syncthreads();
   // b[k][j][aa] = sum_i J[i][aa] r[k][j][i]
   for (int t = tid; t < Nf * Nf * Nc; t += bs) {
@@ -107,12 +112,13 @@ void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStrea
 }
 
 template <typename T>
-void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s, int nv) {
+void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStream_t s, int nv,
+                     const T *bf) {
   const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
   const T *w = sizeof(T) == 8 ? (const T *)F.w64 : (const T *)F.w32;
   hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)F.E, (unsigned)nv), dim3(transfer_threads(F.N)),
                      0, s, F.N,
-                     C.N, J, w, rf, rc);
+                     C.N, J, w, rf, bf, rc);
   SEM_LAUNCH("k_restrict");
 }
 
@@ -121,8 +127,8 @@ template void launch_prolong<double>(const Level &, const Level &, const double 
 template void launch_prolong<float>(const Level &, const Level &, const float *, float *,
                                     hipStream_t, int);
 template void launch_restrict<double>(const Level &, const Level &, const double *, double *,
-                                      hipStream_t, int);
+                                      hipStream_t, int, const double *);
 template void launch_restrict<float>(const Level &, const Level &, const float *, float *,
-                                     hipStream_t, int);
+                                     hipStream_t, int, const float *);
 
 }  // namespace sem
