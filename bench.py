@@ -234,7 +234,7 @@ def batch_mode(a):
 
 def sensitivity_mode(a):
     """The (lambda_min, lambda_max) multiplier grid of the paper's bound study
-    (Sec. 3, Table 1): 24^3 elements, p = 7, Cheby-ASM(2) in the (7, 3, 1)
+    (Sec. 2.2, Table 1): 24^3 elements, p = 7, Cheby-ASM(2) in the (7, 3, 1)
     V-cycle, tol 1e-8, at most 1000 iterations, on the layer-shift mesh (seed 3)
     standing in for Kershaw eps = 0.3.  The Arnoldi estimate of every level is
     taken once and reused, so only the multipliers change between entries."""
