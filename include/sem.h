@@ -104,6 +104,10 @@ typedef struct {
                               /* over z-planes (3 nz (nx ny)^2 doubles of workspace;      */
                               /* falls back to the PCG if the level is singular), -1      */
                               /* library default: 1 when that storage is <= 4 GiB         */
+  int32_t proj_max;           /* > 0: sem_solve starts from the A-conjugate projection of */
+                              /* b onto up to proj_max prior solutions (successive right  */
+                              /* sides, Sec. 3.2 / 4.2) and stops at ||r|| <= rtol ||b||; */
+                              /* 0: off (the default).  At most 32.                       */
 } sem_opts;
 
 typedef struct {
@@ -200,9 +204,19 @@ sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
 /* Solves A x = b to ||b - A x|| <= rtol ||b - A x0|| (2-norm over unique free
  * nodes) with the context's Krylov method, x_inout the initial guess and result.
  * Returns SEM_ENOCONV at maxit (x and info hold the last iterate), SEM_ENAN on a
- * NaN/Inf residual.  info may be NULL. */
+ * NaN/Inf residual.  info may be NULL.
+ * With opts.proj_max > 0 (successive right sides, Sec. 3.2 / 4.2): the input x
+ * is ignored; the initial guess is x0 = sum_i (x_i, b) x_i over the context's
+ * A-orthonormal basis of prior solutions, the test is ||b - A x|| <= rtol ||b||
+ * (0 iterations when x0 already passes it; rel_res and true_rel_res are then
+ * relative to ||b||), and afterwards the correction x - x0 is A-orthogonalised
+ * against the basis (classical Gram-Schmidt, two passes, one extra product with
+ * A) and appended; a full basis restarts from the latest solution alone. */
 sem_status sem_solve(sem_ctx *ctx, const double *b, double *x_inout, double rtol, int32_t maxit,
                      sem_solve_info *info, void *stream);
+
+/* Empties the basis of prior solutions used by opts.proj_max. */
+sem_status sem_projection_reset(sem_ctx *ctx);
 
 /* Kernel timing of the finest level, for roofline reporting.  While enabled, the
  * library records a pair of HIP events on the call's stream around every launch

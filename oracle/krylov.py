@@ -137,3 +137,63 @@ def fgmres(apply_A, apply_M, b, wdot, tol, maxit, m=20, x0=None):
         if rel <= tol:
             return Result(x, it, rel, hist, True)
     return Result(x, it, rel, hist, False)
+
+
+class Projection:
+    """Initial guesses for successive right-hand sides (Sec. 3.2 and 4.2: the
+    solution is projected onto up to 10 prior solution vectors).  Reading: the
+    basis X is A-orthonormal in the weighted (unique free node) inner product,
+    (x_i, A x_j) = delta_ij, with A X kept beside it, so the guess
+    x0 = sum_i (x_i, b) x_i is the A-norm best approximation of A^{-1} b in
+    span(X).  After a solve the correction x - x0 is A-orthogonalised against
+    X by classical Gram-Schmidt (two passes) and appended when it adds a new
+    direction (A-norm above 1e-10 of its value before orthogonalisation); a
+    full basis restarts from the latest solution alone."""
+
+    def __init__(self, apply_A, wdot, lmax):
+        self.apply_A, self.wdot, self.lmax = apply_A, wdot, lmax
+        self.X, self.AX = [], []
+
+    def guess(self, b):
+        x0 = np.zeros_like(b)
+        for xi in self.X:
+            x0 = x0 + self.wdot(xi, b) * xi
+        return x0
+
+    def update(self, x0, x):
+        if len(self.X) == self.lmax:
+            self.X, self.AX = [], []
+            w = x.copy()
+        else:
+            w = x - x0
+        Aw = self.apply_A(w)
+        n0 = self.wdot(w, Aw)
+        for _ in range(2):
+            if not self.X:
+                break
+            beta = [self.wdot(xi, Aw) for xi in self.X]
+            for bi, xi, axi in zip(beta, self.X, self.AX):
+                w = w - bi * xi
+                Aw = Aw - bi * axi
+        nn = self.wdot(w, Aw)
+        if nn > 0.0 and nn > 1e-20 * n0:
+            s = 1.0 / np.sqrt(nn)
+            self.X.append(w * s)
+            self.AX.append(Aw * s)
+
+
+def projected_solve(solver, proj, apply_A, apply_M, b, wdot, tol, maxit, **kw):
+    """solver (pcg, fcg or fgmres) from the projected guess, stopping at
+    ||b - A x|| <= tol ||b||; the basis is updated afterwards.  Result.rel is
+    relative to ||b||."""
+    nb = np.sqrt(wdot(b, b))
+    x0 = proj.guess(b)
+    r = b - apply_A(x0)
+    r0 = np.sqrt(wdot(r, r))
+    if r0 == 0.0 or r0 <= tol * nb:
+        res = Result(x0, 0, r0 / nb if nb > 0 else 0.0, [r0 / nb if nb > 0 else 0.0], True)
+    else:
+        res = solver(apply_A, apply_M, b, wdot, tol * nb / r0, maxit, x0=x0, **kw)
+        res.rel = res.rel * r0 / nb
+    proj.update(x0, res.x)
+    return res

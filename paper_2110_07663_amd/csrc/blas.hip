@@ -55,7 +55,9 @@ void launch_copy_cvt_f2d(int64_t n, const float *x, double *y, hipStream_t s) {
 template <typename T>
 __global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < n) y[t] = a * x[t] + b * y[t];
+  if (t >= n) return;
+  // b = 0 overwrites y without reading it (y may be uninitialised: 0 * NaN = NaN)
+  y[t] = b == T(0) ? a * x[t] : a * x[t] + b * y[t];
 }
 template <typename T>
 void launch_axpby(int64_t n, T a, const T *x, T b, T *y, hipStream_t s) {

@@ -211,6 +211,10 @@ struct Ctx {
   double *kr = nullptr, *kz = nullptr, *kzold = nullptr, *kp = nullptr, *kq = nullptr,
          *kx = nullptr;
   double *gV = nullptr, *gZ = nullptr;  // FGMRES bases [(m+1)][nloc], [m][nloc]
+  // A-conjugate projection onto prior solutions: X [proj_max][nloc] (A-orthonormal),
+  // AX = A X, and two work vectors; nproj basis vectors in use
+  double *projX = nullptr, *projAX = nullptr, *projW = nullptr, *projAW = nullptr;
+  int nproj = 0;
   // coarse PCG vectors (FP64, coarsest level)
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
   int last_coarse_iters = 0;

@@ -95,6 +95,7 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
   if (o->ax_variant < -1 || o->ax_variant > 2) fail(SEM_EINVAL, "ax_variant must be in [-1, 2]");
   if (o->batch_rhs < 0 || o->batch_rhs > 64) fail(SEM_EINVAL, "batch_rhs must be in [0, 64]");
   if (o->coarse_solver < -1 || o->coarse_solver > 1) fail(SEM_EINVAL, "coarse_solver must be in [-1, 1]");
+  if (o->proj_max < 0 || o->proj_max > 32) fail(SEM_EINVAL, "proj_max must be in [0, 32]");
   for (int f = 0; f < 6; ++f)
     if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
   int64_t E = (int64_t)m->nex * m->ney * m->nez;
@@ -187,6 +188,13 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   if (o.krylov == SEM_KRYLOV_FGMRES) {
     c.gV = A.take<double>((size_t)(o.gmres_restart + 1) * F.nloc);
     c.gZ = A.take<double>((size_t)o.gmres_restart * F.nloc);
+  }
+  c.nproj = 0;
+  if (o.proj_max > 0) {
+    c.projX = A.take<double>((size_t)o.proj_max * F.nloc);
+    c.projAX = A.take<double>((size_t)o.proj_max * F.nloc);
+    c.projW = A.take<double>(F.nloc);
+    c.projAW = A.take<double>(F.nloc);
   }
   const Level &C = c.lev[c.nlev - 1];
   c.cx = A.take<double>(nv * C.nloc);
@@ -680,8 +688,9 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
 
 // ---------------------------------------------------------------------------
 // Krylov solvers (FP64 on the finest level)
+// rref > 0: the residual test is ||r|| <= rtol * rref instead of rtol * ||r_0||
 static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, bool flexible,
-                    sem_solve_info *info, hipStream_t s) {
+                    sem_solve_info *info, hipStream_t s, double rref = 0.0) {
   Level &F = c.lev[0];
   const int64_t n = F.nloc;
   double *r = c.kr, *z = c.kz, *zo = c.kzold, *p = c.kp, *q = c.kq;
@@ -689,11 +698,12 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
   launch_sub<double>(n, b, q, r, s);
   const double r0 = wnorm(c, F, r, s);
   info->r0_norm = r0;
-  if (r0 == 0.0) {
-    info->rel_res = info->true_rel_res = 0.0;
+  if (r0 == 0.0 || (rref > 0.0 && r0 <= rtol * rref)) {
+    info->rel_res = info->true_rel_res = rref > 0.0 ? r0 / rref : 0.0;
     info->converged = 1;
     return 0;
   }
+  const double den = rref > 0.0 ? rref : r0;
   int it = 0;
   double rel = 1.0;
   bool breakdown = false;
@@ -721,7 +731,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
       host_scalars(c, c.dres, sizeof(double), s);
       if (!std::isfinite(c.hres[0])) fail(SEM_ENAN, "NaN/Inf in an inner product");
       ++it;
-      rel = std::sqrt(c.hres[0]) / r0;
+      rel = std::sqrt(c.hres[0]) / den;
       if (rel <= rtol) break;
       std::swap(z, zo);
       precondition(c, r, z, s);
@@ -744,7 +754,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
     // true residual
     opA<double>(c, F, x, q, s);
     launch_sub<double>(n, b, q, r, s);
-    double tr = wnorm(c, F, r, s) / r0;
+    double tr = wnorm(c, F, r, s) / den;
     info->rel_res = rel;
     info->true_rel_res = tr;
     if (tr <= rtol) {
@@ -758,7 +768,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
 }
 
 static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int maxit,
-                        sem_solve_info *info, hipStream_t s) {
+                        sem_solve_info *info, hipStream_t s, double rref = 0.0) {
   Level &F = c.lev[0];
   const int64_t n = F.nloc;
   const int m = c.opts.gmres_restart;
@@ -768,11 +778,12 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
   launch_sub<double>(n, b, q, r, s);
   const double r0 = wnorm(c, F, r, s);
   info->r0_norm = r0;
-  if (r0 == 0.0) {
-    info->rel_res = info->true_rel_res = 0.0;
+  if (r0 == 0.0 || (rref > 0.0 && r0 <= rtol * rref)) {
+    info->rel_res = info->true_rel_res = rref > 0.0 ? r0 / rref : 0.0;
     info->converged = 1;
     return 0;
   }
+  const double den = rref > 0.0 ? rref : r0;
   int it = 0;
   double rel = 1.0;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -809,7 +820,7 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
       g[j] = cs[j] * g[j];
       ++it;
       jused = j + 1;
-      rel = std::fabs(g[j + 1]) / r0;
+      rel = std::fabs(g[j + 1]) / den;
       if (!std::isfinite(rel)) fail(SEM_ENAN, "NaN in FGMRES");
       if (rel <= rtol || it >= maxit || hn == 0.0) break;
       launch_axpby<double>(n, 1.0 / hn, w, 0.0, w, s);
@@ -824,7 +835,7 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
     launch_mupdate(n, jused, Z, n, c.dres, x, 1.0, s);
     opA<double>(c, F, x, q, s);
     launch_sub<double>(n, b, q, r, s);
-    double tr = wnorm(c, F, r, s) / r0;
+    double tr = wnorm(c, F, r, s) / den;
     info->rel_res = rel;
     info->true_rel_res = tr;
     if (tr <= rtol) {
@@ -833,6 +844,60 @@ static int solve_fgmres(Ctx &c, const double *b, double *x, double rtol, int max
     }
   }
   info->converged = 0;
+  return it;
+}
+
+// Successive right sides (Sec. 3.2 / 4.2): start from the A-conjugate
+// projection of b onto the prior solutions, x0 = sum_i (x_i, b) x_i with
+// (x_i, A x_j) = delta_ij, so x0 is the A-norm best approximation of A^{-1} b in
+// their span; stop at ||r|| <= rtol ||b||; then A-orthogonalise the correction
+// x - x0 against the basis (classical Gram-Schmidt, two passes, using the
+// stored A x_i) and append it.  A full basis restarts from the solution alone.
+static int solve_projected(Ctx &c, const double *b, double *x, double rtol, int maxit,
+                           sem_solve_info *info, hipStream_t s) {
+  Level &F = c.lev[0];
+  const int64_t n = F.nloc;
+  const int L = c.nproj;
+  double *X = c.projX, *AX = c.projAX, *w = c.projW, *Aw = c.projAW;
+  const double nb = wnorm(c, F, b, s);
+  launch_fill(n, 0.0, x, s);
+  if (L > 0) {
+    launch_mdot(c, n, F.w64, L, X, n, b, c.dres, s);  // alpha_i = (x_i, b)
+    launch_mupdate(n, L, X, n, c.dres, x, 1.0, s);   // x0 = sum_i alpha_i x_i
+  }
+  launch_copy<double>(n, x, w, s);
+  int it;
+  if (c.opts.krylov == SEM_KRYLOV_FGMRES)
+    it = solve_fgmres(c, b, x, rtol, maxit, info, s, nb > 0.0 ? nb : 1.0);
+  else
+    it = solve_cg(c, b, x, rtol, maxit, c.opts.krylov == SEM_KRYLOV_FCG, info, s,
+                  nb > 0.0 ? nb : 1.0);
+  // the new direction: x - x0, or the whole solution when the basis is full
+  int Lb = L;
+  if (L == c.opts.proj_max) {
+    Lb = 0;
+    launch_copy<double>(n, x, w, s);
+  } else {
+    launch_axpby<double>(n, 1.0, x, -1.0, w, s);
+  }
+  opA<double>(c, F, w, Aw, s);
+  const double *pw[1] = {w}, *paw[1] = {Aw};
+  double n0;
+  dots(c, F, 1, pw, paw, &n0, s);
+  for (int pass = 0; pass < 2 && Lb > 0; ++pass) {
+    launch_mdot(c, n, F.w64, Lb, X, n, Aw, c.dres, s);  // beta_i = (x_i, A w)
+    launch_mupdate(n, Lb, X, n, c.dres, w, -1.0, s);
+    launch_mupdate(n, Lb, AX, n, c.dres, Aw, -1.0, s);
+  }
+  double nn;
+  dots(c, F, 1, pw, paw, &nn, s);
+  if (nn > 0.0 && nn > 1e-20 * n0) {  // keep only a direction the basis does not hold
+    const double inv = 1.0 / std::sqrt(nn);
+    launch_axpby<double>(n, inv, w, 0.0, X + (int64_t)Lb * n, s);
+    launch_axpby<double>(n, inv, Aw, 0.0, AX + (int64_t)Lb * n, s);
+    ++Lb;
+  }
+  c.nproj = Lb;
   return it;
 }
 
@@ -888,6 +953,7 @@ void sem_default_opts(sem_opts *o) {
   o->ax_variant = -1;
   o->batch_rhs = 0;
   o->coarse_solver = -1;
+  o->proj_max = 0;
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }
@@ -1120,7 +1186,9 @@ sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int3
     hipStream_t s = as_stream(stream);
     for (int l = 0; l < ctx->nlev; ++l) inf->lambda_tilde[l] = ctx->lev[l].lam_tilde;
     int it;
-    if (ctx->opts.krylov == SEM_KRYLOV_FGMRES)
+    if (ctx->opts.proj_max > 0)
+      it = solve_projected(*ctx, b, x, rtol, maxit, inf, s);
+    else if (ctx->opts.krylov == SEM_KRYLOV_FGMRES)
       it = solve_fgmres(*ctx, b, x, rtol, maxit, inf, s);
     else
       it = solve_cg(*ctx, b, x, rtol, maxit, ctx->opts.krylov == SEM_KRYLOV_FCG, inf, s);
@@ -1134,6 +1202,13 @@ sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int3
     return SEM_ENOCONV;
   }
   return st;
+}
+
+sem_status sem_projection_reset(sem_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) fail(SEM_EINVAL, "null context");
+    ctx->nproj = 0;
+  });
 }
 
 }  // extern "C"

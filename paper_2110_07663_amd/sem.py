@@ -28,7 +28,7 @@ EXPORTS = ("sem_default_opts", "sem_last_error", "sem_plan", "sem_setup", "sem_d
            "sem_level_info", "sem_gll", "sem_coords", "sem_gather", "sem_rhs", "sem_apply_A",
            "sem_apply_S", "sem_smooth", "sem_prolong", "sem_restrict", "sem_vcycle", "sem_solve",
            "sem_profile", "sem_profile_read", "sem_tune_space", "sem_tune_plan", "sem_tune",
-           "sem_batch_solve")
+           "sem_batch_solve", "sem_projection_reset")
 TUNE_MAX = 96
 PROF_NAMES = ("ax64", "ax32", "fdm", "gs64", "gs32", "coarse", "vcycle")
 
@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
                 ("krylov", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32),
                 ("ax_variant", ctypes.c_int32), ("batch_rhs", ctypes.c_int32),
-                ("coarse_solver", ctypes.c_int32)]
+                ("coarse_solver", ctypes.c_int32), ("proj_max", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -120,6 +120,7 @@ def lib():
         L.sem_batch_solve.argtypes = [i32, ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), dp, i32, i32, ctypes.POINTER(SolveInfo), vp]
         L.sem_profile.argtypes = [vp, i32]
+        L.sem_projection_reset.argtypes = [vp]
         L.sem_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS:
@@ -209,7 +210,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
               lmax_fac=1.1, arnoldi_steps=10, seed=0, lambda_override=None, smoother_prec=F64,
               fdm_prec=F64, krylov=KRYLOV_FCG, gmres_restart=20, coarse_tol=1e-10,
               coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1, batch_rhs=0,
-              coarse_solver=-1):
+              coarse_solver=-1, proj_max=0):
     o = default_opts()
     o.nlevels = len(schedule)
     for l, p in enumerate(schedule):
@@ -226,6 +227,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
     o.ax_variant = ax_variant
     o.batch_rhs = batch_rhs
     o.coarse_solver = coarse_solver
+    o.proj_max = proj_max
     return o
 
 
@@ -264,6 +266,10 @@ class Solver:
         if self.ctx:
             check(lib().sem_destroy(self.ctx))
             self.ctx = None
+
+    def projection_reset(self):
+        """Forget the prior solutions kept for opts.proj_max."""
+        check(lib().sem_projection_reset(self.ctx))
 
     def __del__(self):
         try:

@@ -289,3 +289,45 @@ def test_asm_vcycle_and_solve():
     L = Q.ora.fine
     r = bo - L.apply_A(host(xg).reshape(bo.shape))
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+
+
+@pytest.mark.parametrize("krylov", [sem.KRYLOV_FCG, sem.KRYLOV_FGMRES])
+def test_projection_of_successive_right_sides_matches_oracle(krylov):
+    """A-conjugate projection onto prior solutions (Sec. 3.2 / 4.2), room for
+    two: the projected initial residual, the iteration counts and the solutions
+    follow the oracle; a repeated right side needs no iteration; the third new
+    direction restarts the basis; reset empties it."""
+    from oracle import krylov as okr
+    P = Pair((2, 2, 2), 4, mesh="sin", schedule=(4, 2, 1), smoother="jacobi",
+             lambda_override=[1.8, 1.6], coarse="dense", krylov=krylov, proj_max=2)
+    L = P.ora.fine
+    solver = okr.fcg if krylov == sem.KRYLOV_FCG else okr.fgmres
+    proj = okr.Projection(L.apply_A, L.wdot, 2)
+    Xg = host(P.gpu.coords(0))
+    Xo = L.X
+    seq = [(1, 1, 1), (1, 1, 1), (1, 2, 1), (2, 1, 1), (1, 2, 1)]
+    for k, fr in enumerate(seq):
+        f, _ = wl.sinusoid(*fr)
+        bg = P.gpu.rhs(dev(f(Xg[0], Xg[1], Xg[2])))
+        bo = P.ora.rhs(f(Xo[0], Xo[1], Xo[2]))
+        nb = np.sqrt(L.wdot(bo, bo))
+        x0 = proj.guess(bo)
+        r = bo - L.apply_A(x0)
+        r0 = np.sqrt(L.wdot(r, r))
+        xg, ig = P.gpu.solve(bg, rtol=1e-9, maxit=100)
+        ro = okr.projected_solve(solver, proj, L.apply_A, P.ora.vcycle, bo, L.wdot, 1e-9, 100)
+        assert ig.converged and ro.converged
+        assert abs(ig.r0_norm - r0) <= 1e-6 * r0 + 1e-9 * nb, (k, ig.r0_norm, r0)
+        assert abs(ig.iters - ro.iters) <= 1, (k, ig.iters, ro.iters)
+        if k == 1:
+            assert ig.iters == 0 and ro.iters == 0
+        assert rel_err(host(xg), ro.x) < 1e-7
+        res = bo - L.apply_A(host(xg).reshape(bo.shape))
+        assert np.sqrt(L.wdot(res, res)) <= 2e-9 * nb
+    P.gpu.projection_reset()
+    f, _ = wl.sinusoid(1, 1, 1)
+    bg = P.gpu.rhs(dev(f(Xg[0], Xg[1], Xg[2])))
+    _, ig = P.gpu.solve(bg, rtol=1e-9, maxit=100)
+    b1 = P.ora.rhs(f(Xo[0], Xo[1], Xo[2]))
+    nb1 = np.sqrt(L.wdot(b1, b1))
+    assert abs(ig.r0_norm - nb1) <= 1e-12 * nb1  # empty basis: x0 = 0, r0 = ||b||

@@ -51,6 +51,15 @@ def test_host_side_validation_without_gpu():
     assert L.sem_plan(ctypes.byref(mesh), 12, bc, ctypes.byref(o_hi), ctypes.byref(n)) == sem.SEM_EUNSUPPORTED
     o_p0 = sem.make_opts(schedule=(5, 3, 1))
     assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_p0), ctypes.byref(n)) == sem.SEM_EINVAL
+    o_proj = sem.make_opts(schedule=(7, 3, 1), proj_max=33)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_proj), ctypes.byref(n)) == sem.SEM_EINVAL
+    assert b"proj_max" in L.sem_last_error()
+    o_proj.proj_max = 10  # room for 10 prior solutions and their products with A
+    n_proj = ctypes.c_size_t(0)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_proj), ctypes.byref(n_proj)) == sem.SEM_OK
+    n_plain = ctypes.c_size_t(0)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o), ctypes.byref(n_plain)) == sem.SEM_OK
+    assert n_proj.value >= n_plain.value + 20 * 8 * 8 ** 3 * 8  # 20 vectors of E (p+1)^3 doubles
     bad_bc = (ctypes.c_int8 * 6)(1, 1, 2, 1, 1, 1)
     assert L.sem_plan(ctypes.byref(mesh), 7, bad_bc, ctypes.byref(o), ctypes.byref(n)) == sem.SEM_EINVAL
     # plan grows with the problem

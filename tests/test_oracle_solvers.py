@@ -164,3 +164,66 @@ def test_chebyshev_bounds_sensitivity_underestimate_hurts():
     it_good = S_good.solve(b, tol=1e-8, maxit=300).iters
     it_bad = S_bad.solve(b, tol=1e-8, maxit=300).iters
     assert it_bad > it_good, (it_good, it_bad)
+
+
+def _projection_setup():
+    from oracle import krylov
+    S = _small_solver([4, 2, 1], smoother="jacobi", coarse="dense")
+    L = S.fine
+    A, free = _dense_operator(S)
+    rhs = []
+    for fr in [(1, 1, 1), (1, 2, 1), (2, 1, 1), (1, 1, 2)]:
+        f, _ = wl.sinusoid(*fr)
+        rhs.append(S.rhs(f(L.X[0], L.X[1], L.X[2])))
+    return krylov, S, L, A, free, rhs
+
+
+def test_projection_basis_is_a_orthonormal_and_guess_is_best_in_a_norm():
+    """Successive right sides (Sec. 3.2 / 4.2): after three solves the basis is
+    A-orthonormal, and the guess for a new b is the A-norm best approximation of
+    the exact solution in its span (the error is A-orthogonal to the basis)."""
+    krylov, S, L, A, free, rhs = _projection_setup()
+    P = krylov.Projection(L.apply_A, L.wdot, 5)
+    for b in rhs[:3]:
+        res = krylov.projected_solve(krylov.fcg, P, L.apply_A, S.vcycle, b, L.wdot, 1e-12, 200)
+        assert res.converged
+    G = np.array([[L.wdot(xi, L.apply_A(xj)) for xj in P.X] for xi in P.X])
+    np.testing.assert_allclose(G, np.eye(len(P.X)), atol=1e-10)
+    b = rhs[3]
+    x0 = P.guess(b)
+    exact = np.zeros(L.num.n)
+    exact[free] = np.linalg.solve(A, L.num.to_global(b)[free])
+    err = L.num.Q(exact) - x0
+    for xi in P.X:
+        assert abs(L.wdot(xi, L.apply_A(err))) < 1e-10 * np.sqrt(L.wdot(b, b))
+
+
+def test_projection_repeated_right_side_needs_no_iteration():
+    """A right side already solved is reproduced by the guess alone, and the
+    answer matches the dense solve; a new one converges to tol * ||b||."""
+    krylov, S, L, A, free, rhs = _projection_setup()
+    P = krylov.Projection(L.apply_A, L.wdot, 4)
+    b = rhs[0]
+    first = krylov.projected_solve(krylov.fcg, P, L.apply_A, S.vcycle, b, L.wdot, 1e-10, 200)
+    again = krylov.projected_solve(krylov.fcg, P, L.apply_A, S.vcycle, b, L.wdot, 1e-8, 200)
+    assert first.iters > 0 and again.iters == 0 and again.converged
+    ref = np.zeros(L.num.n)
+    ref[free] = np.linalg.solve(A, L.num.to_global(b)[free])
+    np.testing.assert_allclose(L.num.to_global(again.x), ref, atol=1e-8 * np.abs(ref).max())
+    other = krylov.projected_solve(krylov.fcg, P, L.apply_A, S.vcycle, rhs[1], L.wdot, 1e-8, 200)
+    r = rhs[1] - L.apply_A(other.x)
+    assert np.sqrt(L.wdot(r, r)) <= 1e-8 * np.sqrt(L.wdot(rhs[1], rhs[1]))
+
+
+def test_projection_restarts_when_full():
+    """With room for two vectors the third update restarts from the solution alone."""
+    krylov, S, L, A, free, rhs = _projection_setup()
+    P = krylov.Projection(L.apply_A, L.wdot, 2)
+    sizes = []
+    for b in rhs[:3]:
+        res = krylov.projected_solve(krylov.fcg, P, L.apply_A, S.vcycle, b, L.wdot, 1e-10, 200)
+        sizes.append(len(P.X))
+    assert sizes == [1, 2, 1]
+    x = res.x / np.sqrt(L.wdot(res.x, L.apply_A(res.x)))  # the third solution, A-normalised
+    np.testing.assert_allclose(P.X[0], x, atol=1e-12 * np.abs(x).max())
+    np.testing.assert_allclose(P.AX[0], L.apply_A(x), atol=1e-12 * np.abs(L.apply_A(x)).max())
