@@ -83,7 +83,10 @@ typedef struct {
   int32_t p_levels[8];        /* strictly decreasing degrees, e.g. {7, 3, 1}              */
   int32_t precond;            /* sem_precond                                              */
   int32_t smoother;           /* sem_smoother, used on every level except the coarsest    */
-  int32_t cheb_order;         /* K of Algorithm 2 (K products with A per application)     */
+  int32_t cheb_order;         /* K of Algorithm 2 (K products with A per application);    */
+                              /* 0: no acceleration (Sec. 2.2.2): the smoother S once,    */
+                              /* x += S(b - Ax), in an additive V-cycle x = S b +         */
+                              /* P V(P^T b) without post-smoothing                        */
   double lmin_fac, lmax_fac;  /* (lambda_min, lambda_max) = (lmin_fac, lmax_fac)*lambda~  */
   int32_t arnoldi_steps;      /* Arnoldi steps on S*A for lambda~ (<= 16)                 */
   uint64_t seed;              /* Arnoldi start vector: SplitMix64(seed XOR gid) in [-1,1) */

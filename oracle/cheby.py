@@ -25,12 +25,17 @@ import numpy as np
 
 
 def chebyshev(apply_A, apply_S, b, x, lmin, lmax, K):
-    """Return the correction e of Algorithm 2 (x is None means x = 0)."""
+    """Return the correction e of Algorithm 2 (x is None means x = 0).
+
+    K = 0 reads as the smoother without Chebyshev acceleration (Sec. 2.2.2):
+    e = S (b - A x), undamped."""
+    r = apply_S(b if x is None else b - apply_A(x))
+    if K == 0:
+        return r
     theta = 0.5 * (lmax + lmin)
     delta = 0.5 * (lmax - lmin)
     sigma = theta / delta
     rho = 1.0 / sigma
-    r = apply_S(b if x is None else b - apply_A(x))
     d = r / theta
     e = np.zeros_like(b)
     for _ in range(K):

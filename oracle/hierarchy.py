@@ -70,6 +70,7 @@ class Solver:
         for l in range(len(self.levels) - 1):
             self.levels[l].J_to_coarse = _gll.interpolation(self.schedule[l + 1], self.schedule[l])
         self.coarse_tol, self.coarse_maxit, self.coarse = coarse_tol, coarse_maxit, coarse
+        self.cheb_order = cheb_order
         self.seed = seed
         for l, L in enumerate(self.levels[:-1]):
             L.K = cheb_order
@@ -123,6 +124,8 @@ class Solver:
         return res.x
 
     def vcycle(self, r):
+        if self.cheb_order == 0:  # smoothers without acceleration: additive cycle
+            return _mg.vcycle_additive(self.levels, r, self.coarse_solve)
         return _mg.vcycle(self.levels, r, self.coarse_solve)
 
     def solve(self, b, tol=1e-8, maxit=500, krylov='fcg', x0=None, restart=20):

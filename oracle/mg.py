@@ -49,3 +49,17 @@ def vcycle(levels, b, coarse_solve, level=0):
     x = x + prolong(L.J_to_coarse, ec)
     x = x + L.smooth(b, x)
     return x
+
+
+def vcycle_additive(levels, b, coarse_solve, level=0):
+    """V-cycle for smoothers without Chebyshev acceleration (Sec. 2.2.2): the
+    smoother and the coarse-grid correction act on the same right side and are
+    added, with no residual re-evaluation and no post-smoothing:
+    x = S_l b + P_l V_{l+1}(P_l^T b), the coarsest level solved."""
+    if level == len(levels) - 1:
+        return coarse_solve(b)
+    L, C = levels[level], levels[level + 1]
+    x = L.apply_S(b)
+    bc = restrict(L.num, C.num, L.J_to_coarse, b)
+    ec = vcycle_additive(levels, bc, coarse_solve, level + 1)
+    return x + prolong(L.J_to_coarse, ec)

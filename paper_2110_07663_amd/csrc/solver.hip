@@ -436,9 +436,11 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
     launch_sub<T>(n, b, w, w, s);
     opS<T>(c, L, w, r, s, nv);
   }
-  if (L.K == 0) {
-    launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), x_zero, s);
-    launch_axpby<T>(n, (T)1, d, (T)1, x, s);
+  if (L.K == 0) {  // no acceleration: the smoother alone, x += S (b - A x)
+    if (x_zero)
+      launch_copy<T>(n, r, x, s);
+    else
+      launch_axpby<T>(n, (T)1, r, (T)1, x, s);
     return;
   }
   // a zero start is not written: the first update takes x as zero
@@ -522,6 +524,14 @@ static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1) {
   }
   Level &C = c.lev[l + 1];
   T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *w = Vec<T>::w(L);
+  if (L.K == 0) {  // smoother without acceleration: additive cycle, x = S b + P V(P^T b)
+    opS<T>(c, L, b, x, s, nv);
+    launch_restrict<T>(L, C, b, Vec<T>::b(C), s, nv);
+    launch_gs<T>(C, Vec<T>::b(C), s, nv);
+    vcycle_level<T>(c, l + 1, s, nv);
+    launch_prolong<T>(L, C, Vec<T>::x(C), x, s, nv);
+    return;
+  }
   chebyshev<T>(c, L, b, x, true, s, nv);                // x = M b
   opA<T>(c, L, x, w, s, nv);                            // r_C = P^T (b - A x)
   launch_restrict<T>(L, C, w, Vec<T>::b(C), s, nv, b);

@@ -331,3 +331,34 @@ def test_projection_of_successive_right_sides_matches_oracle(krylov):
     b1 = P.ora.rhs(f(Xo[0], Xo[1], Xo[2]))
     nb1 = np.sqrt(L.wdot(b1, b1))
     assert abs(ig.r0_norm - nb1) <= 1e-12 * nb1  # empty basis: x0 = 0, r0 = ||b||
+
+
+@pytest.mark.parametrize("smoother,sched,prec", [
+    ("jacobi", (4, 2, 1), sem.F64), ("ras", (5, 3, 1), sem.F64), ("asm", (5, 3, 1), sem.F64),
+    ("ras", (7, 3, 1), sem.F32),
+])
+def test_additive_vcycle_without_acceleration(smoother, sched, prec):
+    """cheb_order = 0 (Sec. 2.2.2, smoothers without Chebyshev acceleration):
+    additive V-cycle x = S b + P V(P^T b) against the oracle (FP64 1e-12, FP32
+    1e-5), the un-accelerated smoothing step x + S(b - A x), and a solve that
+    reaches the tolerance."""
+    t = _torch()
+    P = Pair((3, 2, 3), sched[0], mesh="sin", schedule=sched, smoother=smoother, cheb_order=0,
+             coarse="dense", smoother_prec=prec, lambda_override=[1.5] * (len(sched) - 1))
+    tol = 1e-12 if prec == sem.F64 else 1e-5
+    for seed in (71, 72):
+        g, o = P.random_local(seed)
+        assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < tol
+    if prec == sem.F64:
+        b, bo = P.random_local(73)
+        x, xo = P.random_local(74)
+        xs = x.clone()
+        P.gpu.smooth(b, xs)
+        ref = xo + P.ora.fine.smooth(bo, xo)
+        assert rel_err(host(xs), ref) < 1e-12
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=300)
+    assert info.converged
+    L = P.ora.fine
+    r = bo - L.apply_A(host(xg).reshape(bo.shape))
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8

@@ -227,3 +227,49 @@ def test_projection_restarts_when_full():
     x = res.x / np.sqrt(L.wdot(res.x, L.apply_A(res.x)))  # the third solution, A-normalised
     np.testing.assert_allclose(P.X[0], x, atol=1e-12 * np.abs(x).max())
     np.testing.assert_allclose(P.AX[0], L.apply_A(x), atol=1e-12 * np.abs(L.apply_A(x)).max())
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "asm", "ras"])
+def test_additive_vcycle_is_the_sum_of_smoother_and_coarse_correction(smoother):
+    """Smoothers without Chebyshev acceleration (Sec. 2.2.2) use an additive
+    V-cycle: on global free vectors M = S_0 + P_0 (S_1 + P_1 A_2^{-1} P_1^T) P_0^T,
+    assembled here column by column from the level operators and a dense coarse
+    solve; with the symmetric Jacobi smoother M is symmetric (the Schwarz forms
+    carry a diagonal weight after their sum and are not)."""
+    S = _small_solver([4, 2, 1], smoother=smoother, coarse="dense", cheb_order=0)
+    L0, L1, L2 = S.levels
+    f0 = np.nonzero(L0.num.mask_global > 0)[0]
+    f1 = np.nonzero(L1.num.mask_global > 0)[0]
+
+    def columns(apply, num_in, num_out, free_in, free_out):
+        out = np.zeros((free_out.size, free_in.size))
+        for j, g in enumerate(free_in):
+            e = np.zeros(num_in.n)
+            e[g] = 1.0
+            out[:, j] = num_out.to_global(apply(num_in.Q(e)))[free_out]
+        return out
+
+    M = columns(S.vcycle, L0.num, L0.num, f0, f0)
+    S0 = columns(L0.apply_S, L0.num, L0.num, f0, f0)
+    S1 = columns(L1.apply_S, L1.num, L1.num, f1, f1)
+    R0 = columns(lambda v: mg.restrict(L0.num, L1.num, L0.J_to_coarse, v), L0.num, L1.num, f0, f1)
+    P0 = columns(lambda v: mg.prolong(L0.J_to_coarse, v), L1.num, L0.num, f1, f0)
+    f2 = np.nonzero(L2.num.mask_global > 0)[0]
+    R1 = columns(lambda v: mg.restrict(L1.num, L2.num, L1.J_to_coarse, v), L1.num, L2.num, f1, f2)
+    P1 = columns(lambda v: mg.prolong(L1.J_to_coarse, v), L2.num, L1.num, f2, f1)
+    A2, _ = _dense_operator(S, level=2)
+    np.testing.assert_allclose(R0, P0.T, atol=1e-13)
+    ref = S0 + P0 @ (S1 + P1 @ np.linalg.solve(A2, R1)) @ R0
+    np.testing.assert_allclose(M, ref, atol=1e-11 * np.abs(ref).max())
+    if smoother == "jacobi":
+        np.testing.assert_allclose(M, M.T, atol=1e-11 * np.abs(M).max())
+
+
+def test_unaccelerated_smoother_is_plain_schwarz():
+    """cheb_order = 0: the smoothing step is x + S (b - A x), undamped."""
+    S = _small_solver([4, 2, 1], smoother="ras", coarse="dense", cheb_order=0)
+    L = S.fine
+    rng = np.random.default_rng(3)
+    b = L.num.mask * L.num.Q(rng.standard_normal(L.num.n))
+    x = L.num.mask * L.num.Q(rng.standard_normal(L.num.n))
+    np.testing.assert_allclose(L.smooth(b, x), L.apply_S(b - L.apply_A(x)), atol=1e-14)
