@@ -257,8 +257,18 @@ __device__ inline double2 ld2(const double *p, int64_t t) {
   if constexpr (V::value) return reinterpret_cast<const double2 *>(p)[t];
   return make_double2(p[2 * t], p[2 * t + 1]);
 }
-template <int ND, typename V>
-__global__ __launch_bounds__(256) void k_wdots(int64_t n, const double *__restrict__ w, Ptr4 a,
+// the dot weights mask/multiplicity (0, 1, 1/2, 1/4, 1/8) are exact in FP32:
+// the FP32 copy gives the same products with half the weight traffic
+template <typename V>
+__device__ inline double2 ld2(const float *p, int64_t t) {
+  if constexpr (V::value) {
+    const float2 v = reinterpret_cast<const float2 *>(p)[t];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  return make_double2((double)p[2 * t], (double)p[2 * t + 1]);
+}
+template <int ND, typename V, typename WT>
+__global__ __launch_bounds__(256) void k_wdots(int64_t n, const WT *__restrict__ w, Ptr4 a,
                                                Ptr4 b, double *partials, unsigned *counter,
                                                double *out) {
   double acc[ND], acc2[ND];
@@ -278,7 +288,7 @@ __global__ __launch_bounds__(256) void k_wdots(int64_t n, const double *__restri
   }
   if (t0 == 0 && (n & 1)) {
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc[j] += w[n - 1] * a.p[j][n - 1] * b.p[j][n - 1];
+    for (int j = 0; j < ND; ++j) acc[j] += (double)w[n - 1] * a.p[j][n - 1] * b.p[j][n - 1];
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
@@ -298,9 +308,9 @@ __device__ inline void st2(double *p, int64_t t, double2 v) {
     p[2 * t + 1] = v.y;
   }
 }
-template <typename V>
+template <typename V, typename WT>
 __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
-                                                const double *__restrict__ w,
+                                                const WT *__restrict__ w,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, double *partials,
@@ -323,44 +333,132 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
   if (t0 == 0 && (n & 1)) {
     x[n - 1] += alpha * p[n - 1];
     r[n - 1] -= alpha * q[n - 1];
-    acc[0] += w[n - 1] * r[n - 1] * r[n - 1];
+    acc[0] += (double)w[n - 1] * r[n - 1] * r[n - 1];
   }
   acc[0] += acc2;
   if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) out[0] = acc[0];
 }
 
 void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
-                   const double *q, double *x, double *r, double *out, hipStream_t s) {
-  if (aligned16(w) && aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r))
-    hipLaunchKernelGGL(k_fcg_xr<std::true_type>, dim3(red_grid(n)), dim3(256), 0, s, n, alpha, w,
+                   const double *q, double *x, double *r, double *out, hipStream_t s,
+                   const float *w32) {
+  const bool al = aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r);
+  const unsigned g = red_grid(n);
+  if (w32 && al && ((uintptr_t)w32 & 7) == 0)
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, alpha, w32,
+                       p, q, x, r, c.partials, c.counter, out);
+  else if (al && aligned16(w))
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
                        p, q, x, r, c.partials, c.counter, out);
   else
-    hipLaunchKernelGGL(k_fcg_xr<std::false_type>, dim3(red_grid(n)), dim3(256), 0, s, n, alpha, w,
+    hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
                        p, q, x, r, c.partials, c.counter, out);
   SEM_LAUNCH("k_fcg_xr");
 }
 
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
-                  const double *const *b, double *out, hipStream_t s) {
+                  const double *const *b, double *out, hipStream_t s, const float *w32) {
   Ptr4 pa{}, pb{};
   for (int j = 0; j < nd; ++j) {
     pa.p[j] = a[j];
     pb.p[j] = b[j];
   }
   unsigned g = red_grid(n);
-  bool al = aligned16(w);
+  bool al = true;
   for (int j = 0; j < nd; ++j) al = al && aligned16(a[j]) && aligned16(b[j]);
-#define WD(ND, V) hipLaunchKernelGGL((k_wdots<ND, V>), dim3(g), dim3(256), 0, s, n, w, pa, pb, c.partials, c.counter, out)
   if (nd < 1 || nd > 4) fail(SEM_EINVAL, "wdots: at most 4 products");
-  if (al) {
-    if (nd == 1) WD(1, std::true_type); else if (nd == 2) WD(2, std::true_type);
-    else if (nd == 3) WD(3, std::true_type); else WD(4, std::true_type);
-  } else {
-    if (nd == 1) WD(1, std::false_type); else if (nd == 2) WD(2, std::false_type);
-    else if (nd == 3) WD(3, std::false_type); else WD(4, std::false_type);
-  }
+#define WD(ND, V, WT, W) hipLaunchKernelGGL((k_wdots<ND, V, WT>), dim3(g), dim3(256), 0, s, n, W, pa, pb, c.partials, c.counter, out)
+#define WD_ALL(V, WT, W)                                                     \
+  do {                                                                       \
+    if (nd == 1) WD(1, V, WT, W);                                            \
+    else if (nd == 2) WD(2, V, WT, W);                                       \
+    else if (nd == 3) WD(3, V, WT, W);                                       \
+    else WD(4, V, WT, W);                                                    \
+  } while (0)
+  if (w32 && al && ((uintptr_t)w32 & 7) == 0)
+    WD_ALL(std::true_type, float, w32);
+  else if (al && aligned16(w))
+    WD_ALL(std::true_type, double, w);
+  else
+    WD_ALL(std::false_type, double, w);
+#undef WD_ALL
 #undef WD
   SEM_LAUNCH("k_wdots");
+}
+
+// (r, z_j)_w for FP32 z_j (j < ND): the preconditioned residual of the mixed
+// path is the exact FP64 widening of the V-cycle's FP32 output, so it is read
+// in FP32; same pairing and partial sums as k_wdots (the same results)
+template <int ND, typename WT>
+__global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restrict__ w,
+                                                  const double *__restrict__ r,
+                                                  const float *__restrict__ z0,
+                                                  const float *__restrict__ z1, double *partials,
+                                                  unsigned *counter, double *out) {
+  double acc[ND], acc2[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = acc2[j] = 0.0;
+  const int64_t n2 = n / 2;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wt = ld2<std::true_type>(w, t);
+    const double2 x = ld2<std::true_type>(r, t);
+    const float *zs[2] = {z0, z1};
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const double2 y = ld2<std::true_type>(zs[j], t);
+      acc[j] += wt.x * x.x * y.x;
+      acc2[j] += wt.y * x.y * y.y;
+    }
+  }
+  if (t0 == 0 && (n & 1)) {
+    const float *zs[2] = {z0, z1};
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += (double)w[n - 1] * r[n - 1] * (double)zs[j][n - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
+  if (last_block_sum<ND>(acc, partials, counter) && threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) out[j] = acc[j];
+  }
+}
+
+void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32, const double *r,
+                     const float *z0, const float *z1, double *out, hipStream_t s) {
+  const int nd = z1 ? 2 : 1;
+  const unsigned g = red_grid(n);
+  if (!aligned16(r) || ((uintptr_t)z0 & 7) || (z1 && ((uintptr_t)z1 & 7)))
+    fail(SEM_EINVAL, "wdots_rz: misaligned vectors");
+  if (w32 && ((uintptr_t)w32 & 7) == 0) {
+    if (nd == 1)
+      hipLaunchKernelGGL((k_wdots_rz<1, float>), dim3(g), dim3(256), 0, s, n, w32, r, z0, z1,
+                         c.partials, c.counter, out);
+    else
+      hipLaunchKernelGGL((k_wdots_rz<2, float>), dim3(g), dim3(256), 0, s, n, w32, r, z0, z1,
+                         c.partials, c.counter, out);
+  } else {
+    if (!aligned16(w)) fail(SEM_EINVAL, "wdots_rz: misaligned weights");
+    if (nd == 1)
+      hipLaunchKernelGGL((k_wdots_rz<1, double>), dim3(g), dim3(256), 0, s, n, w, r, z0, z1,
+                         c.partials, c.counter, out);
+    else
+      hipLaunchKernelGGL((k_wdots_rz<2, double>), dim3(g), dim3(256), 0, s, n, w, r, z0, z1,
+                         c.partials, c.counter, out);
+  }
+  SEM_LAUNCH("k_wdots_rz");
+}
+
+// p = z + beta p with FP32 z (FP64 p)
+__global__ void k_zp(int64_t n, const float *__restrict__ z, double beta, double *__restrict__ p) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double a = 1.0;
+  p[t] = a * (double)z[t] + beta * p[t];
+}
+void launch_zp(int64_t n, const float *z, double beta, double *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zp, dim3(nb(n, 256)), dim3(256), 0, s, n, z, beta, p);
+  SEM_LAUNCH("k_zp");
 }
 
 // block of inner products <V_j, x>_w for j < k (k <= 8 per pass)

@@ -210,6 +210,7 @@ struct Ctx {
   // outer Krylov vectors (FP64, finest level)
   double *kr = nullptr, *kz = nullptr, *kzold = nullptr, *kp = nullptr, *kq = nullptr,
          *kx = nullptr;
+  float *fzo = nullptr;  // mixed path: the previous FP32 preconditioned residual (nvmax x nloc)
   double *gV = nullptr, *gZ = nullptr;  // FGMRES bases [(m+1)][nloc], [m][nloc]
   // A-conjugate projection onto prior solutions: X [proj_max][nloc] (A-orthonormal),
   // AX = A X, and two work vectors; nproj basis vectors in use
@@ -294,10 +295,16 @@ void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zer
 void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
                        hipStream_t s);
 // weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)
+// (w32: an FP32 copy of the weights, used when given; the weights are exact in FP32)
 void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
-                   const double *q, double *x, double *r, double *out, hipStream_t s);
+                   const double *q, double *x, double *r, double *out, hipStream_t s,
+                   const float *w32 = nullptr);
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
-                  const double *const *b, double *out, hipStream_t s);
+                  const double *const *b, double *out, hipStream_t s, const float *w32 = nullptr);
+// out[j] = (r, z_j)_w for FP32 z_0 (and z_1 when not null), on the device
+void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32, const double *r,
+                     const float *z0, const float *z1, double *out, hipStream_t s);
+void launch_zp(int64_t n, const float *z, double beta, double *p, hipStream_t s);  // p = z + beta p
 // block dots for Gram-Schmidt: out[j] = sum_i w_i V_j(i) x(i), j < k
 void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *V, int64_t ld,
                  const double *x, double *out, hipStream_t s);

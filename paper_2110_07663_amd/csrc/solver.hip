@@ -185,6 +185,8 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
   c.kp = A.take<double>(F.nloc);
   c.kq = A.take<double>(F.nloc);
   c.kx = A.take<double>(F.nloc);
+  c.fzo = nullptr;
+  if (lowp && o.precond == SEM_PRECOND_PMG && c.nlev > 1) c.fzo = A.take<float>(nv * F.nloc);
   if (o.krylov == SEM_KRYLOV_FGMRES) {
     c.gV = A.take<double>((size_t)(o.gmres_restart + 1) * F.nloc);
     c.gZ = A.take<double>((size_t)o.gmres_restart * F.nloc);
@@ -569,10 +571,23 @@ static void precondition(Ctx &c, const double *r, double *z, hipStream_t s, int 
   }
 }
 
+// Mixed path: z = M r is the exact FP64 widening of the V-cycle's FP32 output,
+// so the outer iteration keeps it in FP32 (F.f_x, and the previous one in
+// c.fzo, swapped each iteration) instead of storing an FP64 copy.
+static bool z_in_f32(const Ctx &c) {
+  return c.lowp && c.fzo && c.opts.precond == SEM_PRECOND_PMG && !c.lev[0].coarse;
+}
+static void precondition_f32(Ctx &c, const double *r, hipStream_t s) {
+  Level &F = c.lev[0];
+  ProfScope ps(c, F, SEM_PROF_VCYCLE, s);
+  launch_copy_cvt_d2f(F.nloc, r, F.f_b, s);
+  vcycle_level<float>(c, 0, s);
+}
+
 // weighted dots on the finest level, read back to the host
 static void dots(Ctx &c, const Level &L, int nd, const double *const *a, const double *const *b,
                  double *out, hipStream_t s) {
-  launch_wdots(c, L.nloc, L.w64, nd, a, b, c.dres, s);
+  launch_wdots(c, L.nloc, L.w64, nd, a, b, c.dres, s, L.w32);
   host_scalars(c, c.dres, nd * sizeof(double), s);
   for (int j = 0; j < nd; ++j) {
     out[j] = c.hres[j];
@@ -717,14 +732,31 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
   int it = 0;
   double rel = 1.0;
   bool breakdown = false;
-  while (it < maxit) {
-    precondition(c, r, z, s);
-    SEM_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    double rz;
-    {
-      const double *a[1] = {r}, *bb[1] = {z};
-      dots(c, F, 1, a, bb, &rz, s);
+  const bool zf = z_in_f32(c);
+  // (r, z) and, for the flexible variant, (r, z_old), read back
+  auto rz_dots = [&](int nd, double *out) {
+    if (zf) {
+      launch_wdots_rz(c, n, F.w64, F.w32, r, F.f_x, nd == 2 ? c.fzo : nullptr, c.dres, s);
+      host_scalars(c, c.dres, nd * sizeof(double), s);
+      for (int j = 0; j < nd; ++j) {
+        out[j] = c.hres[j];
+        if (!std::isfinite(out[j])) fail(SEM_ENAN, "NaN/Inf in an inner product");
+      }
+    } else {
+      const double *a[2] = {r, r}, *bb[2] = {z, zo};
+      dots(c, F, nd, a, bb, out, s);
     }
+  };
+  while (it < maxit) {
+    double rz;
+    if (zf) {
+      precondition_f32(c, r, s);
+      launch_copy_cvt_f2d(n, F.f_x, p, s);
+    } else {
+      precondition(c, r, z, s);
+      SEM_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    rz_dots(1, &rz);
     while (it < maxit) {
       opA<double>(c, F, p, q, s);
       double pq;
@@ -737,29 +769,35 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
         break;
       }
       const double alpha = rz / pq;
-      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s);  // x, r and (r, r) in one pass
+      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s, F.w32);  // x, r, (r, r) in one pass
       host_scalars(c, c.dres, sizeof(double), s);
       if (!std::isfinite(c.hres[0])) fail(SEM_ENAN, "NaN/Inf in an inner product");
       ++it;
       rel = std::sqrt(c.hres[0]) / den;
       if (rel <= rtol) break;
-      std::swap(z, zo);
-      precondition(c, r, z, s);
+      if (zf) {
+        std::swap(F.f_x, c.fzo);  // the V-cycle writes the new z; the old one stays
+        precondition_f32(c, r, s);
+      } else {
+        std::swap(z, zo);
+        precondition(c, r, z, s);
+      }
       double beta;
       if (flexible) {
-        const double *a[2] = {r, r}, *bb[2] = {z, zo};
         double d2[2];
-        dots(c, F, 2, a, bb, d2, s);
+        rz_dots(2, d2);
         beta = (d2[0] - d2[1]) / rz;
         rz = d2[0];
       } else {
-        const double *a[1] = {r}, *bb[1] = {z};
         double rzn;
-        dots(c, F, 1, a, bb, &rzn, s);
+        rz_dots(1, &rzn);
         beta = rzn / rz;
         rz = rzn;
       }
-      launch_axpby<double>(n, 1.0, z, beta, p, s);
+      if (zf)
+        launch_zp(n, F.f_x, beta, p, s);
+      else
+        launch_axpby<double>(n, 1.0, z, beta, p, s);
     }
     // true residual
     opA<double>(c, F, x, q, s);
