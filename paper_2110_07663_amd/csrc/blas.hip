@@ -81,27 +81,6 @@ void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s) {
 template void launch_sub<double>(int64_t, const double *, const double *, double *, hipStream_t);
 template void launch_sub<float>(int64_t, const float *, const float *, float *, hipStream_t);
 
-// Chebyshev (Algorithm 2): d = r / theta, x = 0 when starting from zero (the
-// caller may instead let the first update treat x as zero: x_zero = false here)
-template <typename T>
-__global__ void k_cheb_init(int64_t n, T *__restrict__ x, const T *__restrict__ r,
-                            T *__restrict__ d, T inv_theta, int x_zero) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  d[t] = r[t] * inv_theta;
-  if (x_zero) x[t] = T(0);
-}
-template <typename T>
-void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zero, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_init<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, inv_theta,
-                     (int)x_zero);
-  SEM_LAUNCH("k_cheb_init");
-}
-template void launch_cheb_init<double>(int64_t, double *, const double *, double *, double, bool,
-                                       hipStream_t);
-template void launch_cheb_init<float>(int64_t, float *, const float *, float *, float, bool,
-                                      hipStream_t);
-
 // one pass of the loop body: x += d_k; r -= S A d_k (= t); d = a d_k + c r
 // (xz: x is zero on entry and is not read)
 template <typename T>
@@ -126,6 +105,40 @@ template void launch_cheb_update<double>(int64_t, double *, double *, double *, 
                                          double, double, hipStream_t, bool);
 template void launch_cheb_update<float>(int64_t, float *, float *, float *, const float *, float,
                                         float, hipStream_t, bool);
+
+// The first pass of the loop without forming d_0 = r_0 / theta beforehand: A
+// and S are linear, so the caller applies them to r_0 and this pass scales
+// (tv = S A r_0).  x += d_0; r -= tv / theta; d = a d_0 + c r; with `last` the
+// closing x += d as well (r and d then unwritten).  xz: x is zero on entry.
+template <typename T>
+__global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
+                             const T *__restrict__ tv, T inv_theta, T a, T c, int xz, int last) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const T r0 = r[t];
+  const T d0 = r0 * inv_theta;
+  const T x1 = xz ? d0 : x[t] + d0;
+  const T rn = r0 - tv[t] * inv_theta;
+  const T dn = a * d0 + c * rn;
+  if (last) {
+    x[t] = dn + x1;
+  } else {
+    x[t] = x1;
+    r[t] = rn;
+    d[t] = dn;
+  }
+}
+template <typename T>
+void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a, T c,
+                       bool x_zero, bool last, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, inv_theta,
+                     a, c, (int)x_zero, (int)last);
+  SEM_LAUNCH("k_cheb_first");
+}
+template void launch_cheb_first<double>(int64_t, double *, double *, double *, const double *,
+                                        double, double, double, bool, bool, hipStream_t);
+template void launch_cheb_first<float>(int64_t, float *, float *, float *, const float *, float,
+                                       float, float, bool, bool, hipStream_t);
 
 // the last pass of the loop and the closing x += d in one: r and d are not
 // needed afterwards, so only x is written (same roundings as the two passes)
@@ -313,8 +326,8 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
                                                 const WT *__restrict__ w,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
-                                                double *__restrict__ r, double *partials,
-                                                unsigned *counter, double *out) {
+                                                double *__restrict__ r, float *__restrict__ rf,
+                                                double *partials, unsigned *counter, double *out) {
   double acc[1] = {0.0}, acc2 = 0.0;
   const int64_t n2 = n / 2;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -327,12 +340,17 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
     rv.y -= alpha * qv.y;
     st2<V>(x, t, xv);
     st2<V>(r, t, rv);
+    if (rf) {  // the V-cycle's FP32 input, written on the way
+      rf[2 * t] = (float)rv.x;
+      rf[2 * t + 1] = (float)rv.y;
+    }
     acc[0] += wt.x * rv.x * rv.x;
     acc2 += wt.y * rv.y * rv.y;
   }
   if (t0 == 0 && (n & 1)) {
     x[n - 1] += alpha * p[n - 1];
     r[n - 1] -= alpha * q[n - 1];
+    if (rf) rf[n - 1] = (float)r[n - 1];
     acc[0] += (double)w[n - 1] * r[n - 1] * r[n - 1];
   }
   acc[0] += acc2;
@@ -341,18 +359,18 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
 
 void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
                    const double *q, double *x, double *r, double *out, hipStream_t s,
-                   const float *w32) {
+                   const float *w32, float *rf) {
   const bool al = aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r);
   const unsigned g = red_grid(n);
   if (w32 && al && ((uintptr_t)w32 & 7) == 0)
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, alpha, w32,
-                       p, q, x, r, c.partials, c.counter, out);
+                       p, q, x, r, rf, c.partials, c.counter, out);
   else if (al && aligned16(w))
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
-                       p, q, x, r, c.partials, c.counter, out);
+                       p, q, x, r, rf, c.partials, c.counter, out);
   else
     hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
-                       p, q, x, r, c.partials, c.counter, out);
+                       p, q, x, r, rf, c.partials, c.counter, out);
   SEM_LAUNCH("k_fcg_xr");
 }
 

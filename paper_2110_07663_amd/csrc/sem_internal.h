@@ -290,15 +290,18 @@ void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipSt
 template <typename T>
 void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c,
                       hipStream_t s, bool x_zero = false);  // x += d + (a d + c (r - t))
+// first pass from r_0 and t = S A r_0 (d_0 = r_0 / theta formed inside)
 template <typename T>
-void launch_cheb_init(int64_t n, T *x, const T *r, T *d, T inv_theta, bool x_zero, hipStream_t s);
+void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a, T c,
+                       bool x_zero, bool last, hipStream_t s);
 void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
                        hipStream_t s);
 // weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)
 // (w32: an FP32 copy of the weights, used when given; the weights are exact in FP32)
+// (rf: also store the new r in FP32 there, when given)
 void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
                    const double *q, double *x, double *r, double *out, hipStream_t s,
-                   const float *w32 = nullptr);
+                   const float *w32 = nullptr, float *rf = nullptr);
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
                   const double *const *b, double *out, hipStream_t s, const float *w32 = nullptr);
 // out[j] = (r, z_j)_w for FP32 z_0 (and z_1 when not null), on the device

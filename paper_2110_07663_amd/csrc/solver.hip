@@ -445,18 +445,20 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
       launch_axpby<T>(n, (T)1, r, (T)1, x, s);
     return;
   }
-  // a zero start is not written: the first update takes x as zero
-  launch_cheb_init<T>(n, x, r, d, (T)(1.0 / theta), false, s);
+  // pass 0 works from r_0 itself (d_0 = r_0 / theta is formed inside the update,
+  // A and S being linear); a zero start is not written
   for (int k = 0; k < L.K; ++k) {
-    opA<T>(c, L, d, w, s, nv);
+    opA<T>(c, L, k == 0 ? r : d, w, s, nv);
     opS<T>(c, L, w, t, s, nv);
     double rho_new = 1.0 / (2.0 * sigma - rho);
     const T a = (T)(rho_new * rho), cc = (T)(2.0 * rho_new / delta);
-    const bool xz = x_zero && k == 0;
-    if (k + 1 < L.K)
-      launch_cheb_update<T>(n, x, r, d, t, a, cc, s, xz);
+    const bool last = k + 1 == L.K;
+    if (k == 0)
+      launch_cheb_first<T>(n, x, r, d, t, (T)(1.0 / theta), a, cc, x_zero, last, s);
+    else if (!last)
+      launch_cheb_update<T>(n, x, r, d, t, a, cc, s);
     else  // last pass and the closing x += d together
-      launch_cheb_last<T>(n, x, r, d, t, a, cc, s, xz);
+      launch_cheb_last<T>(n, x, r, d, t, a, cc, s);
     rho = rho_new;
   }
 }
@@ -577,10 +579,10 @@ static void precondition(Ctx &c, const double *r, double *z, hipStream_t s, int 
 static bool z_in_f32(const Ctx &c) {
   return c.lowp && c.fzo && c.opts.precond == SEM_PRECOND_PMG && !c.lev[0].coarse;
 }
-static void precondition_f32(Ctx &c, const double *r, hipStream_t s) {
+static void precondition_f32(Ctx &c, const double *r, hipStream_t s, bool have_f32 = false) {
   Level &F = c.lev[0];
   ProfScope ps(c, F, SEM_PROF_VCYCLE, s);
-  launch_copy_cvt_d2f(F.nloc, r, F.f_b, s);
+  if (!have_f32) launch_copy_cvt_d2f(F.nloc, r, F.f_b, s);  // else F.f_b holds it already
   vcycle_level<float>(c, 0, s);
 }
 
@@ -769,7 +771,8 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
         break;
       }
       const double alpha = rz / pq;
-      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s, F.w32);  // x, r, (r, r) in one pass
+      // x, r, (r, r) in one pass (and the V-cycle's FP32 copy of r on the mixed path)
+      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s, F.w32, zf ? F.f_b : nullptr);
       host_scalars(c, c.dres, sizeof(double), s);
       if (!std::isfinite(c.hres[0])) fail(SEM_ENAN, "NaN/Inf in an inner product");
       ++it;
@@ -777,7 +780,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
       if (rel <= rtol) break;
       if (zf) {
         std::swap(F.f_x, c.fzo);  // the V-cycle writes the new z; the old one stays
-        precondition_f32(c, r, s);
+        precondition_f32(c, r, s, true);
       } else {
         std::swap(z, zo);
         precondition(c, r, z, s);
