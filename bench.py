@@ -371,11 +371,7 @@ def fdm_flops(L):
 # values in profiles/kernels_layer_shift_32cube_p7.md).  A kernel whose code
 # changed after its counters were taken is left out (traffic null).
 TRAFFIC_32CUBE_P7 = {
-    "ax64": 1073871232,   # k_ax8_f64<true>
-    "ax32": 536992085,    # k_ax8_f32<true>
     "fdm": 300670635,     # k_fdm_lines<7,float,false>
-    "gs32": 249354760,    # k_gs_dir<float,0..2>, the three passes of one application
-    "gs64": 439530087,    # k_gs_dir<double,0..2>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 

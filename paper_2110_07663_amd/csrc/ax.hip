@@ -149,7 +149,13 @@ __device__ __forceinline__ void st(T *p, T v) {
   else *p = v;
 }
 
-template <typename T, bool NT>
+// XF: the four elements of a workgroup are consecutive along x (nex a multiple
+// of 4), and the copies on their three shared x-faces are summed here, in LDS,
+// before the store (the first pass of the direction-by-direction gather-scatter
+// for those faces; the faces between workgroups and the Dirichlet x-faces are
+// left to the gather-scatter).  Each pair is summed as (p-face + 0-face), the
+// order the gather-scatter uses.
+template <typename T, bool NT, bool XF>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
                                          const T *__restrict__ G, const T *__restrict__ Dg,
                                          T *__restrict__ v, int nv, T *sD, T (*sU)[72],
@@ -211,58 +217,93 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
     acc[k] += a;
     __builtin_amdgcn_wave_barrier();
   }
+  if constexpr (XF) {  // every wave of the block is live (E is a multiple of 4)
+    if (i == 0) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) sr[k * N + j] = acc[k];
+    }
+    if (i == N - 1) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) ss[k * N + j] = acc[k];
+    }
+    __syncthreads();
+    if (i == N - 1 && w < 3) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc[k] = sS[w][k * N + j] + sR[w + 1][k * N + j];
+    }
+    if (i == 0 && w > 0) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc[k] = sS[w - 1][k * N + j] + sR[w][k * N + j];
+    }
+  }
   T *ve = v + e * N3 + lane;
 #pragma unroll
   for (int k = 0; k < N; ++k) st<NT>(ve + k * NN, acc[k]);
 }
 
 // register budgets: FP64 at 4 waves/SIMD, FP32 at 6
-template <bool NT>
+template <bool NT, bool XF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ax8_f64(
     int64_t E, const double *__restrict__ u, const double *__restrict__ G,
     const double *__restrict__ Dg, double *__restrict__ v, int nv) {
   __shared__ double sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<double, NT>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
+  ax8_body<double, NT, XF>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
 }
-template <bool NT>
+template <bool NT, bool XF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32(
     int64_t E, const float *__restrict__ u, const float *__restrict__ G,
     const float *__restrict__ Dg, float *__restrict__ v, int nv) {
   __shared__ float sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<float, NT>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
+  ax8_body<float, NT, XF>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
+}
+
+template <typename T, bool XF>
+static void ax8_launch(const Level &L, const T *u, T *v, const T *G, const T *D, int nv,
+                       hipStream_t s) {
+  // several right sides share G through L2: plain loads (non-temporal ones would bypass it)
+  const dim3 grid((unsigned)((L.E + 3) / 4 * nv));
+  const bool nt = L.ax_variant == 2 && nv == 1;
+  if constexpr (sizeof(T) == 8) {
+    if (nt)
+      hipLaunchKernelGGL((k_ax8_f64<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+    else
+      hipLaunchKernelGGL((k_ax8_f64<false, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((k_ax8_f32<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+    else
+      hipLaunchKernelGGL((k_ax8_f32<false, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+  }
+  SEM_LAUNCH("k_ax8");
 }
 
 template <typename T, int N>
-static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, int nv, hipStream_t s) {
+static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, int nv, bool xf,
+                 hipStream_t s) {
   if constexpr (N == 8) {
-    // several right sides share G through L2: plain loads (non-temporal ones would bypass it)
     if (L.ax_variant >= 1) {
-      const dim3 grid((unsigned)((L.E + 3) / 4 * nv));
-      const bool nt = L.ax_variant == 2 && nv == 1;
-      if constexpr (sizeof(T) == 8) {
-        if (nt)
-          hipLaunchKernelGGL(k_ax8_f64<true>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
-        else
-          hipLaunchKernelGGL(k_ax8_f64<false>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
-      } else {
-        if (nt)
-          hipLaunchKernelGGL(k_ax8_f32<true>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
-        else
-          hipLaunchKernelGGL(k_ax8_f32<false>, grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
-      }
-      SEM_LAUNCH("k_ax8");
+      if (xf)
+        ax8_launch<T, true>(L, u, v, G, D, nv, s);
+      else
+        ax8_launch<T, false>(L, u, v, G, D, nv, s);
       return;
     }
   }
+  if (xf) fail(SEM_EINVAL, "x-face summation in Ax needs the p = 7 one-wave kernel");
   using S = AxShape<N>;
   unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB * nv);
   hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v, nv);
   SEM_LAUNCH("k_ax");
 }
 
+bool ax_sums_x_faces(const Level &L) {
+  return L.gs_struct && L.xfuse && L.N == 8 && L.ax_variant >= 1 && L.nex % 4 == 0;
+}
+
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv) {
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv, bool xf) {
   if (nv < 1) fail(SEM_EINVAL, "Ax: no right side");
+  if (xf && !ax_sums_x_faces(L)) fail(SEM_EINVAL, "Ax: x-face summation not available here");
   const T *G;
   const T *D;
   if constexpr (sizeof(T) == 8) {
@@ -274,21 +315,21 @@ void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv) {
   }
   if (!G || !D) fail(SEM_EINVAL, "geometric factors of this precision were not built");
   switch (L.N) {
-    case 2: ax_n<T, 2>(L, u, v, G, D, nv, s); break;
-    case 3: ax_n<T, 3>(L, u, v, G, D, nv, s); break;
-    case 4: ax_n<T, 4>(L, u, v, G, D, nv, s); break;
-    case 5: ax_n<T, 5>(L, u, v, G, D, nv, s); break;
-    case 6: ax_n<T, 6>(L, u, v, G, D, nv, s); break;
-    case 7: ax_n<T, 7>(L, u, v, G, D, nv, s); break;
-    case 8: ax_n<T, 8>(L, u, v, G, D, nv, s); break;
-    case 9: ax_n<T, 9>(L, u, v, G, D, nv, s); break;
-    case 10: ax_n<T, 10>(L, u, v, G, D, nv, s); break;
-    case 11: ax_n<T, 11>(L, u, v, G, D, nv, s); break;
+    case 2: ax_n<T, 2>(L, u, v, G, D, nv, xf, s); break;
+    case 3: ax_n<T, 3>(L, u, v, G, D, nv, xf, s); break;
+    case 4: ax_n<T, 4>(L, u, v, G, D, nv, xf, s); break;
+    case 5: ax_n<T, 5>(L, u, v, G, D, nv, xf, s); break;
+    case 6: ax_n<T, 6>(L, u, v, G, D, nv, xf, s); break;
+    case 7: ax_n<T, 7>(L, u, v, G, D, nv, xf, s); break;
+    case 8: ax_n<T, 8>(L, u, v, G, D, nv, xf, s); break;
+    case 9: ax_n<T, 9>(L, u, v, G, D, nv, xf, s); break;
+    case 10: ax_n<T, 10>(L, u, v, G, D, nv, xf, s); break;
+    case 11: ax_n<T, 11>(L, u, v, G, D, nv, xf, s); break;
     default: fail(SEM_EUNSUPPORTED, "Ax: unsupported degree");
   }
 }
-template void launch_ax<double>(const Level &, const double *, double *, hipStream_t, int);
-template void launch_ax<float>(const Level &, const float *, float *, hipStream_t, int);
+template void launch_ax<double>(const Level &, const double *, double *, hipStream_t, int, bool);
+template void launch_ax<float>(const Level &, const float *, float *, hipStream_t, int, bool);
 
 // diag(A^e) per point: only q' on the r-, s- or t-line through q contribute, and
 // the cross terms only at q' = q.

@@ -331,15 +331,54 @@ __global__ void k_gs_dir(T *__restrict__ v, GsGrid g, int64_t E) {
   if (pos == cnt - 1 && bhi) v[hi] = T(0);
 }
 
+// The x pass when the faces inside each group of 4 consecutive elements along x
+// are summed already: thread (group q, line) sums the face between the group's
+// last element and the next group's first, and zeroes the Dirichlet x-faces of
+// the row ends (the low face of the group's first element, the high face of
+// its last).  Requires nex to be a multiple of 4.
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s, int nv) {
+__global__ void k_gs_xb(T *__restrict__ v, GsGrid g, int64_t E) {
+  const int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
+  const int N = g.N, N2 = N * N;
+  const int64_t groups = E / 4;
+  if (t >= groups * N2) return;
+  v += blockIdx.y * E * N2 * N;  // right side blockIdx.y
+  const unsigned ut = (unsigned)t;
+  const int64_t q = ut / (unsigned)N2;
+  const int rem = (int)(ut - (unsigned)q * (unsigned)N2);
+  const int64_t N3 = (int64_t)N2 * N;
+  const int64_t e0 = 4 * q, e3 = e0 + 3;
+  const int64_t ex0 = e0 % g.nex, ex3 = ex0 + 3;
+  const int64_t line = (int64_t)rem * N;
+  if (g.bc[0] && ex0 == 0) v[e0 * N3 + line] = T(0);
+  const int64_t hi = e3 * N3 + line + g.p;
+  if (ex3 + 1 < g.nex) {
+    const int64_t lo = (e3 + 1) * N3 + line;
+    const T sum = v[hi] + v[lo];
+    v[hi] = sum;
+    v[lo] = sum;
+  } else if (g.bc[1]) {
+    v[hi] = T(0);
+  }
+}
+
+template <typename T>
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks) {
+  if (x_in_blocks && (!L.gs_struct || L.nex % 4 != 0))
+    fail(SEM_EINVAL, "gather-scatter: block x-faces need the direction passes and nex % 4 == 0");
   if (L.gs_struct) {
     GsGrid g;
     g.nex = L.nex; g.ney = L.ney; g.nez = L.nez; g.p = L.p; g.N = L.N;
     for (int f = 0; f < 6; ++f) g.bc[f] = L.bc[f];
     const dim3 grid(nb(L.E * L.N * L.N, 256), (unsigned)nv);
-    hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
-    SEM_LAUNCH("k_gs_dir");
+    if (x_in_blocks) {
+      const dim3 gx(nb(L.E / 4 * L.N * L.N, 256), (unsigned)nv);
+      hipLaunchKernelGGL((k_gs_xb<T>), gx, dim3(256), 0, s, v, g, L.E);
+      SEM_LAUNCH("k_gs_xb");
+    } else {
+      hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
+      SEM_LAUNCH("k_gs_dir");
+    }
     hipLaunchKernelGGL((k_gs_dir<T, 1>), dim3(grid), dim3(256), 0, s, v, g, L.E);
     SEM_LAUNCH("k_gs_dir");
     hipLaunchKernelGGL((k_gs_dir<T, 2>), dim3(grid), dim3(256), 0, s, v, g, L.E);
@@ -353,8 +392,8 @@ void launch_gs(const Level &L, T *v, hipStream_t s, int nv) {
     SEM_LAUNCH("k_gs");
   }
 }
-template void launch_gs<double>(const Level &, double *, hipStream_t, int);
-template void launch_gs<float>(const Level &, float *, hipStream_t, int);
+template void launch_gs<double>(const Level &, double *, hipStream_t, int, bool);
+template void launch_gs<float>(const Level &, float *, hipStream_t, int, bool);
 
 void launch_weights(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_fill1, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, L.w64, L.w32);

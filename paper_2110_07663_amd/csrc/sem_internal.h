@@ -94,6 +94,7 @@ struct Level {
   int nex = 0, ney = 0, nez = 0;
   int bc[6] = {0, 0, 0, 0, 0, 0};
   bool gs_struct = true;             // false: the sorted-numbering segments (perm/off)
+  bool xfuse = true;                 // the p = 7 Ax sums x-faces inside its workgroups
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
   double *xi = nullptr, *wq = nullptr, *D64 = nullptr;
@@ -264,14 +265,20 @@ void build_gather_scatter(const Ctx &c, Level &L, Arena &scratch, hipStream_t s)
 void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, hipStream_t s,
                    int nv = 1, int64_t ug_stride = 0);
 // nv > 1: nv vectors nloc apart (several right sides of one problem)
+// x_in_blocks: the x-faces inside each group of 4 elements along x are summed
+// already (Ax with xf); only the faces between groups and the Dirichlet x-faces
+// remain for the x pass
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1);
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1, bool x_in_blocks = false);
 void launch_weights(const Level &L, hipStream_t s);
 void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s);
 
 // ax.hip
+// xf: also sum the x-faces shared inside each workgroup (see ax_sums_x_faces);
+// the following launch_gs must then be told (x_in_blocks)
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv = 1);
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv = 1, bool xf = false);
+bool ax_sums_x_faces(const Level &L);
 void launch_diag(const Level &L, double *d, hipStream_t s);
 
 // blas.hip

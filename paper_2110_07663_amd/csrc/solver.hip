@@ -301,9 +301,12 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
     L.ney = m->ney;
     L.nez = m->nez;
     for (int f = 0; f < 6; ++f) L.bc[f] = bc[f];
-    {
+    {  // SEM_GS_SORTED=1: the sorted-segment gather-scatter instead of the direction passes
       const char *gsv = getenv("SEM_GS_SORTED");
       L.gs_struct = !(gsv && gsv[0] == '1');
+      // SEM_AX_XFUSE=0: the p = 7 Ax leaves every x-face to the gather-scatter
+      const char *xfv = getenv("SEM_AX_XFUSE");
+      L.xfuse = !(xfv && xfv[0] == '0');
     }
     L.lowp = c.lowp;
     // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element,
@@ -387,12 +390,13 @@ struct ProfScope {
 // nv right sides, nloc apart (batch lanes sharing a V-cycle); 1 otherwise
 template <typename T>
 static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv = 1) {
+  const bool xf = ax_sums_x_faces(L);  // Ax sums the x-faces inside its workgroups
   {
     ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_AX64 : SEM_PROF_AX32, s);
-    launch_ax<T>(L, u, Au, s, nv);
+    launch_ax<T>(L, u, Au, s, nv, xf);
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, Au, s, nv);
+  launch_gs<T>(L, Au, s, nv, xf);
 }
 
 template <typename T>

@@ -55,17 +55,21 @@ def test_apply_A_fp64(shape, p, mesh):
     assert rel_err(Ag, Ao) < 1e-12
 
 
-@pytest.mark.parametrize("sorted_gs", [False, True])
+@pytest.mark.parametrize("sorted_gs,xfuse", [(False, True), (False, False), (True, True)])
 @pytest.mark.parametrize("shape,p,bc", [
     ((3, 2, 5), 3, (1, 0, 1, 1, 0, 1)), ((1, 4, 2), 7, (1,) * 6), ((2, 2, 2), 1, (0,) * 6),
-    ((4, 3, 2), 7, (0, 1, 1, 0, 0, 1)),
+    ((4, 3, 2), 7, (0, 1, 1, 0, 0, 1)), ((8, 2, 3), 7, (1, 1, 0, 1, 1, 0)),
+    ((12, 1, 2), 7, (0, 0, 1, 1, 1, 1)),
 ])
-def test_gather_scatter_paths(monkeypatch, sorted_gs, shape, p, bc):
-    """Direction-by-direction (default) and sorted-segment QQ^T: A matches the
-    oracle, every copy of a global node holds the same bits, Dirichlet copies
-    are exactly zero; FP32 likewise to its tolerance."""
+def test_gather_scatter_paths(monkeypatch, sorted_gs, xfuse, shape, p, bc):
+    """Direction passes (default; at p = 7 with nex a multiple of 4 the Ax
+    kernel sums the x-faces inside its workgroups first), the same without that
+    fusion, and sorted segments for QQ^T: A matches the oracle, every copy of a
+    global node holds the same bits, Dirichlet copies are exactly zero; FP32
+    likewise to its tolerance."""
     t = __import__("torch")
     monkeypatch.setenv("SEM_GS_SORTED", "1" if sorted_gs else "0")
+    monkeypatch.setenv("SEM_AX_XFUSE", "1" if xfuse else "0")
     P = Pair(shape, p, mesh="sin", bc=bc, smoother_prec=sem.F32)
     num = P.ora.levels[0].num
     g, o = P.random_local(21, masked=False)
