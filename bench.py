@@ -371,7 +371,6 @@ def fdm_flops(L):
 # values in profiles/kernels_layer_shift_32cube_p7.md).  A kernel whose code
 # changed after its counters were taken is left out (traffic null).
 TRAFFIC_32CUBE_P7 = {
-    "fdm": 300670635,     # k_fdm_lines<7,float,false>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 

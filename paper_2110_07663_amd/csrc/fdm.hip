@@ -345,7 +345,7 @@ struct FdmLines {
   static constexpr int N = P + 1;
   static constexpr int BS = ((PB * PB + 63) / 64) * 64;
   static constexpr int RS = PB | 1;
-  static constexpr int PS = (PB * RS) | 1;
+  static constexpr int PS = PB * RS;  // fewer bank conflicts than an odd plane stride (modelled)
 };
 
 template <int P, typename T, bool ASM>
@@ -442,29 +442,33 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
       for (int m = 0; m < PB; ++m) o[m] += Sz[k * PB + m] * v[k];
 #pragma unroll
     for (int m = 0; m < PB; ++m) o[m] *= fdm_inv<T>(lxy + le[2 * PB + m]);
+    // RAS keeps the element's own nodes only: the way back needs planes
+    // k = 1..p+1 (and below, rows j = 1..p+1); ASM needs the whole box
+    constexpr int K0 = ASM ? 0 : 1, K1 = ASM ? PB : PB - 1;
 #pragma unroll
-    for (int k = 0; k < PB; ++k) v[k] = T(0);
+    for (int k = K0; k < K1; ++k) v[k] = T(0);
 #pragma unroll
     for (int m = 0; m < PB; ++m)
 #pragma unroll
-      for (int k = 0; k < PB; ++k) v[k] += Sz[k * PB + m] * o[m];
+      for (int k = K0; k < K1; ++k) v[k] += Sz[k * PB + m] * o[m];
 #pragma unroll
-    for (int k = 0; k < PB; ++k) buf1[k * PS + b * RS + a] = v[k];
+    for (int k = K0; k < K1; ++k) buf1[k * PS + b * RS + a] = v[k];
   }
   __syncthreads();
   // y back: t[c][j][a] = sum_m Sy[j][m] t[c][m][a]    line (a, c)
-  if (act) {
+  if (act && (ASM || (hi >= 1 && hi <= PB - 2))) {
+    constexpr int J0 = ASM ? 0 : 1, J1 = ASM ? PB : PB - 1;
     const int a = lo, c = hi;
 #pragma unroll
     for (int m = 0; m < PB; ++m) v[m] = buf1[c * PS + m * RS + a];
 #pragma unroll
-    for (int j = 0; j < PB; ++j) o[j] = T(0);
+    for (int j = J0; j < J1; ++j) o[j] = T(0);
 #pragma unroll
     for (int m = 0; m < PB; ++m)
 #pragma unroll
-      for (int j = 0; j < PB; ++j) o[j] += Sy[j * PB + m] * v[m];
+      for (int j = J0; j < J1; ++j) o[j] += Sy[j * PB + m] * v[m];
 #pragma unroll
-    for (int j = 0; j < PB; ++j) buf0[c * PS + j * RS + a] = o[j];
+    for (int j = J0; j < J1; ++j) buf0[c * PS + j * RS + a] = o[j];
   }
   __syncthreads();
   // x back: out[c][b][i] = sum_m Sx[i][m] t[c][b][m]
