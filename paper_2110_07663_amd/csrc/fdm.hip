@@ -234,21 +234,25 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
   elem_coords(e, nex, ney, ex, ey, ez);
   T col[PB];
   if (act) {
-    // box node (a, b, c): direction offsets and local indices
-    int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0);
-    int li = a == 0 ? P - 1 : (a == PB - 1 ? 1 : a - 1);
-    int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
-    int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
-    bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
+    // box node (a, b, c): direction offsets and local indices; one base pointer
+    // per column, unconditional loads, as in k_fdm_lines
+    const int dx = a == 0 ? -1 : (a == PB - 1 ? 1 : 0);
+    const int li = a == 0 ? P - 1 : (a == PB - 1 ? 1 : a - 1);
+    const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
+    const int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+    const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
+    const bool okd = okxy && ez > 0, oku = okxy && ez + 1 < nez;
+    const int64_t plane = (int64_t)nex * ney * N3;
+    const T *cp = r + (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
+    const T lower = cp[okd ? (P - 1) * N * N - plane : 0];
+    const T upper = cp[oku ? N * N + plane : 0];
 #pragma unroll
-    for (int c = 0; c < PB; ++c) {  // unconditional loads, as in k_fdm_lines
-      int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
-      int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
-      bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
-      int64_t en = ok ? e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
-      T v = r[en * N3 + (lk * N + lj) * N + li];
-      col[c] = ok ? v : T(0);
+    for (int c = 1; c < PB - 1; ++c) {
+      const T v = cp[(c - 1) * N * N];
+      col[c] = okxy ? v : T(0);
     }
+    col[0] = okd ? lower : T(0);
+    col[PB - 1] = oku ? upper : T(0);
 #pragma unroll
     for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
   }
@@ -371,7 +375,11 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
   const T *__restrict__ le = lamg + e * 3 * PB;
   T v[PB], o[PB];
 
-  // gather the box: thread (a, b) = (lo, hi) reads the line along c
+  // gather the box: thread (a, b) = (lo, hi) reads the line along c.  One base
+  // pointer per line (the x/y neighbour's column) and compile-time offsets for
+  // the planes; the two overlap planes come from the z neighbours.  Loads are
+  // unconditional (an outside neighbour reads the element itself and is
+  // replaced by 0), so that all PB loads are in flight together.
   {
     int64_t ex, ey, ez;
     elem_coords(e, nex, ney, ex, ey, ez);
@@ -382,17 +390,18 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
       const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0);
       const int lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
       const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
-      // unconditional loads (an outside neighbour reads the element itself and
-      // is replaced by 0), so that all PB loads are in flight together
+      const bool okd = okxy && ez > 0, oku = okxy && ez + 1 < nez;
+      const int64_t plane = (int64_t)nex * ney * N3;
+      const T *col = r + (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
+      const T lower = col[okd ? (P - 1) * N * N - plane : 0];
+      const T upper = col[oku ? N * N + plane : 0];
 #pragma unroll
-      for (int c = 0; c < PB; ++c) {
-        const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0);
-        const int lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
-        const bool ok = okxy && (ez + dz >= 0) && (ez + dz < nez);
-        const int64_t en = ok ? e + dx + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
-        const T val = r[en * N3 + (lk * N + lj) * N + li];
-        v[c] = ok ? val : T(0);
+      for (int c = 1; c < PB - 1; ++c) {
+        const T val = col[(c - 1) * N * N];
+        v[c] = okxy ? val : T(0);
       }
+      v[0] = okd ? lower : T(0);
+      v[PB - 1] = oku ? upper : T(0);
 #pragma unroll
       for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = v[c];
     }
