@@ -371,6 +371,9 @@ def fdm_flops(L):
 # values in profiles/kernels_layer_shift_32cube_p7.md).  A kernel whose code
 # changed after its counters were taken is left out (traffic null).
 TRAFFIC_32CUBE_P7 = {
+    "ax64": 1073880235,   # k_ax8_f64<true,true>
+    "ax32": 536988629,    # k_ax8_f32<true,true>
+    "fdm": 301148288,     # k_fdm_lines<7,float,false>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
