@@ -373,7 +373,7 @@ def fdm_flops(L):
 TRAFFIC_32CUBE_P7 = {
     "ax64": 1073880235,   # k_ax8_f64<true,true>
     "ax32": 536988629,    # k_ax8_f32<true,true>
-    "fdm": 301148288,     # k_fdm_lines<7,float,false>
+    "fdm": 301107243,     # k_fdm_lines<7,float,false>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 

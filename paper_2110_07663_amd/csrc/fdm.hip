@@ -194,10 +194,12 @@ __device__ inline float fdm_inv<float>(float d) {
   return d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;
 }
 
+// rs (may be null): the local solves act on r - rs (a residual formed as read)
 template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
-    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
-    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z, int nv) {
+    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ rs,
+    const T *__restrict__ Sg, const T *__restrict__ lamg, const T *__restrict__ W,
+    T *__restrict__ z, int nv) {
   using F = FdmShape<P>;
   constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
   constexpr int N3 = N * N * N, PB2 = PB * PB;
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
   int vec;
   const int64_t e = split_rhs(xcd_block(), nv, vec);
   r += (int64_t)vec * E * N3;
+  if (rs) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
   const int tid = threadIdx.x;
   const int a = tid % PB, b = tid / PB;
@@ -243,14 +246,22 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
     const bool okd = okxy && ez > 0, oku = okxy && ez + 1 < nez;
     const int64_t plane = (int64_t)nex * ney * N3;
-    const T *cp = r + (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
-    const T lower = cp[okd ? (P - 1) * N * N - plane : 0];
-    const T upper = cp[oku ? N * N + plane : 0];
+    const int64_t base = (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
+    const T *cp = r + base;
+    const int64_t od = okd ? (P - 1) * N * N - plane : 0, ou = oku ? N * N + plane : 0;
+    T lower = cp[od];
+    T upper = cp[ou];
 #pragma unroll
-    for (int c = 1; c < PB - 1; ++c) {
-      const T v = cp[(c - 1) * N * N];
-      col[c] = okxy ? v : T(0);
+    for (int c = 1; c < PB - 1; ++c) col[c] = cp[(c - 1) * N * N];
+    if (rs) {
+      const T *cs = rs + base;
+      lower -= cs[od];
+      upper -= cs[ou];
+#pragma unroll
+      for (int c = 1; c < PB - 1; ++c) col[c] -= cs[(c - 1) * N * N];
     }
+#pragma unroll
+    for (int c = 1; c < PB - 1; ++c) col[c] = okxy ? col[c] : T(0);
     col[0] = okd ? lower : T(0);
     col[PB - 1] = oku ? upper : T(0);
 #pragma unroll
@@ -354,8 +365,9 @@ struct FdmLines {
 
 template <int P, typename T, bool ASM>
 __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
-    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ Sg,
-    const T *__restrict__ lamg, const T *__restrict__ W, T *__restrict__ z, int nv) {
+    int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ rs,
+    const T *__restrict__ Sg, const T *__restrict__ lamg, const T *__restrict__ W,
+    T *__restrict__ z, int nv) {
   using F = FdmLines<P>;
   constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
   constexpr int N3 = N * N * N, PB2 = PB * PB;
@@ -365,6 +377,7 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
   int vec;
   const int64_t e = split_rhs(xcd_block(), nv, vec);
   r += (int64_t)vec * E * N3;
+  if (rs) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
   const int tid = threadIdx.x;
   const bool act = tid < PB2;
@@ -392,14 +405,22 @@ __global__ __launch_bounds__(FdmLines<P>::BS) void k_fdm_lines(
       const bool okxy = (ex + dx >= 0) && (ex + dx < nex) && (ey + dy >= 0) && (ey + dy < ney);
       const bool okd = okxy && ez > 0, oku = okxy && ez + 1 < nez;
       const int64_t plane = (int64_t)nex * ney * N3;
-      const T *col = r + (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
-      const T lower = col[okd ? (P - 1) * N * N - plane : 0];
-      const T upper = col[oku ? N * N + plane : 0];
+      const int64_t base = (okxy ? e + dx + (int64_t)dy * nex : e) * N3 + lj * N + li;
+      const T *col = r + base;
+      const int64_t od = okd ? (P - 1) * N * N - plane : 0, ou = oku ? N * N + plane : 0;
+      T lower = col[od];
+      T upper = col[ou];
 #pragma unroll
-      for (int c = 1; c < PB - 1; ++c) {
-        const T val = col[(c - 1) * N * N];
-        v[c] = okxy ? val : T(0);
+      for (int c = 1; c < PB - 1; ++c) v[c] = col[(c - 1) * N * N];
+      if (rs) {  // r - rs: the residual formed as it is read
+        const T *cs = rs + base;
+        lower -= cs[od];
+        upper -= cs[ou];
+#pragma unroll
+        for (int c = 1; c < PB - 1; ++c) v[c] -= cs[(c - 1) * N * N];
       }
+#pragma unroll
+      for (int c = 1; c < PB - 1; ++c) v[c] = okxy ? v[c] : T(0);
       v[0] = okd ? lower : T(0);
       v[PB - 1] = oku ? upper : T(0);
 #pragma unroll
@@ -569,21 +590,21 @@ template void launch_asm_sum<float>(const Ctx &, const Level &, const float *, f
                                     hipStream_t);
 
 template <int P, typename T, bool ASM>
-static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *S, const T *lam,
-                       const T *W, T *out, hipStream_t s, int nv) {
+static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *rs, const T *S,
+                       const T *lam, const T *W, T *out, hipStream_t s, int nv) {
   const dim3 grid((unsigned)(L.E * nv));
   if (FdmLines<P>::PB * FdmLines<P>::PB > 64 && c.fdm_lines)
     hipLaunchKernelGGL((k_fdm_lines<P, T, ASM>), grid, dim3(FdmLines<P>::BS), 0, s, L.E, c.nex,
-                       c.ney, c.nez, r, S, lam, W, out, nv);
+                       c.ney, c.nez, r, rs, S, lam, W, out, nv);
   else
     hipLaunchKernelGGL((k_fdm<P, T, ASM>), grid, dim3(FdmShape<P>::BS), 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, S, lam, W, out, nv);
+                       c.nez, r, rs, S, lam, W, out, nv);
   SEM_LAUNCH("k_fdm");
 }
 
 template <typename T, int P>
 static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                  int nv) {
+                  int nv, const T *rs) {
   const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
   const T *lam = sizeof(T) == 8 ? (const T *)L.lam64 : (const T *)L.lam32;
   const T *W = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
@@ -592,33 +613,34 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
     T *box = sizeof(T) == 8 ? (T *)L.box64 : (T *)L.box32;
     if (!box) fail(SEM_EINVAL, "ASM box buffer was not built");
     for (int k = 0; k < nv; ++k) {  // one box buffer: right sides in turn
-      fdm_launch<P, T, true>(c, L, r + k * L.nloc, S, lam, W, box, s, 1);
+      fdm_launch<P, T, true>(c, L, r + k * L.nloc, rs ? rs + k * L.nloc : nullptr, S, lam, W, box,
+                             s, 1);
       launch_asm_sum<T>(c, L, box, z + k * L.nloc, s);
     }
     return;
   }
-  fdm_launch<P, T, false>(c, L, r, S, lam, W, z, s, nv);
+  fdm_launch<P, T, false>(c, L, r, rs, S, lam, W, z, s, nv);
 }
 
 template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                int nv) {
+                int nv, const T *rs) {
   switch (L.p) {
-    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s, nv); break;
-    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s, nv); break;
-    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s, nv); break;
-    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s, nv); break;
-    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s, nv); break;
-    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s, nv); break;
-    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s, nv); break;
-    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s, nv); break;
-    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s, nv); break;
+    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s, nv, rs); break;
     default: fail(SEM_EUNSUPPORTED, "FDM: unsupported degree");
   }
 }
 template void launch_fdm<double>(const Ctx &, const Level &, const double *, double *, bool,
-                                 hipStream_t, int);
+                                 hipStream_t, int, const double *);
 template void launch_fdm<float>(const Ctx &, const Level &, const float *, float *, bool,
-                                hipStream_t, int);
+                                hipStream_t, int, const float *);
 
 }  // namespace sem

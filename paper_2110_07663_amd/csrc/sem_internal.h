@@ -340,9 +340,10 @@ void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStre
 
 // fdm.hip
 void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s);
+// rs (may be null): solve on r - rs (a residual formed as it is read)
 template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                int nv = 1);
+                int nv = 1, const T *rs = nullptr);
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
                      int prec, hipStream_t s, int nv = 1);
 template <typename T>

@@ -399,11 +399,20 @@ static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, 
   launch_gs<T>(L, Au, s, nv, xf);
 }
 
+// rs (may be null): apply S to r - rs; r - rs is formed as the VALU FDM reads
+// it, else stored into rs first
 template <typename T>
-static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1) {
+static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1,
+                T *rs = nullptr) {
   const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
   const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
+  const bool mfma = sizeof(T) == 4 && (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16);
+  if (rs && (!schwarz || asm_mode || mfma)) {  // form r - rs in rs, then apply S to it
+    launch_sub<T>(L.nloc * nv, r, rs, rs, s);
+    r = rs;
+    rs = nullptr;
+  }
   if (!schwarz) {
     const T *dinv = Vec<T>::dinv(L);
     if (!dinv) fail(SEM_EINVAL, "Jacobi data of this precision were not built");
@@ -419,7 +428,7 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
         mma = true;
       }
     }
-    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv);
+    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs);
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
@@ -439,8 +448,7 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
     opS<T>(c, L, b, r, s, nv);
   } else {
     opA<T>(c, L, x, w, s, nv);
-    launch_sub<T>(n, b, w, w, s);
-    opS<T>(c, L, w, r, s, nv);
+    opS<T>(c, L, b, r, s, nv, w);  // r = S (b - A x)
   }
   if (L.K == 0) {  // no acceleration: the smoother alone, x += S (b - A x)
     if (x_zero)
