@@ -175,13 +175,33 @@ void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // apply: one element per workgroup, thread (a, b) owns the box column
 // (a, b, 0..pb-1) in registers; the x and y contractions go through LDS.
-template <int P>
+// Boxes with fewer than 64 lines (p <= 4) can put EB elements in one workgroup
+// of at most TMAX threads so that the lanes of its wavefronts are nearly all
+// busy (36 lines per element at p = 3 leave 28 of 64 lanes idle; 7 elements fill
+// 252 of 256 lanes).  EB is the count within TMAX threads and 32 KB of LDS with
+// the best lane use.  Measured on the p = 3 level of a 32^3 mesh: 256 threads
+// beat one wavefront by 10 % (FP32) and 1024 threads (fewer workgroups in
+// flight between barriers); at p = 4 one wavefront per element stays faster.
+constexpr int fdm_group(int pb2, int lim) {
+  int best = 1;
+  for (int e = 2; e <= lim; ++e) {
+    const long ue = (long)e * pb2 * (((best * pb2 + 63) / 64) * 64);
+    const long ub = (long)best * pb2 * (((e * pb2 + 63) / 64) * 64);
+    if (ue > ub) best = e;
+  }
+  return best;
+}
+template <int P, typename T, int TMAX>
 struct FdmShape {
   static constexpr int PB = P + 3;
   static constexpr int N = P + 1;
-  static constexpr int BS = ((PB * PB + 63) / 64) * 64;
+  static constexpr int PB2 = PB * PB;
   static constexpr int RS = PB;
   static constexpr int PS = PB * RS;
+  static constexpr int EB_T = TMAX / PB2;
+  static constexpr int EB_L = 32768 / (2 * PB * PS * (int)sizeof(T));
+  static constexpr int EB = PB2 >= 64 ? 1 : fdm_group(PB2, EB_T < EB_L ? EB_T : EB_L);
+  static constexpr int BS = ((EB * PB2 + 63) / 64) * 64;
 };
 
 template <typename T>
@@ -195,29 +215,37 @@ __device__ inline float fdm_inv<float>(float d) {
 }
 
 // rs (may be null): the local solves act on r - rs (a residual formed as read)
-template <int P, typename T, bool ASM>
-__global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
+template <int P, typename T, bool ASM, int TMAX>
+__global__ __launch_bounds__((FdmShape<P, T, TMAX>::BS)) void k_fdm(
     int64_t E, int nex, int ney, int nez, const T *__restrict__ r, const T *__restrict__ rs,
     const T *__restrict__ Sg, const T *__restrict__ lamg, const T *__restrict__ W,
     T *__restrict__ z, int nv) {
-  using F = FdmShape<P>;
-  constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS;
+  using F = FdmShape<P, T, TMAX>;
+  constexpr int PB = F::PB, N = F::N, RS = F::RS, PS = F::PS, EB = F::EB;
   constexpr int N3 = N * N * N, PB2 = PB * PB;
-  __shared__ T buf0[PB * PS];
-  __shared__ T buf1[PB * PS];
+  __shared__ T sb0[EB][PB * PS];
+  __shared__ T sb1[EB][PB * PS];
+  __shared__ T sZ[EB][EB > 1 ? PB2 + PB : 1];  // S_z, lambda_z of each element of a group
 
   int vec;
-  const int64_t e = split_rhs(xcd_block(), nv, vec);
+  const int64_t grp = split_rhs(xcd_block(), nv, vec);
   r += (int64_t)vec * E * N3;
   if (rs) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
   const int tid = threadIdx.x;
-  const int a = tid % PB, b = tid / PB;
-  const bool act = tid < PB2;
+  // element of the group (0 when the group is one element: e stays uniform)
+  const int lel = EB == 1 ? 0 : tid / PB2, lt = tid - lel * PB2;
+  const int a = lt % PB, b = lt / PB;
+  const int64_t e = (int64_t)grp * EB + lel;
+  const bool act = (EB == 1 ? tid < PB2 : lel < EB) && e < E;
+  T *buf0 = sb0[lel < EB ? lel : 0];
+  T *buf1 = sb1[lel < EB ? lel : 0];
   // the thread's rows and columns of S_x (index a) and S_y (index b) live in
-  // registers; S_z and lambda_z are the same for the whole block (scalar loads)
-  const T *Se = Sg + e * 3 * PB2;
-  const T *le = lamg + e * 3 * PB;
+  // registers; S_z and lambda_z are the same for the element's lanes (scalar
+  // loads when the workgroup holds one element, else staged in LDS)
+  const int64_t es = e < E ? e : E - 1;  // uniform when the group is one element
+  const T *Se = Sg + es * 3 * PB2;
+  const T *le = lamg + es * 3 * PB;
   const T *__restrict__ Sz = Se + 2 * PB2;
   const T *__restrict__ lz = le + 2 * PB;
   T Sxc[PB], Sxr[PB], Syc[PB], Syr[PB];
@@ -266,6 +294,10 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
     col[PB - 1] = oku ? upper : T(0);
 #pragma unroll
     for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
+    if constexpr (EB > 1) {
+      sZ[lel][lt] = Sz[lt];
+      if (lt < PB) sZ[lel][PB2 + lt] = lz[lt];
+    }
   }
   __syncthreads();
   // x: t[c][b][a] = sum_i Sx[i][a] box[c][b][i]
@@ -288,22 +320,28 @@ __global__ __launch_bounds__(FdmShape<P>::BS) void k_fdm(
       for (int j = 0; j < PB; ++j) s += Syc[j] * buf1[c * PS + j * RS + a];
       col[c] = s;
     }
-    T h[PB];
+    // along z and back: S_z from scalar loads (one element) or LDS (a group)
+    auto zpass = [&](const T *SZ, const T *LZ) {
+      T h[PB];
 #pragma unroll
-    for (int cc = 0; cc < PB; ++cc) {
-      T s = 0;
+      for (int cc = 0; cc < PB; ++cc) {
+        T s = 0;
 #pragma unroll
-      for (int k = 0; k < PB; ++k) s += Sz[k * PB + cc] * col[k];
-      h[cc] = s * fdm_inv<T>(lxy + lz[cc]);
-    }
-    // back along z
+        for (int k = 0; k < PB; ++k) s += SZ[k * PB + cc] * col[k];
+        h[cc] = s * fdm_inv<T>(lxy + LZ[cc]);
+      }
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-      T s = 0;
+      for (int k = 0; k < PB; ++k) {
+        T s = 0;
 #pragma unroll
-      for (int cc = 0; cc < PB; ++cc) s += Sz[k * PB + cc] * h[cc];
-      col[k] = s;
-    }
+        for (int cc = 0; cc < PB; ++cc) s += SZ[k * PB + cc] * h[cc];
+        col[k] = s;
+      }
+    };
+    if constexpr (EB > 1)
+      zpass(sZ[lel], sZ[lel] + PB2);
+    else
+      zpass(Sz, lz);
 #pragma unroll
     for (int c = 0; c < PB; ++c) buf0[c * PS + b * RS + a] = col[c];
   }
@@ -589,6 +627,15 @@ template void launch_asm_sum<double>(const Ctx &, const Level &, const double *,
 template void launch_asm_sum<float>(const Ctx &, const Level &, const float *, float *,
                                     hipStream_t);
 
+template <int P, typename T, bool ASM, int TMAX>
+static void fdm_launch_grouped(const Ctx &c, const Level &L, const T *r, const T *rs, const T *S,
+                               const T *lam, const T *W, T *out, hipStream_t s, int nv) {
+  using F = FdmShape<P, T, TMAX>;
+  const dim3 grid((unsigned)((L.E + F::EB - 1) / F::EB * nv));
+  hipLaunchKernelGGL((k_fdm<P, T, ASM, TMAX>), grid, dim3(F::BS), 0, s, L.E, c.nex, c.ney, c.nez,
+                     r, rs, S, lam, W, out, nv);
+}
+
 template <int P, typename T, bool ASM>
 static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *rs, const T *S,
                        const T *lam, const T *W, T *out, hipStream_t s, int nv) {
@@ -596,9 +643,10 @@ static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *rs, co
   if (FdmLines<P>::PB * FdmLines<P>::PB > 64 && c.fdm_lines)
     hipLaunchKernelGGL((k_fdm_lines<P, T, ASM>), grid, dim3(FdmLines<P>::BS), 0, s, L.E, c.nex,
                        c.ney, c.nez, r, rs, S, lam, W, out, nv);
+  else if (P <= 3 && c.fdm_group)  // measured: faster up to p = 3, slower at p = 4
+    fdm_launch_grouped<P, T, ASM, (P <= 3 ? 256 : 64)>(c, L, r, rs, S, lam, W, out, s, nv);
   else
-    hipLaunchKernelGGL((k_fdm<P, T, ASM>), grid, dim3(FdmShape<P>::BS), 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, rs, S, lam, W, out, nv);
+    fdm_launch_grouped<P, T, ASM, 64>(c, L, r, rs, S, lam, W, out, s, nv);
   SEM_LAUNCH("k_fdm");
 }
 

@@ -239,6 +239,7 @@ struct Ctx {
   double *av = nullptr;
   int fdm_prec = SEM_F32;
   bool fdm_lines = true;  // line-organised VALU FDM kernel for pbar^2 > 64
+  bool fdm_group = true;  // p <= 3: several elements' boxes per workgroup of 256 threads
   bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
 };
 

@@ -316,6 +316,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   }
   const char *fl = getenv("SEM_FDM_LINES");
   c.fdm_lines = !(fl && fl[0] == '0');
+  const char *fg = getenv("SEM_FDM_GROUP");
+  c.fdm_group = !(fg && fg[0] == '0');
   const char *fm = getenv("SEM_FDM_MFMA1");
   c.fdm_mfma1 = fm && fm[0] == '1';
 }

@@ -276,6 +276,24 @@ def test_asm_surrogate(p, prec):
     assert err < (1e-12 if prec == sem.F64 else 1e-5), err
 
 
+@pytest.mark.parametrize("p,prec,smoother,group", [
+    (3, sem.F32, "ras", "1"), (3, sem.F64, "ras", "1"), (3, sem.F32, "ras", "0"),
+    (3, sem.F64, "asm", "0"), (4, sem.F32, "ras", "1"), (4, sem.F64, "asm", "1"),
+    (2, sem.F32, "asm", "1"), (3, sem.F32, "asm", "1"), (2, sem.F64, "ras", "0")])
+def test_small_box_fdm_groups(monkeypatch, p, prec, smoother, group):
+    """p <= 3: one workgroup solves the boxes of several elements (7 at p = 3 in
+    FP32); E = 30 leaves the last group partly empty.  SEM_FDM_GROUP=0 keeps one
+    wavefront per workgroup."""
+    monkeypatch.setenv("SEM_FDM_GROUP", group)
+    t = _torch()
+    f32 = prec == sem.F32
+    P = Pair((5, 3, 2), p, mesh="sin", schedule=(p, 1), smoother=smoother, lambda_override=[2.0],
+             smoother_prec=prec, bc=(1, 0, 1, 1, 0, 1))
+    g, o = P.random_local(11)
+    err = rel_err(host(P.gpu.apply_S(g.to(t.float32) if f32 else g)), P.ora.levels[0].apply_S(o))
+    assert err < (1e-5 if f32 else 1e-12), err
+
+
 def test_asm_vcycle_and_solve():
     P = Pair(3, 5, mesh="shift", schedule=(5, 3, 1), smoother="asm", coarse_tol=0.0,
              coarse_maxit=6, lambda_override=[1.5, 1.5])
