@@ -104,9 +104,11 @@ typedef struct {
   int32_t batch_rhs;          /* right sides this context can take in sem_batch_solve     */
   int32_t coarse_solver;      /* p = 1 coarsest level: 0 Jacobi-PCG (coarse_tol,          */
                               /* coarse_maxit), 1 exact block-tridiagonal elimination     */
-                              /* over z-planes (3 nz (nx ny)^2 doubles of workspace;      */
-                              /* falls back to the PCG if the level is singular), -1      */
-                              /* library default: 1 when that storage is <= 4 GiB         */
+                              /* over z-planes (3 nz (nx ny)^2 doubles of workspace, and  */
+                              /* as many floats under an FP32 smoother, whose sweeps read */
+                              /* FP32 copies; falls back to the PCG if the level is       */
+                              /* singular), -1 library default: 1 when the doubles take   */
+                              /* <= 4 GiB                                                 */
   int32_t proj_max;           /* > 0: sem_solve starts from the A-conjugate projection of */
                               /* b onto up to proj_max prior solutions (successive right  */
                               /* sides, Sec. 3.2 / 4.2) and stops at ||r|| <= rtol ||b||; */

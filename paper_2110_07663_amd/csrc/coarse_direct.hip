@@ -24,7 +24,10 @@
 // Storage: G, H, J as K dense [Mp][Mp] FP64 blocks, Mp = nx*ny rounded up to
 // 32 (identity / zero padding); Hu_c sits in J's slot c.  A solve reads each
 // block once: 3 K Mp^2 * 8 bytes, in about K dependent matrix-vector launches
-// with no host interaction, so it can be recorded into a graph.
+// with no host interaction, so it can be recorded into a graph.  Under an FP32
+// smoother the sweeps read FP32 copies of the factored blocks instead (half the
+// bytes; vectors and sums stay FP64): the solve is then exact to about 1e-6,
+// below what the FP32 V-cycle around it resolves.
 #include <algorithm>
 
 #include "sem_internal.h"
@@ -35,9 +38,10 @@ constexpr int kGB = 32;  // Gauss-Jordan block
 
 static inline int64_t padded(int64_t m) { return (m + kGB - 1) / kGB * kGB; }
 
-size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz) {
+size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz, bool f32) {
   const int64_t Mp = padded(nx * ny);
-  return (size_t)(3 * nz * Mp * Mp + nx * ny * nz) * sizeof(double);
+  return (size_t)(3 * nz * Mp * Mp + nx * ny * nz) * sizeof(double) +
+         (f32 ? (size_t)(3 * nz * Mp * Mp) * sizeof(float) : 0);
 }
 
 // ---- setup kernels ----------------------------------------------------------
@@ -219,53 +223,70 @@ __global__ void k_bt_transpose(int Mp, const double *__restrict__ H, double *__r
 
 // ---- solve kernel -------------------------------------------------------------
 
-// One product of a sweep: out = c + s1 * (M1 v1) - (M2 v2) (absent terms null)
+// One product of a sweep: out = c + s1 * (M1 v1) - (M2 v2) (absent terms null);
+// MT is the type of the stored blocks
+template <typename MT>
 struct BtOp {
-  const double *M1, *v1, *M2, *v2, *c;
+  const MT *M1;
+  const double *v1;
+  const MT *M2;
+  const double *v2, *c;
   double *out;
   double s1;
 };
+
+__global__ void k_bt_narrow(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
 
 // Up to two independent products (the two chains of the sweep) for NV right
 // sides (vectors vs apart in v1, v2, c and out); one wavefront per row, the
 // matrix rows are read once for all right sides.  Each right side is summed in
 // the same order for any NV (four strided partial sums per lane, then the wave
 // reduction).
-template <int NV>
-__global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, BtOp o0, BtOp o1, int64_t vs) {
+template <int NV, typename MT>
+__global__ __launch_bounds__(256) void k_bt_mv(int m, int Mp, BtOp<MT> o0, BtOp<MT> o1,
+                                               int64_t vs) {
+  constexpr int W = 16 / (int)sizeof(MT);  // entries per 16-byte load
+  struct alignas(16) Chunk {
+    MT e[W];
+  };
   const int rb = (m + 3) / 4;
   const int which = (int)blockIdx.x >= rb;
-  const BtOp &o = which ? o1 : o0;
+  const BtOp<MT> &o = which ? o1 : o0;
   const int row = ((int)blockIdx.x - which * rb) * 4 + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= m) return;  // whole wave
   double a1[NV], a2[NV];
   // The matrix row (16-byte aligned: Mp is a multiple of 32) streams as 16-byte
-  // loads, four per lane per step (512 entries a wave), into four partial sums
-  // per right side; x (L2 resident, any alignment) is read per entry.
-  auto rowdot = [&](const double *__restrict__ r, const double *__restrict__ x, double *acc) {
+  // loads of W entries, four per lane per step (256 W entries a wave), into four
+  // partial sums per right side; x (L2 resident, any alignment) is read per
+  // entry.  (Issuing a whole row's loads before the first use, with the last
+  // chunk guarded entry by entry, measured slower.)
+  auto rowdot = [&](const MT *__restrict__ r, const double *__restrict__ x, double *acc) {
     double t[NV][4];
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v][0] = t[v][1] = t[v][2] = t[v][3] = 0.0;
-    const double2 *__restrict__ r2 = reinterpret_cast<const double2 *>(r);
+    const Chunk *__restrict__ rc = reinterpret_cast<const Chunk *>(r);
     int j0 = 0;
-    for (; j0 + 512 <= m; j0 += 512) {
-      double2 q[4];
+    for (; j0 + 256 * W <= m; j0 += 256 * W) {
+      Chunk q[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) q[u] = r2[(j0 >> 1) + 64 * u + lane];
+      for (int u = 0; u < 4; ++u) q[u] = rc[j0 / W + 64 * u + lane];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int j = j0 + 128 * u + 2 * lane;
+        const int j = j0 + 64 * W * u + W * lane;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double *xv = x + v * vs;
-          t[v][u] += q[u].x * xv[j];
-          t[v][u] += q[u].y * xv[j + 1];
+#pragma unroll
+          for (int w = 0; w < W; ++w) t[v][u] += (double)q[u].e[w] * xv[j + w];
         }
       }
     }
     for (int j = j0 + lane; j < m; j += 64) {
-      const double r0 = r[j];
+      const double r0 = (double)r[j];
 #pragma unroll
       for (int v = 0; v < NV; ++v) t[v][0] += r0 * x[v * vs + j];
     }
@@ -375,28 +396,39 @@ void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hi
     hipLaunchKernelGGL(k_bt_transpose, dim3(nbk, nbk), dim3(256), 0, s, Mp, src, J(k));
     SEM_LAUNCH("k_bt_transpose");
   }
+  if (S.fG) {
+    const int64_t nb = (int64_t)K * M2;
+    hipLaunchKernelGGL(k_bt_narrow, dim3(nblk(nb)), dim3(256), 0, s, nb, (const double *)S.dG,
+                       S.fG);
+    hipLaunchKernelGGL(k_bt_narrow, dim3(nblk(nb)), dim3(256), 0, s, nb, (const double *)S.dH,
+                       S.fH);
+    hipLaunchKernelGGL(k_bt_narrow, dim3(nblk(nb)), dim3(256), 0, s, nb, (const double *)S.dJ,
+                       S.fJ);
+    SEM_LAUNCH("k_bt_narrow");
+  }
   int flag = 0;
   SEM_HIP(hipMemcpyAsync(&flag, S.dflag, sizeof(int), hipMemcpyDeviceToHost, s));
   SEM_HIP(hipStreamSynchronize(s));
   S.direct = flag == 0;
 }
 
-template <int NV>
-static void bt_sweeps(const CoarseSolver &S, int m, int K, int Mp, const double *b, double *x,
-                      double *y, hipStream_t s) {
+template <int NV, typename MT>
+static void bt_sweeps(const CoarseSolver &S, const MT *dG, const MT *dH, const MT *dJ, int m,
+                      int K, int Mp, const double *b, double *x, double *y, hipStream_t s) {
+  using BtOp = sem::BtOp<MT>;
   const int64_t M2 = (int64_t)Mp * Mp, vs = S.n;
   const int c = K / 2;
   const unsigned rb = (unsigned)((m + 3) / 4);
-  auto G = [&](int k) { return (const double *)(S.dG + k * M2); };
-  auto H = [&](int k) { return (const double *)(S.dH + k * M2); };
-  auto J = [&](int k) { return (const double *)(S.dJ + k * M2); };
+  auto G = [&](int k) { return dG + k * M2; };
+  auto H = [&](int k) { return dH + k * M2; };
+  auto J = [&](int k) { return dJ + k * M2; };
   // y_k of the sweep; y_0 and y_{K-1} are b itself
   auto Y = [&](int k) -> const double * {
     return (k == 0 || k == K - 1) ? b + (int64_t)k * m : (const double *)(y + (int64_t)k * m);
   };
   auto launch = [&](const BtOp &o0, const BtOp *o1) {
     const BtOp none{};
-    hipLaunchKernelGGL(k_bt_mv<NV>, dim3(o1 ? 2 * rb : rb), dim3(256), 0, s, m, Mp, o0,
+    hipLaunchKernelGGL((k_bt_mv<NV, MT>), dim3(o1 ? 2 * rb : rb), dim3(256), 0, s, m, Mp, o0,
                        o1 ? *o1 : none, vs);
     SEM_LAUNCH("k_bt_mv");
   };
@@ -430,19 +462,28 @@ static void bt_sweeps(const CoarseSolver &S, int m, int K, int Mp, const double 
   }
 }
 
+template <typename MT>
+static void bt_apply(const CoarseSolver &S, const MT *G, const MT *H, const MT *J, int m, int K,
+                     int Mp, const double *b, double *x, hipStream_t s, int nv) {
+  for (int v0 = 0; v0 < nv; v0 += 4) {  // up to four right sides per sweep
+    const int64_t o = (int64_t)v0 * S.n;
+    switch (std::min(4, nv - v0)) {
+      case 1: bt_sweeps<1, MT>(S, G, H, J, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      case 2: bt_sweeps<2, MT>(S, G, H, J, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      case 3: bt_sweeps<3, MT>(S, G, H, J, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+      default: bt_sweeps<4, MT>(S, G, H, J, m, K, Mp, b + o, x + o, S.dy + o, s); break;
+    }
+  }
+}
+
 void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,
                          double *x, hipStream_t s, int nv) {
   const int m = (int)(nx * ny), K = (int)nz;
   const int Mp = (int)padded(m);
-  for (int v0 = 0; v0 < nv; v0 += 4) {  // up to four right sides per sweep
-    const int64_t o = (int64_t)v0 * S.n;
-    switch (std::min(4, nv - v0)) {
-      case 1: bt_sweeps<1>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
-      case 2: bt_sweeps<2>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
-      case 3: bt_sweeps<3>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
-      default: bt_sweeps<4>(S, m, K, Mp, b + o, x + o, S.dy + o, s); break;
-    }
-  }
+  if (S.fG)
+    bt_apply<float>(S, S.fG, S.fH, S.fJ, m, K, Mp, b, x, s, nv);
+  else
+    bt_apply<double>(S, S.dG, S.dH, S.dJ, m, K, Mp, b, x, s, nv);
 }
 
 }  // namespace sem

@@ -170,6 +170,7 @@ struct CoarseSolver {
   // exact block-tridiagonal solve (coarse_direct.hip): G, H, J blocks, work vector
   bool direct = false;
   double *dG = nullptr, *dH = nullptr, *dJ = nullptr, *dy = nullptr;
+  float *fG = nullptr, *fH = nullptr, *fJ = nullptr;  // FP32 copies read by the sweeps (FP32 smoother)
   int *dflag = nullptr;
   hipStream_t cap = nullptr;       // private capture stream
   hipGraph_t graph = nullptr;
@@ -355,7 +356,7 @@ bool coarse_assembled_ok(const Ctx &c, const Level &C);
 void coarse_setup(Ctx &c, Level &C, hipStream_t s);
 void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv = 1);
 void coarse_release(CoarseSolver &S);
-size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz);
+size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz, bool f32);
 void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s);
 // nv right sides, S.n apart in b, x and the work vector S.dy
 void coarse_direct_apply(const CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, const double *b,

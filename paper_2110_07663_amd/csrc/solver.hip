@@ -235,16 +235,25 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     // exact block-tridiagonal solve of the p = 1 level (chosen, or by size)
     {
       const int64_t nx = m->nex + 1, ny = m->ney + 1, nz = m->nez + 1;
-      const size_t db = coarse_direct_bytes(nx, ny, nz);
+      // FP32 smoother: the sweeps read FP32 copies of the blocks (SEM_COARSE_F64=1 keeps FP64)
+      const char *cf = getenv("SEM_COARSE_F64");
+      const bool f32 = lowp && !(cf && cf[0] == '1');
+      const size_t db = coarse_direct_bytes(nx, ny, nz, false);
       const bool want = o.coarse_solver == 1 || (o.coarse_solver < 0 && db <= ((size_t)4 << 30));
       S.direct = false;
       S.dG = S.dH = S.dJ = S.dy = nullptr;
+      S.fG = S.fH = S.fJ = nullptr;
       S.dflag = nullptr;
       if (want) {
         const int64_t Mp = (nx * ny + 31) / 32 * 32;
         S.dG = A.take<double>((size_t)(nz * Mp * Mp));
         S.dH = A.take<double>((size_t)(nz * Mp * Mp));
         S.dJ = A.take<double>((size_t)(nz * Mp * Mp));
+        if (f32) {
+          S.fG = A.take<float>((size_t)(nz * Mp * Mp));
+          S.fH = A.take<float>((size_t)(nz * Mp * Mp));
+          S.fJ = A.take<float>((size_t)(nz * Mp * Mp));
+        }
         S.dy = A.take<double>(std::max<size_t>(nv * S.n, Mp));  // also the pivot-test diagonal
         S.dflag = A.take<int>(64);
         S.direct = true;  // until the setup finds the level singular
@@ -570,7 +579,7 @@ static void precondition(Ctx &c, const double *r, double *z, hipStream_t s, int 
       launch_scale<double>(F.nloc, F.dinv64, r + k * F.nloc, z + k * F.nloc, s);
     return;
   }
-  if (F.coarse) {  // single-level schedule: the coarse solve itself, in FP64
+  if (F.coarse) {  // single-level schedule: the coarse solve itself, on FP64 vectors
     launch_copy<double>(n, r, F.d_b, s);
     coarse_solve(c, F, s, nv);
     launch_copy<double>(n, c.cx, z, s);

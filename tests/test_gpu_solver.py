@@ -181,6 +181,23 @@ def test_direct_coarse_falls_back_when_singular():
     assert rel_err(za, zb) < 1e-14
 
 
+@pytest.mark.parametrize("keep_f64", ["0", "1"])
+def test_direct_coarse_fp32_factors(monkeypatch, keep_f64):
+    """Under an FP32 smoother the exact coarse sweeps read FP32 copies of the
+    factored blocks (FP64 vectors and sums): the single-level solve then meets
+    the oracle's dense solve to about 1e-7 rather than 1e-12.  SEM_COARSE_F64=1
+    keeps the FP64 blocks.  7x6x3 elements: 8x7 planes, two 32-row blocks."""
+    monkeypatch.setenv("SEM_COARSE_F64", keep_f64)
+    P = Pair((7, 6, 3), 1, mesh="sin", schedule=(1,), coarse="dense", smoother_prec=sem.F32)
+    for seed in (54, 55):
+        g, o = P.random_local(seed)
+        err = rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o))
+        if keep_f64 == "1":
+            assert err < 1e-12, err
+        else:
+            assert 1e-12 < err < 2e-6, err
+
+
 def test_solve_with_direct_coarse():
     P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", coarse="dense")
     bg, bo = _rhs(P)
