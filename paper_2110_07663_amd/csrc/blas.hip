@@ -311,7 +311,9 @@ __global__ __launch_bounds__(256) void k_wdots(int64_t n, const WT *__restrict__
   }
 }
 
-// FCG step: x += alpha p, r -= alpha q, and (r, r)_w of the new r
+// FCG step: x += alpha p, r -= alpha q, and (r, r)_w of the new r, with
+// alpha = (r, z) / (p, q) formed from the device scalars (0 when (p, q) <= 0:
+// the breakdown leaves x and r as they are; the host reads (p, q) afterwards)
 template <typename V>
 __device__ inline void st2(double *p, int64_t t, double2 v) {
   if constexpr (V::value) {
@@ -322,12 +324,15 @@ __device__ inline void st2(double *p, int64_t t, double2 v) {
   }
 }
 template <typename V, typename WT>
-__global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
+__global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restrict__ rz,
+                                                const double *__restrict__ pq,
                                                 const WT *__restrict__ w,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, float *__restrict__ rf,
                                                 double *partials, unsigned *counter, double *out) {
+  const double pqv = *pq;
+  const double alpha = pqv > 0.0 ? *rz / pqv : 0.0;
   double acc[1] = {0.0}, acc2 = 0.0;
   const int64_t n2 = n / 2;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -357,20 +362,20 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, double alpha,
   if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) out[0] = acc[0];
 }
 
-void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
-                   const double *q, double *x, double *r, double *out, hipStream_t s,
-                   const float *w32, float *rf) {
+void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
+                   const double *p, const double *q, double *x, double *r, double *out,
+                   hipStream_t s, const float *w32, float *rf) {
   const bool al = aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r);
   const unsigned g = red_grid(n);
   if (w32 && al && ((uintptr_t)w32 & 7) == 0)
-    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, alpha, w32,
-                       p, q, x, r, rf, c.partials, c.counter, out);
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, rz, pq,
+                       w32, p, q, x, r, rf, c.partials, c.counter, out);
   else if (al && aligned16(w))
-    hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq, w,
                        p, q, x, r, rf, c.partials, c.counter, out);
   else
-    hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, alpha, w,
-                       p, q, x, r, rf, c.partials, c.counter, out);
+    hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq,
+                       w, p, q, x, r, rf, c.partials, c.counter, out);
   SEM_LAUNCH("k_fcg_xr");
 }
 
@@ -467,17 +472,28 @@ void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32,
   SEM_LAUNCH("k_wdots_rz");
 }
 
-// p = z + beta p with FP32 z (FP64 p)
-__global__ void k_zp(int64_t n, const float *__restrict__ z, double beta, double *__restrict__ p) {
+// p = z + beta p (FP64 p; z in FP32 on the mixed path), beta from the device
+// scalars: (r, z) / rz_old, or ((r, z) - (r, z_old)) / rz_old when flexible
+template <typename ZT>
+__global__ void k_zp(int64_t n, const ZT *__restrict__ z, const double *__restrict__ rzn,
+                     const double *__restrict__ rzo, int flexible, double *__restrict__ p) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
+  const double beta = (flexible ? rzn[0] - rzn[1] : rzn[0]) / rzo[0];
   const double a = 1.0;
   p[t] = a * (double)z[t] + beta * p[t];
 }
-void launch_zp(int64_t n, const float *z, double beta, double *p, hipStream_t s) {
-  hipLaunchKernelGGL(k_zp, dim3(nb(n, 256)), dim3(256), 0, s, n, z, beta, p);
+template <typename ZT>
+void launch_zp(int64_t n, const ZT *z, const double *rzn, const double *rzo, bool flexible,
+               double *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zp<ZT>, dim3(nb(n, 256)), dim3(256), 0, s, n, z, rzn, rzo,
+                     flexible ? 1 : 0, p);
   SEM_LAUNCH("k_zp");
 }
+template void launch_zp<float>(int64_t, const float *, const double *, const double *, bool,
+                               double *, hipStream_t);
+template void launch_zp<double>(int64_t, const double *, const double *, const double *, bool,
+                                double *, hipStream_t);
 
 // block of inner products <V_j, x>_w for j < k (k <= 8 per pass)
 template <int KB>

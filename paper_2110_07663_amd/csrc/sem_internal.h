@@ -308,15 +308,19 @@ void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *d
 // weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)
 // (w32: an FP32 copy of the weights, used when given; the weights are exact in FP32)
 // (rf: also store the new r in FP32 there, when given)
-void launch_fcg_xr(const Ctx &c, int64_t n, double alpha, const double *w, const double *p,
-                   const double *q, double *x, double *r, double *out, hipStream_t s,
-                   const float *w32 = nullptr, float *rf = nullptr);
+// (alpha = rz / pq from the device, 0 when pq <= 0)
+void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
+                   const double *p, const double *q, double *x, double *r, double *out,
+                   hipStream_t s, const float *w32 = nullptr, float *rf = nullptr);
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
                   const double *const *b, double *out, hipStream_t s, const float *w32 = nullptr);
 // out[j] = (r, z_j)_w for FP32 z_0 (and z_1 when not null), on the device
 void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32, const double *r,
                      const float *z0, const float *z1, double *out, hipStream_t s);
-void launch_zp(int64_t n, const float *z, double beta, double *p, hipStream_t s);  // p = z + beta p
+// p = z + beta p, beta = (rzn[0] (- rzn[1] when flexible)) / rzo[0] on the device
+template <typename ZT>
+void launch_zp(int64_t n, const ZT *z, const double *rzn, const double *rzo, bool flexible,
+               double *p, hipStream_t s);
 // block dots for Gram-Schmidt: out[j] = sum_i w_i V_j(i) x(i), j < k
 void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *V, int64_t ld,
                  const double *x, double *out, hipStream_t s);

@@ -758,22 +758,22 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
   double rel = 1.0;
   bool breakdown = false;
   const bool zf = z_in_f32(c);
-  // (r, z) and, for the flexible variant, (r, z_old), read back
+  // Device scalars: (r, z) and (r, z_old) in two alternating pairs, (p, q) and
+  // (r, r).  alpha and beta are formed on the device from them, so an iteration
+  // reads back once: after the x, r update, (r, r) for the stopping test with
+  // (p, q) and (r, z) for the breakdown and NaN checks.
+  double *ds = c.dres + 2 * kMaxRestart + 32;
+  double *const dpq = ds + 4, *const drr = ds + 5;
+  int slot = 0;  // pair holding the current (r, z)
   auto rz_dots = [&](int nd, double *out) {
     if (zf) {
-      launch_wdots_rz(c, n, F.w64, F.w32, r, F.f_x, nd == 2 ? c.fzo : nullptr, c.dres, s);
-      host_scalars(c, c.dres, nd * sizeof(double), s);
-      for (int j = 0; j < nd; ++j) {
-        out[j] = c.hres[j];
-        if (!std::isfinite(out[j])) fail(SEM_ENAN, "NaN/Inf in an inner product");
-      }
+      launch_wdots_rz(c, n, F.w64, F.w32, r, F.f_x, nd == 2 ? c.fzo : nullptr, out, s);
     } else {
       const double *a[2] = {r, r}, *bb[2] = {z, zo};
-      dots(c, F, nd, a, bb, out, s);
+      launch_wdots(c, n, F.w64, nd, a, bb, out, s, F.w32);
     }
   };
   while (it < maxit) {
-    double rz;
     if (zf) {
       precondition_f32(c, r, s);
       launch_copy_cvt_f2d(n, F.f_x, p, s);
@@ -781,25 +781,26 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
       precondition(c, r, z, s);
       SEM_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    rz_dots(1, &rz);
+    rz_dots(1, ds + 2 * slot);
     while (it < maxit) {
       opA<double>(c, F, p, q, s);
-      double pq;
       {
         const double *a[1] = {p}, *bb[1] = {q};
-        dots(c, F, 1, a, bb, &pq, s);
+        launch_wdots(c, n, F.w64, 1, a, bb, dpq, s, F.w32);
       }
-      if (!(pq > 0.0)) {  // exact breakdown: p = 0, the iterate is final
+      // x, r, (r, r) in one pass (and the V-cycle's FP32 copy of r on the mixed path)
+      launch_fcg_xr(c, n, ds + 2 * slot, dpq, F.w64, p, q, x, r, drr, s, F.w32,
+                    zf ? F.f_b : nullptr);
+      host_scalars(c, ds, 6 * sizeof(double), s);
+      const double *h = c.hres;
+      if (!std::isfinite(h[2 * slot]) || !std::isfinite(h[4]) || !std::isfinite(h[5]))
+        fail(SEM_ENAN, "NaN/Inf in an inner product");
+      if (!(h[4] > 0.0)) {  // exact breakdown: p = 0, the iterate is final (x, r unchanged)
         breakdown = true;
         break;
       }
-      const double alpha = rz / pq;
-      // x, r, (r, r) in one pass (and the V-cycle's FP32 copy of r on the mixed path)
-      launch_fcg_xr(c, n, alpha, F.w64, p, q, x, r, c.dres, s, F.w32, zf ? F.f_b : nullptr);
-      host_scalars(c, c.dres, sizeof(double), s);
-      if (!std::isfinite(c.hres[0])) fail(SEM_ENAN, "NaN/Inf in an inner product");
       ++it;
-      rel = std::sqrt(c.hres[0]) / den;
+      rel = std::sqrt(h[5]) / den;
       if (rel <= rtol) break;
       if (zf) {
         std::swap(F.f_x, c.fzo);  // the V-cycle writes the new z; the old one stays
@@ -808,22 +809,12 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
         std::swap(z, zo);
         precondition(c, r, z, s);
       }
-      double beta;
-      if (flexible) {
-        double d2[2];
-        rz_dots(2, d2);
-        beta = (d2[0] - d2[1]) / rz;
-        rz = d2[0];
-      } else {
-        double rzn;
-        rz_dots(1, &rzn);
-        beta = rzn / rz;
-        rz = rzn;
-      }
+      slot ^= 1;
+      rz_dots(flexible ? 2 : 1, ds + 2 * slot);
       if (zf)
-        launch_zp(n, F.f_x, beta, p, s);
+        launch_zp<float>(n, F.f_x, ds + 2 * slot, ds + 2 * (slot ^ 1), flexible, p, s);
       else
-        launch_axpby<double>(n, 1.0, z, beta, p, s);
+        launch_zp<double>(n, z, ds + 2 * slot, ds + 2 * (slot ^ 1), flexible, p, s);
     }
     // true residual
     opA<double>(c, F, x, q, s);
