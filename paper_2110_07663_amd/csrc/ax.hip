@@ -155,11 +155,17 @@ __device__ __forceinline__ void st(T *p, T v) {
 // for those faces; the faces between workgroups and the Dirichlet x-faces are
 // left to the gather-scatter).  Each pair is summed as (p-face + 0-face), the
 // order the gather-scatter uses.
+//
+// dotp (may be null; one right side): element e's share of u^T A_L u, the sum
+// of u times its unassembled product over the element's points, goes to
+// dotp[e].  For u consistent and zero on Dirichlet nodes the element shares add
+// up to (u, Au) over the unique free nodes, the product the gather-scatter
+// completes (the copies of a node sum to its assembled row).
 template <typename T, bool NT, bool XF>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
                                          const T *__restrict__ G, const T *__restrict__ Dg,
                                          T *__restrict__ v, int nv, T *sD, T (*sU)[72],
-                                         T (*sR)[72], T (*sS)[72]) {
+                                         T (*sR)[72], T (*sS)[72], double *dotp = nullptr) {
   constexpr int N = 8, NN = 64, N3 = 512, RS = 9;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 7, j = lane >> 3;
@@ -217,6 +223,14 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
     acc[k] += a;
     __builtin_amdgcn_wave_barrier();
   }
+  if (dotp) {  // fixed order: the lane's k-line, then a butterfly over the wave
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) d += (double)uk[k] * (double)acc[k];
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) d += __shfl_xor(d, sh, 64);
+    if (lane == 0) dotp[e] = d;
+  }
   if constexpr (XF) {  // every wave of the block is live (E is a multiple of 4)
     if (i == 0) {
 #pragma unroll
@@ -245,9 +259,9 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
 template <bool NT, bool XF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ax8_f64(
     int64_t E, const double *__restrict__ u, const double *__restrict__ G,
-    const double *__restrict__ Dg, double *__restrict__ v, int nv) {
+    const double *__restrict__ Dg, double *__restrict__ v, int nv, double *dotp) {
   __shared__ double sD[64], sU[4][72], sR[4][72], sS[4][72];
-  ax8_body<double, NT, XF>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
+  ax8_body<double, NT, XF>(E, u, G, Dg, v, nv, sD, sU, sR, sS, dotp);
 }
 template <bool NT, bool XF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32(
@@ -259,15 +273,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 
 template <typename T, bool XF>
 static void ax8_launch(const Level &L, const T *u, T *v, const T *G, const T *D, int nv,
-                       hipStream_t s) {
+                       hipStream_t s, double *dotp) {
   // several right sides share G through L2: plain loads (non-temporal ones would bypass it)
   const dim3 grid((unsigned)((L.E + 3) / 4 * nv));
   const bool nt = L.ax_variant == 2 && nv == 1;
   if constexpr (sizeof(T) == 8) {
     if (nt)
-      hipLaunchKernelGGL((k_ax8_f64<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+      hipLaunchKernelGGL((k_ax8_f64<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv, dotp);
     else
-      hipLaunchKernelGGL((k_ax8_f64<false, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
+      hipLaunchKernelGGL((k_ax8_f64<false, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv,
+                         dotp);
   } else {
     if (nt)
       hipLaunchKernelGGL((k_ax8_f32<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);
@@ -279,13 +294,13 @@ static void ax8_launch(const Level &L, const T *u, T *v, const T *G, const T *D,
 
 template <typename T, int N>
 static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, int nv, bool xf,
-                 hipStream_t s) {
+                 hipStream_t s, double *dotp) {
   if constexpr (N == 8) {
     if (L.ax_variant >= 1) {
       if (xf)
-        ax8_launch<T, true>(L, u, v, G, D, nv, s);
+        ax8_launch<T, true>(L, u, v, G, D, nv, s, dotp);
       else
-        ax8_launch<T, false>(L, u, v, G, D, nv, s);
+        ax8_launch<T, false>(L, u, v, G, D, nv, s, dotp);
       return;
     }
   }
@@ -300,10 +315,14 @@ bool ax_sums_x_faces(const Level &L) {
   return L.gs_struct && L.xfuse && L.N == 8 && L.ax_variant >= 1 && L.nex % 4 == 0;
 }
 
+bool ax_forms_dot(const Level &L, int nv) { return L.N == 8 && L.ax_variant >= 1 && nv == 1; }
+
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv, bool xf) {
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv, bool xf, double *dotp) {
   if (nv < 1) fail(SEM_EINVAL, "Ax: no right side");
   if (xf && !ax_sums_x_faces(L)) fail(SEM_EINVAL, "Ax: x-face summation not available here");
+  if (dotp && (sizeof(T) != 8 || !ax_forms_dot(L, nv)))
+    fail(SEM_EINVAL, "Ax: the element shares of (u, Au) need the FP64 p = 7 one-wave kernel");
   const T *G;
   const T *D;
   if constexpr (sizeof(T) == 8) {
@@ -315,21 +334,23 @@ void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv, bool xf)
   }
   if (!G || !D) fail(SEM_EINVAL, "geometric factors of this precision were not built");
   switch (L.N) {
-    case 2: ax_n<T, 2>(L, u, v, G, D, nv, xf, s); break;
-    case 3: ax_n<T, 3>(L, u, v, G, D, nv, xf, s); break;
-    case 4: ax_n<T, 4>(L, u, v, G, D, nv, xf, s); break;
-    case 5: ax_n<T, 5>(L, u, v, G, D, nv, xf, s); break;
-    case 6: ax_n<T, 6>(L, u, v, G, D, nv, xf, s); break;
-    case 7: ax_n<T, 7>(L, u, v, G, D, nv, xf, s); break;
-    case 8: ax_n<T, 8>(L, u, v, G, D, nv, xf, s); break;
-    case 9: ax_n<T, 9>(L, u, v, G, D, nv, xf, s); break;
-    case 10: ax_n<T, 10>(L, u, v, G, D, nv, xf, s); break;
-    case 11: ax_n<T, 11>(L, u, v, G, D, nv, xf, s); break;
+    case 2: ax_n<T, 2>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 3: ax_n<T, 3>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 4: ax_n<T, 4>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 5: ax_n<T, 5>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 6: ax_n<T, 6>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 7: ax_n<T, 7>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 8: ax_n<T, 8>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 9: ax_n<T, 9>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 10: ax_n<T, 10>(L, u, v, G, D, nv, xf, s, dotp); break;
+    case 11: ax_n<T, 11>(L, u, v, G, D, nv, xf, s, dotp); break;
     default: fail(SEM_EUNSUPPORTED, "Ax: unsupported degree");
   }
 }
-template void launch_ax<double>(const Level &, const double *, double *, hipStream_t, int, bool);
-template void launch_ax<float>(const Level &, const float *, float *, hipStream_t, int, bool);
+template void launch_ax<double>(const Level &, const double *, double *, hipStream_t, int, bool,
+                                double *);
+template void launch_ax<float>(const Level &, const float *, float *, hipStream_t, int, bool,
+                               double *);
 
 // diag(A^e) per point: only q' on the r-, s- or t-line through q contribute, and
 // the cross terms only at q' = q.

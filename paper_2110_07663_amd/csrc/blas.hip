@@ -262,6 +262,21 @@ struct Ptr4 {
   const double *p[4];
 };
 
+// out = sum of n partial values in a fixed order (one workgroup: strided sums
+// per thread, then the LDS tree)
+__global__ __launch_bounds__(256) void k_sum_partials(int64_t n, const double *__restrict__ part,
+                                                      double *out) {
+  __shared__ double sh[1][256];
+  double acc[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc[0] += part[i];
+  block_reduce<1>(acc, sh);
+  if (threadIdx.x == 0) out[0] = sh[0][0];
+}
+void launch_sum_partials(int64_t n, const double *part, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, n, part, out);
+  SEM_LAUNCH("k_sum_partials");
+}
+
 // per-thread strided pairs (16-byte loads when every operand is 16-byte
 // aligned), two partial sums per product; an odd last entry goes to the
 // first thread

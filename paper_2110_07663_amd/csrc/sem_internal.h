@@ -95,6 +95,7 @@ struct Level {
   int bc[6] = {0, 0, 0, 0, 0, 0};
   bool gs_struct = true;             // false: the sorted-numbering segments (perm/off)
   bool xfuse = true;                 // the p = 7 Ax sums x-faces inside its workgroups
+  double *dotpart = nullptr;         // [E] element shares of (p, Ap) (finest level)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
   double *xi = nullptr, *wq = nullptr, *D64 = nullptr;
@@ -279,7 +280,12 @@ void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v,
 // xf: also sum the x-faces shared inside each workgroup (see ax_sums_x_faces);
 // the following launch_gs must then be told (x_in_blocks)
 template <typename T>
-void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv = 1, bool xf = false);
+void launch_ax(const Level &L, const T *u, T *v, hipStream_t s, int nv = 1, bool xf = false,
+               double *dotp = nullptr);
+// the FP64 Ax of this level can write each element's share of (u, Au) (dotp[e])
+bool ax_forms_dot(const Level &L, int nv);
+// out = sum of part[0..n) in a fixed order
+void launch_sum_partials(int64_t n, const double *part, double *out, hipStream_t s);
 bool ax_sums_x_faces(const Level &L);
 void launch_diag(const Level &L, double *d, hipStream_t s);
 

@@ -132,6 +132,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     L.G64 = A.take<double>(6 * L.nloc);
     if (lowp) L.G32 = A.take<float>(6 * L.nloc);
     if (L.fine) L.BL = A.take<double>(L.nloc);
+    if (L.fine) L.dotpart = A.take<double>(L.E);
     L.w64 = A.take<double>(L.nloc);
     if (lowp) L.w32 = A.take<float>(L.nloc);
     L.dinv64 = A.take<double>(L.nloc);
@@ -400,14 +401,30 @@ struct ProfScope {
 
 // nv right sides, nloc apart (batch lanes sharing a V-cycle); 1 otherwise
 template <typename T>
-static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv = 1) {
+static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv = 1,
+                double *dotp = nullptr) {
   const bool xf = ax_sums_x_faces(L);  // Ax sums the x-faces inside its workgroups
   {
     ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_AX64 : SEM_PROF_AX32, s);
-    launch_ax<T>(L, u, Au, s, nv, xf);
+    launch_ax<T>(L, u, Au, s, nv, xf, dotp);
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
   launch_gs<T>(L, Au, s, nv, xf);
+}
+
+// q = A p and (p, q) into *pq (device).  For p consistent and zero on the
+// Dirichlet nodes (every search direction of the CG drivers) the p = 7 FP64 Ax
+// forms (p, q) from its element shares of p^T A_L p; else a weighted dot.
+static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, double *pq,
+                    hipStream_t s) {
+  if (L.dotpart && ax_forms_dot(L, 1)) {
+    opA<double>(c, L, p, q, s, 1, L.dotpart);
+    launch_sum_partials(L.E, L.dotpart, pq, s);
+    return;
+  }
+  opA<double>(c, L, p, q, s);
+  const double *a[1] = {p}, *bb[1] = {q};
+  launch_wdots(c, L.nloc, L.w64, 1, a, bb, pq, s, L.w32);
 }
 
 // rs (may be null): apply S to r - rs; r - rs is formed as the VALU FDM reads
@@ -783,11 +800,7 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
     }
     rz_dots(1, ds + 2 * slot);
     while (it < maxit) {
-      opA<double>(c, F, p, q, s);
-      {
-        const double *a[1] = {p}, *bb[1] = {q};
-        launch_wdots(c, n, F.w64, 1, a, bb, dpq, s, F.w32);
-      }
+      opA_dot(c, F, p, q, dpq, s);
       // x, r, (r, r) in one pass (and the V-cycle's FP32 copy of r on the mixed path)
       launch_fcg_xr(c, n, ds + 2 * slot, dpq, F.w64, p, q, x, r, drr, s, F.w32,
                     zf ? F.f_b : nullptr);

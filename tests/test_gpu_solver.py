@@ -137,6 +137,22 @@ def test_solve_fixed_iterations(krylov, smoother):
     assert rel_err(host(xg), res.x) < 1e-11
 
 
+@pytest.mark.parametrize("krylov,shape", [(sem.KRYLOV_FCG, (4, 2, 3)), (sem.KRYLOV_PCG, (4, 2, 3)),
+                                          (sem.KRYLOV_FCG, (3, 2, 2))])
+def test_solve_fixed_iterations_p7(krylov, shape):
+    """p = 7: (p, Ap) comes from the Ax kernel's element shares of p^T A_L p
+    (with and without the in-workgroup x-face sums: nex = 4 and 3); six
+    iterations agree with the oracle's weighted-dot iteration to rounding."""
+    kname = {sem.KRYLOV_FCG: "fcg", sem.KRYLOV_PCG: "pcg"}[krylov]
+    P = Pair(shape, 7, mesh="sin", schedule=(7, 3, 1), smoother="ras", krylov=krylov,
+             coarse_tol=0.0, coarse_maxit=12, lambda_override=[1.6, 1.8])
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-30, maxit=6, allow_noconv=True)
+    res = P.ora.solve(bo, tol=1e-30, maxit=6, krylov=kname)
+    assert info.iters == res.iters == 6
+    assert rel_err(host(xg), res.x) < 1e-11
+
+
 @pytest.mark.parametrize("krylov", [sem.KRYLOV_FCG, sem.KRYLOV_FGMRES])
 def test_solve_to_tolerance(krylov):
     P = Pair(3, 7, mesh="shift", schedule=(7, 3, 1), smoother="ras", krylov=krylov)
