@@ -258,6 +258,52 @@ __device__ inline bool last_block_sum(double (&acc)[ND], double *partials, unsig
   return true;
 }
 
+// The hot reductions end in two launches instead: each block writes its
+// partials, and a one-workgroup kernel sums them in the same order as the
+// last-block path (so the results are the same).  A ticket counter taken by
+// every block serialises on one address (about 45 ns a block), which at 1024
+// blocks costs more than the second launch.
+template <int ND>
+__device__ inline void block_partials(double (&acc)[ND], double *partials) {
+  __shared__ double sh[ND][256];
+  block_reduce<ND>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = sh[j][0];
+  }
+}
+template <int ND>
+__global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict__ partials,
+                                                double *out) {
+  __shared__ double sh[ND][256];
+  double acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += partials[b * 8 + j];
+  }
+  block_reduce<ND>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) out[j] = sh[j][0];
+  }
+}
+static void launch_finish(int nd, unsigned nblocks, const double *partials, double *out,
+                          hipStream_t s) {
+  switch (nd) {
+    case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 3: hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 5: hipLaunchKernelGGL(k_finish<5>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 6: hipLaunchKernelGGL(k_finish<6>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 7: hipLaunchKernelGGL(k_finish<7>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    default: hipLaunchKernelGGL(k_finish<8>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+  }
+  SEM_LAUNCH("k_finish");
+}
+
 struct Ptr4 {
   const double *p[4];
 };
@@ -297,8 +343,7 @@ __device__ inline double2 ld2(const float *p, int64_t t) {
 }
 template <int ND, typename V, typename WT>
 __global__ __launch_bounds__(256) void k_wdots(int64_t n, const WT *__restrict__ w, Ptr4 a,
-                                               Ptr4 b, double *partials, unsigned *counter,
-                                               double *out) {
+                                               Ptr4 b, double *partials) {
   double acc[ND], acc2[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = acc2[j] = 0.0;
@@ -320,10 +365,7 @@ __global__ __launch_bounds__(256) void k_wdots(int64_t n, const WT *__restrict__
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
-  if (last_block_sum<ND>(acc, partials, counter) && threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < ND; ++j) out[j] = acc[j];
-  }
+  block_partials<ND>(acc, partials);
 }
 
 // FCG step: x += alpha p, r -= alpha q, and (r, r)_w of the new r, with
@@ -345,7 +387,7 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, float *__restrict__ rf,
-                                                double *partials, unsigned *counter, double *out) {
+                                                double *partials) {
   const double pqv = *pq;
   const double alpha = pqv > 0.0 ? *rz / pqv : 0.0;
   double acc[1] = {0.0}, acc2 = 0.0;
@@ -374,7 +416,7 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
     acc[0] += (double)w[n - 1] * r[n - 1] * r[n - 1];
   }
   acc[0] += acc2;
-  if (last_block_sum<1>(acc, partials, counter) && threadIdx.x == 0) out[0] = acc[0];
+  block_partials<1>(acc, partials);
 }
 
 void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
@@ -384,14 +426,15 @@ void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, 
   const unsigned g = red_grid(n);
   if (w32 && al && ((uintptr_t)w32 & 7) == 0)
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w32, p, q, x, r, rf, c.partials, c.counter, out);
+                       w32, p, q, x, r, rf, c.partials);
   else if (al && aligned16(w))
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq, w,
-                       p, q, x, r, rf, c.partials, c.counter, out);
+                       p, q, x, r, rf, c.partials);
   else
     hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w, p, q, x, r, rf, c.partials, c.counter, out);
+                       w, p, q, x, r, rf, c.partials);
   SEM_LAUNCH("k_fcg_xr");
+  launch_finish(1, g, c.partials, out, s);
 }
 
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
@@ -405,7 +448,7 @@ void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double
   bool al = true;
   for (int j = 0; j < nd; ++j) al = al && aligned16(a[j]) && aligned16(b[j]);
   if (nd < 1 || nd > 4) fail(SEM_EINVAL, "wdots: at most 4 products");
-#define WD(ND, V, WT, W) hipLaunchKernelGGL((k_wdots<ND, V, WT>), dim3(g), dim3(256), 0, s, n, W, pa, pb, c.partials, c.counter, out)
+#define WD(ND, V, WT, W) hipLaunchKernelGGL((k_wdots<ND, V, WT>), dim3(g), dim3(256), 0, s, n, W, pa, pb, c.partials)
 #define WD_ALL(V, WT, W)                                                     \
   do {                                                                       \
     if (nd == 1) WD(1, V, WT, W);                                            \
@@ -422,6 +465,7 @@ void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double
 #undef WD_ALL
 #undef WD
   SEM_LAUNCH("k_wdots");
+  launch_finish(nd, g, c.partials, out, s);
 }
 
 // (r, z_j)_w for FP32 z_j (j < ND): the preconditioned residual of the mixed
@@ -431,8 +475,7 @@ template <int ND, typename WT>
 __global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restrict__ w,
                                                   const double *__restrict__ r,
                                                   const float *__restrict__ z0,
-                                                  const float *__restrict__ z1, double *partials,
-                                                  unsigned *counter, double *out) {
+                                                  const float *__restrict__ z1, double *partials) {
   double acc[ND], acc2[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = acc2[j] = 0.0;
@@ -456,10 +499,7 @@ __global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restric
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
-  if (last_block_sum<ND>(acc, partials, counter) && threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < ND; ++j) out[j] = acc[j];
-  }
+  block_partials<ND>(acc, partials);
 }
 
 void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32, const double *r,
@@ -471,20 +511,21 @@ void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32,
   if (w32 && ((uintptr_t)w32 & 7) == 0) {
     if (nd == 1)
       hipLaunchKernelGGL((k_wdots_rz<1, float>), dim3(g), dim3(256), 0, s, n, w32, r, z0, z1,
-                         c.partials, c.counter, out);
+                         c.partials);
     else
       hipLaunchKernelGGL((k_wdots_rz<2, float>), dim3(g), dim3(256), 0, s, n, w32, r, z0, z1,
-                         c.partials, c.counter, out);
+                         c.partials);
   } else {
     if (!aligned16(w)) fail(SEM_EINVAL, "wdots_rz: misaligned weights");
     if (nd == 1)
       hipLaunchKernelGGL((k_wdots_rz<1, double>), dim3(g), dim3(256), 0, s, n, w, r, z0, z1,
-                         c.partials, c.counter, out);
+                         c.partials);
     else
       hipLaunchKernelGGL((k_wdots_rz<2, double>), dim3(g), dim3(256), 0, s, n, w, r, z0, z1,
-                         c.partials, c.counter, out);
+                         c.partials);
   }
   SEM_LAUNCH("k_wdots_rz");
+  launch_finish(nd, g, c.partials, out, s);
 }
 
 // p = z + beta p (FP64 p; z in FP32 on the mixed path), beta from the device
@@ -514,8 +555,7 @@ template void launch_zp<double>(int64_t, const double *, const double *, const d
 template <int KB>
 __global__ __launch_bounds__(256) void k_mdot(int64_t n, const double *__restrict__ w,
                                               const double *__restrict__ V, int64_t ld,
-                                              const double *__restrict__ x, double *partials,
-                                              unsigned *counter, double *out) {
+                                              const double *__restrict__ x, double *partials) {
   double acc[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) acc[j] = 0.0;
@@ -525,10 +565,7 @@ __global__ __launch_bounds__(256) void k_mdot(int64_t n, const double *__restric
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] += wx * V[j * ld + t];
   }
-  if (last_block_sum<KB>(acc, partials, counter) && threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < KB; ++j) out[j] = acc[j];
-  }
+  block_partials<KB>(acc, partials);
 }
 
 void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *V, int64_t ld,
@@ -538,7 +575,7 @@ void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *
     int kb = k - j0 < 8 ? k - j0 : 8;
     const double *Vj = V + j0 * ld;
     double *o = out + j0;
-#define MD(KB) hipLaunchKernelGGL(k_mdot<KB>, dim3(g), dim3(256), 0, s, n, w, Vj, ld, x, c.partials, c.counter, o)
+#define MD(KB) hipLaunchKernelGGL(k_mdot<KB>, dim3(g), dim3(256), 0, s, n, w, Vj, ld, x, c.partials)
     switch (kb) {
       case 1: MD(1); break;
       case 2: MD(2); break;
@@ -551,6 +588,7 @@ void launch_mdot(const Ctx &c, int64_t n, const double *w, int k, const double *
     }
 #undef MD
     SEM_LAUNCH("k_mdot");
+    launch_finish(kb, g, c.partials, o, s);
   }
 }
 
