@@ -30,37 +30,12 @@ struct LaneScalars {
   int done, iters, maxit, breakdown;
 };
 
+// Lane reductions in two launches: the blocks write partials, then one
+// workgroup per lane sums them in block order and applies the scalar step (a
+// ticket counter taken by every block would serialise on one address).
 template <int ND>
-__device__ inline bool lane_last_block(double (&acc)[ND], double *partials, unsigned *counter) {
-  __shared__ double sh[ND][256];
-  __shared__ bool is_last;
+__device__ inline void lane_tree(double (&acc)[ND], double (*sh)[256]) {
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-#pragma unroll
-      for (int j = 0; j < ND; ++j) sh[j][tid] += sh[j][tid + h];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-#pragma unroll
-    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = sh[j][0];
-    __threadfence();
-    is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-#pragma unroll
-  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  for (int b = tid; b < (int)gridDim.x; b += 256)
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      acc[j] += __hip_atomic_load(&partials[b * 8 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
 #pragma unroll
   for (int j = 0; j < ND; ++j) sh[j][tid] = acc[j];
   __syncthreads();
@@ -73,8 +48,26 @@ __device__ inline bool lane_last_block(double (&acc)[ND], double *partials, unsi
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = sh[j][0];
-  if (tid == 0) *counter = 0u;
-  return true;
+}
+template <int ND>
+__device__ inline void lane_partials(double (&acc)[ND], double *partials) {
+  __shared__ double sh[ND][256];
+  lane_tree<ND>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = acc[j];
+  }
+}
+// sum of the nb block partials, in block order, in every thread
+template <int ND>
+__device__ inline void lane_sum(double (&acc)[ND], const double *partials, int nb) {
+  __shared__ double sh[ND][256];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+    for (int j = 0; j < ND; ++j) acc[j] += partials[b * 8 + j];
+  lane_tree<ND>(acc, sh);
 }
 
 __global__ void k_lane_init(LaneScalars *L, double rz, double rr0, double tol2, int maxit) {
@@ -90,13 +83,12 @@ __global__ void k_lane_init(LaneScalars *L, double rz, double rr0, double tol2, 
 }
 
 // The lane kernels run over blockIdx.y = lanes lane0, lane0 + 1, ... of one
-// problem: vectors n apart, reduction partials kRedBlocks * 8 apart, counters
-// 16 apart, scalars consecutive.  A finished lane's blocks return at once.
+// problem: vectors n apart, reduction partials kRedBlocks * 8 apart, scalars
+// consecutive.  A finished lane's blocks return at once.
 #define SEM_LANE_OFFSETS(...)                        \
   do {                                               \
     const int64_t y = blockIdx.y;                    \
     partials += y * kRedBlocks * 8;                  \
-    counter += y * 16;                               \
     L += y;                                          \
     __VA_ARGS__                                      \
   } while (0)
@@ -105,14 +97,21 @@ __global__ void k_lane_init(LaneScalars *L, double rz, double rr0, double tol2, 
 __global__ __launch_bounds__(256) void k_lane_pq(int64_t n, const double *__restrict__ w,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ q, double *partials,
-                                                 unsigned *counter, LaneScalars *L) {
+                                                 LaneScalars *L) {
   SEM_LANE_OFFSETS(p += y * n; q += y * n;);
   if (L->done) return;
   double acc[1] = {0.0};
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
     acc[0] += w[t] * p[t] * q[t];
-  if (lane_last_block<1>(acc, partials, counter) && threadIdx.x == 0) {
+  lane_partials<1>(acc, partials);
+}
+__global__ __launch_bounds__(256) void k_lane_pq_fin(int nb, double *partials, LaneScalars *L) {
+  SEM_LANE_OFFSETS();
+  if (L->done) return;
+  double acc[1];
+  lane_sum<1>(acc, partials, nb);
+  if (threadIdx.x == 0) {
     L->pq = acc[0];
     if (acc[0] > 0.0) {
       L->alpha = L->rz / acc[0];
@@ -129,8 +128,7 @@ __global__ __launch_bounds__(256) void k_lane_update(int64_t n, const double *__
                                                      double *__restrict__ x, double *__restrict__ r,
                                                      const double *__restrict__ p,
                                                      const double *__restrict__ q,
-                                                     double *partials, unsigned *counter,
-                                                     LaneScalars *L) {
+                                                     double *partials, LaneScalars *L) {
   SEM_LANE_OFFSETS(x += y * n; r += y * n; p += y * n; q += y * n;);
   if (L->done) return;
   const double alpha = L->alpha;
@@ -142,7 +140,15 @@ __global__ __launch_bounds__(256) void k_lane_update(int64_t n, const double *__
     r[t] = rv;
     acc[0] += w[t] * rv * rv;
   }
-  if (lane_last_block<1>(acc, partials, counter) && threadIdx.x == 0) {
+  lane_partials<1>(acc, partials);
+}
+__global__ __launch_bounds__(256) void k_lane_update_fin(int nb, double *partials,
+                                                         LaneScalars *L) {
+  SEM_LANE_OFFSETS();
+  if (L->done) return;
+  double acc[1];
+  lane_sum<1>(acc, partials, nb);
+  if (threadIdx.x == 0) {
     L->rr = acc[0];
     L->iters += 1;
     if (acc[0] <= L->tol2 * L->rr0 || L->iters >= L->maxit || !(acc[0] == acc[0])) L->done = 1;
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(256) void k_lane_beta(int64_t n, const double *__re
                                                    const double *__restrict__ r,
                                                    const double *__restrict__ z,
                                                    const double *__restrict__ zo, double *partials,
-                                                   unsigned *counter, LaneScalars *L) {
+                                                   LaneScalars *L) {
   SEM_LANE_OFFSETS(r += y * n; z += y * n; zo += y * n;);
   if (L->done) return;
   double acc[2] = {0.0, 0.0};
@@ -164,7 +170,14 @@ __global__ __launch_bounds__(256) void k_lane_beta(int64_t n, const double *__re
     acc[0] += wr * z[t];
     acc[1] += wr * zo[t];
   }
-  if (lane_last_block<2>(acc, partials, counter) && threadIdx.x == 0) {
+  lane_partials<2>(acc, partials);
+}
+__global__ __launch_bounds__(256) void k_lane_beta_fin(int nb, double *partials, LaneScalars *L) {
+  SEM_LANE_OFFSETS();
+  if (L->done) return;
+  double acc[2];
+  lane_sum<2>(acc, partials, nb);
+  if (threadIdx.x == 0) {
     L->beta = (acc[0] - acc[1]) / L->rz;
     L->rz = acc[0];
   }
@@ -220,21 +233,28 @@ static void lane_iteration(Lane *ln, int nv, hipStream_t s) {
   const int64_t n = F.nloc;
   const int k = ln->k;
   double *part = c.lpartials + (int64_t)k * kRedBlocks * 8;
-  unsigned *cnt = c.lcounter + k * 16;
-  const dim3 rg(rgrid(n), (unsigned)nv), eg(egrid(n), (unsigned)nv);
+  const int nb = (int)rgrid(n);
+  const dim3 rg(rgrid(n), (unsigned)nv), eg(egrid(n), (unsigned)nv), fg(1, (unsigned)nv);
   batch_opA(c, F, ln->p, ln->q, s, nv);
-  hipLaunchKernelGGL(k_lane_pq, rg, dim3(256), 0, s, n, F.w64, ln->p, ln->q, part, cnt, ln->sc);
+  hipLaunchKernelGGL(k_lane_pq, rg, dim3(256), 0, s, n, F.w64, ln->p, ln->q, part, ln->sc);
   SEM_LAUNCH("k_lane_pq");
+  hipLaunchKernelGGL(k_lane_pq_fin, fg, dim3(256), 0, s, nb, part, ln->sc);
+  SEM_LAUNCH("k_lane_pq_fin");
   for (int j = 0; j < nv; ++j) {
     Lane &lj = ln[j];
+    double *pj = part + (int64_t)j * kRedBlocks * 8;
     hipLaunchKernelGGL(k_lane_update, dim3(rgrid(n)), dim3(256), 0, s, n, F.w64, lj.x, lj.r, lj.p,
-                       lj.q, part + (int64_t)j * kRedBlocks * 8, cnt + j * 16, lj.sc);
+                       lj.q, pj, lj.sc);
     SEM_LAUNCH("k_lane_update");
+    hipLaunchKernelGGL(k_lane_update_fin, dim3(1), dim3(256), 0, s, nb, pj, lj.sc);
+    SEM_LAUNCH("k_lane_update_fin");
   }
   batch_precondition(c, ln->r, ln->z, s, nv);
-  hipLaunchKernelGGL(k_lane_beta, rg, dim3(256), 0, s, n, F.w64, ln->r, ln->z, ln->zo, part, cnt,
+  hipLaunchKernelGGL(k_lane_beta, rg, dim3(256), 0, s, n, F.w64, ln->r, ln->z, ln->zo, part,
                      ln->sc);
   SEM_LAUNCH("k_lane_beta");
+  hipLaunchKernelGGL(k_lane_beta_fin, fg, dim3(256), 0, s, nb, part, ln->sc);
+  SEM_LAUNCH("k_lane_beta_fin");
   hipLaunchKernelGGL(k_lane_p, eg, dim3(256), 0, s, n, ln->z, ln->p, ln->zo, ln->sc);
   SEM_LAUNCH("k_lane_p");
 }

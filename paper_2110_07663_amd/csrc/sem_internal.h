@@ -231,7 +231,6 @@ struct Ctx {
   double *lanev = nullptr;           // [5][nlanes][nloc]: r, z, z_old, p, q of every lane
   void *lanes = nullptr;
   double *lpartials = nullptr;       // [nlanes][kRedBlocks][8] lane reductions
-  unsigned *lcounter = nullptr;      // [nlanes][16] last-block counters
   // level work vectors (and the coarse solve's vectors) hold nvmax right sides,
   // so the lanes of a batched solve share one V-cycle (nvmax = nlanes), else 1
   int nvmax = 1;

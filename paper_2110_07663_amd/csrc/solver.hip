@@ -212,7 +212,6 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     c.lanev = A.take<double>((size_t)c.nlanes * 5 * F.nloc);
     c.lanes = A.take<char>((size_t)c.nlanes * 128);
     c.lpartials = A.take<double>((size_t)c.nlanes * kRedBlocks * 8);
-    c.lcounter = A.take<unsigned>((size_t)c.nlanes * 16);
   }
   // assembled coarse solve when the coarsest level is p = 1
   c.cs = nullptr;
@@ -701,7 +700,6 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
                          hipMemcpyHostToDevice, s));
   SEM_HIP(hipMemsetAsync(sc.bad, 0, 64 * sizeof(int), s));
   SEM_HIP(hipMemsetAsync(c.counter, 0, 64 * sizeof(unsigned), s));
-  if (c.lcounter) SEM_HIP(hipMemsetAsync(c.lcounter, 0, c.nlanes * 16 * sizeof(unsigned), s));
   launch_gll(m->p_geom, sc.xig, nullptr, s);
 
   for (int l = 0; l < c.nlev; ++l) {
