@@ -308,18 +308,34 @@ struct Ptr4 {
   const double *p[4];
 };
 
-// out = sum of n partial values in a fixed order (one workgroup: strided sums
-// per thread, then the LDS tree)
-__global__ __launch_bounds__(256) void k_sum_partials(int64_t n, const double *__restrict__ part,
-                                                      double *out) {
-  __shared__ double sh[1][256];
-  double acc[1] = {0.0};
-  for (int64_t i = threadIdx.x; i < n; i += 256) acc[0] += part[i];
-  block_reduce<1>(acc, sh);
-  if (threadIdx.x == 0) out[0] = sh[0][0];
+// out = sum of n partial values in a fixed order: one workgroup of 1024
+// threads, eight loads in flight per thread and step (into four running sums),
+// then an LDS tree
+__global__ __launch_bounds__(1024) void k_sum_partials(int64_t n, const double *__restrict__ part,
+                                                       double *out) {
+  __shared__ double sh[1024];
+  const int tid = threadIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = 0; i0 < n; i0 += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + u * 1024 + tid;
+      v[u] = i < n ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u & 3] += v[u];
+  }
+  sh[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (tid < h) sh[tid] += sh[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = sh[0];
 }
 void launch_sum_partials(int64_t n, const double *part, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, n, part, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, n, part, out);
   SEM_LAUNCH("k_sum_partials");
 }
 
