@@ -376,6 +376,10 @@ TRAFFIC_32CUBE_P7 = {
     "fdm": 301107243,     # k_fdm_lines<7,float,false>
 }
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# The same VALU without packed FP32 (two results per lane and cycle): 256 CUs x
+# 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.  The library is built with packed
+# FP32 instructions switched off, so this is the ceiling its FP32 kernels face.
+FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def main():
@@ -471,6 +475,8 @@ def main():
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(d["TFLOPs"], 2),
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(d["TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "peak_unpacked": round(FP32_UNPACKED_PEAK_TFLOPS, 1),
+                    "frac_unpacked": round(d["TFLOPs"] / FP32_UNPACKED_PEAK_TFLOPS, 4),
                     "traffic": traffic, "hbm_GBs": round(d["GBs"], 1)}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBs"], 1),
