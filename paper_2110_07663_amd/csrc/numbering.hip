@@ -362,6 +362,110 @@ __global__ void k_gs_xb(T *__restrict__ v, GsGrid g, int64_t E) {
   }
 }
 
+// The y and z passes in one launch, with the same sums in the same order.
+// Thread sets (i fastest in each):
+//   Y: rows of a y-face with k = 1..p-1 (the z pass never touches them),
+//   Z: rows of a z-face with j = 1..p-1 (the y pass never touches them),
+//   E: the x-lines where y- and z-faces meet (j, k in {0, p}): up to four
+//      copies; the y step (pair sum, or the Dirichlet zero / the value itself
+//      at a y boundary) is taken on each z side, then the z step on the
+//      results, and the total goes to every copy: (a + b) + (c + d), as the
+//      two passes compute it.
+// Every face node belongs to exactly one thread; the whole vector is read
+// once instead of once per pass.  Measured at 32^3, p = 7: 10 % faster than the
+// two passes in FP64, 7 % slower in FP32; used for FP64 by default.
+template <typename T>
+__global__ void k_gs_yz(T *__restrict__ v, GsGrid g, int64_t E, int64_t ny_t, int64_t nz_t,
+                        int64_t ne_t) {
+  // thread counts and element indices stay below 2^31 (E N^2 < 2^31): 32-bit
+  // unsigned index arithmetic
+  const unsigned t0 = xcd_block() * blockDim.x + threadIdx.x;
+  const unsigned nyz = (unsigned)(ny_t + nz_t);
+  if (t0 >= nyz + (unsigned)ne_t) return;
+  const unsigned N = (unsigned)g.N, p = (unsigned)g.p, N2 = N * N;
+  const unsigned nex = (unsigned)g.nex, ney = (unsigned)g.ney, nez = (unsigned)g.nez;
+  const int64_t N3 = (int64_t)N2 * N;
+  v += blockIdx.y * E * N3;  // right side blockIdx.y
+  auto elem = [&](unsigned ex, unsigned ey, unsigned ez) {
+    return (int64_t)((ez * ney + ey) * nex + ex);
+  };
+  if (t0 < nyz) {  // a y-face row (k interior) or a z-face row (j interior)
+    const bool yf = t0 < (unsigned)ny_t;
+    unsigned t = yf ? t0 : t0 - (unsigned)ny_t;
+    const unsigned i = t % N;
+    t /= N;
+    const unsigned m = 1 + t % (p - 1);  // k (y-face) or j (z-face)
+    t /= p - 1;
+    const unsigned ex = t % nex;
+    t /= nex;
+    const unsigned cnt = yf ? ney : nez;
+    const unsigned gf = t % (cnt + 1), other = t / (cnt + 1);  // face index; ez (y) or ey (z)
+    const bool has_lo = gf >= 1, has_up = gf < cnt;
+    const int64_t lo_e = has_lo ? (yf ? elem(ex, gf - 1, other) : elem(ex, other, gf - 1)) : 0;
+    const int64_t up_e = has_up ? (yf ? elem(ex, gf, other) : elem(ex, other, gf)) : 0;
+    // lower copy: the element's p-face; upper copy: the 0-face
+    const unsigned lo = yf ? m * N2 + p * N + i : p * N2 + m * N + i;
+    const unsigned up = yf ? m * N2 + i : m * N + i;
+    const int blo = yf ? g.bc[2] : g.bc[4], bhi = yf ? g.bc[3] : g.bc[5];
+    T *const a = v + lo_e * N3 + lo;
+    T *const b = v + up_e * N3 + up;
+    if (has_lo && has_up) {
+      const T sum = *a + *b;
+      *a = sum;
+      *b = sum;
+    } else if (has_lo) {
+      if (bhi) *a = T(0);
+    } else if (has_up) {
+      if (blo) *b = T(0);
+    }
+    return;
+  }
+  // an x-line where y- and z-faces meet
+  unsigned t = t0 - nyz;
+  const unsigned i = t % N;
+  t /= N;
+  const unsigned ex = t % nex;
+  t /= nex;
+  const unsigned gy = t % (ney + 1), gz = t / (ney + 1);
+  int64_t idx[2][2];  // [z side][y side], -1 when absent
+#pragma unroll
+  for (int zs = 0; zs < 2; ++zs)
+#pragma unroll
+    for (int ys = 0; ys < 2; ++ys) {
+      const bool in = (ys ? gy < ney : gy >= 1) && (zs ? gz < nez : gz >= 1);
+      idx[zs][ys] = in ? elem(ex, gy - 1 + ys, gz - 1 + zs) * N3 + (zs ? 0 : p) * N2 +
+                             (ys ? 0 : p) * N + i
+                       : -1;
+    }
+  T zv[2];
+  bool zin[2];
+#pragma unroll
+  for (int zs = 0; zs < 2; ++zs) {
+    const int64_t a = idx[zs][0], b = idx[zs][1];
+    zin[zs] = a >= 0 || b >= 0;
+    if (a >= 0 && b >= 0)
+      zv[zs] = v[a] + v[b];
+    else if (a >= 0)
+      zv[zs] = g.bc[3] ? T(0) : v[a];
+    else if (b >= 0)
+      zv[zs] = g.bc[2] ? T(0) : v[b];
+    else
+      zv[zs] = T(0);
+  }
+  T tot;
+  if (zin[0] && zin[1])
+    tot = zv[0] + zv[1];
+  else if (zin[0])
+    tot = g.bc[5] ? T(0) : zv[0];
+  else
+    tot = g.bc[4] ? T(0) : zv[1];
+#pragma unroll
+  for (int zs = 0; zs < 2; ++zs)
+#pragma unroll
+    for (int ys = 0; ys < 2; ++ys)
+      if (idx[zs][ys] >= 0) v[idx[zs][ys]] = tot;
+}
+
 template <typename T>
 void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks) {
   if (x_in_blocks && (!L.gs_struct || L.nex % 4 != 0))
@@ -378,6 +482,16 @@ void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks) {
     } else {
       hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
       SEM_LAUNCH("k_gs_dir");
+    }
+    const bool yz = L.gs_yz == 1 || (L.gs_yz < 0 && sizeof(T) == 8);
+    if (yz && L.p >= 2) {
+      const int64_t ny_t = (int64_t)L.nex * (L.ney + 1) * L.nez * (L.p - 1) * L.N;
+      const int64_t nz_t = (int64_t)L.nex * L.ney * (L.nez + 1) * (L.p - 1) * L.N;
+      const int64_t ne_t = (int64_t)L.nex * (L.ney + 1) * (L.nez + 1) * L.N;
+      const dim3 gyz(nb(ny_t + nz_t + ne_t, 256), (unsigned)nv);
+      hipLaunchKernelGGL((k_gs_yz<T>), gyz, dim3(256), 0, s, v, g, L.E, ny_t, nz_t, ne_t);
+      SEM_LAUNCH("k_gs_yz");
+      return;
     }
     hipLaunchKernelGGL((k_gs_dir<T, 1>), dim3(grid), dim3(256), 0, s, v, g, L.E);
     SEM_LAUNCH("k_gs_dir");

@@ -95,6 +95,7 @@ struct Level {
   int bc[6] = {0, 0, 0, 0, 0, 0};
   bool gs_struct = true;             // false: the sorted-numbering segments (perm/off)
   bool xfuse = true;                 // the p = 7 Ax sums x-faces inside its workgroups
+  int gs_yz = -1;                    // y and z passes in one launch: 1 yes, 0 no, -1 FP64 only
   double *dotpart = nullptr;         // [E] element shares of (p, Ap) (finest level)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)

@@ -316,6 +316,11 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
       // SEM_AX_XFUSE=0: the p = 7 Ax leaves every x-face to the gather-scatter
       const char *xfv = getenv("SEM_AX_XFUSE");
       L.xfuse = !(xfv && xfv[0] == '0');
+      // SEM_GS_YZ=0 / 1: the y and z passes as two launches / one launch in
+      // both precisions (default: one launch for FP64, measured faster there
+      // and slower in FP32)
+      const char *yzv = getenv("SEM_GS_YZ");
+      L.gs_yz = yzv ? (yzv[0] == '1' ? 1 : 0) : -1;
     }
     L.lowp = c.lowp;
     // Ax kernel shape at p = 7 (option, else SEM_AX_VARIANT, else one wave/element,

@@ -55,21 +55,24 @@ def test_apply_A_fp64(shape, p, mesh):
     assert rel_err(Ag, Ao) < 1e-12
 
 
-@pytest.mark.parametrize("sorted_gs,xfuse", [(False, True), (False, False), (True, True)])
+@pytest.mark.parametrize("sorted_gs,xfuse,yz", [(False, True, True), (False, False, True),
+                                               (False, True, False), (True, True, True)])
 @pytest.mark.parametrize("shape,p,bc", [
     ((3, 2, 5), 3, (1, 0, 1, 1, 0, 1)), ((1, 4, 2), 7, (1,) * 6), ((2, 2, 2), 1, (0,) * 6),
     ((4, 3, 2), 7, (0, 1, 1, 0, 0, 1)), ((8, 2, 3), 7, (1, 1, 0, 1, 1, 0)),
     ((12, 1, 2), 7, (0, 0, 1, 1, 1, 1)),
 ])
-def test_gather_scatter_paths(monkeypatch, sorted_gs, xfuse, shape, p, bc):
+def test_gather_scatter_paths(monkeypatch, sorted_gs, xfuse, yz, shape, p, bc):
     """Direction passes (default; at p = 7 with nex a multiple of 4 the Ax
-    kernel sums the x-faces inside its workgroups first), the same without that
-    fusion, and sorted segments for QQ^T: A matches the oracle, every copy of a
-    global node holds the same bits, Dirichlet copies are exactly zero; FP32
-    likewise to its tolerance."""
+    kernel sums the x-faces inside its workgroups first; the y and z passes run
+    as one launch), the same without the x-face fusion, with the y and z passes
+    as two launches, and sorted segments for QQ^T: A matches the oracle, every
+    copy of a global node holds the same bits, Dirichlet copies are exactly
+    zero; FP32 likewise to its tolerance."""
     t = __import__("torch")
     monkeypatch.setenv("SEM_GS_SORTED", "1" if sorted_gs else "0")
     monkeypatch.setenv("SEM_AX_XFUSE", "1" if xfuse else "0")
+    monkeypatch.setenv("SEM_GS_YZ", "1" if yz else "0")
     P = Pair(shape, p, mesh="sin", bc=bc, smoother_prec=sem.F32)
     num = P.ora.levels[0].num
     g, o = P.random_local(21, masked=False)
@@ -204,3 +207,21 @@ def test_apply_A_full_size_sampled(n, p):
     # each element alone is held to 1e-11
     assert rel_err(np.concatenate(gots), np.concatenate(refs)) < 1e-12, per
     assert max(per) < 1e-11, per
+
+
+@pytest.mark.parametrize("shape,p,bc", [((3, 2, 5), 3, (1, 0, 1, 1, 0, 1)), ((4, 3, 2), 7, (0, 1, 1, 0, 0, 1)),
+                                        ((2, 1, 3), 5, (0,) * 6), ((1, 3, 1), 2, (1,) * 6)])
+def test_gather_scatter_yz_launch_is_bitwise(monkeypatch, shape, p, bc):
+    """The one-launch y/z pass gives the two passes' results bit for bit (same
+    sums in the same order), FP64 and FP32, for A and for the smoother."""
+    t = __import__("torch")
+    out = {}
+    for yz in ("1", "0"):
+        monkeypatch.setenv("SEM_GS_YZ", yz)
+        P = Pair(shape, p, mesh="sin", bc=bc, smoother_prec=sem.F32, schedule=(p, 1),
+                 smoother="ras", lambda_override=[2.0], oracle=False)
+        g, _ = P.random_local(22, masked=False)
+        out[yz] = [host(P.gpu.apply_A(g)), host(P.gpu.apply_A(g.to(t.float32))),
+                   host(P.gpu.apply_S(g.to(t.float32)))]
+    for a, b in zip(out["1"], out["0"]):
+        np.testing.assert_array_equal(a, b)
