@@ -12,14 +12,17 @@ namespace sem {
 
 constexpr int kTN = 11;  // largest N handled (p <= 10)
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__restrict__ J,
+// NF, NC > 0: sizes fixed at compile time (the loops unroll, 256 threads);
+// 0: taken from the arguments
+template <typename T, int NF = 0, int NC = 0>
+__global__ __launch_bounds__(256) void k_prolong(int Nf_, int Nc_, const T *__restrict__ J,
                                                  const T *__restrict__ xc, T *__restrict__ xf) {
   __shared__ T sJ[kTN * kTN];
   __shared__ T a[kTN * kTN * kTN];
   __shared__ T b[kTN * kTN * kTN];
+  const int Nf = NF ? NF : Nf_, Nc = NC ? NC : Nc_;
   const int64_t e = blockIdx.x;
-  const int tid = threadIdx.x, bs = blockDim.x;
+  const int tid = threadIdx.x, bs = NF ? 256 : (int)blockDim.x;
   const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
   xc += blockIdx.y * (int64_t)gridDim.x * Nc3;  // right side blockIdx.y
   xf += blockIdx.y * (int64_t)gridDim.x * Nf3;
@@ -30,6 +33,7 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__rest
   for (int t = tid; t < Nc * Nc * Nf; t += bs) {
     int i = t % Nf, cb = t / Nf;
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nc; ++q) s += sJ[i * Nc + q] * a[cb * Nc + q];
     b[t] = s;
   }
@@ -38,6 +42,7 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__rest
   for (int t = tid; t < Nc * Nf * Nf; t += bs) {
     int i = t % Nf, j = (t / Nf) % Nf, c = t / (Nf * Nf);
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nc; ++q) s += sJ[j * Nc + q] * b[(c * Nc + q) * Nf + i];
     a[t] = s;
   }
@@ -46,20 +51,22 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf, int Nc, const T *__rest
   for (int t = tid; t < Nf3; t += bs) {
     int ji = t % (Nf * Nf), k = t / (Nf * Nf);
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nc; ++q) s += sJ[k * Nc + q] * a[q * Nf * Nf + ji];
     xf[e * Nf3 + t] += s;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__restrict__ J,
+template <typename T, int NF = 0, int NC = 0>
+__global__ __launch_bounds__(256) void k_restrict(int Nf_, int Nc_, const T *__restrict__ J,
                                                   const T *__restrict__ w, const T *__restrict__ rf,
                                                   const T *__restrict__ bf, T *__restrict__ rc) {
   __shared__ T sJ[kTN * kTN];
   __shared__ T a[kTN * kTN * kTN];
   __shared__ T b[kTN * kTN * kTN];
+  const int Nf = NF ? NF : Nf_, Nc = NC ? NC : Nc_;
   const int64_t e = blockIdx.x;
-  const int tid = threadIdx.x, bs = blockDim.x;
+  const int tid = threadIdx.x, bs = NF ? 256 : (int)blockDim.x;
   const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
   rf += blockIdx.y * (int64_t)gridDim.x * Nf3;  // right side blockIdx.y
   rc += blockIdx.y * (int64_t)gridDim.x * Nc3;
@@ -75,6 +82,7 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__res
   for (int t = tid; t < Nf * Nf * Nc; t += bs) {
     int aa = t % Nc, kj = t / Nc;
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + aa] * a[kj * Nf + q];
     b[t] = s;
   }
@@ -83,6 +91,7 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__res
   for (int t = tid; t < Nf * Nc * Nc; t += bs) {
     int aa = t % Nc, bb = (t / Nc) % Nc, k = t / (Nc * Nc);
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + bb] * b[(k * Nf + q) * Nc + aa];
     a[t] = s;
   }
@@ -91,6 +100,7 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf, int Nc, const T *__res
   for (int t = tid; t < Nc3; t += bs) {
     int ba = t % (Nc * Nc), c = t / (Nc * Nc);
     T s = 0;
+#pragma unroll
     for (int q = 0; q < Nf; ++q) s += sJ[q * Nc + c] * a[q * Nc * Nc + ba];
     rc[e * Nc3 + t] = s;
   }
@@ -102,12 +112,23 @@ static int transfer_threads(int Nf) {
   return t > 256 ? 256 : t;
 }
 
+// compile-time sizes for the pairs of the usual schedules (fine N >= 6, so
+// 256 threads), the generic kernel otherwise
+#define SEM_TRANSFER_PAIRS(X) X(8, 4) X(6, 4) X(10, 6) X(10, 8) X(8, 6)
+
 template <typename T>
 void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStream_t s, int nv) {
   const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
-  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)F.E, (unsigned)nv), dim3(transfer_threads(F.N)),
-                     0, s, F.N,
-                     C.N, J, xc, xf);
+  const dim3 grid((unsigned)F.E, (unsigned)nv);
+#define SEM_PROLONG_CASE(NF, NC)                                                             \
+  if (F.N == NF && C.N == NC) {                                                              \
+    hipLaunchKernelGGL((k_prolong<T, NF, NC>), grid, dim3(256), 0, s, F.N, C.N, J, xc, xf); \
+    SEM_LAUNCH("k_prolong");                                                                 \
+    return;                                                                                  \
+  }
+  SEM_TRANSFER_PAIRS(SEM_PROLONG_CASE)
+#undef SEM_PROLONG_CASE
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(transfer_threads(F.N)), 0, s, F.N, C.N, J, xc, xf);
   SEM_LAUNCH("k_prolong");
 }
 
@@ -116,11 +137,21 @@ void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStre
                      const T *bf) {
   const T *J = sizeof(T) == 8 ? (const T *)F.J64 : (const T *)F.J32;
   const T *w = sizeof(T) == 8 ? (const T *)F.w64 : (const T *)F.w32;
-  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)F.E, (unsigned)nv), dim3(transfer_threads(F.N)),
-                     0, s, F.N,
-                     C.N, J, w, rf, bf, rc);
+  const dim3 grid((unsigned)F.E, (unsigned)nv);
+#define SEM_RESTRICT_CASE(NF, NC)                                                          \
+  if (F.N == NF && C.N == NC) {                                                            \
+    hipLaunchKernelGGL((k_restrict<T, NF, NC>), grid, dim3(256), 0, s, F.N, C.N, J, w, rf, \
+                       bf, rc);                                                            \
+    SEM_LAUNCH("k_restrict");                                                              \
+    return;                                                                                \
+  }
+  SEM_TRANSFER_PAIRS(SEM_RESTRICT_CASE)
+#undef SEM_RESTRICT_CASE
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(transfer_threads(F.N)), 0, s, F.N, C.N, J, w, rf,
+                     bf, rc);
   SEM_LAUNCH("k_restrict");
 }
+#undef SEM_TRANSFER_PAIRS
 
 template void launch_prolong<double>(const Level &, const Level &, const double *, double *,
                                      hipStream_t, int);
