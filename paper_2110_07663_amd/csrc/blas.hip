@@ -5,6 +5,7 @@
 // fixed launch shape and a fixed summation tree (per-thread strided partial
 // sums, an LDS tree per block, then the last block to finish sums the block
 // partials in block order), so results are bitwise repeatable.
+#include <initializer_list>
 #include <type_traits>
 
 #include "sem_internal.h"
@@ -13,6 +14,28 @@ namespace sem {
 
 static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// 16-byte vectors (4 floats or 2 doubles) for the pointwise kernels: one load
+// or store instruction per operand and thread; arithmetic acts per element
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct V16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+// the vector form applies when n is a multiple of the width and every
+// operand is 16-byte aligned
+template <typename T>
+static inline bool vec16_ok(int64_t n, std::initializer_list<const void *> ps) {
+  if (n % (int64_t)(16 / sizeof(T)) != 0) return false;
+  for (const void *q : ps)
+    if (q && !aligned16(q)) return false;
+  return true;
+}
 static inline unsigned red_grid(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > kRedBlocks) g = kRedBlocks;
@@ -97,8 +120,15 @@ __global__ void k_cheb_update(int64_t n, T *__restrict__ x, T *__restrict__ r, T
 template <typename T>
 void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s,
                         bool x_zero) {
-  hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
-                     (int)x_zero);
+  if (vec16_ok<T>(n, {x, r, d, t})) {
+    using VT = typename V16<T>::type;
+    const int64_t m = n / (int64_t)(16 / sizeof(T));
+    hipLaunchKernelGGL(k_cheb_update<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x, (VT *)r,
+                       (VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero);
+  } else {
+    hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                       (int)x_zero);
+  }
   SEM_LAUNCH("k_cheb_update");
 }
 template void launch_cheb_update<double>(int64_t, double *, double *, double *, const double *,
@@ -131,8 +161,16 @@ __global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T 
 template <typename T>
 void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a, T c,
                        bool x_zero, bool last, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, inv_theta,
-                     a, c, (int)x_zero, (int)last);
+  if (vec16_ok<T>(n, {x, r, d, t})) {
+    using VT = typename V16<T>::type;
+    const int64_t m = n / (int64_t)(16 / sizeof(T));
+    hipLaunchKernelGGL(k_cheb_first<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x, (VT *)r,
+                       (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c, (int)x_zero,
+                       (int)last);
+  } else {
+    hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t,
+                       inv_theta, a, c, (int)x_zero, (int)last);
+  }
   SEM_LAUNCH("k_cheb_first");
 }
 template void launch_cheb_first<double>(int64_t, double *, double *, double *, const double *,
@@ -156,8 +194,15 @@ __global__ void k_cheb_last(int64_t n, T *__restrict__ x, const T *__restrict__ 
 template <typename T>
 void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c, hipStream_t s,
                       bool x_zero) {
-  hipLaunchKernelGGL(k_cheb_last<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
-                     (int)x_zero);
+  if (vec16_ok<T>(n, {x, r, d, t})) {
+    using VT = typename V16<T>::type;
+    const int64_t m = n / (int64_t)(16 / sizeof(T));
+    hipLaunchKernelGGL(k_cheb_last<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
+                       (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero);
+  } else {
+    hipLaunchKernelGGL(k_cheb_last<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                       (int)x_zero);
+  }
   SEM_LAUNCH("k_cheb_last");
 }
 template void launch_cheb_last<double>(int64_t, double *, const double *, const double *,
