@@ -106,49 +106,118 @@ template void launch_sub<float>(int64_t, const float *, const float *, float *, 
 
 // one pass of the loop body: x += d_k; r -= S A d_k (= t); d = a d_k + c r
 // (xz: x is zero on entry and is not read)
-template <typename T>
+// t read as assembled (XD::value false), or with the deferred x step of the
+// gather-scatter taken on the way (16-byte vectors VT of T; a vector never
+// straddles an element row, so only its first lane can be an i = 0 node and
+// only its last an i = p node)
+struct XDev {
+  unsigned nex, N, p, vrow, vel, vside;  // vectors per row, per element, per right side
+  int bc0, bc1;
+};
+template <typename XD, typename VT>
+__device__ inline VT read_t(const VT *__restrict__ tv, int64_t m, const XDev &f) {
+  VT v = tv[m];
+  if constexpr (XD::value) {
+    using T = std::decay_t<decltype(v[0])>;
+    constexpr int W = sizeof(VT) / sizeof(T);
+    const T *__restrict__ ts = reinterpret_cast<const T *>(tv);
+    const unsigned mq = (unsigned)(m % f.vside);
+    const unsigned e = mq / f.vel;
+    const unsigned i0 = (mq - e * f.vel) % f.vrow * W;
+    const unsigned ex = e % f.nex;
+    const int64_t q = m * W;
+    const int64_t N3 = (int64_t)f.vel * W;
+    if (i0 == 0) {
+      if (ex > 0)
+        v[0] = ts[q - N3 + f.p] + v[0];
+      else if (f.bc0)
+        v[0] = T(0);
+    }
+    if (i0 + W - 1 == f.p) {
+      if (ex + 1 < f.nex)
+        v[W - 1] = v[W - 1] + ts[q + (W - 1) - f.p + N3];
+      else if (f.bc1)
+        v[W - 1] = T(0);
+    }
+  }
+  return v;
+}
+
+template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_update(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
-                              const T *__restrict__ tv, T a, T c, int xz) {
+                              const T *__restrict__ tv, T a, T c, int xz, XDev f) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   T dk = d[t];
   x[t] = xz ? dk : x[t] + dk;
-  T rn = r[t] - tv[t];
+  T rn = r[t] - read_t<XD>(tv, t, f);
   r[t] = rn;
   d[t] = a * dk + c * rn;
 }
 template <typename T>
+bool cheb_can_defer_x(int N, int64_t n, std::initializer_list<const void *> ps) {
+  return N % (int)(16 / sizeof(T)) == 0 && vec16_ok<T>(n, ps);
+}
+template bool cheb_can_defer_x<float>(int, int64_t, std::initializer_list<const void *>);
+template bool cheb_can_defer_x<double>(int, int64_t, std::initializer_list<const void *>);
+
+template <typename T>
+static XDev xdev(const XDefer &xd) {
+  constexpr unsigned W = 16 / sizeof(T);
+  XDev f{};
+  if (!xd.on) return f;
+  if (xd.N % (int)W != 0 || xd.nloc % ((int64_t)xd.N * xd.N * xd.N) != 0)
+    fail(SEM_EINVAL, "deferred x step: vectors straddle element rows");
+  f.nex = (unsigned)xd.nex;
+  f.N = (unsigned)xd.N;
+  f.p = (unsigned)xd.N - 1;
+  f.vrow = (unsigned)xd.N / W;
+  f.vel = (unsigned)(xd.N * xd.N * xd.N) / W;
+  f.vside = (unsigned)(xd.nloc / W);
+  f.bc0 = xd.bc0;
+  f.bc1 = xd.bc1;
+  return f;
+}
+
+template <typename T>
 void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s,
-                        bool x_zero) {
+                        bool x_zero, const XDefer &xd) {
+  const XDev f = xdev<T>(xd);
   if (vec16_ok<T>(n, {x, r, d, t})) {
     using VT = typename V16<T>::type;
     const int64_t m = n / (int64_t)(16 / sizeof(T));
-    hipLaunchKernelGGL(k_cheb_update<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x, (VT *)r,
-                       (VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero);
+    if (xd.on)
+      hipLaunchKernelGGL((k_cheb_update<VT, std::true_type>), dim3(nb(m, 256)), dim3(256), 0, s, m,
+                         (VT *)x, (VT *)r, (VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero, f);
+    else
+      hipLaunchKernelGGL((k_cheb_update<VT>), dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
+                         (VT *)r, (VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero, f);
   } else {
-    hipLaunchKernelGGL(k_cheb_update<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
-                       (int)x_zero);
+    if (xd.on) fail(SEM_EINVAL, "deferred x step needs the vector form");
+    hipLaunchKernelGGL((k_cheb_update<T>), dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                       (int)x_zero, f);
   }
   SEM_LAUNCH("k_cheb_update");
 }
 template void launch_cheb_update<double>(int64_t, double *, double *, double *, const double *,
-                                         double, double, hipStream_t, bool);
+                                         double, double, hipStream_t, bool, const XDefer &);
 template void launch_cheb_update<float>(int64_t, float *, float *, float *, const float *, float,
-                                        float, hipStream_t, bool);
+                                        float, hipStream_t, bool, const XDefer &);
 
 // The first pass of the loop without forming d_0 = r_0 / theta beforehand: A
 // and S are linear, so the caller applies them to r_0 and this pass scales
 // (tv = S A r_0).  x += d_0; r -= tv / theta; d = a d_0 + c r; with `last` the
 // closing x += d as well (r and d then unwritten).  xz: x is zero on entry.
-template <typename T>
+template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
-                             const T *__restrict__ tv, T inv_theta, T a, T c, int xz, int last) {
+                             const T *__restrict__ tv, T inv_theta, T a, T c, int xz, int last,
+                             XDev f) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const T r0 = r[t];
   const T d0 = r0 * inv_theta;
   const T x1 = xz ? d0 : x[t] + d0;
-  const T rn = r0 - tv[t] * inv_theta;
+  const T rn = r0 - read_t<XD>(tv, t, f) * inv_theta;
   const T dn = a * d0 + c * rn;
   if (last) {
     x[t] = dn + x1;
@@ -160,55 +229,74 @@ __global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T 
 }
 template <typename T>
 void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a, T c,
-                       bool x_zero, bool last, hipStream_t s) {
+                       bool x_zero, bool last, hipStream_t s, const XDefer &xd) {
+  const XDev f = xdev<T>(xd);
   if (vec16_ok<T>(n, {x, r, d, t})) {
     using VT = typename V16<T>::type;
     const int64_t m = n / (int64_t)(16 / sizeof(T));
-    hipLaunchKernelGGL(k_cheb_first<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x, (VT *)r,
-                       (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c, (int)x_zero,
-                       (int)last);
+    if (xd.on)
+      hipLaunchKernelGGL((k_cheb_first<VT, std::true_type>), dim3(nb(m, 256)), dim3(256), 0, s, m,
+                         (VT *)x, (VT *)r, (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c,
+                         (int)x_zero, (int)last, f);
+    else
+      hipLaunchKernelGGL((k_cheb_first<VT>), dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
+                         (VT *)r, (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c,
+                         (int)x_zero, (int)last, f);
   } else {
-    hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t,
-                       inv_theta, a, c, (int)x_zero, (int)last);
+    if (xd.on) fail(SEM_EINVAL, "deferred x step needs the vector form");
+    hipLaunchKernelGGL((k_cheb_first<T>), dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t,
+                       inv_theta, a, c, (int)x_zero, (int)last, f);
   }
   SEM_LAUNCH("k_cheb_first");
 }
 template void launch_cheb_first<double>(int64_t, double *, double *, double *, const double *,
-                                        double, double, double, bool, bool, hipStream_t);
+                                        double, double, double, bool, bool, hipStream_t,
+                                        const XDefer &);
 template void launch_cheb_first<float>(int64_t, float *, float *, float *, const float *, float,
-                                       float, float, bool, bool, hipStream_t);
+                                       float, float, bool, bool, hipStream_t, const XDefer &);
 
 // the last pass of the loop and the closing x += d in one: r and d are not
 // needed afterwards, so only x is written (same roundings as the two passes)
-template <typename T>
+template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_last(int64_t n, T *__restrict__ x, const T *__restrict__ r,
-                            const T *__restrict__ d, const T *__restrict__ tv, T a, T c, int xz) {
+                            const T *__restrict__ d, const T *__restrict__ tv, T a, T c, int xz,
+                            XDev f) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const T dk = d[t];
   const T x1 = xz ? dk : x[t] + dk;
-  const T rn = r[t] - tv[t];
+  const T rn = r[t] - read_t<XD>(tv, t, f);
   const T dn = a * dk + c * rn;
   x[t] = dn + x1;
 }
 template <typename T>
 void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c, hipStream_t s,
-                      bool x_zero) {
+                      bool x_zero, const XDefer &xd) {
+  const XDev f = xdev<T>(xd);
   if (vec16_ok<T>(n, {x, r, d, t})) {
     using VT = typename V16<T>::type;
     const int64_t m = n / (int64_t)(16 / sizeof(T));
-    hipLaunchKernelGGL(k_cheb_last<VT>, dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
-                       (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero);
+    if (xd.on)
+      hipLaunchKernelGGL((k_cheb_last<VT, std::true_type>), dim3(nb(m, 256)), dim3(256), 0, s, m,
+                         (VT *)x, (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c,
+                         (int)x_zero, f);
+    else
+      hipLaunchKernelGGL((k_cheb_last<VT>), dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
+                         (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero,
+                         f);
   } else {
-    hipLaunchKernelGGL(k_cheb_last<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
-                       (int)x_zero);
+    if (xd.on) fail(SEM_EINVAL, "deferred x step needs the vector form");
+    hipLaunchKernelGGL((k_cheb_last<T>), dim3(nb(n, 256)), dim3(256), 0, s, n, x, r, d, t, a, c,
+                       (int)x_zero, f);
   }
   SEM_LAUNCH("k_cheb_last");
 }
 template void launch_cheb_last<double>(int64_t, double *, const double *, const double *,
-                                       const double *, double, double, hipStream_t, bool);
+                                       const double *, double, double, hipStream_t, bool,
+                                       const XDefer &);
 template void launch_cheb_last<float>(int64_t, float *, const float *, const float *,
-                                      const float *, float, float, hipStream_t, bool);
+                                      const float *, float, float, hipStream_t, bool,
+                                      const XDefer &);
 
 __global__ void k_jacobi_inv(int64_t n, const double *__restrict__ diag, const double *__restrict__ w,
                              double *__restrict__ dinv, float *__restrict__ dinv32) {

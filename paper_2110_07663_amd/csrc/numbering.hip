@@ -467,15 +467,18 @@ __global__ void k_gs_yz(T *__restrict__ v, GsGrid g, int64_t E, int64_t ny_t, in
 }
 
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks) {
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks, bool skip_x) {
   if (x_in_blocks && (!L.gs_struct || L.nex % 4 != 0))
     fail(SEM_EINVAL, "gather-scatter: block x-faces need the direction passes and nex % 4 == 0");
+  if (skip_x && !L.gs_struct) fail(SEM_EINVAL, "gather-scatter: skip_x needs the direction passes");
   if (L.gs_struct) {
     GsGrid g;
     g.nex = L.nex; g.ney = L.ney; g.nez = L.nez; g.p = L.p; g.N = L.N;
     for (int f = 0; f < 6; ++f) g.bc[f] = L.bc[f];
     const dim3 grid(nb(L.E * L.N * L.N, 256), (unsigned)nv);
-    if (x_in_blocks) {
+    if (skip_x) {
+      // the consumer takes the x step (the passes commute up to rounding)
+    } else if (x_in_blocks) {
       const dim3 gx(nb(L.E / 4 * L.N * L.N, 256), (unsigned)nv);
       hipLaunchKernelGGL((k_gs_xb<T>), gx, dim3(256), 0, s, v, g, L.E);
       SEM_LAUNCH("k_gs_xb");
@@ -506,8 +509,8 @@ void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks) {
     SEM_LAUNCH("k_gs");
   }
 }
-template void launch_gs<double>(const Level &, double *, hipStream_t, int, bool);
-template void launch_gs<float>(const Level &, float *, hipStream_t, int, bool);
+template void launch_gs<double>(const Level &, double *, hipStream_t, int, bool, bool);
+template void launch_gs<float>(const Level &, float *, hipStream_t, int, bool, bool);
 
 void launch_weights(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_fill1, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, L.w64, L.w32);

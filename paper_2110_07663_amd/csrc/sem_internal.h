@@ -7,6 +7,7 @@
 #include <cstring>
 #include <string>
 #include <utility>
+#include <initializer_list>
 #include <vector>
 
 #include "sem.h"
@@ -96,6 +97,7 @@ struct Level {
   bool gs_struct = true;             // false: the sorted-numbering segments (perm/off)
   bool xfuse = true;                 // the p = 7 Ax sums x-faces inside its workgroups
   int gs_yz = -1;                    // y and z passes in one launch: 1 yes, 0 no, -1 FP64 only
+  bool xdefer = true;                // Chebyshev updates may take the x step of S's gather-scatter
   double *dotpart = nullptr;         // [E] element shares of (p, Ap) (finest level)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
@@ -272,7 +274,8 @@ void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, h
 // already (Ax with xf); only the faces between groups and the Dirichlet x-faces
 // remain for the x pass
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1, bool x_in_blocks = false);
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1, bool x_in_blocks = false,
+               bool skip_x = false);  // skip_x: y and z passes only (direction passes)
 void launch_weights(const Level &L, hipStream_t s);
 void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s);
 
@@ -298,17 +301,31 @@ template <typename T>
 void launch_axpby(int64_t n, T a, const T *x, T b, T *y, hipStream_t s);  // y = a x + b y
 template <typename T>
 void launch_sub(int64_t n, const T *a, const T *b, T *y, hipStream_t s);  // y = a - b
+// The x step of the gather-scatter left to the Chebyshev update that reads t
+// (the y and z passes done): each copy on an x-face adds its neighbour's copy
+// as it reads, (p-face + 0-face), and the Dirichlet x-faces read as zero.
+// on = false: t is assembled already.
+struct XDefer {
+  bool on = false;
+  int nex = 0, N = 0, bc0 = 0, bc1 = 0;
+  int64_t nloc = 0;  // right sides nloc apart
+};
+// whether launch_cheb_* can take the x step for these vectors (16-byte
+// vectors that do not straddle the element rows)
+template <typename T>
+bool cheb_can_defer_x(int N, int64_t n, std::initializer_list<const void *> ps);
 // x_zero: x is zero on entry (not read)
 template <typename T>
 void launch_cheb_update(int64_t n, T *x, T *r, T *d, const T *t, T a, T c, hipStream_t s,
-                        bool x_zero = false);
+                        bool x_zero = false, const XDefer &xd = XDefer());
 template <typename T>
 void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c,
-                      hipStream_t s, bool x_zero = false);  // x += d + (a d + c (r - t))
+                      hipStream_t s, bool x_zero = false,
+                      const XDefer &xd = XDefer());  // x += d + (a d + c (r - t))
 // first pass from r_0 and t = S A r_0 (d_0 = r_0 / theta formed inside)
 template <typename T>
 void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a, T c,
-                       bool x_zero, bool last, hipStream_t s);
+                       bool x_zero, bool last, hipStream_t s, const XDefer &xd = XDefer());
 void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *dinv, float *dinv32,
                        hipStream_t s);
 // weighted dots: out[j] = sum_i w_i a_j(i) b_j(i), j < nd <= 4 (fixed-order reduction)

@@ -316,6 +316,10 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
       // SEM_AX_XFUSE=0: the p = 7 Ax leaves every x-face to the gather-scatter
       const char *xfv = getenv("SEM_AX_XFUSE");
       L.xfuse = !(xfv && xfv[0] == '0');
+      // SEM_GS_XDEFER=0: the gather-scatter after an FDM that only feeds a
+      // Chebyshev update takes its x step itself
+      const char *xdv = getenv("SEM_GS_XDEFER");
+      L.xdefer = !(xdv && xdv[0] == '0');
       // SEM_GS_YZ=0 / 1: the y and z passes as two launches / one launch in
       // both precisions (default: one launch for FP64, measured faster there
       // and slower in FP32)
@@ -433,9 +437,11 @@ static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, do
 
 // rs (may be null): apply S to r - rs; r - rs is formed as the VALU FDM reads
 // it, else stored into rs first
+// xd (may be null): when the result only feeds a Chebyshev update, the x step
+// of the gather-scatter may be left to that update (xd->on says so)
 template <typename T>
 static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1,
-                T *rs = nullptr) {
+                T *rs = nullptr, XDefer *xd = nullptr) {
   const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
   const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
@@ -463,8 +469,17 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
     if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs);
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
+  const bool defer = xd && L.gs_struct && L.xdefer && cheb_can_defer_x<T>(L.N, L.nloc * nv, {z});
+  if (defer) {
+    xd->on = true;
+    xd->nex = L.nex;
+    xd->N = L.N;
+    xd->bc0 = L.bc[0];
+    xd->bc1 = L.bc[1];
+    xd->nloc = L.nloc;
+  }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, z, s, nv);
+  launch_gs<T>(L, z, s, nv, false, defer);
 }
 
 // Algorithm 2 read as a correction: x <- x + e (x_zero: x <- e)
@@ -493,16 +508,17 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
   // A and S being linear); a zero start is not written
   for (int k = 0; k < L.K; ++k) {
     opA<T>(c, L, k == 0 ? r : d, w, s, nv);
-    opS<T>(c, L, w, t, s, nv);
+    XDefer xd;  // t only feeds the update below: it may take the x step itself
+    opS<T>(c, L, w, t, s, nv, nullptr, cheb_can_defer_x<T>(L.N, n, {x, r, d, t}) ? &xd : nullptr);
     double rho_new = 1.0 / (2.0 * sigma - rho);
     const T a = (T)(rho_new * rho), cc = (T)(2.0 * rho_new / delta);
     const bool last = k + 1 == L.K;
     if (k == 0)
-      launch_cheb_first<T>(n, x, r, d, t, (T)(1.0 / theta), a, cc, x_zero, last, s);
+      launch_cheb_first<T>(n, x, r, d, t, (T)(1.0 / theta), a, cc, x_zero, last, s, xd);
     else if (!last)
-      launch_cheb_update<T>(n, x, r, d, t, a, cc, s);
+      launch_cheb_update<T>(n, x, r, d, t, a, cc, s, false, xd);
     else  // last pass and the closing x += d together
-      launch_cheb_last<T>(n, x, r, d, t, a, cc, s);
+      launch_cheb_last<T>(n, x, r, d, t, a, cc, s, false, xd);
     rho = rho_new;
   }
 }

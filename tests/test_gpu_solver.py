@@ -57,6 +57,27 @@ def test_chebyshev_smooth(smoother):
     assert rel_err(host(x1), P.ora.smooth(bo1, xo1, level=1)) < 1e-12
 
 
+@pytest.mark.parametrize("p,prec,xdefer,bc", [
+    (7, sem.F32, "1", (1,) * 6), (7, sem.F32, "0", (1,) * 6), (7, sem.F64, "1", (0, 1, 1, 0, 1, 1)),
+    (3, sem.F32, "1", (1, 0, 1, 1, 0, 1)), (5, sem.F64, "1", (0,) * 6)])
+def test_chebyshev_takes_the_x_step(monkeypatch, p, prec, xdefer, bc):
+    """Cheby-RAS smoothing where the gather-scatter after each FDM leaves its x
+    step to the Chebyshev update that reads the result (default when the
+    vectors allow; SEM_GS_XDEFER=0 assembles first), against the oracle; Neumann
+    x-faces included (the Dirichlet ones read as zero)."""
+    t = _torch()
+    monkeypatch.setenv("SEM_GS_XDEFER", xdefer)
+    P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=3, bc=bc,
+             smoother_prec=prec, lambda_override=[1.8])
+    b, bo = P.random_local(16)
+    x, xo = P.random_local(17)
+    if prec == sem.F32:
+        b, x = b.to(t.float32), x.to(t.float32)
+    P.gpu.smooth(b, x, level=0)
+    ref = P.ora.smooth(bo, xo, level=0)
+    assert rel_err(host(x), ref) < (1e-5 if prec == sem.F32 else 1e-12)
+
+
 @pytest.mark.parametrize("smoother", ["jacobi", "ras"])
 def test_arnoldi_lambda_tilde(smoother):
     P = Pair((3, 2, 2), 6, mesh="sin", schedule=(6, 3, 1), smoother=smoother, seed=77)
