@@ -111,8 +111,9 @@ template void launch_sub<float>(int64_t, const float *, const float *, float *, 
 // straddles an element row, so only its first lane can be an i = 0 node and
 // only its last an i = p node)
 struct XDev {
-  unsigned nex, N, p, vrow, vel, vside;  // vectors per row, per element, per right side
-  int bc0, bc1;
+  unsigned nex, ney, N, p, vrow, vel, vside;  // vectors per row, per element, per right side
+  int bc0, bc1, bc2, bc3;
+  int y;  // the y step is deferred too (taken before the x step)
 };
 template <typename XD, typename VT>
 __device__ inline VT read_t(const VT *__restrict__ tv, int64_t m, const XDev &f) {
@@ -123,19 +124,46 @@ __device__ inline VT read_t(const VT *__restrict__ tv, int64_t m, const XDev &f)
     const T *__restrict__ ts = reinterpret_cast<const T *>(tv);
     const unsigned mq = (unsigned)(m % f.vside);
     const unsigned e = mq / f.vel;
-    const unsigned i0 = (mq - e * f.vel) % f.vrow * W;
+    const unsigned vi = mq - e * f.vel;
+    const unsigned i0 = vi % f.vrow * W;
     const unsigned ex = e % f.nex;
     const int64_t q = m * W;
     const int64_t N3 = (int64_t)f.vel * W;
+    // y step (rows j = 0 and j = p): (p-row of the lower element + 0-row of the
+    // upper), Dirichlet y-faces zero; ys gives the same for one x-neighbour value
+    int ymode = 0;  // 0 none, 1 j = 0 with a lower copy, 2 j = p with an upper copy, 3 zero
+    int64_t yoff = 0;
+    if (f.y) {
+      const unsigned j = (vi / f.vrow) % f.N;
+      const unsigned ey = (e / f.nex) % f.ney;
+      yoff = (int64_t)f.nex * N3 - (int64_t)f.p * f.N;
+      if (j == 0)
+        ymode = ey > 0 ? 1 : (f.bc2 ? 3 : 0);
+      else if (j == f.p)
+        ymode = ey + 1 < f.ney ? 2 : (f.bc3 ? 3 : 0);
+      if (ymode == 1)
+        v = tv[m - yoff / W] + v;
+      else if (ymode == 2)
+        v = v + tv[m + yoff / W];
+      else if (ymode == 3)
+        v = VT(T(0));
+    }
+    auto ys = [&](int64_t idx) -> T {
+      const T own = ts[idx];
+      if (ymode == 1) return ts[idx - yoff] + own;
+      if (ymode == 2) return own + ts[idx + yoff];
+      if (ymode == 3) return T(0);
+      return own;
+    };
     if (i0 == 0) {
       if (ex > 0)
-        v[0] = ts[q - N3 + f.p] + v[0];
+        v[0] = ys(q - N3 + f.p) + v[0];
       else if (f.bc0)
         v[0] = T(0);
     }
     if (i0 + W - 1 == f.p) {
       if (ex + 1 < f.nex)
-        v[W - 1] = v[W - 1] + ts[q + (W - 1) - f.p + N3];
+        v[W - 1] = v[W - 1] + ys(q + (W - 1) - f.p + N3);
       else if (f.bc1)
         v[W - 1] = T(0);
     }
@@ -176,6 +204,10 @@ static XDev xdev(const XDefer &xd) {
   f.vside = (unsigned)(xd.nloc / W);
   f.bc0 = xd.bc0;
   f.bc1 = xd.bc1;
+  f.y = xd.y ? 1 : 0;
+  f.ney = (unsigned)xd.ney;
+  f.bc2 = xd.bc2;
+  f.bc3 = xd.bc3;
   return f;
 }
 

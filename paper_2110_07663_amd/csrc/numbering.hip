@@ -467,10 +467,12 @@ __global__ void k_gs_yz(T *__restrict__ v, GsGrid g, int64_t E, int64_t ny_t, in
 }
 
 template <typename T>
-void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks, bool skip_x) {
+void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks, bool skip_x,
+               bool skip_y) {
   if (x_in_blocks && (!L.gs_struct || L.nex % 4 != 0))
     fail(SEM_EINVAL, "gather-scatter: block x-faces need the direction passes and nex % 4 == 0");
-  if (skip_x && !L.gs_struct) fail(SEM_EINVAL, "gather-scatter: skip_x needs the direction passes");
+  if ((skip_x || skip_y) && !L.gs_struct)
+    fail(SEM_EINVAL, "gather-scatter: skipping a pass needs the direction passes");
   if (L.gs_struct) {
     GsGrid g;
     g.nex = L.nex; g.ney = L.ney; g.nez = L.nez; g.p = L.p; g.N = L.N;
@@ -485,6 +487,11 @@ void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks, bo
     } else {
       hipLaunchKernelGGL((k_gs_dir<T, 0>), dim3(grid), dim3(256), 0, s, v, g, L.E);
       SEM_LAUNCH("k_gs_dir");
+    }
+    if (skip_y) {  // z pass only (the consumer takes the y step)
+      hipLaunchKernelGGL((k_gs_dir<T, 2>), dim3(grid), dim3(256), 0, s, v, g, L.E);
+      SEM_LAUNCH("k_gs_dir");
+      return;
     }
     const bool yz = L.gs_yz == 1 || (L.gs_yz < 0 && sizeof(T) == 8);
     if (yz && L.p >= 2) {
@@ -509,8 +516,8 @@ void launch_gs(const Level &L, T *v, hipStream_t s, int nv, bool x_in_blocks, bo
     SEM_LAUNCH("k_gs");
   }
 }
-template void launch_gs<double>(const Level &, double *, hipStream_t, int, bool, bool);
-template void launch_gs<float>(const Level &, float *, hipStream_t, int, bool, bool);
+template void launch_gs<double>(const Level &, double *, hipStream_t, int, bool, bool, bool);
+template void launch_gs<float>(const Level &, float *, hipStream_t, int, bool, bool, bool);
 
 void launch_weights(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_fill1, dim3(nb(L.nloc, 256)), dim3(256), 0, s, L.nloc, L.w64, L.w32);

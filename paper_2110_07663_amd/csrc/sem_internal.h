@@ -98,6 +98,7 @@ struct Level {
   bool xfuse = true;                 // the p = 7 Ax sums x-faces inside its workgroups
   int gs_yz = -1;                    // y and z passes in one launch: 1 yes, 0 no, -1 FP64 only
   bool xdefer = true;                // Chebyshev updates may take the x step of S's gather-scatter
+  bool ydefer = true;                // ... and its y step
   double *dotpart = nullptr;         // [E] element shares of (p, Ap) (finest level)
 
   // 1D operators (device): GLL nodes/weights, derivative matrix D[i][j] = h_j'(xi_i)
@@ -275,7 +276,7 @@ void launch_gather(const Ctx &c, const Level &L, const double *ug, double *ul, h
 // remain for the x pass
 template <typename T>
 void launch_gs(const Level &L, T *v, hipStream_t s, int nv = 1, bool x_in_blocks = false,
-               bool skip_x = false);  // skip_x: y and z passes only (direction passes)
+               bool skip_x = false, bool skip_y = false);  // skip: leave that pass out
 void launch_weights(const Level &L, hipStream_t s);
 void launch_start_vector(const Ctx &c, const Level &L, uint64_t seed, double *v, hipStream_t s);
 
@@ -309,6 +310,8 @@ struct XDefer {
   bool on = false;
   int nex = 0, N = 0, bc0 = 0, bc1 = 0;
   int64_t nloc = 0;  // right sides nloc apart
+  bool y = false;    // the y step too (the gather-scatter ran its z pass only)
+  int ney = 0, bc2 = 0, bc3 = 0;
 };
 // whether launch_cheb_* can take the x step for these vectors (16-byte
 // vectors that do not straddle the element rows)

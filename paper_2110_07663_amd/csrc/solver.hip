@@ -320,6 +320,9 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
       // Chebyshev update takes its x step itself
       const char *xdv = getenv("SEM_GS_XDEFER");
       L.xdefer = !(xdv && xdv[0] == '0');
+      // SEM_GS_YDEFER=0: ... its x step only (y and z passes run)
+      const char *ydv = getenv("SEM_GS_YDEFER");
+      L.ydefer = !(ydv && ydv[0] == '0');
       // SEM_GS_YZ=0 / 1: the y and z passes as two launches / one launch in
       // both precisions (default: one launch for FP64, measured faster there
       // and slower in FP32)
@@ -477,9 +480,13 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
     xd->bc0 = L.bc[0];
     xd->bc1 = L.bc[1];
     xd->nloc = L.nloc;
+    xd->y = L.ydefer;
+    xd->ney = L.ney;
+    xd->bc2 = L.bc[2];
+    xd->bc3 = L.bc[3];
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, z, s, nv, false, defer);
+  launch_gs<T>(L, z, s, nv, false, defer, defer && L.ydefer);
 }
 
 // Algorithm 2 read as a correction: x <- x + e (x_zero: x <- e)

@@ -57,16 +57,19 @@ def test_chebyshev_smooth(smoother):
     assert rel_err(host(x1), P.ora.smooth(bo1, xo1, level=1)) < 1e-12
 
 
-@pytest.mark.parametrize("p,prec,xdefer,bc", [
-    (7, sem.F32, "1", (1,) * 6), (7, sem.F32, "0", (1,) * 6), (7, sem.F64, "1", (0, 1, 1, 0, 1, 1)),
-    (3, sem.F32, "1", (1, 0, 1, 1, 0, 1)), (5, sem.F64, "1", (0,) * 6)])
-def test_chebyshev_takes_the_x_step(monkeypatch, p, prec, xdefer, bc):
+@pytest.mark.parametrize("p,prec,xdefer,ydefer,bc", [
+    (7, sem.F32, "1", "1", (1,) * 6), (7, sem.F32, "0", "1", (1,) * 6),
+    (7, sem.F32, "1", "0", (0, 1, 1, 0, 1, 1)), (7, sem.F64, "1", "1", (0, 1, 1, 0, 1, 1)),
+    (7, sem.F32, "1", "1", (1, 0, 0, 1, 0, 1)), (3, sem.F32, "1", "1", (1, 0, 1, 1, 0, 1)),
+    (5, sem.F64, "1", "1", (0,) * 6), (5, sem.F64, "1", "0", (1,) * 6)])
+def test_chebyshev_takes_the_x_step(monkeypatch, p, prec, xdefer, ydefer, bc):
     """Cheby-RAS smoothing where the gather-scatter after each FDM leaves its x
-    step to the Chebyshev update that reads the result (default when the
-    vectors allow; SEM_GS_XDEFER=0 assembles first), against the oracle; Neumann
-    x-faces included (the Dirichlet ones read as zero)."""
+    step, and by default its y step, to the Chebyshev update that reads the
+    result (SEM_GS_XDEFER=0 assembles first, SEM_GS_YDEFER=0 defers x only),
+    against the oracle; Neumann faces included (Dirichlet ones read as zero)."""
     t = _torch()
     monkeypatch.setenv("SEM_GS_XDEFER", xdefer)
+    monkeypatch.setenv("SEM_GS_YDEFER", ydefer)
     P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=3, bc=bc,
              smoother_prec=prec, lambda_override=[1.8])
     b, bo = P.random_local(16)
