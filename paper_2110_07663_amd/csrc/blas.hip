@@ -561,21 +561,31 @@ __device__ inline void st2(double *p, int64_t t, double2 v) {
     p[2 * t + 1] = v.y;
   }
 }
-template <typename V, typename WT>
+// XD: q arrives without the x and y steps of its gather-scatter, which are
+// taken as it is read (the Chebyshev updates' read_t)
+template <typename V, typename WT, typename XD = std::false_type>
 __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restrict__ rz,
                                                 const double *__restrict__ pq,
                                                 const WT *__restrict__ w,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, float *__restrict__ rf,
-                                                double *partials) {
+                                                double *partials, XDev f) {
   const double pqv = *pq;
   const double alpha = pqv > 0.0 ? *rz / pqv : 0.0;
   double acc[1] = {0.0}, acc2 = 0.0;
   const int64_t n2 = n / 2;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
-    const double2 pv = ld2<V>(p, t), qv = ld2<V>(q, t), wt = ld2<V>(w, t);
+    double2 qv;
+    if constexpr (XD::value) {
+      using VT = typename V16<double>::type;
+      const VT qq = read_t<XD>(reinterpret_cast<const VT *>(q), t, f);
+      qv = make_double2(qq[0], qq[1]);
+    } else {
+      qv = ld2<V>(q, t);
+    }
+    const double2 pv = ld2<V>(p, t), wt = ld2<V>(w, t);
     double2 xv = ld2<V>(x, t), rv = ld2<V>(r, t);
     xv.x += alpha * pv.x;
     xv.y += alpha * pv.y;
@@ -602,18 +612,24 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
 
 void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
                    const double *p, const double *q, double *x, double *r, double *out,
-                   hipStream_t s, const float *w32, float *rf) {
+                   hipStream_t s, const float *w32, float *rf, const XDefer &xq) {
   const bool al = aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r);
   const unsigned g = red_grid(n);
-  if (w32 && al && ((uintptr_t)w32 & 7) == 0)
+  const XDev f = xdev<double>(xq);
+  if (xq.on) {
+    if (!(w32 && al && ((uintptr_t)w32 & 7) == 0) || (n & 1))
+      fail(SEM_EINVAL, "FCG update: a deferred gather-scatter step needs aligned vectors");
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float, std::true_type>), dim3(g), dim3(256), 0,
+                       s, n, rz, pq, w32, p, q, x, r, rf, c.partials, f);
+  } else if (w32 && al && ((uintptr_t)w32 & 7) == 0)
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w32, p, q, x, r, rf, c.partials);
+                       w32, p, q, x, r, rf, c.partials, f);
   else if (al && aligned16(w))
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq, w,
-                       p, q, x, r, rf, c.partials);
+                       p, q, x, r, rf, c.partials, f);
   else
     hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w, p, q, x, r, rf, c.partials);
+                       w, p, q, x, r, rf, c.partials, f);
   SEM_LAUNCH("k_fcg_xr");
   launch_finish(1, g, c.partials, out, s);
 }

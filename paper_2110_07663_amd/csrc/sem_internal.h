@@ -335,9 +335,10 @@ void launch_jacobi_inv(int64_t n, const double *diag, const double *w, double *d
 // (w32: an FP32 copy of the weights, used when given; the weights are exact in FP32)
 // (rf: also store the new r in FP32 there, when given)
 // (alpha = rz / pq from the device, 0 when pq <= 0)
+// (xq.on: q comes without the x and y steps of its gather-scatter, taken as read)
 void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
                    const double *p, const double *q, double *x, double *r, double *out,
-                   hipStream_t s, const float *w32 = nullptr, float *rf = nullptr);
+                   hipStream_t s, const float *w32, float *rf, const XDefer &xq);
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
                   const double *const *b, double *out, hipStream_t s, const float *w32 = nullptr);
 // out[j] = (r, z_j)_w for FP32 z_0 (and z_1 when not null), on the device

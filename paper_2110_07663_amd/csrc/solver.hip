@@ -426,10 +426,36 @@ static void opA(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, 
 // q = A p and (p, q) into *pq (device).  For p consistent and zero on the
 // Dirichlet nodes (every search direction of the CG drivers) the p = 7 FP64 Ax
 // forms (p, q) from its element shares of p^T A_L p; else a weighted dot.
+//
+// q only feeds the FCG update (the dot comes from the element shares), so
+// when the vectors allow, its gather-scatter runs the z pass only and the
+// update takes the x and y steps as it reads q (*xq says so).
 static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, double *pq,
-                    hipStream_t s) {
+                    hipStream_t s, XDefer *xq = nullptr) {
   if (L.dotpart && ax_forms_dot(L, 1)) {
-    opA<double>(c, L, p, q, s, 1, L.dotpart);
+    if (xq && L.gs_struct && L.xdefer && L.ydefer && L.w32 &&
+        cheb_can_defer_x<double>(L.N, L.nloc, {p, q, L.w32})) {
+      {
+        ProfScope ps(c, L, SEM_PROF_AX64, s);
+        launch_ax<double>(L, p, q, s, 1, false, L.dotpart);
+      }
+      {
+        ProfScope ps(c, L, SEM_PROF_GS64, s);
+        launch_gs<double>(L, q, s, 1, false, true, true);
+      }
+      xq->on = true;
+      xq->nex = L.nex;
+      xq->N = L.N;
+      xq->bc0 = L.bc[0];
+      xq->bc1 = L.bc[1];
+      xq->nloc = L.nloc;
+      xq->y = true;
+      xq->ney = L.ney;
+      xq->bc2 = L.bc[2];
+      xq->bc3 = L.bc[3];
+    } else {
+      opA<double>(c, L, p, q, s, 1, L.dotpart);
+    }
     launch_sum_partials(L.E, L.dotpart, pq, s);
     return;
   }
@@ -826,10 +852,11 @@ static int solve_cg(Ctx &c, const double *b, double *x, double rtol, int maxit, 
     }
     rz_dots(1, ds + 2 * slot);
     while (it < maxit) {
-      opA_dot(c, F, p, q, dpq, s);
+      XDefer xq;
+      opA_dot(c, F, p, q, dpq, s, &xq);
       // x, r, (r, r) in one pass (and the V-cycle's FP32 copy of r on the mixed path)
       launch_fcg_xr(c, n, ds + 2 * slot, dpq, F.w64, p, q, x, r, drr, s, F.w32,
-                    zf ? F.f_b : nullptr);
+                    zf ? F.f_b : nullptr, xq);
       host_scalars(c, ds, 6 * sizeof(double), s);
       const double *h = c.hres;
       if (!std::isfinite(h[2 * slot]) || !std::isfinite(h[4]) || !std::isfinite(h[5]))

@@ -277,6 +277,30 @@ def test_mixed_precision_solve():
     assert info.iters <= res.iters + 2
 
 
+@pytest.mark.parametrize("shape,bc", [((4, 3, 2), (1,) * 6), ((3, 2, 3), (0, 1, 1, 0, 1, 1))])
+def test_mixed_solve_with_deferred_steps_matches_assembled(monkeypatch, shape, bc):
+    """Mixed FCG at p = 7: the outer A p and the smoother's S w leave their x
+    and y gather-scatter steps to the pointwise updates that read them
+    (default), or run assembled (SEM_GS_XDEFER=0).  Both reach the oracle's
+    residual with the same iteration count, and the solutions agree to the
+    FP32 preconditioner's rounding."""
+    sols = {}
+    for xdefer in ("1", "0"):
+        monkeypatch.setenv("SEM_GS_XDEFER", xdefer)
+        P = Pair(shape, 7, mesh="sin", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
+                 bc=bc, lambda_override=[1.8, 1.6], coarse="dense")
+        bg, bo = _rhs(P)
+        xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
+        assert info.converged
+        L = P.ora.fine
+        x = host(xg).reshape(bo.shape)
+        r = bo - L.apply_A(x)
+        assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+        sols[xdefer] = (x, info.iters)
+    assert abs(sols["1"][1] - sols["0"][1]) <= 1
+    assert rel_err(sols["1"][0], sols["0"][0]) < 1e-7
+
+
 def test_error_paths():
     t = _torch()
     P = Pair(2, 3, mesh="box", schedule=(3, 1), oracle=False)
