@@ -371,7 +371,7 @@ def fdm_flops(L):
 # values in profiles/kernels_layer_shift_32cube_p7.md).  A kernel whose code
 # changed after its counters were taken is left out (traffic null).
 TRAFFIC_32CUBE_P7 = {
-    "ax64": None,         # the solve's k_ax8_f64 now leaves its x-faces to the FCG update: to re-take
+    "ax64": 1072564224,   # k_ax8_f64<true,false> as the solve runs it (x-faces left to the FCG update)
     "ax32": 536988629,    # k_ax8_f32<true,true>
     "fdm": 301107243,     # k_fdm_lines<7,float,false>
 }
