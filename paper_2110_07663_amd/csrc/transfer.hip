@@ -48,12 +48,29 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf_, int Nc_, const T *__re
   }
   __syncthreads();
   // xf[k][j][i] += sum_c J[k][c] a[c][j][i]
-  for (int t = tid; t < Nf3; t += bs) {
-    int ji = t % (Nf * Nf), k = t / (Nf * Nf);
-    T s = 0;
+  if constexpr (NF > 0 && (NF * NF) % 2 == 0 && NF * NF * NF == 2 * 256) {
+    // two neighbouring points per thread (same k), one 2-wide load and store
+    const int t = 2 * tid, ji = t % (NF * NF), k = t / (NF * NF);
+    T s0 = 0, s1 = 0;
 #pragma unroll
-    for (int q = 0; q < Nc; ++q) s += sJ[k * Nc + q] * a[q * Nf * Nf + ji];
-    xf[e * Nf3 + t] += s;
+    for (int q = 0; q < NC; ++q) {
+      s0 += sJ[k * NC + q] * a[q * NF * NF + ji];
+      s1 += sJ[k * NC + q] * a[q * NF * NF + ji + 1];
+    }
+    using T2 = T __attribute__((ext_vector_type(2)));
+    T2 *dst = reinterpret_cast<T2 *>(xf + e * Nf3 + t);
+    T2 v = *dst;
+    v[0] += s0;
+    v[1] += s1;
+    *dst = v;
+  } else {
+    for (int t = tid; t < Nf3; t += bs) {
+      int ji = t % (Nf * Nf), k = t / (Nf * Nf);
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < Nc; ++q) s += sJ[k * Nc + q] * a[q * Nf * Nf + ji];
+      xf[e * Nf3 + t] += s;
+    }
   }
 }
 
@@ -71,8 +88,17 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf_, int Nc_, const T *__r
   rf += blockIdx.y * (int64_t)gridDim.x * Nf3;  // right side blockIdx.y
   rc += blockIdx.y * (int64_t)gridDim.x * Nc3;
   for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
-  if (bf) {  // residual b - A x formed on the way in
-    bf += blockIdx.y * (int64_t)gridDim.x * Nf3;
+  if (bf) bf += blockIdx.y * (int64_t)gridDim.x * Nf3;
+  if constexpr (NF > 0 && NF * NF * NF == 2 * 256) {
+    // two neighbouring points per thread, 2-wide loads
+    using T2 = T __attribute__((ext_vector_type(2)));
+    const int64_t o = e * Nf3 + 2 * tid;
+    const T2 wv = *reinterpret_cast<const T2 *>(w + o);
+    const T2 rv = *reinterpret_cast<const T2 *>(rf + o);
+    const T2 res = bf ? *reinterpret_cast<const T2 *>(bf + o) - rv : rv;  // b - A x on the way in
+    a[2 * tid] = wv[0] * res[0];
+    a[2 * tid + 1] = wv[1] * res[1];
+  } else if (bf) {  // residual b - A x formed on the way in
     for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * (bf[e * Nf3 + t] - rf[e * Nf3 + t]);
   } else {
     for (int t = tid; t < Nf3; t += bs) a[t] = w[e * Nf3 + t] * rf[e * Nf3 + t];
