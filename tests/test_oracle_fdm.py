@@ -159,3 +159,80 @@ def test_schwarz_weights_partition_of_unity():
     s = np.bincount(fdm.box_gid[ok], weights=ones / nbox[fdm.box_gid[ok]], minlength=num.n)
     np.testing.assert_allclose(s, 1.0, atol=1e-15)
     assert nbox.min() >= 1 and nbox.max() <= 27
+
+
+def _box_nodes(nex, ney, nez, p, e):
+    """Global ids of the nodes of element e's box extended by one node per side
+    (Sec. 2.2.2), clipped to the domain; written from the node grid alone."""
+    ex, ey, ez = e % nex, (e // nex) % ney, e // (nex * ney)
+    nx, ny, nz = nex * p + 1, ney * p + 1, nez * p + 1
+    xs = [x for x in range(ex * p - 1, ex * p + p + 2) if 0 <= x < nx]
+    ys = [y for y in range(ey * p - 1, ey * p + p + 2) if 0 <= y < ny]
+    zs = [z for z in range(ez * p - 1, ez * p + p + 2) if 0 <= z < nz]
+    return np.array([(z * ny + y) * nx + x for z in zs for y in ys for x in xs])
+
+
+def _own_nodes(nex, ney, nez, p, e):
+    ex, ey, ez = e % nex, (e // nex) % ney, e // (nex * ney)
+    nx, ny = nex * p + 1, ney * p + 1
+    return np.array([((ez * p + k) * ny + ey * p + j) * nx + ex * p + i
+                     for k in range(p + 1) for j in range(p + 1) for i in range(p + 1)])
+
+
+@pytest.mark.parametrize("p,bc", [(3, (1, 0, 1, 1, 0, 1)), (4, (0, 1, 1, 0, 1, 1))])
+def test_schwarz_sum_equals_dense_galerkin_assembly(p, bc):
+    """Eq. 4 and the RAS paragraph of Sec. 2.2.2 over many elements, from dense matrices.
+
+    On a rectilinear tensor mesh the box operator equals the Galerkin restriction
+    R_e A R_e^T of the assembled A to the box's free nodes, so the two smoothers
+    are fixed without any FDM data:
+      ASM: s = W * sum_e R_e^T (R_e A R_e^T)^{-1} R_e r with W = 1/#boxes per node;
+      RAS: the same local solves, each kept on the element's own nodes only,
+           weighted by 1/(number of elements owning the node), then summed.
+    Both are compared with the oracle's FDM form on a random consistent r.
+    """
+    nex, ney, nez = 3, 3, 2
+    xyz = _rectilinear(nex, ney, nez, seed=10 + p)
+    num, X, G = _level(nex, ney, nez, p, xyz, 1, bc)
+    fdm = FDM(num, X)
+    A = dense_global_A(num, G)
+    free = num.mask_global > 0
+    rng = np.random.default_rng(p)
+    r_glob = rng.standard_normal(num.n) * free
+    r_loc = num.Q(r_glob)
+
+    asm = np.zeros(num.n)
+    nbox = np.zeros(num.n)
+    ras = np.zeros(num.n)
+    owners = np.zeros(num.n)
+    for e in range(num.E):
+        own = _own_nodes(nex, ney, nez, p, e)
+        owners[own] += 1
+    for e in range(num.E):
+        box = _box_nodes(nex, ney, nez, p, e)
+        nbox[box] += 1
+        bf = box[free[box]]
+        y = np.zeros(num.n)
+        y[bf] = np.linalg.solve(A[np.ix_(bf, bf)], r_glob[bf])
+        asm += y
+        own = _own_nodes(nex, ney, nez, p, e)
+        ras[own] += y[own] / owners[own]
+    asm /= nbox
+
+    got_asm = fdm.apply_asm(r_loc)
+    got_ras = fdm.apply_ras(r_loc)
+    scale_a, scale_r = np.abs(asm).max(), np.abs(ras).max()
+    np.testing.assert_allclose(got_asm, num.Q(asm), atol=1e-11 * scale_a)
+    np.testing.assert_allclose(got_ras, num.Q(ras), atol=1e-11 * scale_r)
+    # the two smoothers differ (the overlap matters), and both are consistent E-vectors
+    assert np.abs(asm - ras).max() > 1e-3 * scale_a
+    # a plausible misreading is caught: RAS weighted by 1/#boxes instead of 1/#owners
+    wrong = np.zeros(num.n)
+    for e in range(num.E):
+        box = _box_nodes(nex, ney, nez, p, e)
+        bf = box[free[box]]
+        y = np.zeros(num.n)
+        y[bf] = np.linalg.solve(A[np.ix_(bf, bf)], r_glob[bf])
+        own = _own_nodes(nex, ney, nez, p, e)
+        wrong[own] += y[own] / nbox[own]
+    assert np.abs(num.Q(wrong) - got_ras).max() > 1e-3 * scale_r
