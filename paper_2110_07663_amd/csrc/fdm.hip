@@ -667,6 +667,12 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
     }
     return;
   }
+  if constexpr (sizeof(T) == 4) {
+    if (c.fdm_mf32 && fdm_mf32_supported(P)) {
+      launch_fdm_mf32(c, L, (const float *)r, (float *)z, s, nv, (const float *)rs);
+      return;
+    }
+  }
   fdm_launch<P, T, false>(c, L, r, rs, S, lam, W, z, s, nv);
 }
 

@@ -1,0 +1,388 @@
+// RAS local solves by the fast diagonalisation method (Sec. 2.2.2, eqs. 8-9)
+// in FP32 on the matrix cores.
+//
+// Each of the six 1D contractions of the (p+3)^3 box is a product of the box
+// lines with a (p+3)x(p+3) factor: out[line][m] = sum_k in[line][k] S[k][m].
+// A lane owns one line (in each pass of one wavefront, lines 64s + lane of
+// slot s) and v_mfma_f32_4x4x1 forms four outputs of all 64 lines at a time:
+// its 16 blocks (4 lanes each) all take the same four-entry A operand, read
+// from one block by the broadcast controls (CBSZ = 4, ABID = q), and their own
+// lanes' line values as B, so register i of lane l receives
+// out[line of l][4g + i].  One register then carries the A operands of 16
+// (k, g) pairs, lane 4q + i holding S[k][4g + i], and a whole factor fits in
+// two or three registers loaded once per element.  Against the FP32 vector
+// pipe (one multiply-add per lane and cycle without packed instructions) the
+// matrix core does four per lane in the same time, at the cost of padding the
+// modes to a multiple of 4.
+//
+// One wavefront per element, four per workgroup, no workgroup barriers.  The
+// first pass reads its x-lines straight from the E-vector (the element's own
+// row and one node of each x-neighbour); every later pass reads lines that
+// the previous pass wrote contiguously into the wave's LDS buffer (16-byte
+// reads).  The z pass divides by the eigenvalue sums of eq. 9 in registers
+// and goes straight back along z; the backward passes form only the nodes
+// RAS keeps, and the last one writes the element's rows times the RAS weight.
+#include "sem_internal.h"
+
+namespace sem {
+
+namespace {
+
+typedef float mf4_t __attribute__((ext_vector_type(4)));
+
+// D += A_q (x) B on the 16 blocks, A broadcast from block q (a constant once
+// the loops are unrolled)
+__device__ __attribute__((always_inline)) inline mf4_t mfma_bq(float a, float b, mf4_t c, int q) {
+  switch (q) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 0, 0);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 1, 0);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 2, 0);
+    case 3: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 3, 0);
+    case 4: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 4, 0);
+    case 5: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 5, 0);
+    case 6: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 6, 0);
+    case 7: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 7, 0);
+    case 8: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 8, 0);
+    case 9: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 9, 0);
+    case 10: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 10, 0);
+    case 11: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 11, 0);
+    case 12: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 12, 0);
+    case 13: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 13, 0);
+    case 14: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 14, 0);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 15, 0);
+  }
+}
+
+template <int P>
+struct Mf {
+  static constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
+  static constexpr int NL = PB * PB, SF = (NL + 63) / 64;  // forward lines, slots
+  static constexpr int MG = (PB + 3) / 4;                  // groups of 4 modes
+  static constexpr int KG = (N + 3) / 4;                   // groups of 4 kept nodes
+  static constexpr int LS = (PB + 3) / 4 * 4;              // LDS line stride
+  static constexpr int QF = PB * MG, QB = PB * KG;         // A operands per pass
+  static constexpr int UF = (QF + 15) / 16, UB = (QB + 15) / 16;
+  static constexpr int NLY = PB * N, SY = (NLY + 63) / 64;  // backward y lines (kept planes)
+  static constexpr int NLX = N * N, SX = (NLX + 63) / 64;   // backward x lines (kept rows)
+  static constexpr int BUF = NL * LS;                        // floats per wavefront
+  static constexpr int WAVES = 4;
+};
+
+__device__ inline float mf_inv(float d) { return d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f; }
+
+// forward contraction of one slot: acc[g][i] = sum_k v[k] S[k][4g + i]
+template <int P>
+__device__ __attribute__((always_inline)) inline void mf_forward(const float *A, const float *v,
+                                                                 mf4_t *acc) {
+  using F = Mf<P>;
+#pragma unroll
+  for (int g = 0; g < F::MG; ++g) acc[g] = mf4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < F::PB; ++k)
+#pragma unroll
+    for (int g = 0; g < F::MG; ++g) {
+      const int q = k * F::MG + g;
+      acc[g] = mfma_bq(A[q >> 4], v[k], acc[g], q & 15);
+    }
+}
+
+// backward contraction to the kept nodes: acc[g][i] = sum_m S[1 + 4g + i][m] h[m]
+template <int P>
+__device__ __attribute__((always_inline)) inline void mf_backward(const float *A, const float *h,
+                                                                  mf4_t *acc) {
+  using F = Mf<P>;
+#pragma unroll
+  for (int g = 0; g < F::KG; ++g) acc[g] = mf4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < F::PB; ++m)
+#pragma unroll
+    for (int g = 0; g < F::KG; ++g) {
+      const int q = m * F::KG + g;
+      acc[g] = mfma_bq(A[q >> 4], h[m], acc[g], q & 15);
+    }
+}
+
+template <int P>
+__device__ __attribute__((always_inline)) inline void mf_read_line(const float *buf, int line,
+                                                                   float *v) {
+  using F = Mf<P>;
+  const mf4_t *src = reinterpret_cast<const mf4_t *>(buf + line * F::LS);
+#pragma unroll
+  for (int q = 0; q < F::LS / 4; ++q) {
+    const mf4_t t = src[q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * q + i < F::PB) v[4 * q + i] = t[i];
+  }
+}
+
+__device__ inline void mf_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// r, rs (may be null: solve on r - rs), S and lambda of the level (FP32),
+// W = RAS weight (mask / multiplicity), z = output E-vector(s)
+template <int P>
+__global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
+                                                  const float *__restrict__ r,
+                                                  const float *__restrict__ rs,
+                                                  const float *__restrict__ Sg,
+                                                  const float *__restrict__ lamg,
+                                                  const float *__restrict__ W,
+                                                  float *__restrict__ z, int nv) {
+  using F = Mf<P>;
+  constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
+  __shared__ mf4_t lds4[F::WAVES * F::BUF / 4];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int vec;
+  const int64_t e = (int64_t)split_rhs(xcd_block(), nv, vec) * F::WAVES + wave;
+  if (e >= E) return;  // whole wave leaves; nothing below waits on other waves
+  r += (int64_t)vec * E * N3;
+  if (rs) rs += (int64_t)vec * E * N3;
+  z += (int64_t)vec * E * N3;
+  float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
+  const float *Se = Sg + e * 3 * PB * PB;
+  const float *le = lamg + e * 3 * PB;
+
+  // A operands: forward (k, g) -> lane 4q + i holds S_d[k][4g + i]; backward
+  // (m, g) -> S_d[1 + 4g + i][m]; zero where the index runs past the factor
+  float Af[3][F::UF], Ab[3][F::UB];
+  {
+    const int i = lane & 3, qb = lane >> 2;
+#pragma unroll
+    for (int u = 0; u < F::UF; ++u) {
+      const int q = 16 * u + qb, k = q / MG, m = 4 * (q % MG) + i;
+      const bool ok = q < F::QF && m < PB;
+      const int at = ok ? k * PB + m : 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float s = Se[d * PB * PB + at];
+        Af[d][u] = ok ? s : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < F::UB; ++u) {
+      const int q = 16 * u + qb, m = q / KG, k = 1 + 4 * (q % KG) + i;
+      const bool ok = q < F::QB && k <= N;
+      const int at = ok ? k * PB + m : 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float s = Se[d * PB * PB + at];
+        Ab[d][u] = ok ? s : 0.f;
+      }
+    }
+  }
+
+  int64_t ex, ey, ez;
+  elem_coords(e, nex, ney, ex, ey, ez);
+  float v[F::SF][PB];
+  mf4_t acc[F::SF][MG];
+
+  // gather the box by x-lines (b, c): the x-neighbours' nodes p-1 and 1 around
+  // the element's own row of a y/z neighbour (or itself); outside the domain 0
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    const bool act = l < F::NL;
+    const int lc = act ? l : 0, b = lc % PB, c = lc / PB;
+    const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0), lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
+    const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0), lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
+    const bool okyz = act && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 && ez + dz < nez;
+    const int64_t em = okyz ? e + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
+    const int64_t row = em * N3 + (lk * N + lj) * N;
+    const bool okl = okyz && ex > 0, okr = okyz && ex < nex - 1;
+    const int64_t il = okl ? row - N3 + P - 1 : row, ir = okr ? row + N3 + 1 : row;
+    float own[N];
+    float left = r[il], right = r[ir];
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < N / 4; ++q) {
+        const mf4_t t = *reinterpret_cast<const mf4_t *>(r + row + 4 * q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) own[4 * q + i] = t[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) own[i] = r[row + i];
+    }
+    if (rs) {
+      left -= rs[il];
+      right -= rs[ir];
+      if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 4; ++q) {
+          const mf4_t t = *reinterpret_cast<const mf4_t *>(rs + row + 4 * q);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) own[4 * q + i] -= t[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) own[i] -= rs[row + i];
+      }
+    }
+    v[s][0] = okl ? left : 0.f;
+    v[s][PB - 1] = okr ? right : 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[s][i + 1] = okyz ? own[i] : 0.f;
+  }
+
+  // x: line (b, c) -> modes a'; written as y-lines (a', c), position b
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) mf_forward<P>(Af[0], v[s], acc[s]);
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    if (l < F::NL) {
+      const int b = l % PB, c = l / PB;
+#pragma unroll
+      for (int g = 0; g < MG; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < PB) buf[(4 * g + i + PB * c) * LS + b] = acc[s][g][i];
+    }
+  }
+  mf_sync();
+
+  // y: line (a', c) -> modes b'; written as z-lines (a', b'), position c
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    mf_read_line<P>(buf, l < F::NL ? l : 0, v[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) mf_forward<P>(Af[1], v[s], acc[s]);
+  mf_sync();
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    if (l < F::NL) {
+      const int a = l % PB, c = l / PB;
+#pragma unroll
+      for (int g = 0; g < MG; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < PB) buf[(a + PB * (4 * g + i)) * LS + c] = acc[s][g][i];
+    }
+  }
+  mf_sync();
+
+  // z: line (a', b') -> modes c'; divide by lambda_x + lambda_y + lambda_z;
+  // back along z to the kept planes k = 1..N, written as y-lines (a', k), position b'
+  mf4_t bk[F::SF][KG];
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    mf_read_line<P>(buf, l < F::NL ? l : 0, v[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    const int lc = l < F::NL ? l : 0;
+    mf_forward<P>(Af[2], v[s], acc[s]);
+    const float lxy = le[lc % PB] + le[PB + lc / PB];
+    float h[PB];
+#pragma unroll
+    for (int m = 0; m < PB; ++m) h[m] = acc[s][m >> 2][m & 3] * mf_inv(lxy + le[2 * PB + m]);
+    mf_backward<P>(Ab[2], h, bk[s]);
+  }
+  mf_sync();
+#pragma unroll
+  for (int s = 0; s < F::SF; ++s) {
+    const int l = 64 * s + lane;
+    if (l < F::NL) {
+      const int a = l % PB, b = l / PB;
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < N) buf[(a + PB * (4 * g + i)) * LS + b] = bk[s][g][i];
+    }
+  }
+  mf_sync();
+
+  // back along y: line (a', k) -> kept rows j = 1..N, written as x-lines (j, k), position a'
+  float w[F::SY][PB];
+  mf4_t by[F::SY][KG];
+#pragma unroll
+  for (int s = 0; s < F::SY; ++s) {
+    const int l = 64 * s + lane;
+    mf_read_line<P>(buf, l < F::NLY ? l : 0, w[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < F::SY; ++s) mf_backward<P>(Ab[1], w[s], by[s]);
+  mf_sync();
+#pragma unroll
+  for (int s = 0; s < F::SY; ++s) {
+    const int l = 64 * s + lane;
+    if (l < F::NLY) {
+      const int a = l % PB, k = l / PB;
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < N) buf[(4 * g + i + N * k) * LS + a] = by[s][g][i];
+    }
+  }
+  mf_sync();
+
+  // back along x: line (j, k) -> kept nodes i = 1..N: the element's row (j, k)
+  // times the RAS weight
+#pragma unroll
+  for (int s = 0; s < F::SX; ++s) {
+    const int l = 64 * s + lane;
+    float u[PB];
+    mf4_t bx[KG];
+    mf_read_line<P>(buf, l < F::NLX ? l : 0, u);
+    mf_backward<P>(Ab[0], u, bx);
+    if (l < F::NLX) {
+      const int64_t row = e * N3 + (int64_t)l * N;  // row (j, k) = k * N + j = l
+      if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          const mf4_t wt = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
+          *reinterpret_cast<mf4_t *>(z + row + 4 * g) = wt * bx[g];
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (4 * g + i < N) z[row + 4 * g + i] = W[row + 4 * g + i] * bx[g][i];
+      }
+    }
+  }
+}
+
+template <int P>
+void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
+                 hipStream_t s, int nv) {
+  using F = Mf<P>;
+  const dim3 grid((unsigned)((L.E + F::WAVES - 1) / F::WAVES * nv));
+  hipLaunchKernelGGL(k_fdm_mf32<P>, grid, dim3(64 * F::WAVES), 0, s, L.E, c.nex, c.ney, c.nez, r,
+                     rs, L.S32, L.lam32, L.w32, z, nv);
+  SEM_LAUNCH("k_fdm_mf32");
+}
+
+}  // namespace
+
+bool fdm_mf32_supported(int p) { return p >= 2 && p <= 9; }
+
+void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
+                     const float *rs) {
+  if (!L.S32 || !L.lam32 || !L.w32) fail(SEM_EINVAL, "FP32 FDM data were not built");
+  switch (L.p) {
+    case 2: mf32_launch<2>(c, L, r, rs, z, s, nv); break;
+    case 3: mf32_launch<3>(c, L, r, rs, z, s, nv); break;
+    case 4: mf32_launch<4>(c, L, r, rs, z, s, nv); break;
+    case 5: mf32_launch<5>(c, L, r, rs, z, s, nv); break;
+    case 6: mf32_launch<6>(c, L, r, rs, z, s, nv); break;
+    case 7: mf32_launch<7>(c, L, r, rs, z, s, nv); break;
+    case 8: mf32_launch<8>(c, L, r, rs, z, s, nv); break;
+    case 9: mf32_launch<9>(c, L, r, rs, z, s, nv); break;
+    default: fail(SEM_EUNSUPPORTED, "FP32 matrix-core FDM: unsupported degree");
+  }
+}
+
+}  // namespace sem

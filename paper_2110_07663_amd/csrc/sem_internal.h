@@ -246,6 +246,7 @@ struct Ctx {
   bool fdm_lines = true;  // line-organised VALU FDM kernel for pbar^2 > 64
   bool fdm_group = true;  // p <= 3: several elements' boxes per workgroup of 256 threads
   bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
+  bool fdm_mf32 = true;   // FP32 RAS local solves on the matrix cores (fdm_mf32.hip)
 };
 
 // ---------------------------------------------------------------------------
@@ -381,6 +382,11 @@ void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, boo
                      int prec, hipStream_t s, int nv = 1);
 template <typename T>
 void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_t s);
+
+// fdm_mf32.hip: FP32 RAS local solves on the matrix cores (2 <= p <= 9)
+bool fdm_mf32_supported(int p);
+void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
+                     const float *rs);
 
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);

@@ -341,6 +341,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_group = !(fg && fg[0] == '0');
   const char *fm = getenv("SEM_FDM_MFMA1");
   c.fdm_mfma1 = fm && fm[0] == '1';
+  const char *f32 = getenv("SEM_FDM_MF32");
+  c.fdm_mf32 = !(f32 && f32[0] == '0');
 }
 
 // ---------------------------------------------------------------------------
