@@ -37,9 +37,17 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+# per-file code generation options
+FILE_FLAGS = {
+    # matrix-core FDM: accumulate in ordinary vector registers (the results feed
+    # LDS stores and further products directly, no moves out of AGPRs)
+    "fdm_mf32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def compile_one(src):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + CXXFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + CXXFLAGS + FILE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

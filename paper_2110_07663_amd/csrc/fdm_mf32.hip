@@ -116,39 +116,38 @@ __device__ __attribute__((always_inline)) inline void mf_read_line(const float *
   }
 }
 
+// orders the LDS traffic of one wavefront between passes (global loads in
+// flight, such as the next element's box, are not waited for)
 __device__ inline void mf_sync() {
-  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only
   __builtin_amdgcn_wave_barrier();
 }
 
-// r, rs (may be null: solve on r - rs), S and lambda of the level (FP32),
-// W = RAS weight (mask / multiplicity), z = output E-vector(s)
-template <int P>
-__global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
-                                                  const float *__restrict__ r,
-                                                  const float *__restrict__ rs,
-                                                  const float *__restrict__ Sg,
-                                                  const float *__restrict__ lamg,
-                                                  const float *__restrict__ W,
-                                                  float *__restrict__ z, int nv) {
+// What one element's solve reads from global memory, loaded ahead of its use:
+// the raw x-lines of the box (the element's own row of a y/z neighbour or
+// itself, and one node of each x-neighbour; RS: also those of the subtrahend),
+// which of them lie inside the domain, and the A operands of its six passes.
+template <int P, bool RS>
+struct MfIn {
   using F = Mf<P>;
-  constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
-  __shared__ mf4_t lds4[F::WAVES * F::BUF / 4];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  int vec;
-  const int64_t e = (int64_t)split_rhs(xcd_block(), nv, vec) * F::WAVES + wave;
-  if (e >= E) return;  // whole wave leaves; nothing below waits on other waves
-  r += (int64_t)vec * E * N3;
-  if (rs) rs += (int64_t)vec * E * N3;
-  z += (int64_t)vec * E * N3;
-  float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
-  const float *Se = Sg + e * 3 * PB * PB;
-  const float *le = lamg + e * 3 * PB;
+  float own[F::SF][F::N], lft[F::SF], rgt[F::SF];
+  float sown[RS ? F::SF : 1][RS ? F::N : 1], slft[RS ? F::SF : 1], srgt[RS ? F::SF : 1];
+  unsigned okyz, okl, okr;  // bit s: slot s's line reads inside the domain
+  float Af[3][F::UF], Ab[3][F::UB];
+  float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
+  mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
+};
 
+template <int P, bool RS>
+__device__ __attribute__((always_inline)) inline void mf_load(
+    MfIn<P, RS> &in, int64_t e, int nex, int ney, int nez, const float *__restrict__ r,
+    const float *__restrict__ rs, const float *__restrict__ Sg, const float *__restrict__ lamg,
+    const float *__restrict__ W, int lane) {
+  using F = Mf<P>;
+  constexpr int PB = F::PB, N = F::N, N3 = F::N3, MG = F::MG, KG = F::KG;
+  const float *Se = Sg + e * 3 * PB * PB;
   // A operands: forward (k, g) -> lane 4q + i holds S_d[k][4g + i]; backward
   // (m, g) -> S_d[1 + 4g + i][m]; zero where the index runs past the factor
-  float Af[3][F::UF], Ab[3][F::UB];
   {
     const int i = lane & 3, qb = lane >> 2;
 #pragma unroll
@@ -158,8 +157,8 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
       const int at = ok ? k * PB + m : 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const float s = Se[d * PB * PB + at];
-        Af[d][u] = ok ? s : 0.f;
+        const float sv = Se[d * PB * PB + at];
+        in.Af[d][u] = ok ? sv : 0.f;
       }
     }
 #pragma unroll
@@ -169,19 +168,39 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
       const int at = ok ? k * PB + m : 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const float s = Se[d * PB * PB + at];
-        Ab[d][u] = ok ? s : 0.f;
+        const float sv = Se[d * PB * PB + at];
+        in.Ab[d][u] = ok ? sv : 0.f;
       }
     }
   }
-
+  // eigenvalue sums of the z pass (line (a', b') of slot s) and the RAS weights
+  // of the rows the last pass writes; loaded here so that a solve issues no
+  // vector loads of its own (they would wait behind the next element's)
+  {
+    const float *le = lamg + e * 3 * PB;
+#pragma unroll
+    for (int s = 0; s < F::SF; ++s) {
+      const int l = 64 * s + lane, lc = l < F::NL ? l : 0;
+      in.lxy[s] = le[lc % PB] + le[PB + lc / PB];
+    }
+#pragma unroll
+    for (int s = 0; s < F::SX; ++s) {
+      const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
+      const int64_t row = e * N3 + (int64_t)lc * N;
+#pragma unroll
+      for (int g = 0; g < F::KG; ++g) {
+        if constexpr (N % 4 == 0) {
+          in.wrow[s][g] = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) in.wrow[s][g][i] = 4 * g + i < N ? W[row + 4 * g + i] : 0.f;
+        }
+      }
+    }
+  }
   int64_t ex, ey, ez;
   elem_coords(e, nex, ney, ex, ey, ez);
-  float v[F::SF][PB];
-  mf4_t acc[F::SF][MG];
-
-  // gather the box by x-lines (b, c): the x-neighbours' nodes p-1 and 1 around
-  // the element's own row of a y/z neighbour (or itself); outside the domain 0
+  in.okyz = in.okl = in.okr = 0u;
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
@@ -194,43 +213,71 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     const int64_t row = em * N3 + (lk * N + lj) * N;
     const bool okl = okyz && ex > 0, okr = okyz && ex < nex - 1;
     const int64_t il = okl ? row - N3 + P - 1 : row, ir = okr ? row + N3 + 1 : row;
-    float own[N];
-    float left = r[il], right = r[ir];
+    in.okyz |= okyz ? 1u << s : 0u;
+    in.okl |= okl ? 1u << s : 0u;
+    in.okr |= okr ? 1u << s : 0u;
+    in.lft[s] = r[il];
+    in.rgt[s] = r[ir];
     if constexpr (N % 4 == 0) {
 #pragma unroll
       for (int q = 0; q < N / 4; ++q) {
         const mf4_t t = *reinterpret_cast<const mf4_t *>(r + row + 4 * q);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) own[4 * q + i] = t[i];
+        for (int i = 0; i < 4; ++i) in.own[s][4 * q + i] = t[i];
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < N; ++i) own[i] = r[row + i];
+      for (int i = 0; i < N; ++i) in.own[s][i] = r[row + i];
     }
-    if (rs) {
-      left -= rs[il];
-      right -= rs[ir];
+    if constexpr (RS) {
+      in.slft[s] = rs[il];
+      in.srgt[s] = rs[ir];
       if constexpr (N % 4 == 0) {
 #pragma unroll
         for (int q = 0; q < N / 4; ++q) {
           const mf4_t t = *reinterpret_cast<const mf4_t *>(rs + row + 4 * q);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) own[4 * q + i] -= t[i];
+          for (int i = 0; i < 4; ++i) in.sown[s][4 * q + i] = t[i];
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < N; ++i) own[i] -= rs[row + i];
+        for (int i = 0; i < N; ++i) in.sown[s][i] = rs[row + i];
       }
     }
-    v[s][0] = okl ? left : 0.f;
-    v[s][PB - 1] = okr ? right : 0.f;
+  }
+}
+
+// the local solve of element e from its loaded inputs; buf = the wave's LDS
+template <int P, bool RS>
+__device__ __attribute__((always_inline)) inline void mf_solve(
+    const MfIn<P, RS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
+    float *buf, int lane) {
+  using F = Mf<P>;
+  constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
+  const float *le = lamg + e * 3 * PB;
+  float v[F::SF][PB];
+  mf4_t acc[F::SF][MG];
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[s][i + 1] = okyz ? own[i] : 0.f;
+  for (int s = 0; s < F::SF; ++s) {
+    const bool okyz = (in.okyz >> s) & 1u, okl = (in.okl >> s) & 1u, okr = (in.okr >> s) & 1u;
+    float lv = in.lft[s], rv = in.rgt[s];
+    if constexpr (RS) {
+      lv -= in.slft[s];
+      rv -= in.srgt[s];
+    }
+    v[s][0] = okl ? lv : 0.f;
+    v[s][PB - 1] = okr ? rv : 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      float o = in.own[s][i];
+      if constexpr (RS) o -= in.sown[s][i];
+      v[s][i + 1] = okyz ? o : 0.f;
+    }
   }
 
   // x: line (b, c) -> modes a'; written as y-lines (a', c), position b
 #pragma unroll
-  for (int s = 0; s < F::SF; ++s) mf_forward<P>(Af[0], v[s], acc[s]);
+  for (int s = 0; s < F::SF; ++s) mf_forward<P>(in.Af[0], v[s], acc[s]);
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
@@ -252,7 +299,7 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     mf_read_line<P>(buf, l < F::NL ? l : 0, v[s]);
   }
 #pragma unroll
-  for (int s = 0; s < F::SF; ++s) mf_forward<P>(Af[1], v[s], acc[s]);
+  for (int s = 0; s < F::SF; ++s) mf_forward<P>(in.Af[1], v[s], acc[s]);
   mf_sync();
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
@@ -278,14 +325,12 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
   }
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
-    const int l = 64 * s + lane;
-    const int lc = l < F::NL ? l : 0;
-    mf_forward<P>(Af[2], v[s], acc[s]);
-    const float lxy = le[lc % PB] + le[PB + lc / PB];
+    mf_forward<P>(in.Af[2], v[s], acc[s]);
+    const float lxy = in.lxy[s];
     float h[PB];
 #pragma unroll
     for (int m = 0; m < PB; ++m) h[m] = acc[s][m >> 2][m & 3] * mf_inv(lxy + le[2 * PB + m]);
-    mf_backward<P>(Ab[2], h, bk[s]);
+    mf_backward<P>(in.Ab[2], h, bk[s]);
   }
   mf_sync();
 #pragma unroll
@@ -311,7 +356,7 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     mf_read_line<P>(buf, l < F::NLY ? l : 0, w[s]);
   }
 #pragma unroll
-  for (int s = 0; s < F::SY; ++s) mf_backward<P>(Ab[1], w[s], by[s]);
+  for (int s = 0; s < F::SY; ++s) mf_backward<P>(in.Ab[1], w[s], by[s]);
   mf_sync();
 #pragma unroll
   for (int s = 0; s < F::SY; ++s) {
@@ -335,23 +380,59 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     float u[PB];
     mf4_t bx[KG];
     mf_read_line<P>(buf, l < F::NLX ? l : 0, u);
-    mf_backward<P>(Ab[0], u, bx);
+    mf_backward<P>(in.Ab[0], u, bx);
     if (l < F::NLX) {
       const int64_t row = e * N3 + (int64_t)l * N;  // row (j, k) = k * N + j = l
       if constexpr (N % 4 == 0) {
 #pragma unroll
-        for (int g = 0; g < KG; ++g) {
-          const mf4_t wt = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
-          *reinterpret_cast<mf4_t *>(z + row + 4 * g) = wt * bx[g];
-        }
+        for (int g = 0; g < KG; ++g)
+          *reinterpret_cast<mf4_t *>(z + row + 4 * g) = in.wrow[s][g] * bx[g];
       } else {
 #pragma unroll
         for (int g = 0; g < KG; ++g)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (4 * g + i < N) z[row + 4 * g + i] = W[row + 4 * g + i] * bx[g][i];
+            if (4 * g + i < N) z[row + 4 * g + i] = in.wrow[s][g][i] * bx[g][i];
       }
     }
+  }
+  mf_sync();  // the next element's first pass rewrites the buffer
+}
+
+// r, rs (RS: solve on r - rs), S and lambda of the level (FP32), W = RAS
+// weight (mask / multiplicity), z = output E-vector(s).  Each wavefront
+// solves C consecutive elements, loading the next element's inputs before it
+// solves the current one, so that the loads of one overlap the other's work.
+template <int P, int C, bool RS>
+__global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
+                                                  const float *__restrict__ r,
+                                                  const float *__restrict__ rs,
+                                                  const float *__restrict__ Sg,
+                                                  const float *__restrict__ lamg,
+                                                  const float *__restrict__ W,
+                                                  float *__restrict__ z, int nv) {
+  using F = Mf<P>;
+  constexpr int N3 = F::N3;
+  __shared__ mf4_t lds4[F::WAVES * F::BUF / 4];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int vec;
+  const int64_t e0 = ((int64_t)split_rhs(xcd_block(), nv, vec) * F::WAVES + wave) * C;
+  if (e0 >= E) return;  // whole wave leaves; nothing below waits on other waves
+  r += (int64_t)vec * E * N3;
+  if (RS) rs += (int64_t)vec * E * N3;
+  z += (int64_t)vec * E * N3;
+  float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
+  MfIn<P, RS> in[2];
+  mf_load<P, RS>(in[0], e0, nex, ney, nez, r, rs, Sg, lamg, W, lane);
+#pragma unroll
+  for (int it = 0; it < C; ++it) {
+    const int64_t e = e0 + it;
+    if (e >= E) break;
+    if (it + 1 < C)  // (past the last element: reloads it, unused)
+      mf_load<P, RS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, r, rs, Sg, lamg, W,
+                     lane);
+    mf_solve<P, RS>(in[it & 1], e, lamg, z, buf, lane);
   }
 }
 
@@ -359,9 +440,22 @@ template <int P>
 void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                  hipStream_t s, int nv) {
   using F = Mf<P>;
-  const dim3 grid((unsigned)((L.E + F::WAVES - 1) / F::WAVES * nv));
-  hipLaunchKernelGGL(k_fdm_mf32<P>, grid, dim3(64 * F::WAVES), 0, s, L.E, c.nex, c.ney, c.nez, r,
-                     rs, L.S32, L.lam32, L.w32, z, nv);
+  const int C = c.fdm_mf32_chain;
+  const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
+  const dim3 block(64 * F::WAVES);
+#define SEM_MF32(CC)                                                                              \
+  do {                                                                                            \
+    if (rs)                                                                                       \
+      hipLaunchKernelGGL((k_fdm_mf32<P, CC, true>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, \
+                         r, rs, L.S32, L.lam32, L.w32, z, nv);                                     \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_fdm_mf32<P, CC, false>), grid, block, 0, s, L.E, c.nex, c.ney,       \
+                         c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);                              \
+  } while (0)
+  if (C == 1) SEM_MF32(1);
+  else if (C == 2) SEM_MF32(2);
+  else SEM_MF32(4);
+#undef SEM_MF32
   SEM_LAUNCH("k_fdm_mf32");
 }
 

@@ -247,6 +247,7 @@ struct Ctx {
   bool fdm_group = true;  // p <= 3: several elements' boxes per workgroup of 256 threads
   bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
   bool fdm_mf32 = true;   // FP32 RAS local solves on the matrix cores (fdm_mf32.hip)
+  int fdm_mf32_chain = 1; // elements per wavefront there (1, 2 or 4), next one's loads ahead
 };
 
 // ---------------------------------------------------------------------------

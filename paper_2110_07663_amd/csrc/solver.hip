@@ -343,6 +343,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_mfma1 = fm && fm[0] == '1';
   const char *f32 = getenv("SEM_FDM_MF32");
   c.fdm_mf32 = !(f32 && f32[0] == '0');
+  const char *fch = getenv("SEM_FDM_MF32_CHAIN");
+  c.fdm_mf32_chain = fch ? (fch[0] == '2' ? 2 : fch[0] == '4' ? 4 : 1) : 1;
 }
 
 // ---------------------------------------------------------------------------

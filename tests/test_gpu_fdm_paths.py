@@ -2,7 +2,10 @@
 matrix cores (v_mfma_f32_4x4x1 with a broadcast S operand, the default for
 2 <= p <= 9) and on the vector pipe (SEM_FDM_MF32=0), for every degree the
 matrix-core form takes, every boundary-condition mix, several right sides in
-one launch, and the residual form r - rs formed as the box is read."""
+one launch, and the residual form r - rs formed as the box is read.  The
+matrix-core form solves 1, 2 or 4 consecutive elements per wavefront
+(SEM_FDM_MF32_CHAIN), loading the next one's inputs ahead; the meshes leave
+partly filled workgroups and wavefronts."""
 import numpy as np
 import pytest
 
@@ -12,13 +15,14 @@ from paper_2110_07663_amd import sem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mf32", ["1", "0"])
+@pytest.mark.parametrize("mf32,chain", [("1", "1"), ("1", "2"), ("1", "4"), ("0", "2")])
 @pytest.mark.parametrize("p,shape,bc", [
     (2, (3, 2, 2), (1,) * 6), (3, (3, 3, 2), (1, 0, 1, 1, 0, 1)), (4, (2, 3, 2), (0,) * 6),
     (5, (3, 2, 3), (1, 1, 0, 1, 1, 0)), (6, (2, 2, 2), (1,) * 6), (7, (4, 3, 2), (0, 1, 1, 0, 1, 1)),
     (7, (1, 1, 1), (1,) * 6), (8, (2, 2, 3), (1,) * 6), (9, (3, 2, 2), (0, 0, 1, 1, 0, 1))])
-def test_ras_fp32_kernel_forms(monkeypatch, mf32, p, shape, bc):
+def test_ras_fp32_kernel_forms(monkeypatch, mf32, chain, p, shape, bc):
     monkeypatch.setenv("SEM_FDM_MF32", mf32)
+    monkeypatch.setenv("SEM_FDM_MF32_CHAIN", chain)
     t = __import__("torch")
     P = Pair(shape, p, mesh="sin", schedule=(p, 1), smoother="ras", bc=bc,
              smoother_prec=sem.F32, lambda_override=[2.0])
@@ -34,12 +38,13 @@ def test_ras_fp32_forms_agree_in_the_smoother(monkeypatch, p):
     """Cheby-RAS smoothing (post-smoothing residual formed as the box is read)
     with each kernel form against the oracle."""
     t = __import__("torch")
-    for mf32 in ("1", "0"):
+    for mf32, chain in (("1", "1"), ("1", "2"), ("1", "4"), ("0", "2")):
         monkeypatch.setenv("SEM_FDM_MF32", mf32)
+        monkeypatch.setenv("SEM_FDM_MF32_CHAIN", chain)
         P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=2,
                  smoother_prec=sem.F32, lambda_override=[1.8])
         b, bo = P.random_local(42)
         x, xo = P.random_local(43)
         b, x = b.to(t.float32), x.to(t.float32)
         P.gpu.smooth(b, x, level=0)
-        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, mf32
+        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, (mf32, chain)
