@@ -13,14 +13,21 @@ value = unique DOF solved per second (GDOF/s) over the timed steps.  Kernel
 durations come from HIP events the library records around every finest-level
 launch during the timed steps (sem_profile), on the stream the kernels run on.
 
-Prints one JSON line.
+After the timed steps the default run also measures, once each: the plain
+FP64 solve and the FP16/BF16 matrix-core FDM solves; the FP64 oracle's
+residual of every solution; the 16^3 sine-map FP64 Cheby-Jacobi solve; the
+64-problem batched workload; and the oracle timed on the host (a bounded
+sample).  Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
+import subprocess
 import sys
 import time
+from types import SimpleNamespace
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -43,12 +50,18 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain-FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle FCG iterations timed")
-    ap.add_argument("--mode", choices=("solve", "kernels", "batch", "sensitivity", "projection"),
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle residual checks")
+    ap.add_argument("--no-config2", action="store_true", help="skip the 16^3 sine-map leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload leg")
+    ap.add_argument("--mode", choices=("solve", "kernels", "batch", "sensitivity", "projection",
+                                       "config2", "cpu"),
                     default="solve",
                     help="kernels: repeat single finest-level kernels (for counter runs); "
                          "batch: the 64-problem x 4-RHS batched workload; sensitivity: "
                          "iteration counts over the Chebyshev bound multipliers; projection: "
-                         "successive right sides with and without prior-solution projection")
+                         "successive right sides with and without prior-solution projection; "
+                         "config2: the 16^3 sine-map FP64 Cheby-Jacobi solve; cpu: the oracle "
+                         "timed on the host (full protocol)")
     ap.add_argument("--nprob", type=int, default=64, help="problems in --mode batch")
     ap.add_argument("--no-tune", action="store_true", help="--mode batch: skip the auto-tuner")
     ap.add_argument("--reps", type=int, default=5, help="repetitions per kernel in --mode kernels")
@@ -101,13 +114,18 @@ def kernels_mode(a):
 
 
 def batch_mode(a):
+    print(json.dumps({"mode": "batch", **batch_run(a, oracle_lanes=not a.no_oracle)}), flush=True)
+
+
+def batch_run(a, oracle_lanes=True):
     """Batched workload: `nprob` independent Poisson solves on the smooth
     sinusoidal map, E = side^3 with side in {8, 12, 16, 24} and p in {5, 7, 9}
     drawn by seed 5, each with 4 sinusoidal right sides of random frequencies
     1..4; mixed precision Cheby-RAS pMG, tol 1e-8.  The auto-tuner picks the
     Chebyshev order and the Ax kernel shape per (p, side) bucket on its first
     problem.  Reports the time of the batched solve (one recorded graph per
-    outer iteration of all 4*nprob lanes) against solving every lane in turn."""
+    outer iteration of all 4*nprob lanes) against solving every lane in turn,
+    and the FP64 oracle's residual of the lanes of the four smallest problems."""
     import torch
     from paper_2110_07663_amd import sem
     from paper_2110_07663_amd import workloads as wl
@@ -185,14 +203,14 @@ def batch_mode(a):
             t0 = time.perf_counter()
             infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=300, iters_per_launch=2)
             torch.cuda.synchronize()
-            return time.perf_counter() - t0, infos
+            return time.perf_counter() - t0, infos, xs
         finally:
             del os.environ["SEM_BATCH_JOINT"]
 
     batched(True)
-    t_bat, infos = batched(True)
+    t_bat, infos, xs_last = batched(True)
     note(f"batched {t_bat:.2f} s")
-    t_turn, infos_turn = batched(False)
+    t_turn, infos_turn, _ = batched(False)
     note(f"batched, lanes of a problem in turn {t_turn:.2f} s")
     # plain FP64 sequential baseline: one context at a time (set up, 4 solves timed, freed)
     t_seq64, iters64 = 0.0, []
@@ -214,7 +232,7 @@ def batch_mode(a):
         if i % 8 == 7:
             note(f"fp64 sequential: {i + 1} problems")
     worst = max(i.true_rel_res for i in infos)
-    out = {"mode": "batch", "problems": len(solvers), "rhs_per_problem": 4,
+    out = {"problems": len(solvers), "rhs_per_problem": 4,
            "lanes": len(infos), "unique_dof_total": int(total_dof),
            "sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
            "speedup_batched_vs_sequential": round(t_seq / t_bat, 3),
@@ -230,7 +248,23 @@ def batch_mode(a):
            "iters_sequential_max": max(iters_seq), "tune_s": round(t_tune, 2),
            "tuned": {f"p{k[0]}_side{k[1]}": {"cheb_order": v.cheb_order, "ax_variant": v.ax_variant}
                      for k, v in tuned.items()}}
-    print(json.dumps(out), flush=True)
+    if oracle_lanes:
+        # the FP64 oracle's residual of every lane of the four smallest problems
+        order = sorted(range(len(spec)), key=lambda i: (spec[i][0], spec[i][1], i))[:4]
+        worst_o = 0.0
+        for i in order:
+            side, p, freqs = spec[i]
+            L, X = oracle_level_sin(side, p)
+            for k, fr in enumerate(freqs):
+                f, _ = wl.sinusoid(*fr)
+                bo = oracle_rhs(L, f, X)
+                worst_o = max(worst_o, oracle_rel_res(L, bo, xs_last[i][k].cpu().numpy()))
+        out["oracle_lanes_checked"] = 16
+        out["oracle_worst_rel_res"] = worst_o
+        note(f"oracle residual of 16 lanes: worst {worst_o:.2e}")
+    for s_ in solvers:
+        s_.close()
+    return out
 
 
 def sensitivity_mode(a):
@@ -373,13 +407,106 @@ def fdm_flops(L):
 TRAFFIC_32CUBE_P7 = {
     "ax64": 1072564224,   # k_ax8_f64<true,false> as the solve runs it (x-faces left to the FCG update)
     "ax32": 536988629,    # k_ax8_f32<true,true>
-    "fdm": 301107243,     # k_fdm_lines<7,float,false>
+    "fdm": 261720661,     # k_fdm_mf32<7,1,false> (matrix-core RAS local solves)
 }
-FP32_VECTOR_PEAK_TFLOPS = 157.3
-# The same VALU without packed FP32 (two results per lane and cycle): 256 CUs x
-# 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.  The library is built with packed
-# FP32 instructions switched off, so this is the ceiling its FP32 kernels face.
-FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# dense FP32 on the matrix cores (the FDM contractions run there)
+FP32_MATRIX_PEAK_TFLOPS = 157.3
+
+
+# --- the oracle as test infrastructure: residual checks and the CPU baseline ---
+
+def oracle_level_shift(n, p):
+    """The oracle's finest level on the layer-shift mesh (FP64 operator only)."""
+    from oracle.hierarchy import Level
+    from paper_2110_07663_amd import workloads as wl
+    L = Level(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, (1,) * 6, "jacobi")
+    return L, L.X
+
+
+def oracle_level_sin(n, p):
+    """The oracle's level on the sine map sampled at the oracle's own GLL nodes."""
+    from oracle import gll as ogll
+    from oracle.hierarchy import Level
+    from paper_2110_07663_amd import workloads as wl
+    xyz = wl.sampled_mesh(n, n, n, ogll.gll_nodes_weights(p)[0], wl.sin_map(0.05))
+    L = Level(n, n, n, xyz, p, p, (1,) * 6, "jacobi")
+    return L, L.X
+
+
+def oracle_rhs(L, f, X):
+    from oracle.operator import rhs
+    return rhs(L.num, L.BL, f(X[0], X[1], X[2]))
+
+
+def oracle_rel_res(L, bo, x):
+    """||b - A x|| / ||b|| with the oracle's FP64 operator (unique free nodes)."""
+    x = np.asarray(x, dtype=np.float64).reshape(bo.shape)
+    r = bo - L.apply_A(x)
+    return float(np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)))
+
+
+def host_info():
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    share = os.environ.get("OMP_NUM_THREADS")
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "threads_all": int(share) if share and share.isdigit() else os.cpu_count()}
+
+
+def config2_run(a):
+    """The 16^3 sine-map workload (x' = x + 0.05 s, likewise y, z) at p = 7:
+    plain FP64 PCG preconditioned by the (7, 3, 1) V-cycle with Chebyshev-
+    Jacobi(2) smoothing and a Jacobi-PCG coarse solve to 1e-10, tol 1e-8.
+    Median of 5 solves from x = 0, and the oracle's residual of the solution."""
+    import torch
+    from paper_2110_07663_amd import sem
+    from paper_2110_07663_amd import workloads as wl
+    n, p = 16, 7
+    xyz = wl.sampled_mesh(n, n, n, sem.gll_nodes(p)[0], wl.sin_map(0.05))
+    opts = sem.make_opts(schedule=(7, 3, 1), smoother=sem.SMOOTH_JACOBI, cheb_order=2,
+                         smoother_prec=sem.F64, krylov=sem.KRYLOV_PCG, coarse_tol=1e-10,
+                         coarse_solver=sem.COARSE_PCG)
+    t0 = time.perf_counter()
+    s = sem.Solver(n, n, n, xyz, p, p, opts=opts)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    f, _ = wl.sinusoid(1, 1, 1)
+    X = s.coords(0).cpu().numpy()
+    b = s.rhs(torch.as_tensor(f(X[0], X[1], X[2])).cuda())
+    s.solve(b, rtol=1e-8, maxit=300)
+    ms, infos = [], []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(b, rtol=1e-8, maxit=300)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+        infos.append(info)
+    L0 = s.levels[0]
+    out = {"workload": "sine map 16^3 hex, p=7 (x'=x+0.05 sin 2pi x sin 2pi y sin 2pi z), Dirichlet, "
+                       "sin RHS; FP64 PCG + pMG(7,3,1) Cheby-Jacobi(2), coarse Jacobi-PCG 1e-10, tol 1e-8",
+           "n_unique": int(L0.nglobal), "setup_s": round(t_setup, 3),
+           "ms_median": round(float(np.median(ms)), 3), "iters": infos[-1].iters,
+           "coarse_iters_last_vcycle": infos[-1].coarse_iters,
+           "true_rel_res": infos[-1].true_rel_res,
+           "gdof_s": round(L0.nglobal / (np.median(ms) * 1e-3) / 1e9, 4)}
+    if not a.no_oracle:
+        Lo, Xo = oracle_level_sin(n, p)
+        out["oracle_rel_res"] = oracle_rel_res(Lo, oracle_rhs(Lo, f, Xo), x.cpu().numpy())
+    s.close()
+    return out
+
+
+def config2_mode(a):
+    import torch
+    torch.cuda.set_device(0)
+    print(json.dumps({"mode": "config2", **config2_run(a)}), flush=True)
 
 
 def main():
@@ -388,10 +515,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    if a.mode == "cpu":
+        cpu_mode(a)
+        return
     if a.mode == "kernels":
         kernels_mode(a)
         return
     if a.mode == "batch":
+        import torch
+        torch.cuda.set_device(0)
         batch_mode(a)
         return
     if a.mode == "sensitivity":
@@ -400,7 +532,9 @@ def main():
     if a.mode == "projection":
         projection_mode(a)
         return
-    import numpy as np
+    if a.mode == "config2":
+        config2_mode(a)
+        return
     import torch
 
     from paper_2110_07663_amd import sem
@@ -413,6 +547,9 @@ def main():
     f, _ = wl.sinusoid(1, 1, 1)
 
     coarse = {"auto": sem.COARSE_AUTO, "pcg": sem.COARSE_PCG, "direct": sem.COARSE_DIRECT}[a.coarse]
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     def make(prec, fdm_prec=None):
         opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
@@ -427,9 +564,9 @@ def main():
     X = mixed.coords(0)
     fl = torch.as_tensor(f(*(X.cpu().numpy())), dtype=torch.float64).cuda()
     b = mixed.rhs(fl)
+    del X, fl
     L0 = mixed.levels[0]
-    print(f"[bench] setup {t_setup:.2f}s  E={L0.E} p={p} n_unique={L0.nglobal} "
-          f"local={L0.nlocal}", file=sys.stderr, flush=True)
+    note(f"setup {t_setup:.2f}s  E={L0.E} p={p} n_unique={L0.nglobal} local={L0.nlocal}")
 
     for _ in range(a.warmup):
         mixed.solve(b, rtol=1e-8, maxit=200)
@@ -448,8 +585,11 @@ def main():
     value = L0.nglobal / (t_total / a.steps) / 1e9
     iters = [i.iters for i in infos]
     coarse_used = "direct" if infos[-1].coarse_iters == 0 else "pcg"
-    print(f"[bench] mixed solve {ms_step:.2f} ms/step iters={iters} "
-          f"true_rel_res={infos[-1].true_rel_res:.2e}", file=sys.stderr, flush=True)
+    lam_tilde = [infos[-1].lambda_tilde[l] for l in range(len(sched) - 1)]
+    note(f"mixed solve {ms_step:.2f} ms/step iters={iters} true_rel_res={infos[-1].true_rel_res:.2e}")
+    sols = {"mixed": (x.cpu().numpy(), infos[-1], ms_step)}
+    mixed.close()
+    del mixed, x
 
     # per-kernel rooflines from the event timings of the timed steps
     kern = {}
@@ -471,12 +611,10 @@ def main():
     dom = max((k for k in kern if "bytes_per_launch" in kern[k]), key=lambda k: kern[k]["total_ms"])
     d = kern[dom]
     traffic = TRAFFIC_32CUBE_P7.get(dom) if (n, p) == (32, 7) else None
-    if dom == "fdm":   # FP32 VALU contractions: arithmetic bound
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(d["TFLOPs"], 2),
-                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(d["TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    "peak_unpacked": round(FP32_UNPACKED_PEAK_TFLOPS, 1),
-                    "frac_unpacked": round(d["TFLOPs"] / FP32_UNPACKED_PEAK_TFLOPS, 4),
+    if dom == "fdm":   # FP32 contractions on the matrix cores
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": round(d["TFLOPs"], 2),
+                    "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(d["TFLOPs"] / FP32_MATRIX_PEAK_TFLOPS, 4),
                     "traffic": traffic, "hbm_GBs": round(d["GBs"], 1)}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBs"], 1),
@@ -484,54 +622,71 @@ def main():
                     "traffic": traffic}
     ax = kern.get("ax64")
     ax_gdofs = L0.nglobal / (ax["avg_us"] * 1e-6) / 1e9 if ax else None
+    fdm_k = kern.get("fdm")
+    fdm_roof = None
+    if fdm_k:
+        fdm_roof = {"bound": "mfma", "achieved": round(fdm_k["TFLOPs"], 2),
+                    "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(fdm_k["TFLOPs"] / FP32_MATRIX_PEAK_TFLOPS, 4),
+                    "traffic": TRAFFIC_32CUBE_P7.get("fdm") if (n, p) == (32, 7) else None}
 
-    # plain FP64 solve for the mixed-vs-FP64 time-to-solution factor
-    fp64 = None
+    # plain FP64 solve, and the FDM contractions in FP16 / BF16 on the matrix cores
     if not a.no_fp64:
-        del x
-        plain, _ = make(sem.F64)
-        plain.solve(b, rtol=1e-8, maxit=200)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        xp, ip = plain.solve(b, rtol=1e-8, maxit=200)
-        torch.cuda.synchronize()
-        t_fp64 = time.perf_counter() - t1
-        fp64 = {"ms": round(1e3 * t_fp64, 2), "iters": ip.iters,
-                "true_rel_res": ip.true_rel_res}
-        print(f"[bench] fp64 solve {1e3 * t_fp64:.2f} ms iters={ip.iters}", file=sys.stderr,
-              flush=True)
-        plain.close()
-        del plain
-        # FDM contractions on the matrix cores (16-bit operands, FP32 accumulation)
-        mfma = {}
-        for name, fp in (("fp16", sem.F16), ("bf16", sem.BF16)):
-            sm, _ = make(sem.F32, fp)
+        for name, prec, fp in (("fp64", sem.F64, None), ("fp16_fdm", sem.F32, sem.F16),
+                               ("bf16_fdm", sem.F32, sem.BF16)):
+            sm, _ = make(prec, fp)
             sm.solve(b, rtol=1e-8, maxit=200)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             xm, im = sm.solve(b, rtol=1e-8, maxit=200)
             torch.cuda.synchronize()
-            tm = time.perf_counter() - t1
-            mfma[name] = {"ms": round(1e3 * tm, 2), "iters": im.iters,
-                          "true_rel_res": im.true_rel_res,
-                          "rel_diff_vs_fp64": float((xm - xp).norm() / xp.norm()),
-                          "speedup_vs_fp64": round(t_fp64 / tm, 3)}
-            print(f"[bench] {name}-FDM solve {1e3 * tm:.2f} ms iters={im.iters}", file=sys.stderr,
-                  flush=True)
+            tm = 1e3 * (time.perf_counter() - t1)
+            sols[name] = (xm.cpu().numpy(), im, tm)
+            note(f"{name} solve {tm:.2f} ms iters={im.iters}")
             sm.close()
             del sm, xm
-        fp64["mfma_fdm"] = mfma
-        del xp
+    solves = {}
+    x64 = sols["fp64"][0] if "fp64" in sols else None
+    for name, (xs, info, tms) in sols.items():
+        rec = {"ms": round(tms, 2), "iters": info.iters, "true_rel_res": info.true_rel_res}
+        if x64 is not None and name != "fp64":
+            rec["rel_diff_vs_fp64_gpu"] = float(np.linalg.norm(xs - x64) / np.linalg.norm(x64))
+            rec["speedup_vs_fp64"] = round(sols["fp64"][2] / tms, 3)
+        solves[name] = rec
 
+    ctx = {}
+    if not a.no_config2:
+        ctx["config2"] = config2_run(a)
+        note(f"config2 {ctx['config2']}")
+    if not a.no_batch:
+        ctx["batch"] = batch_run(SimpleNamespace(nprob=64, no_tune=False), oracle_lanes=not a.no_oracle)
+        note(f"batch {ctx['batch']['batched_s']} s, x{ctx['batch']['speedup_batched_vs_sequential_fp64']}"
+             " vs sequential FP64")
+    torch.cuda.synchronize()
+
+    # the FP64 oracle on the host: residual of every solution, and the CPU baseline
+    osolver = None
+    if not a.no_oracle or not a.no_cpu_baseline:
+        osolver, t_osetup = oracle_solver_shift(n, p, sched, lam_tilde)
+        note(f"oracle set up in {t_osetup:.1f} s")
+    if not a.no_oracle:
+        Lo = osolver.fine
+        bo = oracle_rhs(Lo, f, Lo.X)
+        for name, (xs, info, _) in sols.items():
+            solves[name]["oracle_rel_res"] = oracle_rel_res(Lo, bo, xs)
+            note(f"oracle residual of the {name} solution: {solves[name]['oracle_rel_res']:.3e}")
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(xyz, n, p, sched, f, L0.nglobal, int(np.median(iters)), a.cpu_iters)
-        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_sample(osolver, f, L0.nglobal, int(np.median(iters)), a.cpu_iters)
+        cpu["sample"] += f"; oracle set up in {t_osetup:.0f} s (untimed)"
+        note(f"cpu baseline {cpu}")
 
     out = {
         "metric": "Ax GDOF/s + %HBM roofline at p=7; time-to-1e-8 mixed vs FP64 solve",
         "value": round(value, 4),
         "unit": "GDOF/s",
+        "value_note": "unique DOF per second of the whole timed step: one mixed-precision solve "
+                      "from x = 0 to 1e-8 (the metric's Ax rate is ax64_gdof_s)",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
@@ -552,44 +707,115 @@ def main():
         "cpu_baseline": cpu,
         "iters": iters,
         "true_rel_res": infos[-1].true_rel_res,
-        "lambda_tilde": [round(infos[-1].lambda_tilde[l], 4) for l in range(len(sched) - 1)],
+        "lambda_tilde": [round(v, 4) for v in lam_tilde],
         "setup_s": round(t_setup, 3),
         "ax64_gdof_s": round(ax_gdofs, 3) if ax_gdofs else None,
         "ax64_hbm_frac": round(ax["GBs"] / HBM_PEAK_GBS, 4) if ax else None,
+        "fdm_roofline": fdm_roof,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
-        "fp64_solve": fp64,
-        "speedup_mixed_vs_fp64": round(fp64["ms"] / ms_step, 3) if fp64 else None,
+        "solves": solves,
+        "speedup_mixed_vs_fp64": solves["mixed"].get("speedup_vs_fp64"),
+        **ctx,
     }
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters):
-    """The oracle (plain NumPy FP64) timed on the host: setup once (untimed), then
-    `iters` FCG iterations of the same solve; GDOF/s is scaled to the GPU's
-    iteration count (same algorithm, same iteration count)."""
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        return _cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters)
-
-
-def _cpu_baseline(xyz, n, p, sched, f, nglobal, gpu_iters, iters):
+def oracle_solver_shift(n, p, sched, lam_tilde):
+    """The oracle's pMG solver on the layer-shift mesh, with the GPU's lambda~
+    per level (the same Chebyshev bounds) and a Jacobi-PCG coarse solve to 1e-10."""
     from oracle.hierarchy import Solver as OSolver
+    from paper_2110_07663_amd import workloads as wl
     t0 = time.perf_counter()
-    o = OSolver(n, n, n, xyz, 1, sched, smoother="ras", cheb_order=2, lambda_override=[2.0, 2.0, 0],
-                coarse_tol=1e-10)
-    t_setup = time.perf_counter() - t0
-    Xo = o.fine.X
-    bo = o.rhs(f(Xo[0], Xo[1], Xo[2]))
-    t0 = time.perf_counter()
-    o.solve(bo, tol=1e-30, maxit=iters)
-    t_it = (time.perf_counter() - t0) / iters
+    o = OSolver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, sched, smoother="ras", cheb_order=2,
+                lambda_override=list(lam_tilde) + [0.0], coarse_tol=1e-10)
+    return o, time.perf_counter() - t0
+
+
+def cpu_baseline_sample(o, f, nglobal, gpu_iters, iters):
+    """The oracle (plain NumPy FP64) timed on the host: `iters` FCG iterations
+    of the same solve with all the host's threads available to it, scaled to
+    the GPU's iteration count (same algorithm, same Chebyshev bounds)."""
+    from threadpoolctl import threadpool_limits
+    hi = host_info()
+    Lo = o.fine
+    bo = oracle_rhs(Lo, f, Lo.X)
+    t_ax = {}
+    for th in (1, hi["threads_all"]):
+        with threadpool_limits(limits=th):
+            t0 = time.perf_counter()
+            Lo.apply_A(bo)
+            t_ax[str(th)] = round(time.perf_counter() - t0, 3)
+    with threadpool_limits(limits=hi["threads_all"]):
+        t0 = time.perf_counter()
+        o.solve(bo, tol=1e-30, maxit=iters)
+        t_it = (time.perf_counter() - t0) / iters
     t_solve = t_it * gpu_iters
-    return {"value": round(nglobal / t_solve / 1e9, 6), "unit": "GDOF/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"NumPy FP64 oracle on the same mesh: {iters} FCG iteration(s) timed "
-                      f"({t_it:.1f} s each, setup {t_setup:.0f} s untimed), scaled to the GPU's "
-                      f"{gpu_iters} iterations; one thread (BLAS limited to 1)"}
+    return {"value": round(nglobal / t_solve / 1e9, 7), "unit": "GDOF/s",
+            "cores": hi["threads_all"], "kind": "oracle",
+            "sample": f"NumPy FP64 oracle, same mesh and bounds (GPU lambda~), coarse Jacobi-PCG "
+                      f"1e-10 instead of the GPU's exact solve: {iters} FCG iteration(s) timed "
+                      f"({t_it:.1f} s each) with {hi['threads_all']} threads allowed, scaled to the "
+                      f"GPU's {gpu_iters} iterations",
+            "host": hi["cpu_model"], "nproc": hi["nproc"],
+            "apply_A_s_by_threads": t_ax}
+
+
+def cpu_mode(a):
+    """The oracle timed on the host, as the measurement protocol asks: apply_A
+    at the 16^3 and 32^3 p = 7 workloads, the full 4^3 p = 3 Jacobi-PCG solve
+    and the full 16^3 p = 7 pMG solve, and three FCG iterations of the 32^3
+    p = 7 workload, each at 1 thread and at all threads."""
+    from threadpoolctl import threadpool_limits
+    from oracle.hierarchy import Solver as OSolver
+    from oracle import gll as ogll
+    from paper_2110_07663_amd import workloads as wl
+    hi = host_info()
+    res = {"mode": "cpu", **hi, "runs": {}}
+
+    def log(k, v):
+        res["runs"][k] = v
+        print(f"[cpu] {k}: {v}", file=sys.stderr, flush=True)
+
+    f, _ = wl.sinusoid(1, 1, 1)
+    for th in (1, hi["threads_all"]):
+        with threadpool_limits(limits=th):
+            # config 1: 4^3 undeformed cube, p = 3, Jacobi-PCG to 1e-10
+            t0 = time.perf_counter()
+            o1 = OSolver(4, 4, 4, wl.box_vertices(4, 4, 4), 1, (3,))
+            bo = o1.rhs(f(*o1.fine.X))
+            t1 = time.perf_counter()
+            r1 = o1.jacobi_pcg(bo, 1e-10, 500)
+            log(f"config1_solve_t{th}", {"setup_s": round(t1 - t0, 3),
+                                         "solve_s": round(time.perf_counter() - t1, 3),
+                                         "iters": r1.iters})
+            # config 2: 16^3 sine map, p = 7, pMG (7,3,1) Cheby-Jacobi(2), coarse PCG 1e-10
+            xyz = wl.sampled_mesh(16, 16, 16, ogll.gll_nodes_weights(7)[0], wl.sin_map(0.05))
+            t0 = time.perf_counter()
+            o2 = OSolver(16, 16, 16, xyz, 7, (7, 3, 1), smoother="jacobi", coarse_tol=1e-10)
+            bo = o2.rhs(f(*o2.fine.X))
+            t1 = time.perf_counter()
+            o2.fine.apply_A(bo)
+            t2 = time.perf_counter()
+            r2 = o2.solve(bo, tol=1e-8, maxit=300, krylov="pcg")
+            log(f"config2_t{th}", {"setup_s": round(t1 - t0, 2), "apply_A_s": round(t2 - t1, 3),
+                                   "solve_s": round(time.perf_counter() - t2, 2), "iters": r2.iters})
+            del o2
+            # config 3: 32^3 layer shift, p = 7, Cheby-RAS(2) (7,3,1); 3 FCG iterations
+            t0 = time.perf_counter()
+            o3 = OSolver(32, 32, 32, wl.layer_shift_vertices(32, seed=3), 1, (7, 3, 1),
+                         smoother="ras", lambda_override=[26.4181, 20.1744, 0.0], coarse_tol=1e-10)
+            bo = o3.rhs(f(*o3.fine.X))
+            t1 = time.perf_counter()
+            o3.fine.apply_A(bo)
+            t2 = time.perf_counter()
+            o3.solve(bo, tol=1e-30, maxit=3)
+            t3 = time.perf_counter()
+            log(f"config3_t{th}", {"setup_s": round(t1 - t0, 2), "apply_A_s": round(t2 - t1, 3),
+                                   "fcg_iteration_s": round((t3 - t2) / 3, 2),
+                                   "solve_52_iterations_s_extrapolated": round((t3 - t2) / 3 * 52, 1)})
+            del o3
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -5,8 +5,10 @@ pointers are handed to the library, together with torch's current HIP stream.
 Every computation happens inside the library's kernels.  If the library is
 missing, lib() raises; there is no other implementation to fall back to.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -83,6 +85,18 @@ class SemError(RuntimeError):
 
 
 _lib = None
+_live = weakref.WeakSet()  # contexts not closed yet
+
+
+@atexit.register
+def _close_all():
+    """Destroy every context still open while the interpreter (and with it the
+    HIP runtime) is intact, instead of from object finalisers at teardown."""
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -256,6 +270,7 @@ class Solver:
         check(L.sem_setup(ctypes.byref(self.mesh), p, self.bc, ctypes.byref(self.opts),
                           _ptr(self.workspace), nbytes, _stream(), ctypes.byref(ctx)))
         self.ctx = ctx
+        _live.add(self)
         self.levels = [self.level_info(l) for l in range(self.nlevels)]
 
     @property
@@ -263,9 +278,13 @@ class Solver:
         return 1 if self.opts.precond == PRECOND_JACOBI else self.opts.nlevels
 
     def close(self):
+        """Release the library context (synchronises the device first, so that
+        no enqueued work still uses its workspace)."""
         if self.ctx:
+            self._torch.cuda.synchronize()
             check(lib().sem_destroy(self.ctx))
             self.ctx = None
+            _live.discard(self)
 
     def projection_reset(self):
         """Forget the prior solutions kept for opts.proj_max."""
