@@ -3,8 +3,12 @@
 // Inner products are 2-norm products over unique free nodes, computed on
 // E-vectors with the weight w = mask / multiplicity.  Every reduction uses a
 // fixed launch shape and a fixed summation tree (per-thread strided partial
-// sums, an LDS tree per block, then the last block to finish sums the block
-// partials in block order), so results are bitwise repeatable.
+// sums, an LDS tree per block, then the block partials summed in block
+// order), so results are bitwise repeatable.  The outer Krylov reductions
+// sum the block partials in a second, one-workgroup launch (k_finish); the
+// E-vector coarse CG (a coarsest level other than the assembled p = 1 one)
+// keeps the single-launch form, where the last block to finish, found with a
+// ticket counter, sums them (last_block_sum).
 #include <initializer_list>
 #include <type_traits>
 
