@@ -220,6 +220,20 @@ sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
 sem_status sem_solve(sem_ctx *ctx, const double *b, double *x_inout, double rtol, int32_t maxit,
                      sem_solve_info *info, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): sem_solve with the same arguments,
+ * results and errors, except that the scratch of its reductions (block
+ * partials, reduction results, the recurrence's device scalars, last-block
+ * counters, and the finest level's element shares of (p, A p)) lives in a
+ * 512 KiB array of device memory owned by the library (one per GPU, held
+ * until the process ends) instead of the context's workspace.  The call
+ * allocates nothing.  Limit: the finest level may have at most 56832
+ * elements, else SEM_EINVAL.  Every call on one GPU shares that GPU's array,
+ * so calls that overlap on one GPU (other streams or threads) race; calls in
+ * turn are safe, the array keeps only scratch between them. */
+sem_status sem_solve_static(sem_ctx *ctx, const double *b, double *x_inout, double rtol,
+                            int32_t maxit, sem_solve_info *info, void *stream);
+
 /* Empties the basis of prior solutions used by opts.proj_max. */
 sem_status sem_projection_reset(sem_ctx *ctx);
 

@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1063,6 +1065,83 @@ using namespace sem;
 
 struct sem_ctx : public sem::Ctx {};
 
+// ---------------------------------------------------------------------------
+// Reduction scratch of sem_solve_static: a file-scope device array instead of
+// the context's workspace.  Layout in doubles: block partials of every
+// reduction [kRedBlocks][8], reduction results (FGMRES and projection
+// coefficients included), the device scalars of the Krylov recurrence, the
+// last-block ticket counters, then the finest level's element shares of
+// (p, A p).  Each device holds its own copy, at its own address, for the life
+// of the process.
+constexpr size_t kStPartials = 0;
+constexpr size_t kStDres = kStPartials + (size_t)kRedBlocks * 8;
+constexpr size_t kStDsc = kStDres + 256;
+constexpr size_t kStCounter = kStDsc + 32;
+constexpr size_t kStDot = kStCounter + 32;
+constexpr size_t kStaticDoubles = 65536;  // 512 KiB
+constexpr int64_t kStaticMaxElements = (int64_t)(kStaticDoubles - kStDot);
+static_assert(2 * kMaxRestart + 64 <= 256, "reduction results exceed their slot");
+static_assert(sizeof(DevScalars) <= 32 * sizeof(double), "device scalars exceed their slot");
+static_assert(64 * sizeof(unsigned) <= 32 * sizeof(double), "counters exceed their slot");
+
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Device address of the current device's copy of `scratch` (looked up once per
+// device; host code must never pass the symbol itself to a kernel).
+static double *static_scratch() {
+  int dev = 0;
+  SEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(SEM_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    SEM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(SEM_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Points the context's reduction scratch at the static array for the scope
+// of one call, and back afterwards (also when the call fails).
+struct StaticScratchScope {
+  Ctx &c;
+  double *partials, *dres, *dot;
+  unsigned *counter;
+  DevScalars *dsc;
+  StaticScratchScope(Ctx &cx, hipStream_t s) : c(cx) {
+    partials = c.partials;
+    dres = c.dres;
+    dsc = c.dsc;
+    counter = c.counter;
+    dot = c.lev[0].dotpart;
+    if (c.lev[0].E > kStaticMaxElements)
+      fail(SEM_EINVAL, "sem_solve_static: the finest level has " + std::to_string(c.lev[0].E) +
+                           " elements, more than the static scratch holds (" +
+                           std::to_string(kStaticMaxElements) + ")");
+    double *base = static_scratch();
+    c.partials = base + kStPartials;
+    c.dres = base + kStDres;
+    c.dsc = reinterpret_cast<DevScalars *>(base + kStDsc);
+    c.counter = reinterpret_cast<unsigned *>(base + kStCounter);
+    if (dot) c.lev[0].dotpart = base + kStDot;
+    // the last-block tickets must start at zero (a fill kernel: no memset
+    // node, should the caller capture the call into a graph)
+    launch_fill(32, 0.0, base + kStCounter, s);
+  }
+  ~StaticScratchScope() {
+    c.partials = partials;
+    c.dres = dres;
+    c.dsc = dsc;
+    c.counter = counter;
+    c.lev[0].dotpart = dot;
+  }
+};
+
 extern "C" {
 
 void sem_default_opts(sem_opts *o) {
@@ -1118,6 +1197,7 @@ sem_status sem_setup(const sem_mesh *mesh, int32_t p, const int8_t bc[6], const 
     c = new sem_ctx();
     init_ctx(*c, mesh, p, bc, opts);
     setup(*c, mesh, ws, bytes, as_stream(stream));
+    (void)static_scratch();  // this device's address of the sem_solve_static scratch
     *out = c;
   });
   if (st != SEM_OK && c) {
@@ -1308,8 +1388,8 @@ sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream) {
   });
 }
 
-sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
-                     sem_solve_info *info, void *stream) {
+static sem_status solve_entry(sem_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
+                              sem_solve_info *info, void *stream, bool static_scratch_only) {
   sem_solve_info local{};
   sem_solve_info *inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
@@ -1319,6 +1399,8 @@ sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int3
     if (!b || !x) fail(SEM_EINVAL, "null vector");
     if (!(rtol > 0) || maxit < 0) fail(SEM_EINVAL, "rtol must be > 0 and maxit >= 0");
     hipStream_t s = as_stream(stream);
+    std::unique_ptr<StaticScratchScope> scope;
+    if (static_scratch_only) scope.reset(new StaticScratchScope(*ctx, s));
     for (int l = 0; l < ctx->nlev; ++l) inf->lambda_tilde[l] = ctx->lev[l].lam_tilde;
     int it;
     if (ctx->opts.proj_max > 0)
@@ -1337,6 +1419,16 @@ sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int3
     return SEM_ENOCONV;
   }
   return st;
+}
+
+sem_status sem_solve(sem_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
+                     sem_solve_info *info, void *stream) {
+  return solve_entry(ctx, b, x, rtol, maxit, info, stream, false);
+}
+
+sem_status sem_solve_static(sem_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
+                            sem_solve_info *info, void *stream) {
+  return solve_entry(ctx, b, x, rtol, maxit, info, stream, true);
 }
 
 sem_status sem_projection_reset(sem_ctx *ctx) {

@@ -30,7 +30,7 @@ EXPORTS = ("sem_default_opts", "sem_last_error", "sem_plan", "sem_setup", "sem_d
            "sem_level_info", "sem_gll", "sem_coords", "sem_gather", "sem_rhs", "sem_apply_A",
            "sem_apply_S", "sem_smooth", "sem_prolong", "sem_restrict", "sem_vcycle", "sem_solve",
            "sem_profile", "sem_profile_read", "sem_tune_space", "sem_tune_plan", "sem_tune",
-           "sem_batch_solve", "sem_projection_reset")
+           "sem_batch_solve", "sem_projection_reset", "sem_solve_static")
 TUNE_MAX = 96
 PROF_NAMES = ("ax64", "ax32", "fdm", "gs64", "gs32", "coarse", "vcycle")
 
@@ -125,6 +125,7 @@ def lib():
             getattr(L, name).argtypes = [vp, i32, i32, vp, vp, vp]
         L.sem_vcycle.argtypes = [vp, vp, vp, vp]
         L.sem_solve.argtypes = [vp, vp, vp, dp, i32, ctypes.POINTER(SolveInfo), vp]
+        L.sem_solve_static.argtypes = [vp, vp, vp, dp, i32, ctypes.POINTER(SolveInfo), vp]
         L.sem_tune_space.argtypes = [i32, ctypes.POINTER(Opts), ctypes.POINTER(TuneRequest)]
         L.sem_tune_plan.argtypes = [ctypes.POINTER(Mesh), i32, ctypes.POINTER(ctypes.c_int8),
                                     ctypes.POINTER(TuneRequest), ctypes.POINTER(ctypes.c_size_t)]
@@ -362,10 +363,13 @@ class Solver:
         check(lib().sem_profile_read(self.ctx, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(PROF_NAMES)}
 
-    def solve(self, b, x=None, rtol=1e-8, maxit=500, allow_noconv=False):
-        """Returns (x, SolveInfo); x is updated in place when given."""
+    def solve(self, b, x=None, rtol=1e-8, maxit=500, allow_noconv=False, static_scratch=False):
+        """Returns (x, SolveInfo); x is updated in place when given.
+        static_scratch: call sem_solve_static (reduction scratch in the
+        library's static device array) instead of sem_solve."""
         x = self._torch.zeros_like(b) if x is None else x
         info = SolveInfo()
-        st = lib().sem_solve(self.ctx, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(info), _stream())
+        fn = lib().sem_solve_static if static_scratch else lib().sem_solve
+        st = fn(self.ctx, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(info), _stream())
         check(st, allow=(SEM_ENOCONV,) if allow_noconv else ())
         return x, info
