@@ -668,7 +668,7 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
     return;
   }
   if constexpr (sizeof(T) == 4) {
-    if (c.fdm_mf32 && fdm_mf32_supported(P)) {
+    if (c.fdm_mf32 && fdm_mf32_supported(c, P)) {
       launch_fdm_mf32(c, L, (const float *)r, (float *)z, s, nv, (const float *)rs);
       return;
     }

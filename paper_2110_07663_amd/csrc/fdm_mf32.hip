@@ -68,7 +68,11 @@ struct Mf {
   static constexpr int WAVES = 4;
 };
 
-__device__ inline float mf_inv(float d) { return d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f; }
+// 1 / (lambda_x + lambda_y + lambda_z): +inf (a decoupled node) gives 0.  A
+// zero sum (the constant mode of a box floating on Neumann faces in all three
+// directions) cannot occur here: the launcher sends such meshes to the vector
+// kernel, which drops that mode.
+__device__ inline float mf_inv(float d) { return __builtin_amdgcn_rcpf(d); }
 
 // forward contraction of one slot: acc[g][i] = sum_k v[k] S[k][4g + i]
 template <int P>
@@ -461,7 +465,14 @@ void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, 
 
 }  // namespace
 
-bool fdm_mf32_supported(int p) { return p >= 2 && p <= 9; }
+// A box floats (a zero eigenvalue sum) only when every direction has one
+// element and Neumann faces at both ends: then the 1D problem of each
+// direction keeps its constant mode.
+bool fdm_mf32_supported(const Ctx &c, int p) {
+  const bool floating = c.nex == 1 && c.ney == 1 && c.nez == 1 && !c.bc[0] && !c.bc[1] &&
+                        !c.bc[2] && !c.bc[3] && !c.bc[4] && !c.bc[5];
+  return p >= 2 && p <= 9 && !floating;
+}
 
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
                      const float *rs) {

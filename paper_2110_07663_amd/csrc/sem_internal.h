@@ -384,8 +384,9 @@ void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, boo
 template <typename T>
 void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_t s);
 
-// fdm_mf32.hip: FP32 RAS local solves on the matrix cores (2 <= p <= 9)
-bool fdm_mf32_supported(int p);
+// fdm_mf32.hip: FP32 RAS local solves on the matrix cores (2 <= p <= 9, no
+// floating box)
+bool fdm_mf32_supported(const Ctx &c, int p);
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
                      const float *rs);
 

@@ -19,7 +19,11 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("p,shape,bc", [
     (2, (3, 2, 2), (1,) * 6), (3, (3, 3, 2), (1, 0, 1, 1, 0, 1)), (4, (2, 3, 2), (0,) * 6),
     (5, (3, 2, 3), (1, 1, 0, 1, 1, 0)), (6, (2, 2, 2), (1,) * 6), (7, (4, 3, 2), (0, 1, 1, 0, 1, 1)),
-    (7, (1, 1, 1), (1,) * 6), (8, (2, 2, 3), (1,) * 6), (9, (3, 2, 2), (0, 0, 1, 1, 0, 1))])
+    (7, (1, 1, 1), (1,) * 6), (8, (2, 2, 3), (1,) * 6), (9, (3, 2, 2), (0, 0, 1, 1, 0, 1)),
+    # zero 1D eigenvalues in x and z (one element, Neumann ends), none in y
+    (5, (1, 2, 1), (0,) * 6),
+    # a floating box (zero eigenvalue sum): handled by the vector kernel
+    (4, (1, 1, 1), (0,) * 6)])
 def test_ras_fp32_kernel_forms(monkeypatch, mf32, chain, p, shape, bc):
     monkeypatch.setenv("SEM_FDM_MF32", mf32)
     monkeypatch.setenv("SEM_FDM_MF32_CHAIN", chain)
