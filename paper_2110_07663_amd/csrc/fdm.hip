@@ -652,7 +652,7 @@ static void fdm_launch(const Ctx &c, const Level &L, const T *r, const T *rs, co
 
 template <typename T, int P>
 static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                  int nv, const T *rs) {
+                  int nv, const T *rs, int xin) {
   const T *S = sizeof(T) == 8 ? (const T *)L.S64 : (const T *)L.S32;
   const T *lam = sizeof(T) == 8 ? (const T *)L.lam64 : (const T *)L.lam32;
   const T *W = sizeof(T) == 8 ? (const T *)L.w64 : (const T *)L.w32;
@@ -669,32 +669,34 @@ static void fdm_p(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode,
   }
   if constexpr (sizeof(T) == 4) {
     if (c.fdm_mf32 && fdm_mf32_supported(c, P)) {
-      launch_fdm_mf32(c, L, (const float *)r, (float *)z, s, nv, (const float *)rs);
+      launch_fdm_mf32(c, L, (const float *)r, (float *)z, s, nv, (const float *)rs, xin);
       return;
     }
   }
+  if (xin) fail(SEM_EINVAL, "FDM: this kernel needs assembled inputs");
   fdm_launch<P, T, false>(c, L, r, rs, S, lam, W, z, s, nv);
 }
 
 template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                int nv, const T *rs) {
+                int nv, const T *rs, int xin) {
+  if (xin && asm_mode) fail(SEM_EINVAL, "FDM: ASM needs assembled inputs");
   switch (L.p) {
-    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s, nv, rs); break;
-    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s, nv, rs); break;
+    case 2: fdm_p<T, 2>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 3: fdm_p<T, 3>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 4: fdm_p<T, 4>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 5: fdm_p<T, 5>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 6: fdm_p<T, 6>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 7: fdm_p<T, 7>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 8: fdm_p<T, 8>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 9: fdm_p<T, 9>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
+    case 10: fdm_p<T, 10>(c, L, r, z, asm_mode, s, nv, rs, xin); break;
     default: fail(SEM_EUNSUPPORTED, "FDM: unsupported degree");
   }
 }
 template void launch_fdm<double>(const Ctx &, const Level &, const double *, double *, bool,
-                                 hipStream_t, int, const double *);
+                                 hipStream_t, int, const double *, int);
 template void launch_fdm<float>(const Ctx &, const Level &, const float *, float *, bool,
-                                hipStream_t, int, const float *);
+                                hipStream_t, int, const float *, int);
 
 }  // namespace sem

@@ -131,20 +131,26 @@ __device__ inline void mf_sync() {
 // the raw x-lines of the box (the element's own row of a y/z neighbour or
 // itself, and one node of each x-neighbour; RS: also those of the subtrahend),
 // which of them lie inside the domain, and the A operands of its six passes.
-template <int P, bool RS>
+// XS = 1 (r) or 2 (rs): that input comes from A with the x step of its
+// gather-scatter left out (its y and z steps done), so the x-neighbours'
+// copies of the row's end nodes (their nodes p and 0) are read as well and
+// added: each copy of a node then holds the sum over all its copies, as
+// after the whole gather-scatter (the x step taken last).
+template <int P, bool RS, int XS>
 struct MfIn {
   using F = Mf<P>;
   float own[F::SF][F::N], lft[F::SF], rgt[F::SF];
   float sown[RS ? F::SF : 1][RS ? F::N : 1], slft[RS ? F::SF : 1], srgt[RS ? F::SF : 1];
+  float xlp[XS ? F::SF : 1], xrp[XS ? F::SF : 1];  // x-partner copies of nodes 0 and p
   unsigned okyz, okl, okr;  // bit s: slot s's line reads inside the domain
   float Af[3][F::UF], Ab[3][F::UB];
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
   mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
 };
 
-template <int P, bool RS>
+template <int P, bool RS, int XS>
 __device__ __attribute__((always_inline)) inline void mf_load(
-    MfIn<P, RS> &in, int64_t e, int nex, int ney, int nez, const float *__restrict__ r,
+    MfIn<P, RS, XS> &in, int64_t e, int nex, int ney, int nez, const float *__restrict__ r,
     const float *__restrict__ rs, const float *__restrict__ Sg, const float *__restrict__ lamg,
     const float *__restrict__ W, int lane) {
   using F = Mf<P>;
@@ -222,6 +228,11 @@ __device__ __attribute__((always_inline)) inline void mf_load(
     in.okr |= okr ? 1u << s : 0u;
     in.lft[s] = r[il];
     in.rgt[s] = r[ir];
+    if constexpr (XS != 0) {
+      const float *xs = XS == 1 ? r : rs;
+      in.xlp[s] = xs[okl ? row - N3 + P : row];  // left neighbour's node p
+      in.xrp[s] = xs[okr ? row + N3 : row];      // right neighbour's node 0
+    }
     if constexpr (N % 4 == 0) {
 #pragma unroll
       for (int q = 0; q < N / 4; ++q) {
@@ -252,9 +263,9 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 }
 
 // the local solve of element e from its loaded inputs; buf = the wave's LDS
-template <int P, bool RS>
+template <int P, bool RS, int XS>
 __device__ __attribute__((always_inline)) inline void mf_solve(
-    const MfIn<P, RS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
+    const MfIn<P, RS, XS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
     float *buf, int lane) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
@@ -271,10 +282,26 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     }
     v[s][0] = okl ? lv : 0.f;
     v[s][PB - 1] = okr ? rv : 0.f;
+    float o0 = in.own[s][0], oN = in.own[s][N - 1];
+    float s0 = 0.f, sN = 0.f;
+    if constexpr (RS) {
+      s0 = in.sown[s][0];
+      sN = in.sown[s][N - 1];
+    }
+    if constexpr (XS != 0) {  // the x step: add the x-neighbours' copies
+      const float pl = okl ? in.xlp[s] : 0.f, pr = okr ? in.xrp[s] : 0.f;
+      if constexpr (XS == 1) {
+        o0 += pl;
+        oN += pr;
+      } else {
+        s0 += pl;
+        sN += pr;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      float o = in.own[s][i];
-      if constexpr (RS) o -= in.sown[s][i];
+      float o = i == 0 ? o0 : (i == N - 1 ? oN : in.own[s][i]);
+      if constexpr (RS) o -= i == 0 ? s0 : (i == N - 1 ? sN : in.sown[s][i]);
       v[s][i + 1] = okyz ? o : 0.f;
     }
   }
@@ -407,7 +434,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 // weight (mask / multiplicity), z = output E-vector(s).  Each wavefront
 // solves C consecutive elements, loading the next element's inputs before it
 // solves the current one, so that the loads of one overlap the other's work.
-template <int P, int C, bool RS>
+template <int P, int C, bool RS, int XS>
 __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ rs,
@@ -427,40 +454,49 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
   if (RS) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
   float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
-  MfIn<P, RS> in[2];
-  mf_load<P, RS>(in[0], e0, nex, ney, nez, r, rs, Sg, lamg, W, lane);
+  MfIn<P, RS, XS> in[2];
+  mf_load<P, RS, XS>(in[0], e0, nex, ney, nez, r, rs, Sg, lamg, W, lane);
 #pragma unroll
   for (int it = 0; it < C; ++it) {
     const int64_t e = e0 + it;
     if (e >= E) break;
     if (it + 1 < C)  // (past the last element: reloads it, unused)
-      mf_load<P, RS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, r, rs, Sg, lamg, W,
-                     lane);
-    mf_solve<P, RS>(in[it & 1], e, lamg, z, buf, lane);
+      mf_load<P, RS, XS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, r, rs, Sg, lamg,
+                         W, lane);
+    mf_solve<P, RS, XS>(in[it & 1], e, lamg, z, buf, lane);
   }
 }
 
-template <int P>
-void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
-                 hipStream_t s, int nv) {
+template <int P, bool RS, int XS>
+void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
+                   hipStream_t s, int nv) {
   using F = Mf<P>;
   const int C = c.fdm_mf32_chain;
   const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
   const dim3 block(64 * F::WAVES);
-#define SEM_MF32(CC)                                                                              \
-  do {                                                                                            \
-    if (rs)                                                                                       \
-      hipLaunchKernelGGL((k_fdm_mf32<P, CC, true>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, \
-                         r, rs, L.S32, L.lam32, L.w32, z, nv);                                     \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_fdm_mf32<P, CC, false>), grid, block, 0, s, L.E, c.nex, c.ney,       \
-                         c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);                              \
-  } while (0)
-  if (C == 1) SEM_MF32(1);
-  else if (C == 2) SEM_MF32(2);
-  else SEM_MF32(4);
-#undef SEM_MF32
+  if (C == 2)
+    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, r,
+                       rs, L.S32, L.lam32, L.w32, z, nv);
+  else
+    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, r,
+                       rs, L.S32, L.lam32, L.w32, z, nv);
   SEM_LAUNCH("k_fdm_mf32");
+}
+
+// xin: 0 the inputs are assembled; 1 r, 2 rs lacks the x step of its
+// gather-scatter (the kernel adds the x-neighbours' copies as it reads)
+template <int P>
+void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
+                 hipStream_t s, int nv, int xin) {
+  if (xin == 2 && !rs) fail(SEM_EINVAL, "FDM: no subtrahend to take the x step");
+  if (rs) {
+    if (xin == 2) mf32_launch_x<P, true, 2>(c, L, r, rs, z, s, nv);
+    else if (xin == 1) fail(SEM_EINVAL, "FDM: the x step is taken on the subtrahend only");
+    else mf32_launch_x<P, true, 0>(c, L, r, rs, z, s, nv);
+  } else {
+    if (xin == 1) mf32_launch_x<P, false, 1>(c, L, r, rs, z, s, nv);
+    else mf32_launch_x<P, false, 0>(c, L, r, rs, z, s, nv);
+  }
 }
 
 }  // namespace
@@ -475,17 +511,17 @@ bool fdm_mf32_supported(const Ctx &c, int p) {
 }
 
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
-                     const float *rs) {
+                     const float *rs, int xin) {
   if (!L.S32 || !L.lam32 || !L.w32) fail(SEM_EINVAL, "FP32 FDM data were not built");
   switch (L.p) {
-    case 2: mf32_launch<2>(c, L, r, rs, z, s, nv); break;
-    case 3: mf32_launch<3>(c, L, r, rs, z, s, nv); break;
-    case 4: mf32_launch<4>(c, L, r, rs, z, s, nv); break;
-    case 5: mf32_launch<5>(c, L, r, rs, z, s, nv); break;
-    case 6: mf32_launch<6>(c, L, r, rs, z, s, nv); break;
-    case 7: mf32_launch<7>(c, L, r, rs, z, s, nv); break;
-    case 8: mf32_launch<8>(c, L, r, rs, z, s, nv); break;
-    case 9: mf32_launch<9>(c, L, r, rs, z, s, nv); break;
+    case 2: mf32_launch<2>(c, L, r, rs, z, s, nv, xin); break;
+    case 3: mf32_launch<3>(c, L, r, rs, z, s, nv, xin); break;
+    case 4: mf32_launch<4>(c, L, r, rs, z, s, nv, xin); break;
+    case 5: mf32_launch<5>(c, L, r, rs, z, s, nv, xin); break;
+    case 6: mf32_launch<6>(c, L, r, rs, z, s, nv, xin); break;
+    case 7: mf32_launch<7>(c, L, r, rs, z, s, nv, xin); break;
+    case 8: mf32_launch<8>(c, L, r, rs, z, s, nv, xin); break;
+    case 9: mf32_launch<9>(c, L, r, rs, z, s, nv, xin); break;
     default: fail(SEM_EUNSUPPORTED, "FP32 matrix-core FDM: unsupported degree");
   }
 }

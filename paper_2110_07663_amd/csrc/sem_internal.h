@@ -247,7 +247,8 @@ struct Ctx {
   bool fdm_group = true;  // p <= 3: several elements' boxes per workgroup of 256 threads
   bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
   bool fdm_mf32 = true;   // FP32 RAS local solves on the matrix cores (fdm_mf32.hip)
-  int fdm_mf32_chain = 1; // elements per wavefront there (1, 2 or 4), next one's loads ahead
+  int fdm_mf32_chain = 1; // elements per wavefront there (1 or 2), next one's loads ahead
+  bool fdm_xstep = true;  // that kernel takes the x step of A's gather-scatter as it reads
 };
 
 // ---------------------------------------------------------------------------
@@ -376,9 +377,11 @@ void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStre
 // fdm.hip
 void launch_fdm_setup(const Ctx &c, Level &L, hipStream_t s);
 // rs (may be null): solve on r - rs (a residual formed as it is read)
+// xin: 0 inputs assembled; 1 r, 2 rs comes without the x step of its
+// gather-scatter (only where fdm_takes_x_step says the kernel can add it)
 template <typename T>
 void launch_fdm(const Ctx &c, const Level &L, const T *r, T *z, bool asm_mode, hipStream_t s,
-                int nv = 1, const T *rs = nullptr);
+                int nv = 1, const T *rs = nullptr, int xin = 0);
 void launch_fdm_mfma(const Ctx &c, const Level &L, const float *r, float *z, bool asm_mode,
                      int prec, hipStream_t s, int nv = 1);
 template <typename T>
@@ -388,7 +391,7 @@ void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_
 // floating box)
 bool fdm_mf32_supported(const Ctx &c, int p);
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
-                     const float *rs);
+                     const float *rs, int xin);
 
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);

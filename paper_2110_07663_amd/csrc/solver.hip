@@ -346,7 +346,9 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   const char *f32 = getenv("SEM_FDM_MF32");
   c.fdm_mf32 = !(f32 && f32[0] == '0');
   const char *fch = getenv("SEM_FDM_MF32_CHAIN");
-  c.fdm_mf32_chain = fch ? (fch[0] == '2' ? 2 : fch[0] == '4' ? 4 : 1) : 1;
+  c.fdm_mf32_chain = fch && fch[0] == '2' ? 2 : 1;
+  const char *fxs = getenv("SEM_FDM_XSTEP");
+  c.fdm_xstep = !(fxs && fxs[0] == '0');
 }
 
 // ---------------------------------------------------------------------------
@@ -474,13 +476,36 @@ static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, do
 // it, else stored into rs first
 // xd (may be null): when the result only feeds a Chebyshev update, the x step
 // of the gather-scatter may be left to that update (xd->on says so)
+// Whether the level's Schwarz smoother in precision T reads A's output with
+// the x step of its gather-scatter left out and takes that step itself (the
+// FP32 matrix-core RAS kernel); then the products that only feed it skip it.
+template <typename T>
+static bool fdm_takes_x_step(const Ctx &c, const Level &L) {
+  return sizeof(T) == 4 && c.fdm_xstep && c.fdm_mf32 && c.opts.precond == SEM_PRECOND_PMG &&
+         c.opts.smoother == SEM_SMOOTH_RAS && c.fdm_prec != SEM_BF16 && c.fdm_prec != SEM_F16 &&
+         !L.coarse && L.gs_struct && fdm_mf32_supported(c, L.p);
+}
+
+// A u with the x step of the gather-scatter left to the reader (y and z done)
+template <typename T>
+static void opA_nox(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv) {
+  {
+    ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_AX64 : SEM_PROF_AX32, s);
+    launch_ax<T>(L, u, Au, s, nv, false, nullptr);
+  }
+  ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
+  launch_gs<T>(L, Au, s, nv, false, true, false);
+}
+
+// xin: 0 r and rs assembled; 1 r, 2 rs comes from opA_nox (fdm_takes_x_step)
 template <typename T>
 static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1,
-                T *rs = nullptr, XDefer *xd = nullptr) {
+                T *rs = nullptr, XDefer *xd = nullptr, int xin = 0) {
   const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
   const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
   const bool mfma = sizeof(T) == 4 && (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16);
+  if (xin && !fdm_takes_x_step<T>(c, L)) fail(SEM_EINVAL, "smoother: inputs must be assembled");
   if (rs && (!schwarz || asm_mode || mfma)) {  // form r - rs in rs, then apply S to it
     launch_sub<T>(L.nloc * nv, r, rs, rs, s);
     r = rs;
@@ -501,7 +526,7 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
         mma = true;
       }
     }
-    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs);
+    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs, xin);
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
   const bool defer = xd && L.gs_struct && L.xdefer && cheb_can_defer_x<T>(L.N, L.nloc * nv, {z});
@@ -530,8 +555,13 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
   const double sigma = theta / delta;
   const int64_t n = L.nloc * nv;  // the vector updates are pointwise over all right sides
   double rho = 1.0 / sigma;
+  // A's output that only feeds S may leave the x step of its gather-scatter to S
+  const bool xs = fdm_takes_x_step<T>(c, L);
   if (x_zero) {
     opS<T>(c, L, b, r, s, nv);
+  } else if (xs) {
+    opA_nox<T>(c, L, x, w, s, nv);
+    opS<T>(c, L, b, r, s, nv, w, nullptr, 2);  // r = S (b - A x)
   } else {
     opA<T>(c, L, x, w, s, nv);
     opS<T>(c, L, b, r, s, nv, w);  // r = S (b - A x)
@@ -546,9 +576,13 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
   // pass 0 works from r_0 itself (d_0 = r_0 / theta is formed inside the update,
   // A and S being linear); a zero start is not written
   for (int k = 0; k < L.K; ++k) {
-    opA<T>(c, L, k == 0 ? r : d, w, s, nv);
+    if (xs)
+      opA_nox<T>(c, L, k == 0 ? r : d, w, s, nv);
+    else
+      opA<T>(c, L, k == 0 ? r : d, w, s, nv);
     XDefer xd;  // t only feeds the update below: it may take the x step itself
-    opS<T>(c, L, w, t, s, nv, nullptr, cheb_can_defer_x<T>(L.N, n, {x, r, d, t}) ? &xd : nullptr);
+    opS<T>(c, L, w, t, s, nv, nullptr, cheb_can_defer_x<T>(L.N, n, {x, r, d, t}) ? &xd : nullptr,
+           xs ? 1 : 0);
     double rho_new = 1.0 / (2.0 * sigma - rho);
     const T a = (T)(rho_new * rho), cc = (T)(2.0 * rho_new / delta);
     const bool last = k + 1 == L.K;

@@ -3,9 +3,11 @@ matrix cores (v_mfma_f32_4x4x1 with a broadcast S operand, the default for
 2 <= p <= 9) and on the vector pipe (SEM_FDM_MF32=0), for every degree the
 matrix-core form takes, every boundary-condition mix, several right sides in
 one launch, and the residual form r - rs formed as the box is read.  The
-matrix-core form solves 1, 2 or 4 consecutive elements per wavefront
+matrix-core form solves 1 or 2 consecutive elements per wavefront
 (SEM_FDM_MF32_CHAIN), loading the next one's inputs ahead; the meshes leave
-partly filled workgroups and wavefronts."""
+partly filled workgroups and wavefronts.  Inside the smoother the matrix-core
+form also takes the x step of the gather-scatter of A's output as it reads
+(SEM_FDM_XSTEP=0: A's output is assembled first)."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ from paper_2110_07663_amd import sem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mf32,chain", [("1", "1"), ("1", "2"), ("1", "4"), ("0", "2")])
+@pytest.mark.parametrize("mf32,chain", [("1", "1"), ("1", "2"), ("0", "1")])
 @pytest.mark.parametrize("p,shape,bc", [
     (2, (3, 2, 2), (1,) * 6), (3, (3, 3, 2), (1, 0, 1, 1, 0, 1)), (4, (2, 3, 2), (0,) * 6),
     (5, (3, 2, 3), (1, 1, 0, 1, 1, 0)), (6, (2, 2, 2), (1,) * 6), (7, (4, 3, 2), (0, 1, 1, 0, 1, 1)),
@@ -37,18 +39,23 @@ def test_ras_fp32_kernel_forms(monkeypatch, mf32, chain, p, shape, bc):
     assert np.abs(zg - zo).max() < 1e-5 * np.abs(zo).max()
 
 
-@pytest.mark.parametrize("p", [3, 7])
-def test_ras_fp32_forms_agree_in_the_smoother(monkeypatch, p):
+@pytest.mark.parametrize("p,bc", [(3, (1,) * 6), (7, (1,) * 6), (7, (0, 1, 1, 0, 0, 1)),
+                                  (5, (1, 0, 0, 1, 1, 0)), (2, (0,) * 6)])
+def test_ras_fp32_forms_agree_in_the_smoother(monkeypatch, p, bc):
     """Cheby-RAS smoothing (post-smoothing residual formed as the box is read)
-    with each kernel form against the oracle."""
+    with each kernel form against the oracle, the matrix-core form with and
+    without the x step of A's gather-scatter taken in the FDM, Dirichlet and
+    Neumann x-faces."""
     t = __import__("torch")
-    for mf32, chain in (("1", "1"), ("1", "2"), ("1", "4"), ("0", "2")):
+    for mf32, chain, xstep in (("1", "1", "1"), ("1", "2", "1"), ("1", "1", "0"),
+                               ("0", "1", "1")):
         monkeypatch.setenv("SEM_FDM_MF32", mf32)
         monkeypatch.setenv("SEM_FDM_MF32_CHAIN", chain)
+        monkeypatch.setenv("SEM_FDM_XSTEP", xstep)
         P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=2,
-                 smoother_prec=sem.F32, lambda_override=[1.8])
+                 smoother_prec=sem.F32, lambda_override=[1.8], bc=bc)
         b, bo = P.random_local(42)
         x, xo = P.random_local(43)
         b, x = b.to(t.float32), x.to(t.float32)
         P.gpu.smooth(b, x, level=0)
-        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, (mf32, chain)
+        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, (mf32, chain, xstep)
