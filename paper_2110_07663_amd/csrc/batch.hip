@@ -216,7 +216,8 @@ double batch_wnorm2(Ctx &c, const double *a, const double *b, hipStream_t s);
 
 struct Lane {
   Ctx *c;
-  int k;  // right side index inside its problem
+  int ci;  // index of its problem (context) in the batch
+  int k;   // right side index inside its problem
   const double *b;
   double *x;
   double *r, *z, *zo, *p, *q;
@@ -270,6 +271,25 @@ struct BatchStreams {
   }
 };
 
+// The lane scalars of every context on the host: copies to each context's
+// pinned buffer, enqueued together, then one wait (not one per context).
+static void poll_lanes(const std::vector<Ctx *> &cs, int nrhs, std::vector<LaneScalars> &out,
+                       hipStream_t s) {
+  const size_t bytes = (size_t)nrhs * sizeof(LaneScalars);
+  if (bytes <= 4096) {  // the size of every context's pinned buffer
+    for (auto *c : cs)
+      SEM_HIP(hipMemcpyAsync(c->hres, c->lanes, bytes, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < cs.size(); ++i)
+      std::memcpy(&out[i * nrhs], cs[i]->hres, bytes);
+    return;
+  }
+  for (size_t i = 0; i < cs.size(); ++i) {
+    SEM_HIP(hipMemcpyAsync(&out[i * nrhs], cs[i]->lanes, bytes, hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+  }
+}
+
 }  // namespace sem
 
 using namespace sem;
@@ -301,6 +321,7 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
       for (int k = 0; k < nrhs; ++k) {
         Lane ln;
         ln.c = &c;
+        ln.ci = i;
         ln.k = k;
         ln.b = b[i * nrhs + k];
         ln.x = x[i * nrhs + k];
@@ -351,7 +372,8 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
     SEM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     bs.st.push_back(cap);
 
-    std::vector<LaneScalars> host(nrhs);
+    std::vector<LaneScalars> host_all((size_t)nctx * nrhs);
+    std::vector<char> recorded(nctx, 0), recorded_lane((size_t)nctx * nrhs, 0);
     int iterations = 0;
     while (true) {
       bool any = false;
@@ -368,7 +390,11 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
           SEM_HIP(hipStreamWaitEvent(br, bs.fork, 0));
           Lane *first = &lanes[(size_t)i * nrhs];
           bool any_active = false;
-          for (int k = 0; k < nrhs; ++k) any_active = any_active || first[k].active;
+          for (int k = 0; k < nrhs; ++k) {
+            any_active = any_active || first[k].active;
+            recorded_lane[(size_t)i * nrhs + k] = first[k].active;
+          }
+          recorded[i] = any_active;
           if (!any_active) continue;
           if (joint[i]) {
             lane_iteration(first, nrhs, br);  // finished lanes' own kernels return at once
@@ -401,19 +427,25 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
         const int k = std::min(ipl, maxit - iterations);
         for (int q = 0; q < k; ++q) SEM_HIP(hipGraphLaunch(exec, s));
         iterations += k;
-        for (int i = 0; i < nctx; ++i) {
-          SEM_HIP(hipMemcpyAsync(host.data(), cs[i]->lanes, nrhs * sizeof(LaneScalars),
-                                 hipMemcpyDeviceToHost, s));
-          SEM_HIP(hipStreamSynchronize(s));
-          for (auto &ln : lanes)
-            if (ln.c == cs[i] && ln.active) {
-              const LaneScalars &h = host[ln.k];
-              if (!(h.rr == h.rr)) fail(SEM_ENAN, "NaN in a batched solve");
-              if (h.done) {
-                ln.active = false;
-                changed = true;
-              }
-            }
+        poll_lanes(cs, nrhs, host_all, s);
+        for (auto &ln : lanes)
+          if (ln.active) {
+            const LaneScalars &h = host_all[(size_t)ln.ci * nrhs + ln.k];
+            if (!(h.rr == h.rr)) fail(SEM_ENAN, "NaN in a batched solve");
+            if (h.done) ln.active = false;
+          }
+        // the recorded graph changes only when a problem sharing its launches
+        // finishes all its lanes, or a lane running on its own finishes (the
+        // kernels of a finished lane of a shared problem return at once)
+        for (int i = 0; i < nctx && !changed; ++i) {
+          const Lane *first = &lanes[(size_t)i * nrhs];
+          bool any_active = false;
+          for (int k = 0; k < nrhs; ++k) any_active = any_active || first[k].active;
+          if (joint[i]) {
+            changed = !any_active && recorded[i];
+          } else {
+            for (int k = 0; k < nrhs; ++k) changed = changed || (recorded_lane[(size_t)i * nrhs + k] && !first[k].active);
+          }
         }
       }
       (void)hipGraphExecDestroy(exec);
@@ -421,14 +453,12 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
     }
     // true residuals and per-lane results
     bool all = true;
+    poll_lanes(cs, nrhs, host_all, s);
     for (size_t li = 0; li < lanes.size(); ++li) {
       Lane &ln = lanes[li];
       Ctx &c = *ln.c;
       const Level &F = c.lev[0];
-      SEM_HIP(hipMemcpyAsync(host.data(), c.lanes, nrhs * sizeof(LaneScalars),
-                             hipMemcpyDeviceToHost, s));
-      SEM_HIP(hipStreamSynchronize(s));
-      const LaneScalars &h = host[ln.k];
+      const LaneScalars &h = host_all[(size_t)ln.ci * nrhs + ln.k];
       batch_opA(c, F, ln.x, ln.q, s);
       launch_sub<double>(F.nloc, ln.b, ln.q, ln.r, s);
       double tr = batch_wnorm2(c, ln.r, ln.r, s);
