@@ -74,6 +74,25 @@ struct Mf {
 // kernel, which drops that mode.
 __device__ inline float mf_inv(float d) { return __builtin_amdgcn_rcpf(d); }
 
+// Raw-buffer view of an FP32 array: a load at a byte offset at or past nbytes
+// returns zero (the range check of the buffer instructions).  The box gather
+// reads the nodes outside the domain, and the A operands their zero padding,
+// through such offsets instead of selecting zeros after the loads.
+constexpr uint32_t kOutside = 0x80000000u;  // past every buffer window used here
+constexpr uint32_t kWindowMax = 0x7FFFFF00u;
+struct BufF32 {
+  __amdgpu_buffer_rsrc_t rsrc;
+  __device__ BufF32(const float *p, uint32_t nbytes)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, (int)nbytes,
+                                               0x00020000)) {}
+  __device__ float ld(uint32_t off) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+  }
+  __device__ mf4_t ld4(uint32_t off) const {
+    return __builtin_bit_cast(mf4_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+  }
+};
+
 // forward contraction of one slot: acc[g][i] = sum_k v[k] S[k][4g + i]
 template <int P>
 __device__ __attribute__((always_inline)) inline void mf_forward(const float *A, const float *v,
@@ -128,9 +147,9 @@ __device__ inline void mf_sync() {
 }
 
 // What one element's solve reads from global memory, loaded ahead of its use:
-// the raw x-lines of the box (the element's own row of a y/z neighbour or
-// itself, and one node of each x-neighbour; RS: also those of the subtrahend),
-// which of them lie inside the domain, and the A operands of its six passes.
+// the x-lines of the box (the element's own row of a y/z neighbour or itself,
+// and one node of each x-neighbour; RS: also those of the subtrahend), zero
+// where they lie outside the domain, and the A operands of its six passes.
 // XS = 1 (r) or 2 (rs): that input comes from A with the x step of its
 // gather-scatter left out (its y and z steps done), so the x-neighbours'
 // copies of the row's end nodes (their nodes p and 0) are read as well and
@@ -142,7 +161,6 @@ struct MfIn {
   float own[F::SF][F::N], lft[F::SF], rgt[F::SF];
   float sown[RS ? F::SF : 1][RS ? F::N : 1], slft[RS ? F::SF : 1], srgt[RS ? F::SF : 1];
   float xlp[XS ? F::SF : 1], xrp[XS ? F::SF : 1];  // x-partner copies of nodes 0 and p
-  unsigned okyz, okl, okr;  // bit s: slot s's line reads inside the domain
   float Af[3][F::UF], Ab[3][F::UB];
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
   mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
@@ -150,12 +168,12 @@ struct MfIn {
 
 template <int P, bool RS, int XS>
 __device__ __attribute__((always_inline)) inline void mf_load(
-    MfIn<P, RS, XS> &in, int64_t e, int nex, int ney, int nez, const float *__restrict__ r,
-    const float *__restrict__ rs, const float *__restrict__ Sg, const float *__restrict__ lamg,
+    MfIn<P, RS, XS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
+    int64_t eb, const float *__restrict__ Sg, const float *__restrict__ lamg,
     const float *__restrict__ W, int lane) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, MG = F::MG, KG = F::KG;
-  const float *Se = Sg + e * 3 * PB * PB;
+  const BufF32 Se(Sg + e * 3 * PB * PB, 3 * PB * PB * 4);  // the element's three factors
   // A operands: forward (k, g) -> lane 4q + i holds S_d[k][4g + i]; backward
   // (m, g) -> S_d[1 + 4g + i][m]; zero where the index runs past the factor
   {
@@ -163,24 +181,16 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 #pragma unroll
     for (int u = 0; u < F::UF; ++u) {
       const int q = 16 * u + qb, k = q / MG, m = 4 * (q % MG) + i;
-      const bool ok = q < F::QF && m < PB;
-      const int at = ok ? k * PB + m : 0;
+      const uint32_t at = q < F::QF && m < PB ? (uint32_t)(k * PB + m) * 4 : kOutside;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float sv = Se[d * PB * PB + at];
-        in.Af[d][u] = ok ? sv : 0.f;
-      }
+      for (int d = 0; d < 3; ++d) in.Af[d][u] = Se.ld(at + d * PB * PB * 4);
     }
 #pragma unroll
     for (int u = 0; u < F::UB; ++u) {
       const int q = 16 * u + qb, m = q / KG, k = 1 + 4 * (q % KG) + i;
-      const bool ok = q < F::QB && k <= N;
-      const int at = ok ? k * PB + m : 0;
+      const uint32_t at = q < F::QB && k <= N ? (uint32_t)(k * PB + m) * 4 : kOutside;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float sv = Se[d * PB * PB + at];
-        in.Ab[d][u] = ok ? sv : 0.f;
-      }
+      for (int d = 0; d < 3; ++d) in.Ab[d][u] = Se.ld(at + d * PB * PB * 4);
     }
   }
   // eigenvalue sums of the z pass (line (a', b') of slot s) and the RAS weights
@@ -210,53 +220,51 @@ __device__ __attribute__((always_inline)) inline void mf_load(
   }
   int64_t ex, ey, ez;
   elem_coords(e, nex, ney, ex, ey, ez);
-  in.okyz = in.okl = in.okr = 0u;
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
-    const bool act = l < F::NL;
-    const int lc = act ? l : 0, b = lc % PB, c = lc / PB;
+    const int b = l % PB, c = l / PB;
     const int dy = b == 0 ? -1 : (b == PB - 1 ? 1 : 0), lj = b == 0 ? P - 1 : (b == PB - 1 ? 1 : b - 1);
     const int dz = c == 0 ? -1 : (c == PB - 1 ? 1 : 0), lk = c == 0 ? P - 1 : (c == PB - 1 ? 1 : c - 1);
-    const bool okyz = act && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 && ez + dz < nez;
-    const int64_t em = okyz ? e + (int64_t)dy * nex + (int64_t)dz * nex * ney : e;
-    const int64_t row = em * N3 + (lk * N + lj) * N;
+    const bool okyz = l < F::NL && ey + dy >= 0 && ey + dy < ney && ez + dz >= 0 && ez + dz < nez;
     const bool okl = okyz && ex > 0, okr = okyz && ex < nex - 1;
-    const int64_t il = okl ? row - N3 + P - 1 : row, ir = okr ? row + N3 + 1 : row;
-    in.okyz |= okyz ? 1u << s : 0u;
-    in.okl |= okl ? 1u << s : 0u;
-    in.okr |= okr ? 1u << s : 0u;
-    in.lft[s] = r[il];
-    in.rgt[s] = r[ir];
+    // the row's byte offset from element eb (at most a plane and a line below e)
+    const uint32_t em = (uint32_t)(e - eb) + dy * nex + dz * nex * ney;
+    const uint32_t row = (em * N3 + (lk * N + lj) * N) * 4;
+    const uint32_t orow = okyz ? row : kOutside;
+    const uint32_t il = okl ? row - (N3 - P + 1) * 4 : kOutside;  // left neighbour's node p-1
+    const uint32_t ir = okr ? row + (N3 + 1) * 4 : kOutside;      // right neighbour's node 1
+    in.lft[s] = r.ld(il);
+    in.rgt[s] = r.ld(ir);
     if constexpr (XS != 0) {
-      const float *xs = XS == 1 ? r : rs;
-      in.xlp[s] = xs[okl ? row - N3 + P : row];  // left neighbour's node p
-      in.xrp[s] = xs[okr ? row + N3 : row];      // right neighbour's node 0
+      const BufF32 &xs = XS == 1 ? r : rs;
+      in.xlp[s] = xs.ld(okl ? row - (N3 - P) * 4 : kOutside);  // left neighbour's node p
+      in.xrp[s] = xs.ld(okr ? row + N3 * 4 : kOutside);        // right neighbour's node 0
     }
     if constexpr (N % 4 == 0) {
 #pragma unroll
       for (int q = 0; q < N / 4; ++q) {
-        const mf4_t t = *reinterpret_cast<const mf4_t *>(r + row + 4 * q);
+        const mf4_t t = r.ld4(orow + 16 * q);
 #pragma unroll
         for (int i = 0; i < 4; ++i) in.own[s][4 * q + i] = t[i];
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < N; ++i) in.own[s][i] = r[row + i];
+      for (int i = 0; i < N; ++i) in.own[s][i] = r.ld(orow + 4 * i);
     }
     if constexpr (RS) {
-      in.slft[s] = rs[il];
-      in.srgt[s] = rs[ir];
+      in.slft[s] = rs.ld(il);
+      in.srgt[s] = rs.ld(ir);
       if constexpr (N % 4 == 0) {
 #pragma unroll
         for (int q = 0; q < N / 4; ++q) {
-          const mf4_t t = *reinterpret_cast<const mf4_t *>(rs + row + 4 * q);
+          const mf4_t t = rs.ld4(orow + 16 * q);
 #pragma unroll
           for (int i = 0; i < 4; ++i) in.sown[s][4 * q + i] = t[i];
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < N; ++i) in.sown[s][i] = rs[row + i];
+        for (int i = 0; i < N; ++i) in.sown[s][i] = rs.ld(orow + 4 * i);
       }
     }
   }
@@ -274,14 +282,14 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
   mf4_t acc[F::SF][MG];
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
-    const bool okyz = (in.okyz >> s) & 1u, okl = (in.okl >> s) & 1u, okr = (in.okr >> s) & 1u;
+    // entries outside the domain were loaded as zeros
     float lv = in.lft[s], rv = in.rgt[s];
     if constexpr (RS) {
       lv -= in.slft[s];
       rv -= in.srgt[s];
     }
-    v[s][0] = okl ? lv : 0.f;
-    v[s][PB - 1] = okr ? rv : 0.f;
+    v[s][0] = lv;
+    v[s][PB - 1] = rv;
     float o0 = in.own[s][0], oN = in.own[s][N - 1];
     float s0 = 0.f, sN = 0.f;
     if constexpr (RS) {
@@ -289,20 +297,19 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
       sN = in.sown[s][N - 1];
     }
     if constexpr (XS != 0) {  // the x step: add the x-neighbours' copies
-      const float pl = okl ? in.xlp[s] : 0.f, pr = okr ? in.xrp[s] : 0.f;
       if constexpr (XS == 1) {
-        o0 += pl;
-        oN += pr;
+        o0 += in.xlp[s];
+        oN += in.xrp[s];
       } else {
-        s0 += pl;
-        sN += pr;
+        s0 += in.xlp[s];
+        sN += in.xrp[s];
       }
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       float o = i == 0 ? o0 : (i == N - 1 ? oN : in.own[s][i]);
       if constexpr (RS) o -= i == 0 ? s0 : (i == N - 1 ? sN : in.sown[s][i]);
-      v[s][i + 1] = okyz ? o : 0.f;
+      v[s][i + 1] = o;
     }
   }
 
@@ -454,15 +461,22 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
   if (RS) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
   float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
+  // the wave reads r (and rs) only between a plane and a line below its first
+  // element and as far above its last: one buffer window from there, whose
+  // size the host bounds below 2 GiB
+  const int64_t eb = e0 > (int64_t)nex * ney + nex + 1 ? e0 - ((int64_t)nex * ney + nex + 1) : 0;
+  const int64_t wb = (E - eb) * N3 * 4;
+  const uint32_t wn = wb < (int64_t)kWindowMax ? (uint32_t)wb : kWindowMax;
+  const BufF32 rb(r + eb * N3, wn), rsb(RS ? rs + eb * N3 : r + eb * N3, wn);
   MfIn<P, RS, XS> in[2];
-  mf_load<P, RS, XS>(in[0], e0, nex, ney, nez, r, rs, Sg, lamg, W, lane);
+  mf_load<P, RS, XS>(in[0], e0, nex, ney, nez, rb, rsb, eb, Sg, lamg, W, lane);
 #pragma unroll
   for (int it = 0; it < C; ++it) {
     const int64_t e = e0 + it;
     if (e >= E) break;
     if (it + 1 < C)  // (past the last element: reloads it, unused)
-      mf_load<P, RS, XS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, r, rs, Sg, lamg,
-                         W, lane);
+      mf_load<P, RS, XS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, rb, rsb, eb, Sg,
+                         lamg, W, lane);
     mf_solve<P, RS, XS>(in[it & 1], e, lamg, z, buf, lane);
   }
 }
@@ -504,10 +518,14 @@ void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, 
 // A box floats (a zero eigenvalue sum) only when every direction has one
 // element and Neumann faces at both ends: then the 1D problem of each
 // direction keeps its constant mode.
+//
+// A wave's reads of the box input span two planes and two lines of elements
+// plus its own: their bytes must fit one buffer window.
 bool fdm_mf32_supported(const Ctx &c, int p) {
   const bool floating = c.nex == 1 && c.ney == 1 && c.nez == 1 && !c.bc[0] && !c.bc[1] &&
                         !c.bc[2] && !c.bc[3] && !c.bc[4] && !c.bc[5];
-  return p >= 2 && p <= 9 && !floating;
+  const int64_t span = 2 * ((int64_t)c.nex * c.ney + c.nex + 1) + 4;
+  return p >= 2 && p <= 9 && !floating && span * (p + 1) * (p + 1) * (p + 1) * 4 < kWindowMax;
 }
 
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
