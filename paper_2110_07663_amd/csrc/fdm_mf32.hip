@@ -155,20 +155,28 @@ __device__ inline void mf_sync() {
 // copies of the row's end nodes (their nodes p and 0) are read as well and
 // added: each copy of a node then holds the sum over all its copies, as
 // after the whole gather-scatter (the x step taken last).
-template <int P, bool RS, int XS>
+// YS: that input also comes without the y step (only the z step done): the
+// rows on the element's y-faces (own rows j = 0, p of the element and of its
+// z-neighbours) also read the y-neighbour's copy of the row, of its end nodes'
+// x-partners and of the halo nodes beside it, and add them (y, then x).
+template <int P, bool RS, int XS, bool YS>
 struct MfIn {
   using F = Mf<P>;
   float own[F::SF][F::N], lft[F::SF], rgt[F::SF];
   float sown[RS ? F::SF : 1][RS ? F::N : 1], slft[RS ? F::SF : 1], srgt[RS ? F::SF : 1];
   float xlp[XS ? F::SF : 1], xrp[XS ? F::SF : 1];  // x-partner copies of nodes 0 and p
+  static constexpr int YSF = YS ? F::SF : 1;
+  float yrow[YSF][YS ? F::N : 1];  // y-partner copy of the row
+  float yxl[YSF], yxr[YSF];        // ... of the x-partners of its nodes 0 and p
+  float ylf[YSF], yrg[YSF];        // ... of the halo nodes (left node p-1, right node 1)
   float Af[3][F::UF], Ab[3][F::UB];
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
   mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
 };
 
-template <int P, bool RS, int XS>
+template <int P, bool RS, int XS, bool YS>
 __device__ __attribute__((always_inline)) inline void mf_load(
-    MfIn<P, RS, XS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
+    MfIn<P, RS, XS, YS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
     int64_t eb, const float *__restrict__ Sg, const float *__restrict__ lamg,
     const float *__restrict__ W, int lane) {
   using F = Mf<P>;
@@ -240,6 +248,31 @@ __device__ __attribute__((always_inline)) inline void mf_load(
       const BufF32 &xs = XS == 1 ? r : rs;
       in.xlp[s] = xs.ld(okl ? row - (N3 - P) * 4 : kOutside);  // left neighbour's node p
       in.xrp[s] = xs.ld(okr ? row + N3 * 4 : kOutside);        // right neighbour's node 0
+      if constexpr (YS) {
+        // own row j = 0 (b = 1) pairs with row j = p of the element below in
+        // y, row j = p (b = PB - 2) with row j = 0 of the one above
+        const bool ylo = okyz && b == 1 && ey > 0, yhi = okyz && b == PB - 2 && ey < ney - 1;
+        const uint32_t ystep = ((uint32_t)nex * N3 - P * N) * 4;
+        const bool yp = ylo || yhi;
+        const uint32_t yr = ylo ? row - ystep : (yhi ? row + ystep : 0u);
+        const uint32_t yrow = yp ? yr : kOutside;
+        if constexpr (N % 4 == 0) {
+#pragma unroll
+          for (int q = 0; q < N / 4; ++q) {
+            const mf4_t t = xs.ld4(yrow + 16 * q);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) in.yrow[s][4 * q + i] = t[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < N; ++i) in.yrow[s][i] = xs.ld(yrow + 4 * i);
+        }
+        const bool yl = yp && ex > 0, yh = yp && ex < nex - 1;
+        in.yxl[s] = xs.ld(yl ? yr - (N3 - P) * 4 : kOutside);
+        in.yxr[s] = xs.ld(yh ? yr + N3 * 4 : kOutside);
+        in.ylf[s] = xs.ld(yl ? yr - (N3 - P + 1) * 4 : kOutside);
+        in.yrg[s] = xs.ld(yh ? yr + (N3 + 1) * 4 : kOutside);
+      }
     }
     if constexpr (N % 4 == 0) {
 #pragma unroll
@@ -271,9 +304,9 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 }
 
 // the local solve of element e from its loaded inputs; buf = the wave's LDS
-template <int P, bool RS, int XS>
+template <int P, bool RS, int XS, bool YS>
 __device__ __attribute__((always_inline)) inline void mf_solve(
-    const MfIn<P, RS, XS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
+    const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
     float *buf, int lane) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
@@ -282,35 +315,39 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
   mf4_t acc[F::SF][MG];
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
-    // entries outside the domain were loaded as zeros
-    float lv = in.lft[s], rv = in.rgt[s];
-    if constexpr (RS) {
-      lv -= in.slft[s];
-      rv -= in.srgt[s];
-    }
-    v[s][0] = lv;
-    v[s][PB - 1] = rv;
-    float o0 = in.own[s][0], oN = in.own[s][N - 1];
-    float s0 = 0.f, sN = 0.f;
-    if constexpr (RS) {
-      s0 = in.sown[s][0];
-      sN = in.sown[s][N - 1];
-    }
-    if constexpr (XS != 0) {  // the x step: add the x-neighbours' copies
-      if constexpr (XS == 1) {
-        o0 += in.xlp[s];
-        oN += in.xrp[s];
-      } else {
-        s0 += in.xlp[s];
-        sN += in.xrp[s];
-      }
-    }
+    // entries outside the domain were loaded as zeros; the deferred steps
+    // act on r (XS = 1) or on rs (XS = 2): the y step on the row and its halo
+    // nodes, then the x step on the end nodes (as (own + y) + (x + xy))
+    float ro[N], so[N], rl = in.lft[s], rr = in.rgt[s], sl = 0.f, sr = 0.f;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      float o = i == 0 ? o0 : (i == N - 1 ? oN : in.own[s][i]);
-      if constexpr (RS) o -= i == 0 ? s0 : (i == N - 1 ? sN : in.sown[s][i]);
-      v[s][i + 1] = o;
+      ro[i] = in.own[s][i];
+      so[i] = 0.f;
+      if constexpr (RS) so[i] = in.sown[s][i];
     }
+    if constexpr (RS) {
+      sl = in.slft[s];
+      sr = in.srgt[s];
+    }
+    auto steps = [&](float(&o)[N], float &hl, float &hr) {
+      float xl = in.xlp[s], xr = in.xrp[s];
+      if constexpr (YS) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] += in.yrow[s][i];
+        hl += in.ylf[s];
+        hr += in.yrg[s];
+        xl += in.yxl[s];
+        xr += in.yxr[s];
+      }
+      o[0] += xl;
+      o[N - 1] += xr;
+    };
+    if constexpr (XS == 1) steps(ro, rl, rr);
+    if constexpr (XS == 2) steps(so, sl, sr);
+    v[s][0] = RS ? rl - sl : rl;
+    v[s][PB - 1] = RS ? rr - sr : rr;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[s][i + 1] = RS ? ro[i] - so[i] : ro[i];
   }
 
   // x: line (b, c) -> modes a'; written as y-lines (a', c), position b
@@ -441,7 +478,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 // weight (mask / multiplicity), z = output E-vector(s).  Each wavefront
 // solves C consecutive elements, loading the next element's inputs before it
 // solves the current one, so that the loads of one overlap the other's work.
-template <int P, int C, bool RS, int XS>
+template <int P, int C, bool RS, int XS, bool YS>
 __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ rs,
@@ -468,20 +505,20 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
   const int64_t wb = (E - eb) * N3 * 4;
   const uint32_t wn = wb < (int64_t)kWindowMax ? (uint32_t)wb : kWindowMax;
   const BufF32 rb(r + eb * N3, wn), rsb(RS ? rs + eb * N3 : r + eb * N3, wn);
-  MfIn<P, RS, XS> in[2];
-  mf_load<P, RS, XS>(in[0], e0, nex, ney, nez, rb, rsb, eb, Sg, lamg, W, lane);
+  MfIn<P, RS, XS, YS> in[2];
+  mf_load<P, RS, XS, YS>(in[0], e0, nex, ney, nez, rb, rsb, eb, Sg, lamg, W, lane);
 #pragma unroll
   for (int it = 0; it < C; ++it) {
     const int64_t e = e0 + it;
     if (e >= E) break;
     if (it + 1 < C)  // (past the last element: reloads it, unused)
-      mf_load<P, RS, XS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, rb, rsb, eb, Sg,
+      mf_load<P, RS, XS, YS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, rb, rsb, eb, Sg,
                          lamg, W, lane);
-    mf_solve<P, RS, XS>(in[it & 1], e, lamg, z, buf, lane);
+    mf_solve<P, RS, XS, YS>(in[it & 1], e, lamg, z, buf, lane);
   }
 }
 
-template <int P, bool RS, int XS>
+template <int P, bool RS, int XS, bool YS>
 void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                    hipStream_t s, int nv) {
   using F = Mf<P>;
@@ -489,27 +526,34 @@ void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs
   const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
   const dim3 block(64 * F::WAVES);
   if (C == 2)
-    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, r,
-                       rs, L.S32, L.lam32, L.w32, z, nv);
+    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS>), grid, block, 0, s, L.E, c.nex, c.ney,
+                       c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
   else
-    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS>), grid, block, 0, s, L.E, c.nex, c.ney, c.nez, r,
-                       rs, L.S32, L.lam32, L.w32, z, nv);
+    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS>), grid, block, 0, s, L.E, c.nex, c.ney,
+                       c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
   SEM_LAUNCH("k_fdm_mf32");
 }
 
 // xin: 0 the inputs are assembled; 1 r, 2 rs lacks the x step of its
-// gather-scatter (the kernel adds the x-neighbours' copies as it reads)
+// gather-scatter (the kernel adds the x-neighbours' copies as it reads);
+// + 4: that input lacks the y step as well (only its z step was taken)
 template <int P>
 void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                  hipStream_t s, int nv, int xin) {
-  if (xin == 2 && !rs) fail(SEM_EINVAL, "FDM: no subtrahend to take the x step");
+  const int which = xin & 3;
+  const bool ys = (xin & 4) != 0;
+  if (xin & ~7 || which == 3 || (ys && which == 0))
+    fail(SEM_EINVAL, "FDM: unknown form of the deferred gather-scatter steps");
+  if (which == 2 && !rs) fail(SEM_EINVAL, "FDM: no subtrahend to take the x step");
   if (rs) {
-    if (xin == 2) mf32_launch_x<P, true, 2>(c, L, r, rs, z, s, nv);
-    else if (xin == 1) fail(SEM_EINVAL, "FDM: the x step is taken on the subtrahend only");
-    else mf32_launch_x<P, true, 0>(c, L, r, rs, z, s, nv);
+    if (which == 1) fail(SEM_EINVAL, "FDM: the x step is taken on the subtrahend only");
+    if (which == 2 && ys) mf32_launch_x<P, true, 2, true>(c, L, r, rs, z, s, nv);
+    else if (which == 2) mf32_launch_x<P, true, 2, false>(c, L, r, rs, z, s, nv);
+    else mf32_launch_x<P, true, 0, false>(c, L, r, rs, z, s, nv);
   } else {
-    if (xin == 1) mf32_launch_x<P, false, 1>(c, L, r, rs, z, s, nv);
-    else mf32_launch_x<P, false, 0>(c, L, r, rs, z, s, nv);
+    if (which == 1 && ys) mf32_launch_x<P, false, 1, true>(c, L, r, rs, z, s, nv);
+    else if (which == 1) mf32_launch_x<P, false, 1, false>(c, L, r, rs, z, s, nv);
+    else mf32_launch_x<P, false, 0, false>(c, L, r, rs, z, s, nv);
   }
 }
 

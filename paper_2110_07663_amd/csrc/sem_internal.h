@@ -249,6 +249,7 @@ struct Ctx {
   bool fdm_mf32 = true;   // FP32 RAS local solves on the matrix cores (fdm_mf32.hip)
   int fdm_mf32_chain = 1; // elements per wavefront there (1 or 2), next one's loads ahead
   bool fdm_xstep = true;  // that kernel takes the x step of A's gather-scatter as it reads
+  bool fdm_ystep = true;  // ... and the y step as well (A's gather-scatter takes only z)
 };
 
 // ---------------------------------------------------------------------------

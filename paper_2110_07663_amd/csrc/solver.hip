@@ -349,6 +349,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_mf32_chain = fch && fch[0] == '2' ? 2 : 1;
   const char *fxs = getenv("SEM_FDM_XSTEP");
   c.fdm_xstep = !(fxs && fxs[0] == '0');
+  const char *fys = getenv("SEM_FDM_YSTEP");
+  c.fdm_ystep = !(fys && fys[0] == '0');
 }
 
 // ---------------------------------------------------------------------------
@@ -486,7 +488,14 @@ static bool fdm_takes_x_step(const Ctx &c, const Level &L) {
          !L.coarse && L.gs_struct && fdm_mf32_supported(c, L.p);
 }
 
-// A u with the x step of the gather-scatter left to the reader (y and z done)
+// ... and the y step too: only the z step of A's gather-scatter is taken
+template <typename T>
+static bool fdm_takes_y_step(const Ctx &c, const Level &L) {
+  return fdm_takes_x_step<T>(c, L) && c.fdm_ystep;
+}
+
+// A u with the x step (and, when the smoother takes it, the y step) of the
+// gather-scatter left to the reader
 template <typename T>
 static void opA_nox(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t s, int nv) {
   {
@@ -494,10 +503,11 @@ static void opA_nox(const Ctx &c, const Level &L, const T *u, T *Au, hipStream_t
     launch_ax<T>(L, u, Au, s, nv, false, nullptr);
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, Au, s, nv, false, true, false);
+  launch_gs<T>(L, Au, s, nv, false, true, fdm_takes_y_step<T>(c, L));
 }
 
-// xin: 0 r and rs assembled; 1 r, 2 rs comes from opA_nox (fdm_takes_x_step)
+// xin: 0 r and rs assembled; 1 r, 2 rs comes from opA_nox (fdm_takes_x_step),
+// + 4 when opA_nox left the y step as well (fdm_takes_y_step)
 template <typename T>
 static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, int nv = 1,
                 T *rs = nullptr, XDefer *xd = nullptr, int xin = 0) {
@@ -557,11 +567,12 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
   double rho = 1.0 / sigma;
   // A's output that only feeds S may leave the x step of its gather-scatter to S
   const bool xs = fdm_takes_x_step<T>(c, L);
+  const int ys = fdm_takes_y_step<T>(c, L) ? 4 : 0;
   if (x_zero) {
     opS<T>(c, L, b, r, s, nv);
   } else if (xs) {
     opA_nox<T>(c, L, x, w, s, nv);
-    opS<T>(c, L, b, r, s, nv, w, nullptr, 2);  // r = S (b - A x)
+    opS<T>(c, L, b, r, s, nv, w, nullptr, 2 | ys);  // r = S (b - A x)
   } else {
     opA<T>(c, L, x, w, s, nv);
     opS<T>(c, L, b, r, s, nv, w);  // r = S (b - A x)
@@ -582,7 +593,7 @@ static void chebyshev(const Ctx &c, Level &L, const T *b, T *x, bool x_zero, hip
       opA<T>(c, L, k == 0 ? r : d, w, s, nv);
     XDefer xd;  // t only feeds the update below: it may take the x step itself
     opS<T>(c, L, w, t, s, nv, nullptr, cheb_can_defer_x<T>(L.N, n, {x, r, d, t}) ? &xd : nullptr,
-           xs ? 1 : 0);
+           xs ? 1 | ys : 0);
     double rho_new = 1.0 / (2.0 * sigma - rho);
     const T a = (T)(rho_new * rho), cc = (T)(2.0 * rho_new / delta);
     const bool last = k + 1 == L.K;

@@ -6,8 +6,9 @@ one launch, and the residual form r - rs formed as the box is read.  The
 matrix-core form solves 1 or 2 consecutive elements per wavefront
 (SEM_FDM_MF32_CHAIN), loading the next one's inputs ahead; the meshes leave
 partly filled workgroups and wavefronts.  Inside the smoother the matrix-core
-form also takes the x step of the gather-scatter of A's output as it reads
-(SEM_FDM_XSTEP=0: A's output is assembled first)."""
+form also takes the x step, and then the y step, of the gather-scatter of A's
+output as it reads (SEM_FDM_YSTEP=0: A's gather-scatter takes y and z,
+SEM_FDM_XSTEP=0: A's output is assembled first)."""
 import numpy as np
 import pytest
 
@@ -39,23 +40,29 @@ def test_ras_fp32_kernel_forms(monkeypatch, mf32, chain, p, shape, bc):
     assert np.abs(zg - zo).max() < 1e-5 * np.abs(zo).max()
 
 
-@pytest.mark.parametrize("p,bc", [(3, (1,) * 6), (7, (1,) * 6), (7, (0, 1, 1, 0, 0, 1)),
-                                  (5, (1, 0, 0, 1, 1, 0)), (2, (0,) * 6)])
-def test_ras_fp32_forms_agree_in_the_smoother(monkeypatch, p, bc):
+@pytest.mark.parametrize("p,shape,bc", [
+    (3, (3, 2, 2), (1,) * 6), (7, (3, 2, 2), (1,) * 6), (7, (3, 2, 2), (0, 1, 1, 0, 0, 1)),
+    (5, (3, 2, 2), (1, 0, 0, 1, 1, 0)), (2, (3, 2, 2), (0,) * 6),
+    # interior y-faces on both sides of the middle row, Neumann and Dirichlet y ends
+    (7, (2, 3, 3), (1, 1, 0, 1, 1, 0)), (3, (2, 4, 2), (0, 1, 1, 0, 1, 1))])
+def test_ras_fp32_forms_agree_in_the_smoother(monkeypatch, p, shape, bc):
     """Cheby-RAS smoothing (post-smoothing residual formed as the box is read)
-    with each kernel form against the oracle, the matrix-core form with and
-    without the x step of A's gather-scatter taken in the FDM, Dirichlet and
-    Neumann x-faces."""
+    with each kernel form against the oracle, the matrix-core form taking the
+    x and y steps of A's gather-scatter in the FDM, the x step only, or
+    neither; Dirichlet and Neumann faces."""
     t = __import__("torch")
-    for mf32, chain, xstep in (("1", "1", "1"), ("1", "2", "1"), ("1", "1", "0"),
-                               ("0", "1", "1")):
+    for mf32, chain, xstep, ystep in (("1", "1", "1", "1"), ("1", "2", "1", "1"),
+                                      ("1", "1", "1", "0"), ("1", "1", "0", "1"),
+                                      ("0", "1", "1", "1")):
         monkeypatch.setenv("SEM_FDM_MF32", mf32)
         monkeypatch.setenv("SEM_FDM_MF32_CHAIN", chain)
         monkeypatch.setenv("SEM_FDM_XSTEP", xstep)
-        P = Pair((3, 2, 2), p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=2,
+        monkeypatch.setenv("SEM_FDM_YSTEP", ystep)
+        P = Pair(shape, p, mesh="sin", schedule=(p, 1), smoother="ras", cheb_order=2,
                  smoother_prec=sem.F32, lambda_override=[1.8], bc=bc)
         b, bo = P.random_local(42)
         x, xo = P.random_local(43)
         b, x = b.to(t.float32), x.to(t.float32)
         P.gpu.smooth(b, x, level=0)
-        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, (mf32, chain, xstep)
+        tag = (mf32, chain, xstep, ystep)
+        assert rel_err(host(x), P.ora.smooth(bo, xo, level=0)) < 1e-5, tag

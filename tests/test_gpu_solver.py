@@ -280,13 +280,15 @@ def test_mixed_precision_solve():
 @pytest.mark.parametrize("shape,bc", [((4, 3, 2), (1,) * 6), ((3, 2, 3), (0, 1, 1, 0, 1, 1))])
 def test_mixed_solve_with_deferred_steps_matches_assembled(monkeypatch, shape, bc):
     """Mixed FCG at p = 7: the outer A p and the smoother's S w leave their x
-    and y gather-scatter steps to the pointwise updates that read them
-    (default), or run assembled (SEM_GS_XDEFER=0).  Both reach the oracle's
+    and y gather-scatter steps to the pointwise updates that read them, and
+    the smoother's A w leaves them to the FDM (default); or everything runs
+    assembled (SEM_GS_XDEFER=0, SEM_FDM_XSTEP=0).  Both reach the oracle's
     residual with the same iteration count, and the solutions agree to the
     FP32 preconditioner's rounding."""
     sols = {}
     for xdefer in ("1", "0"):
         monkeypatch.setenv("SEM_GS_XDEFER", xdefer)
+        monkeypatch.setenv("SEM_FDM_XSTEP", xdefer)
         P = Pair(shape, 7, mesh="sin", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
                  bc=bc, lambda_override=[1.8, 1.6], coarse="dense")
         bg, bo = _rhs(P)
