@@ -88,6 +88,11 @@ def kernels_mode(a):
         s.apply_A(u, out=v)
         s.apply_A(u32, out=v32)
         s.apply_S(u32, out=v32)
+    # Cheby-RAS(2) smoothing: the FDM and Ax forms the solve runs (A's output
+    # leaving its x and y gather-scatter steps to the FDM, the residual form)
+    x32 = torch.zeros_like(u32)
+    for _ in range(a.reps):
+        s.smooth(u32, x32, level=0)
     # the other Ax kernel shapes at p = 7 (the default is variant 2)
     for av in (0, 1):
         oa = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,

@@ -132,6 +132,97 @@ __global__ __launch_bounds__(256) void k_restrict(int Nf_, int Nc_, const T *__r
   }
 }
 
+// Small elements (NF^3 <= 64, e.g. p = 3 -> 1): one element per wavefront,
+// four per workgroup, the same contractions and summation order as above;
+// E is passed for the right-side stride (gridDim.x counts workgroups).
+template <typename T, int NF, int NC>
+__global__ __launch_bounds__(256) void k_prolong_w(int64_t E, const T *__restrict__ J,
+                                                   const T *__restrict__ xc, T *__restrict__ xf) {
+  static_assert(NF * NF * NF <= 64, "one element per wavefront");
+  constexpr int Nc3 = NC * NC * NC, Nf3 = NF * NF * NF;
+  __shared__ T sJ[NF * NC];
+  __shared__ T a[4][64];
+  __shared__ T b[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + w;
+  const bool act = e < E;
+  xc += blockIdx.y * E * Nc3;  // right side blockIdx.y
+  xf += blockIdx.y * E * Nf3;
+  if (threadIdx.x < NF * NC) sJ[threadIdx.x] = J[threadIdx.x];
+  if (act && l < Nc3) a[w][l] = xc[e * Nc3 + l];
+  __syncthreads();
+  if (l < NC * NC * NF) {  // b[c][bb][i] = sum_a J[i][a] x[c][bb][a]
+    const int i = l % NF, cb = l / NF;
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) s += sJ[i * NC + q] * a[w][cb * NC + q];
+    b[w][l] = s;
+  }
+  __syncthreads();
+  if (l < NC * NF * NF) {  // a[c][j][i] = sum_bb J[j][bb] b[c][bb][i]
+    const int i = l % NF, j = (l / NF) % NF, c = l / (NF * NF);
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) s += sJ[j * NC + q] * b[w][(c * NC + q) * NF + i];
+    a[w][l] = s;
+  }
+  __syncthreads();
+  if (act && l < Nf3) {  // xf[k][j][i] += sum_c J[k][c] a[c][j][i]
+    const int ji = l % (NF * NF), k = l / (NF * NF);
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) s += sJ[k * NC + q] * a[w][q * NF * NF + ji];
+    xf[e * Nf3 + l] += s;
+  }
+}
+
+template <typename T, int NF, int NC>
+__global__ __launch_bounds__(256) void k_restrict_w(int64_t E, const T *__restrict__ J,
+                                                    const T *__restrict__ wt,
+                                                    const T *__restrict__ rf,
+                                                    const T *__restrict__ bf, T *__restrict__ rc) {
+  static_assert(NF * NF * NF <= 64, "one element per wavefront");
+  constexpr int Nc3 = NC * NC * NC, Nf3 = NF * NF * NF;
+  __shared__ T sJ[NF * NC];
+  __shared__ T a[4][64];
+  __shared__ T b[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + w;
+  const bool act = e < E;
+  rf += blockIdx.y * E * Nf3;  // right side blockIdx.y
+  rc += blockIdx.y * E * Nc3;
+  if (bf) bf += blockIdx.y * E * Nf3;
+  if (threadIdx.x < NF * NC) sJ[threadIdx.x] = J[threadIdx.x];
+  if (act && l < Nf3) {
+    const int64_t o = e * Nf3 + l;
+    a[w][l] = bf ? wt[o] * (bf[o] - rf[o]) : wt[o] * rf[o];  // b - A x on the way in
+  }
+  __syncthreads();
+  if (l < NF * NF * NC) {  // b[k][j][aa] = sum_i J[i][aa] r[k][j][i]
+    const int aa = l % NC, kj = l / NC;
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) s += sJ[q * NC + aa] * a[w][kj * NF + q];
+    b[w][l] = s;
+  }
+  __syncthreads();
+  if (l < NF * NC * NC) {  // a[k][bb][aa] = sum_j J[j][bb] b[k][j][aa]
+    const int aa = l % NC, bb = (l / NC) % NC, k = l / (NC * NC);
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) s += sJ[q * NC + bb] * b[w][(k * NF + q) * NC + aa];
+    a[w][l] = s;
+  }
+  __syncthreads();
+  if (act && l < Nc3) {  // rc[c][bb][aa] = sum_k J[k][c] a[k][bb][aa]
+    const int ba = l % (NC * NC), c = l / (NC * NC);
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) s += sJ[q * NC + c] * a[w][q * NC * NC + ba];
+    rc[e * Nc3 + l] = s;
+  }
+}
+
 static int transfer_threads(int Nf) {
   int n = Nf * Nf * Nf;
   int t = ((n + 63) / 64) * 64;
@@ -154,6 +245,12 @@ void launch_prolong(const Level &F, const Level &C, const T *xc, T *xf, hipStrea
   }
   SEM_TRANSFER_PAIRS(SEM_PROLONG_CASE)
 #undef SEM_PROLONG_CASE
+  if (F.N == 4 && C.N == 2) {
+    const dim3 gw((unsigned)((F.E + 3) / 4), (unsigned)nv);
+    hipLaunchKernelGGL((k_prolong_w<T, 4, 2>), gw, dim3(256), 0, s, F.E, J, xc, xf);
+    SEM_LAUNCH("k_prolong");
+    return;
+  }
   hipLaunchKernelGGL(k_prolong<T>, grid, dim3(transfer_threads(F.N)), 0, s, F.N, C.N, J, xc, xf);
   SEM_LAUNCH("k_prolong");
 }
@@ -173,6 +270,12 @@ void launch_restrict(const Level &F, const Level &C, const T *rf, T *rc, hipStre
   }
   SEM_TRANSFER_PAIRS(SEM_RESTRICT_CASE)
 #undef SEM_RESTRICT_CASE
+  if (F.N == 4 && C.N == 2) {
+    const dim3 gw((unsigned)((F.E + 3) / 4), (unsigned)nv);
+    hipLaunchKernelGGL((k_restrict_w<T, 4, 2>), gw, dim3(256), 0, s, F.E, J, w, rf, bf, rc);
+    SEM_LAUNCH("k_restrict");
+    return;
+  }
   hipLaunchKernelGGL(k_restrict<T>, grid, dim3(transfer_threads(F.N)), 0, s, F.N, C.N, J, w, rf,
                      bf, rc);
   SEM_LAUNCH("k_restrict");
