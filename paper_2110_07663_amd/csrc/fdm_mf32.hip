@@ -303,11 +303,16 @@ __device__ __attribute__((always_inline)) inline void mf_load(
   }
 }
 
-// the local solve of element e from its loaded inputs; buf = the wave's LDS
-template <int P, bool RS, int XS, bool YS>
+// the local solve of element e from its loaded inputs; buf = the wave's LDS.
+// XF: the workgroup's four waves hold four consecutive elements along x, and
+// the copies on the three x-faces between them are summed (through xfx, LDS
+// shared by the workgroup) before the store, each pair as (p-face + 0-face),
+// the order of the gather-scatter's x step, which then covers only the faces
+// between workgroups.
+template <int P, bool RS, int XS, bool YS, bool XF>
 __device__ __attribute__((always_inline)) inline void mf_solve(
     const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
-    float *buf, int lane) {
+    float *buf, int lane, float *xfx, int wave) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
   const float *le = lamg + e * 3 * PB;
@@ -449,6 +454,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 
   // back along x: line (j, k) -> kept nodes i = 1..N: the element's row (j, k)
   // times the RAS weight
+  mf4_t o[F::SX][KG];
 #pragma unroll
   for (int s = 0; s < F::SX; ++s) {
     const int l = 64 * s + lane;
@@ -456,18 +462,43 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     mf4_t bx[KG];
     mf_read_line<P>(buf, l < F::NLX ? l : 0, u);
     mf_backward<P>(in.Ab[0], u, bx);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * bx[g];
+  }
+  if constexpr (XF) {
+    constexpr int NLX = F::NLX, GL = (N - 1) / 4, IL = (N - 1) % 4;
+#pragma unroll
+    for (int s = 0; s < F::SX; ++s) {
+      const int l = 64 * s + lane;
+      if (l < NLX) {
+        xfx[(2 * wave) * NLX + l] = o[s][0][0];
+        xfx[(2 * wave + 1) * NLX + l] = o[s][GL][IL];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < F::SX; ++s) {
+      const int l = 64 * s + lane;
+      if (l < NLX) {
+        if (wave > 0) o[s][0][0] = xfx[(2 * wave - 1) * NLX + l] + o[s][0][0];
+        if (wave < F::WAVES - 1) o[s][GL][IL] = o[s][GL][IL] + xfx[(2 * wave + 2) * NLX + l];
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < F::SX; ++s) {
+    const int l = 64 * s + lane;
     if (l < F::NLX) {
       const int64_t row = e * N3 + (int64_t)l * N;  // row (j, k) = k * N + j = l
       if constexpr (N % 4 == 0) {
 #pragma unroll
-        for (int g = 0; g < KG; ++g)
-          *reinterpret_cast<mf4_t *>(z + row + 4 * g) = in.wrow[s][g] * bx[g];
+        for (int g = 0; g < KG; ++g) *reinterpret_cast<mf4_t *>(z + row + 4 * g) = o[s][g];
       } else {
 #pragma unroll
         for (int g = 0; g < KG; ++g)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (4 * g + i < N) z[row + 4 * g + i] = in.wrow[s][g][i] * bx[g][i];
+            if (4 * g + i < N) z[row + 4 * g + i] = o[s][g][i];
       }
     }
   }
@@ -478,7 +509,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 // weight (mask / multiplicity), z = output E-vector(s).  Each wavefront
 // solves C consecutive elements, loading the next element's inputs before it
 // solves the current one, so that the loads of one overlap the other's work.
-template <int P, int C, bool RS, int XS, bool YS>
+template <int P, int C, bool RS, int XS, bool YS, bool XF>
 __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ rs,
@@ -488,12 +519,16 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
                                                   float *__restrict__ z, int nv) {
   using F = Mf<P>;
   constexpr int N3 = F::N3;
+  static_assert(!XF || C == 1, "x-face sums: one element per wave");
   __shared__ mf4_t lds4[F::WAVES * F::BUF / 4];
+  __shared__ float xfx[XF ? 2 * F::WAVES * F::NLX : 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   int vec;
   const int64_t e0 = ((int64_t)split_rhs(xcd_block(), nv, vec) * F::WAVES + wave) * C;
-  if (e0 >= E) return;  // whole wave leaves; nothing below waits on other waves
+  // whole wave leaves; only XF waits on other waves, and then E is a multiple
+  // of 4 (every wave of a workgroup is live)
+  if (e0 >= E) return;
   r += (int64_t)vec * E * N3;
   if (RS) rs += (int64_t)vec * E * N3;
   z += (int64_t)vec * E * N3;
@@ -514,46 +549,62 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     if (it + 1 < C)  // (past the last element: reloads it, unused)
       mf_load<P, RS, XS, YS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, rb, rsb, eb, Sg,
                          lamg, W, lane);
-    mf_solve<P, RS, XS, YS>(in[it & 1], e, lamg, z, buf, lane);
+    mf_solve<P, RS, XS, YS, XF>(in[it & 1], e, lamg, z, buf, lane, xfx, wave);
   }
 }
 
-template <int P, bool RS, int XS, bool YS>
+template <int P, bool RS, int XS, bool YS, bool XF>
 void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                    hipStream_t s, int nv) {
   using F = Mf<P>;
-  const int C = c.fdm_mf32_chain;
+  const int C = XF ? 1 : c.fdm_mf32_chain;
+  if (XF && (L.E % F::WAVES != 0 || c.nex % F::WAVES != 0))
+    fail(SEM_EINVAL, "FDM: x-face sums need whole groups of four elements along x");
   const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
   const dim3 block(64 * F::WAVES);
-  if (C == 2)
-    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS>), grid, block, 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
-  else
-    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS>), grid, block, 0, s, L.E, c.nex, c.ney,
-                       c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+  if constexpr (XF) {
+    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, true>), grid, block, 0, s, L.E, c.nex,
+                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+  } else if (C == 2) {
+    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
+                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+  } else {
+    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
+                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+  }
   SEM_LAUNCH("k_fdm_mf32");
 }
 
 // xin: 0 the inputs are assembled; 1 r, 2 rs lacks the x step of its
 // gather-scatter (the kernel adds the x-neighbours' copies as it reads);
-// + 4: that input lacks the y step as well (only its z step was taken)
+// + 4: that input lacks the y step as well (only its z step was taken);
+// + 8: sum the output's x-faces inside each workgroup (assembled r, or rs
+// as above), for a gather-scatter that then covers only the faces between
+// workgroups
 template <int P>
 void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                  hipStream_t s, int nv, int xin) {
   const int which = xin & 3;
-  const bool ys = (xin & 4) != 0;
-  if (xin & ~7 || which == 3 || (ys && which == 0))
+  const bool ys = (xin & 4) != 0, xf = (xin & 8) != 0;
+  if (xin & ~15 || which == 3 || (ys && which == 0) || (xf && which == 1))
     fail(SEM_EINVAL, "FDM: unknown form of the deferred gather-scatter steps");
   if (which == 2 && !rs) fail(SEM_EINVAL, "FDM: no subtrahend to take the x step");
   if (rs) {
     if (which == 1) fail(SEM_EINVAL, "FDM: the x step is taken on the subtrahend only");
-    if (which == 2 && ys) mf32_launch_x<P, true, 2, true>(c, L, r, rs, z, s, nv);
-    else if (which == 2) mf32_launch_x<P, true, 2, false>(c, L, r, rs, z, s, nv);
-    else mf32_launch_x<P, true, 0, false>(c, L, r, rs, z, s, nv);
+    if (xf) {
+      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, true>(c, L, r, rs, z, s, nv);
+      else if (which == 2) mf32_launch_x<P, true, 2, false, true>(c, L, r, rs, z, s, nv);
+      else mf32_launch_x<P, true, 0, false, true>(c, L, r, rs, z, s, nv);
+    } else {
+      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, false>(c, L, r, rs, z, s, nv);
+      else if (which == 2) mf32_launch_x<P, true, 2, false, false>(c, L, r, rs, z, s, nv);
+      else mf32_launch_x<P, true, 0, false, false>(c, L, r, rs, z, s, nv);
+    }
   } else {
-    if (which == 1 && ys) mf32_launch_x<P, false, 1, true>(c, L, r, rs, z, s, nv);
-    else if (which == 1) mf32_launch_x<P, false, 1, false>(c, L, r, rs, z, s, nv);
-    else mf32_launch_x<P, false, 0, false>(c, L, r, rs, z, s, nv);
+    if (xf) mf32_launch_x<P, false, 0, false, true>(c, L, r, rs, z, s, nv);
+    else if (which == 1 && ys) mf32_launch_x<P, false, 1, true, false>(c, L, r, rs, z, s, nv);
+    else if (which == 1) mf32_launch_x<P, false, 1, false, false>(c, L, r, rs, z, s, nv);
+    else mf32_launch_x<P, false, 0, false, false>(c, L, r, rs, z, s, nv);
   }
 }
 

@@ -250,6 +250,7 @@ struct Ctx {
   int fdm_mf32_chain = 1; // elements per wavefront there (1 or 2), next one's loads ahead
   bool fdm_xstep = true;  // that kernel takes the x step of A's gather-scatter as it reads
   bool fdm_ystep = true;  // ... and the y step as well (A's gather-scatter takes only z)
+  bool fdm_xfaces = true;  // ... and sums its output's x-faces inside each workgroup
 };
 
 // ---------------------------------------------------------------------------

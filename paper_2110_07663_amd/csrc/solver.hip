@@ -351,6 +351,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_xstep = !(fxs && fxs[0] == '0');
   const char *fys = getenv("SEM_FDM_YSTEP");
   c.fdm_ystep = !(fys && fys[0] == '0');
+  const char *fxf = getenv("SEM_FDM_XFACES");
+  c.fdm_xfaces = !(fxf && fxf[0] == '0');
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +496,15 @@ static bool fdm_takes_y_step(const Ctx &c, const Level &L) {
   return fdm_takes_x_step<T>(c, L) && c.fdm_ystep;
 }
 
+// Whether the FP32 matrix-core RAS kernel sums the x-faces its workgroup
+// shares (four consecutive elements along x) before it stores
+template <typename T>
+static bool fdm_sums_x_faces(const Ctx &c, const Level &L) {
+  return sizeof(T) == 4 && c.fdm_xfaces && c.fdm_mf32 && c.opts.smoother == SEM_SMOOTH_RAS &&
+         c.fdm_prec != SEM_BF16 && c.fdm_prec != SEM_F16 && !L.coarse && L.gs_struct &&
+         L.nex % 4 == 0 && L.E % 4 == 0 && fdm_mf32_supported(c, L.p);
+}
+
 // A u with the x step (and, when the smoother takes it, the y step) of the
 // gather-scatter left to the reader
 template <typename T>
@@ -527,19 +538,19 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
     for (int k = 0; k < nv; ++k) launch_scale<T>(L.nloc, dinv, r + k * L.nloc, z + k * L.nloc, s);
     return;
   }
+  // S's output may leave the x step of its gather-scatter to a reader (xd),
+  // or arrive with the x-faces inside each FDM workgroup summed
+  const bool defer = !asm_mode && xd && L.gs_struct && L.xdefer &&
+                     cheb_can_defer_x<T>(L.N, L.nloc * nv, {z});
+  const bool fxf = !asm_mode && !defer && !mfma && (xin & 3) != 1 && fdm_sums_x_faces<T>(c, L);
   {
     ProfScope ps(c, L, SEM_PROF_FDM, s);
-    bool mma = false;
     if constexpr (sizeof(T) == 4) {
-      if (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16) {
-        launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s, nv);
-        mma = true;
-      }
+      if (mfma) launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s, nv);
     }
-    if (!mma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs, xin);
+    if (!mfma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs, xin | (fxf ? 8 : 0));
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
-  const bool defer = xd && L.gs_struct && L.xdefer && cheb_can_defer_x<T>(L.N, L.nloc * nv, {z});
   if (defer) {
     xd->on = true;
     xd->nex = L.nex;
@@ -553,7 +564,7 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
     xd->bc3 = L.bc[3];
   }
   ProfScope ps(c, L, sizeof(T) == 8 ? SEM_PROF_GS64 : SEM_PROF_GS32, s);
-  launch_gs<T>(L, z, s, nv, false, defer, defer && L.ydefer);
+  launch_gs<T>(L, z, s, nv, fxf, defer, defer && L.ydefer);
 }
 
 // Algorithm 2 read as a correction: x <- x + e (x_zero: x <- e)
