@@ -135,6 +135,55 @@ __global__ void k_coarse_to_global(CoarseGrid g, const double *__restrict__ bl,
   bg[t] = bl[((ez * g.ney + ey) * g.nex + ex) * 8 + q];
 }
 
+// b_g[node] = the sum of the node's copies in b_L as the restriction leaves
+// it (before its gather-scatter), in FP64, the elements in increasing index
+// order; 0 on Dirichlet nodes.  Also clears the grid-barrier state.
+template <typename T>
+__global__ void k_coarse_sum_to_global(CoarseGrid g, const T *__restrict__ bl,
+                                       double *__restrict__ bg, unsigned *bar, int *aborted) {
+  const int64_t n = g.nx * g.ny * g.nz;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t == 0 && blockIdx.y == 0) {
+    *bar = 0u;
+    *aborted = 0;
+  }
+  if (t >= n) return;
+  bl += blockIdx.y * (int64_t)g.nex * g.ney * g.nez * 8;  // right side blockIdx.y
+  bg += blockIdx.y * n;
+  const int64_t x = t % g.nx, y = (t / g.nx) % g.ny, z = t / (g.nx * g.ny);
+  double acc = 0.0;
+  if (!cg_dirichlet(g, x, y, z)) {
+    for (int64_t ez = z - 1; ez <= z; ++ez) {
+      if (ez < 0 || ez >= g.nez) continue;
+      for (int64_t ey = y - 1; ey <= y; ++ey) {
+        if (ey < 0 || ey >= g.ney) continue;
+        for (int64_t ex = x - 1; ex <= x; ++ex) {
+          if (ex < 0 || ex >= g.nex) continue;
+          const int q = (int)((z - ez) * 4 + (y - ey) * 2 + (x - ex));
+          acc += (double)bl[((ez * g.ney + ey) * g.nex + ex) * 8 + q];
+        }
+      }
+    }
+  }
+  bg[t] = acc;
+}
+
+static void launch_to_global(const CoarseSolver &S, const CoarseGrid &g, const double *bl,
+                             CoarseRhs u, int nv, hipStream_t s) {
+  const dim3 grid((unsigned)((S.n + 255) / 256), (unsigned)nv);
+  if (!u.p) {
+    hipLaunchKernelGGL(k_coarse_to_global, grid, dim3(256), 0, s, g, bl, S.b, S.counter + 32,
+                       &S.sc->aborted);
+  } else if (u.f32) {
+    hipLaunchKernelGGL(k_coarse_sum_to_global<float>, grid, dim3(256), 0, s, g,
+                       (const float *)u.p, S.b, S.counter + 32, &S.sc->aborted);
+  } else {
+    hipLaunchKernelGGL(k_coarse_sum_to_global<double>, grid, dim3(256), 0, s, g,
+                       (const double *)u.p, S.b, S.counter + 32, &S.sc->aborted);
+  }
+  SEM_LAUNCH("k_coarse_to_global");
+}
+
 __device__ inline double stencil_apply(const CoarseGrid &g, const double *__restrict__ St,
                                        const double *__restrict__ u, int64_t t, int64_t n) {
   int64_t x = t % g.nx, y = (t / g.nx) % g.ny, z = t / (g.nx * g.ny);
@@ -665,13 +714,11 @@ static void ensure_graph(Ctx &c) {
 
 // one right side: bl (consistent, masked E-vector of the coarsest level) -> xl
 static void coarse_solve_one(Ctx &c, Level &C, double tol, int maxit, hipStream_t s,
-                             const double *bl, double *xl) {
+                             const double *bl, double *xl, CoarseRhs u) {
   CoarseSolver &S = *c.cs;
   CoarseGrid g = cgrid(c);
   CgPtrs P = ptrs(c);
-  hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n)), dim3(256), 0, s, g, bl, S.b,
-                     S.counter + 32, &S.sc->aborted);
-  SEM_LAUNCH("k_coarse_to_global");
+  launch_to_global(S, g, bl, u, 1, s);
   if (!c.capturing && S.persistent) {
     GridSync gs;
     gs.count = S.counter + 32;
@@ -750,21 +797,23 @@ static void coarse_solve_one(Ctx &c, Level &C, double tol, int maxit, hipStream_
 // solve on the coarsest level for nv right sides: C.d_b (consistent, masked
 // E-vectors, nloc apart) -> c.cx.  The exact solve takes all right sides in one
 // pair of sweeps; the iterative one solves them in turn.
-void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv) {
+void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv,
+                            CoarseRhs u) {
   CoarseSolver &S = *c.cs;
   if (nv > c.nvmax) fail(SEM_EINVAL, "coarse solve: more right sides than were set up");
   if (S.direct) {  // exact: no iteration, no host interaction (also inside a recorded graph)
     CoarseGrid g = cgrid(c);
-    hipLaunchKernelGGL(k_coarse_to_global, dim3(nb(S.n), (unsigned)nv), dim3(256), 0, s, g, C.d_b,
-                       S.b, S.counter + 32, &S.sc->aborted);
-    SEM_LAUNCH("k_coarse_to_global");
+    launch_to_global(S, g, C.d_b, u, nv, s);
     coarse_direct_apply(S, g.nx, g.ny, g.nz, S.b, S.x, s, nv);
     if (!c.capturing) c.last_coarse_iters = 0;
     launch_gather(c, C, S.x, c.cx, s, nv, S.n);
     return;
   }
-  for (int v = 0; v < nv; ++v)
-    coarse_solve_one(c, C, tol, maxit, s, C.d_b + v * C.nloc, c.cx + v * C.nloc);
+  for (int v = 0; v < nv; ++v) {
+    CoarseRhs uv = u;
+    if (u.p) uv.p = (const char *)u.p + (size_t)v * C.nloc * (u.f32 ? sizeof(float) : sizeof(double));
+    coarse_solve_one(c, C, tol, maxit, s, C.d_b + v * C.nloc, c.cx + v * C.nloc, uv);
+  }
 }
 
 void coarse_release(CoarseSolver &S) {

@@ -251,6 +251,7 @@ struct Ctx {
   bool fdm_xstep = true;  // that kernel takes the x step of A's gather-scatter as it reads
   bool fdm_ystep = true;  // ... and the y step as well (A's gather-scatter takes only z)
   bool fdm_xfaces = true;  // ... and sums its output's x-faces inside each workgroup
+  bool coarse_sum = true;  // the assembled coarse solve sums the restricted copies itself
 };
 
 // ---------------------------------------------------------------------------
@@ -398,7 +399,15 @@ void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hip
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);
 void coarse_setup(Ctx &c, Level &C, hipStream_t s);
-void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv = 1);
+// The coarse right side as the restriction leaves it, before its
+// gather-scatter (p null: C.d_b, assembled): the mapping to the global
+// numbering then sums the copies of each node itself.
+struct CoarseRhs {
+  const void *p = nullptr;
+  bool f32 = false;
+};
+void coarse_solve_assembled(Ctx &c, Level &C, double tol, int maxit, hipStream_t s, int nv = 1,
+                            CoarseRhs u = {});
 void coarse_release(CoarseSolver &S);
 size_t coarse_direct_bytes(int64_t nx, int64_t ny, int64_t nz, bool f32);
 void coarse_direct_setup(CoarseSolver &S, int64_t nx, int64_t ny, int64_t nz, hipStream_t s);

@@ -353,6 +353,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_ystep = !(fys && fys[0] == '0');
   const char *fxf = getenv("SEM_FDM_XFACES");
   c.fdm_xfaces = !(fxf && fxf[0] == '0');
+  const char *csm = getenv("SEM_COARSE_SUM");
+  c.coarse_sum = !(csm && csm[0] == '0');
 }
 
 // ---------------------------------------------------------------------------
@@ -623,15 +625,17 @@ static void host_scalars(Ctx &c, const void *dev, size_t bytes, hipStream_t s) {
   SEM_HIP(hipStreamSynchronize(s));
 }
 
-// coarse Jacobi-PCG from x = 0: C.d_b -> c.cx (all scalars on the device)
-static void coarse_solve(Ctx &c, Level &C, hipStream_t s, int nv = 1) {
+// coarse Jacobi-PCG from x = 0: C.d_b -> c.cx (all scalars on the device);
+// u.p: the right side as the restriction left it (assembled solver only)
+static void coarse_solve(Ctx &c, Level &C, hipStream_t s, int nv = 1, CoarseRhs u = {}) {
   const double tol = c.opts.coarse_tol;
   const int maxit = c.opts.coarse_maxit;
   ProfScope ps(c, C, SEM_PROF_COARSE, s);
   if (coarse_assembled_ok(c, C)) {
-    coarse_solve_assembled(c, C, tol, maxit, s, nv);
+    coarse_solve_assembled(c, C, tol, maxit, s, nv, u);
     return;
   }
+  if (u.p) fail(SEM_EINVAL, "coarse solve: the right side must be assembled");
   if (nv != 1) fail(SEM_EUNSUPPORTED, "several right sides need the assembled p = 1 coarse solve");
   DevScalars init{};
   init.tol2 = tol * tol;
@@ -667,14 +671,26 @@ static void coarse_solve(Ctx &c, Level &C, hipStream_t s, int nv = 1) {
   }
 }
 
-// one V-cycle of Algorithm 1 from x = 0 on level l (levels l.. in precision T)
+// Whether level C's right side may reach the coarse solve as the restriction
+// leaves it: the assembled solver's mapping to its global numbering then sums
+// the copies of each node (no gather-scatter, no FP64 copy on the level)
+static bool coarse_sums_restricted(const Ctx &c, const Level &C) {
+  return c.coarse_sum && C.coarse && coarse_assembled_ok(c, C);
+}
+
+// one V-cycle of Algorithm 1 from x = 0 on level l (levels l.. in precision T);
+// unassembled: the coarse level's right side is not yet assembled
 template <typename T>
-static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1) {
+static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1, bool unassembled = false) {
   Level &L = c.lev[l];
   const int64_t n = L.nloc * nv;
   if (L.coarse) {
-    if constexpr (sizeof(T) == 4) launch_copy_cvt_f2d(n, L.f_b, L.d_b, s);
-    coarse_solve(c, L, s, nv);
+    if (unassembled) {
+      coarse_solve(c, L, s, nv, CoarseRhs{Vec<T>::b(L), sizeof(T) == 4});
+    } else {
+      if constexpr (sizeof(T) == 4) launch_copy_cvt_f2d(n, L.f_b, L.d_b, s);
+      coarse_solve(c, L, s, nv);
+    }
     if constexpr (sizeof(T) == 4)
       launch_copy_cvt_d2f(n, c.cx, L.f_x, s);
     else
@@ -683,19 +699,20 @@ static void vcycle_level(Ctx &c, int l, hipStream_t s, int nv = 1) {
   }
   Level &C = c.lev[l + 1];
   T *b = Vec<T>::b(L), *x = Vec<T>::x(L), *w = Vec<T>::w(L);
+  const bool csum = coarse_sums_restricted(c, C);
   if (L.K == 0) {  // smoother without acceleration: additive cycle, x = S b + P V(P^T b)
     opS<T>(c, L, b, x, s, nv);
     launch_restrict<T>(L, C, b, Vec<T>::b(C), s, nv);
-    launch_gs<T>(C, Vec<T>::b(C), s, nv);
-    vcycle_level<T>(c, l + 1, s, nv);
+    if (!csum) launch_gs<T>(C, Vec<T>::b(C), s, nv);
+    vcycle_level<T>(c, l + 1, s, nv, csum);
     launch_prolong<T>(L, C, Vec<T>::x(C), x, s, nv);
     return;
   }
   chebyshev<T>(c, L, b, x, true, s, nv);                // x = M b
   opA<T>(c, L, x, w, s, nv);                            // r_C = P^T (b - A x)
   launch_restrict<T>(L, C, w, Vec<T>::b(C), s, nv, b);
-  launch_gs<T>(C, Vec<T>::b(C), s, nv);
-  vcycle_level<T>(c, l + 1, s, nv);                     // e_C
+  if (!csum) launch_gs<T>(C, Vec<T>::b(C), s, nv);
+  vcycle_level<T>(c, l + 1, s, nv, csum);               // e_C
   launch_prolong<T>(L, C, Vec<T>::x(C), x, s, nv);      // x += P e_C
   chebyshev<T>(c, L, b, x, false, s, nv);               // post-smoothing
 }

@@ -200,13 +200,35 @@ def test_solve_to_tolerance(krylov):
     # Arnoldi gives lambda~ = 41.9 and 14.6 for RAS here
     (4, 7, (7, 3, 1), "ras", (1,) * 6, "shift", [42.0, 14.6]),
 ])
-def test_vcycle_direct_coarse_matches_oracle(shape, p, sched, smoother, bc, mesh, lam):
-    """Exact block-tridiagonal coarse solve against the oracle's dense solve."""
+@pytest.mark.parametrize("csum", ["1", "0"])
+def test_vcycle_direct_coarse_matches_oracle(monkeypatch, csum, shape, p, sched, smoother, bc,
+                                             mesh, lam):
+    """Exact block-tridiagonal coarse solve against the oracle's dense solve;
+    the coarse right side reaches it as the restriction leaves it (its copies
+    summed by the mapping to the global numbering) or assembled first
+    (SEM_COARSE_SUM=0)."""
+    monkeypatch.setenv("SEM_COARSE_SUM", csum)
     P = Pair(shape, p, mesh=mesh, schedule=sched, smoother=smoother, bc=bc, coarse="dense",
              lambda_override=lam)
     for seed in (51, 52):
         g, o = P.random_local(seed)
         assert rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o)) < 1e-12
+
+
+@pytest.mark.parametrize("csum", ["1", "0"])
+@pytest.mark.parametrize("prec", [sem.F64, sem.F32])
+def test_vcycle_pcg_coarse_summed_right_side(monkeypatch, csum, prec):
+    """Coarse Jacobi-PCG (fixed count) with the restricted right side summed
+    by its mapping or assembled first: same V-cycle as the oracle's with the
+    same coarse iteration count; mixed faces."""
+    monkeypatch.setenv("SEM_COARSE_SUM", csum)
+    P = Pair((4, 3, 3), 5, mesh="sin", schedule=(5, 3, 1), smoother="ras", coarse="pcg",
+             coarse_tol=0.0, coarse_maxit=12, bc=(1, 0, 1, 1, 0, 1), smoother_prec=prec,
+             lambda_override=[1.7, 1.9])
+    for seed in (56, 57):
+        g, o = P.random_local(seed)
+        err = rel_err(host(P.gpu.vcycle(g)), P.ora.vcycle(o))
+        assert err < (1e-12 if prec == sem.F64 else 1e-5), err
 
 
 def test_direct_coarse_falls_back_when_singular():
