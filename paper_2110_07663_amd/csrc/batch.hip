@@ -374,6 +374,10 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
 
     std::vector<LaneScalars> host_all((size_t)nctx * nrhs);
     std::vector<char> recorded(nctx, 0), recorded_lane((size_t)nctx * nrhs, 0);
+    // SEM_BATCH_RECORD_ONCE=1: keep replaying the first graph to the end (the
+    // finished lanes' kernels return at once; their problems' V-cycles still run)
+    const char *once_env = getenv("SEM_BATCH_RECORD_ONCE");
+    const bool record_once = once_env && once_env[0] == '1';
     int iterations = 0;
     while (true) {
       bool any = false;
@@ -424,6 +428,11 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
       // replay until some lane finishes
       bool changed = false;
       while (!changed && iterations < maxit) {
+        if (record_once) {
+          bool left = false;
+          for (auto &ln : lanes) left = left || ln.active;
+          if (!left) break;
+        }
         const int k = std::min(ipl, maxit - iterations);
         for (int q = 0; q < k; ++q) SEM_HIP(hipGraphLaunch(exec, s));
         iterations += k;
@@ -437,7 +446,7 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
         // the recorded graph changes only when a problem sharing its launches
         // finishes all its lanes, or a lane running on its own finishes (the
         // kernels of a finished lane of a shared problem return at once)
-        for (int i = 0; i < nctx && !changed; ++i) {
+        for (int i = 0; i < nctx && !changed && !record_once; ++i) {
           const Lane *first = &lanes[(size_t)i * nrhs];
           bool any_active = false;
           for (int k = 0; k < nrhs; ++k) any_active = any_active || first[k].active;

@@ -133,3 +133,35 @@ def test_joint_lanes_equal_lanes_in_turn(monkeypatch, shape, p, sched, sm, prec,
     assert out["1"][0] == out["0"][0]
     for a, b in zip(out["1"][1], out["0"][1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_batch_record_once_equals_rerecording(monkeypatch):
+    """Replaying the first recorded iteration to the end (SEM_BATCH_RECORD_ONCE=1:
+    finished problems keep running their V-cycles, their lane kernels return at
+    once) gives the same iterates as recording again when problems finish."""
+    import torch
+    probs = [((3, 3, 3), 5, (5, 3, 1)), ((2, 3, 2), 7, (7, 3, 1)), ((4, 2, 2), 3, (3, 1))]
+    solvers, bs = [], []
+    for shape, p, sched in probs:
+        opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
+                             batch_rhs=2)
+        xyz = wl.sampled_mesh(*shape, sem.gll_nodes(p)[0], wl.sin_map(0.05))
+        S = sem.Solver(*shape, xyz, p, p, opts=opts)
+        X = host(S.coords(0))
+        row = []
+        for fr in ((1, 1, 1), (3, 1, 2)):
+            f, _ = wl.sinusoid(*fr)
+            row.append(S.rhs(dev(f(X[0], X[1], X[2]))))
+        solvers.append(S)
+        bs.append(row)
+    out = {}
+    for once in ("0", "1"):
+        monkeypatch.setenv("SEM_BATCH_RECORD_ONCE", once)
+        xs = [[torch.zeros_like(b) for b in row] for row in bs]
+        infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=200)
+        assert all(i.converged for i in infos)
+        out[once] = ([i.iters for i in infos], [host(x) for row in xs for x in row])
+    assert out["0"][0] == out["1"][0]
+    assert len(set(out["0"][0])) > 1  # the lanes finish at different iterations
+    for a, b in zip(out["0"][1], out["1"][1]):
+        np.testing.assert_array_equal(a, b)
