@@ -113,7 +113,9 @@ template void launch_sub<float>(int64_t, const float *, const float *, float *, 
 // t read as assembled (XD::value false), or with the deferred x step of the
 // gather-scatter taken on the way (16-byte vectors VT of T; a vector never
 // straddles an element row, so only its first lane can be an i = 0 node and
-// only its last an i = p node)
+// only its last an i = p node).  The kernels that read this way take their
+// blocks in XCD-contiguous order (xcd_block), so the x-neighbour copies they
+// read mostly come from rows the same XCD reads: its own L2.
 struct XDev {
   unsigned nex, ney, N, p, vrow, vel, vside;  // vectors per row, per element, per right side
   int bc0, bc1, bc2, bc3;
@@ -178,7 +180,7 @@ __device__ inline VT read_t(const VT *__restrict__ tv, int64_t m, const XDev &f)
 template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_update(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
                               const T *__restrict__ tv, T a, T c, int xz, XDev f) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   T dk = d[t];
   x[t] = xz ? dk : x[t] + dk;
@@ -248,7 +250,7 @@ template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
                              const T *__restrict__ tv, T inv_theta, T a, T c, int xz, int last,
                              XDev f) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const T r0 = r[t];
   const T d0 = r0 * inv_theta;
@@ -297,7 +299,7 @@ template <typename T, typename XD = std::false_type>
 __global__ void k_cheb_last(int64_t n, T *__restrict__ x, const T *__restrict__ r,
                             const T *__restrict__ d, const T *__restrict__ tv, T a, T c, int xz,
                             XDev f) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const T dk = d[t];
   const T x1 = xz ? dk : x[t] + dk;
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
   const double alpha = pqv > 0.0 ? *rz / pqv : 0.0;
   double acc[1] = {0.0}, acc2 = 0.0;
   const int64_t n2 = n / 2;
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t0 = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
     double2 qv;
     if constexpr (XD::value) {
