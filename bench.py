@@ -580,7 +580,11 @@ def main():
     for _ in range(a.warmup):
         mixed.solve(b, rtol=1e-8, maxit=200)
     torch.cuda.synchronize()
-    mixed.profile(True)
+    # the timed steps record HIP events around the roofline's kernel classes
+    # only (Ax and FDM: 12 launches per iteration); the other classes are timed
+    # in extra steps afterwards, outside the timed region
+    timed_kinds = ("ax64", "ax32", "fdm")
+    mixed.profile(True, kinds=timed_kinds)
     infos = []
     t0 = time.perf_counter()
     for _ in range(a.steps):
@@ -589,6 +593,10 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     prof = mixed.profile_read()
+    mixed.profile(True, kinds=tuple(k for k in sem.PROF_NAMES if k not in timed_kinds))
+    for _ in range(max(1, min(a.steps, 3))):
+        mixed.solve(b, rtol=1e-8, maxit=200)
+    prof.update({k: v for k, v in mixed.profile_read().items() if k not in timed_kinds})
     mixed.profile(False)
     ms_step = 1e3 * t_total / a.steps
     value = L0.nglobal / (t_total / a.steps) / 1e9

@@ -240,9 +240,13 @@ sem_status sem_projection_reset(sem_ctx *ctx);
 /* Kernel timing of the finest level, for roofline reporting.  While enabled, the
  * library records a pair of HIP events on the call's stream around every launch
  * of the instrumented kernels below (finest level only; the last two classes
- * bracket whole phases), so durations are those of the kernels themselves.  Enabling clears the counters.  sem_profile_read
- * synchronises on the recorded events and returns, per class, the summed
- * duration in ms (total_ms[SEM_PROF_COUNT]) and the launch count. */
+ * bracket whole phases), so durations are those of the kernels themselves.  The
+ * events are recorded without a system-scope fence (timing only).  enable: 0
+ * off, 1 every class, otherwise a mask whose bit k + 1 records class k (fewer
+ * events, less disturbance of the timed work).  Enabling clears the counters;
+ * a negative value is SEM_EINVAL.  sem_profile_read synchronises on the
+ * recorded events and returns, per class, the summed duration in ms
+ * (total_ms[SEM_PROF_COUNT]) and the launch count. */
 typedef enum {
   SEM_PROF_AX64 = 0,   /* sum-factorised A_L, FP64 (outer Krylov operator)          */
   SEM_PROF_AX32 = 1,   /* sum-factorised A_L, FP32 (smoother operator)              */

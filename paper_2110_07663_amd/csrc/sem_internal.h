@@ -185,6 +185,7 @@ struct CoarseSolver {
 // HIP-event timing of finest-level kernels (sem_profile)
 struct Profiler {
   bool on = false;
+  unsigned kinds = ~0u;  // bit k: record class k
   struct Rec {
     int kind;
     hipEvent_t a, b;

@@ -384,9 +384,11 @@ struct Vec<float> {
 
 size_t Profiler::begin(int kind, hipStream_t s) {
   if (used == pool.size()) {
+    // timing only: no system-scope fence (cache write-back and invalidation)
+    // when an event is recorded, so the instrumented solve runs as it would
     hipEvent_t a, b;
-    SEM_HIP(hipEventCreate(&a));
-    SEM_HIP(hipEventCreate(&b));
+    SEM_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    SEM_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     pool.push_back({a, b});
   }
   Rec r{kind, pool[used].first, pool[used].second};
@@ -414,8 +416,10 @@ struct ProfScope {
   hipStream_t s;
   size_t rec = 0;
   ProfScope(const Ctx &c, const Level &L, int kind, hipStream_t st)
-      : p((c.prof && c.prof->on && !c.capturing && (L.fine || kind >= SEM_PROF_COARSE)) ? c.prof
-                                                                                        : nullptr),
+      : p((c.prof && c.prof->on && ((c.prof->kinds >> kind) & 1u) && !c.capturing &&
+           (L.fine || kind >= SEM_PROF_COARSE))
+              ? c.prof
+              : nullptr),
         s(st) {
     if (p) rec = p->begin(kind, s);
   }
@@ -1295,9 +1299,11 @@ sem_status sem_destroy(sem_ctx *ctx) {
 sem_status sem_profile(sem_ctx *ctx, int32_t enable) {
   return guarded([&] {
     if (!ctx) fail(SEM_EINVAL, "null context");
+    if (enable < 0) fail(SEM_EINVAL, "profile: negative class mask");
     if (!ctx->prof) ctx->prof = new Profiler();
     ctx->prof->reset();
     ctx->prof->on = enable != 0;
+    ctx->prof->kinds = enable == 1 ? ~0u : (unsigned)enable >> 1;
   });
 }
 

@@ -353,8 +353,16 @@ class Solver:
         check(lib().sem_vcycle(self.ctx, _ptr(r), _ptr(out), _stream()))
         return out
 
-    def profile(self, enable=True):
-        check(lib().sem_profile(self.ctx, 1 if enable else 0))
+    def profile(self, enable=True, kinds=None):
+        """Event timing of the finest level's kernel classes; kinds: names of
+        PROF_NAMES to record (None: all)."""
+        if not enable:
+            mask = 0
+        elif kinds is None:
+            mask = 1
+        else:
+            mask = sum(2 << PROF_NAMES.index(k) for k in kinds)
+        check(lib().sem_profile(self.ctx, mask))
 
     def profile_read(self):
         """{kernel class: (total ms, launches)} of the finest level since profile(True)."""

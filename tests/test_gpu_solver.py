@@ -485,3 +485,28 @@ def test_additive_vcycle_without_acceleration(smoother, sched, prec):
     L = P.ora.fine
     r = bo - L.apply_A(host(xg).reshape(bo.shape))
     assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+
+
+def test_profile_classes():
+    """Kernel-class timing: every class, or only those of the mask; a negative
+    mask is rejected."""
+    P = Pair((4, 2, 2), 5, mesh="sin", schedule=(5, 3, 1), smoother="ras", smoother_prec=sem.F32,
+             coarse="dense", oracle=False)
+    f, _ = wl.sinusoid(1, 1, 1)
+    X = host(P.gpu.coords(0))
+    import torch
+    b = P.gpu.rhs(torch.as_tensor(f(X[0], X[1], X[2])).cuda())
+    P.gpu.profile(True)
+    P.gpu.solve(b, rtol=1e-8, maxit=100)
+    allk = P.gpu.profile_read()
+    assert all(allk[k][1] > 0 for k in ("ax64", "ax32", "fdm", "gs32", "vcycle", "coarse"))
+    P.gpu.profile(True, kinds=("ax32", "fdm"))
+    P.gpu.solve(b, rtol=1e-8, maxit=100)
+    some = P.gpu.profile_read()
+    P.gpu.profile(False)
+    assert some["ax32"][1] == allk["ax32"][1] and some["fdm"][1] == allk["fdm"][1]
+    assert all(some[k][1] == 0 for k in ("ax64", "gs32", "gs64", "coarse", "vcycle"))
+    assert all(some[k][0] > 0 for k in ("ax32", "fdm"))
+    with pytest.raises(sem.SemError) as ei:
+        sem.check(sem.lib().sem_profile(P.gpu.ctx, -2))
+    assert ei.value.status == sem.SEM_EINVAL
