@@ -104,6 +104,8 @@ def test_autotuner_picks_a_converged_fast_candidate():
 
 @pytest.mark.parametrize("shape,p,sched,sm,prec,fdm,coarse", [
     ((3, 3, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO),
+    # four elements along x: the FDM and Ax sum their in-workgroup x-faces
+    ((4, 2, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO),
     ((2, 3, 3), 5, (5, 3, 1), sem.SMOOTH_RAS, sem.F32, sem.BF16, sem.COARSE_AUTO),
     ((3, 2, 2), 5, (5, 1), sem.SMOOTH_ASM, sem.F64, None, sem.COARSE_AUTO),
     ((2, 2, 3), 4, (4, 2, 1), sem.SMOOTH_JACOBI, sem.F32, None, sem.COARSE_PCG),
