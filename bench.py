@@ -521,7 +521,7 @@ def config2_mode(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     if a.mode == "cpu":

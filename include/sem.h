@@ -48,7 +48,7 @@ typedef enum {
   SEM_EHIP = -3,         /* a HIP runtime call failed (message names it)                */
   SEM_ENOCONV = -4,      /* solve stopped at maxit; x and info hold the last iterate     */
   SEM_ENAN = -5,         /* NaN/Inf met in a residual norm or an inner product          */
-  SEM_EUNSUPPORTED = -6, /* valid request this build does not implement                 */
+  SEM_EUNSUPPORTED = -6, /* valid request the library does not implement               */
   SEM_EGEOM = -7         /* non-positive Jacobian determinant (inverted element)        */
 } sem_status;
 
