@@ -378,8 +378,61 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
     // finished lanes' kernels return at once; their problems' V-cycles still run)
     const char *once_env = getenv("SEM_BATCH_RECORD_ONCE");
     const bool record_once = once_env && once_env[0] == '1';
+    // one outer iteration of every active lane, forked from `root` onto the
+    // branch streams and joined back (recorded into a graph, or launched)
+    auto enqueue_iteration = [&](hipStream_t root) {
+      SEM_HIP(hipEventRecord(bs.fork, root));
+      for (int i = 0; i < nctx; ++i) {
+        hipStream_t br = bs.st[i % nbs];
+        SEM_HIP(hipStreamWaitEvent(br, bs.fork, 0));
+        Lane *first = &lanes[(size_t)i * nrhs];
+        bool any_active = false;
+        for (int k = 0; k < nrhs; ++k) {
+          any_active = any_active || first[k].active;
+          recorded_lane[(size_t)i * nrhs + k] = first[k].active;
+        }
+        recorded[i] = any_active;
+        if (!any_active) continue;
+        if (joint[i]) {
+          lane_iteration(first, nrhs, br);  // finished lanes' own kernels return at once
+        } else {
+          for (int k = 0; k < nrhs; ++k)
+            if (first[k].active) lane_iteration(first + k, 1, br);
+        }
+      }
+      for (int q = 0; q < nbs; ++q) {
+        SEM_HIP(hipEventRecord(bs.ev[q], bs.st[q]));
+        SEM_HIP(hipStreamWaitEvent(root, bs.ev[q], 0));
+      }
+    };
+    // SEM_BATCH_GRAPH=0: launch every iteration's kernels directly (the same
+    // kernels on the same streams, no recording)
+    const char *graph_env = getenv("SEM_BATCH_GRAPH");
+    const bool use_graph = !(graph_env && graph_env[0] == '0');
     int iterations = 0;
-    while (true) {
+    while (!use_graph) {
+      bool any = false;
+      for (auto &ln : lanes) any = any || ln.active;
+      if (!any || iterations >= maxit) break;
+      const int k = std::min(ipl, maxit - iterations);
+      for (auto *c : cs) c->capturing = true;  // no host interaction inside
+      try {
+        for (int q = 0; q < k; ++q) enqueue_iteration(s);
+      } catch (...) {
+        for (auto *c : cs) c->capturing = false;
+        throw;
+      }
+      for (auto *c : cs) c->capturing = false;
+      iterations += k;
+      poll_lanes(cs, nrhs, host_all, s);
+      for (auto &ln : lanes)
+        if (ln.active) {
+          const LaneScalars &h = host_all[(size_t)ln.ci * nrhs + ln.k];
+          if (!(h.rr == h.rr)) fail(SEM_ENAN, "NaN in a batched solve");
+          if (h.done) ln.active = false;
+        }
+    }
+    while (use_graph) {
       bool any = false;
       for (auto &ln : lanes) any = any || ln.active;
       if (!any || iterations >= maxit) break;
@@ -388,29 +441,7 @@ extern "C" sem_status sem_batch_solve(int32_t nctx, sem_ctx *const *ctxs, int32_
       SEM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        SEM_HIP(hipEventRecord(bs.fork, cap));
-        for (int i = 0; i < nctx; ++i) {
-          hipStream_t br = bs.st[i % nbs];
-          SEM_HIP(hipStreamWaitEvent(br, bs.fork, 0));
-          Lane *first = &lanes[(size_t)i * nrhs];
-          bool any_active = false;
-          for (int k = 0; k < nrhs; ++k) {
-            any_active = any_active || first[k].active;
-            recorded_lane[(size_t)i * nrhs + k] = first[k].active;
-          }
-          recorded[i] = any_active;
-          if (!any_active) continue;
-          if (joint[i]) {
-            lane_iteration(first, nrhs, br);  // finished lanes' own kernels return at once
-          } else {
-            for (int k = 0; k < nrhs; ++k)
-              if (first[k].active) lane_iteration(first + k, 1, br);
-          }
-        }
-        for (int q = 0; q < nbs; ++q) {
-          SEM_HIP(hipEventRecord(bs.ev[q], bs.st[q]));
-          SEM_HIP(hipStreamWaitEvent(cap, bs.ev[q], 0));
-        }
+        enqueue_iteration(cap);
       } catch (...) {
         (void)hipStreamEndCapture(cap, &graph);
         if (graph) (void)hipGraphDestroy(graph);

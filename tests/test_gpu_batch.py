@@ -140,7 +140,8 @@ def test_joint_lanes_equal_lanes_in_turn(monkeypatch, shape, p, sched, sm, prec,
 def test_batch_record_once_equals_rerecording(monkeypatch):
     """Replaying the first recorded iteration to the end (SEM_BATCH_RECORD_ONCE=1:
     finished problems keep running their V-cycles, their lane kernels return at
-    once) gives the same iterates as recording again when problems finish."""
+    once), or launching every iteration directly (SEM_BATCH_GRAPH=0), gives the
+    same iterates as recording again when problems finish."""
     import torch
     probs = [((3, 3, 3), 5, (5, 3, 1)), ((2, 3, 2), 7, (7, 3, 1)), ((4, 2, 2), 3, (3, 1))]
     solvers, bs = [], []
@@ -157,13 +158,15 @@ def test_batch_record_once_equals_rerecording(monkeypatch):
         solvers.append(S)
         bs.append(row)
     out = {}
-    for once in ("0", "1"):
+    for mode, once, graph in (("rerecord", "0", "1"), ("once", "1", "1"), ("direct", "0", "0")):
         monkeypatch.setenv("SEM_BATCH_RECORD_ONCE", once)
+        monkeypatch.setenv("SEM_BATCH_GRAPH", graph)
         xs = [[torch.zeros_like(b) for b in row] for row in bs]
         infos = sem.batch_solve(solvers, bs, xs, rtol=1e-8, maxit=200)
         assert all(i.converged for i in infos)
-        out[once] = ([i.iters for i in infos], [host(x) for row in xs for x in row])
-    assert out["0"][0] == out["1"][0]
-    assert len(set(out["0"][0])) > 1  # the lanes finish at different iterations
-    for a, b in zip(out["0"][1], out["1"][1]):
-        np.testing.assert_array_equal(a, b)
+        out[mode] = ([i.iters for i in infos], [host(x) for row in xs for x in row])
+    assert len(set(out["rerecord"][0])) > 1  # the lanes finish at different iterations
+    for mode in ("once", "direct"):
+        assert out[mode][0] == out["rerecord"][0], mode
+        for a, b in zip(out[mode][1], out["rerecord"][1]):
+            np.testing.assert_array_equal(a, b)
