@@ -15,13 +15,16 @@
 // matrix core does four per lane in the same time, at the cost of padding the
 // modes to a multiple of 4.
 //
-// One wavefront per element, four per workgroup, no workgroup barriers.  The
-// first pass reads its x-lines straight from the E-vector (the element's own
-// row and one node of each x-neighbour); every later pass reads lines that
-// the previous pass wrote contiguously into the wave's LDS buffer (16-byte
-// reads).  The z pass divides by the eigenvalue sums of eq. 9 in registers
-// and goes straight back along z; the backward passes form only the nodes
-// RAS keeps, and the last one writes the element's rows times the RAS weight.
+// One wavefront per element, four per workgroup; the waves of a workgroup
+// meet at a barrier only in the form that sums their shared x-faces before
+// the store (XF).  The first pass reads its x-lines straight from the
+// E-vector through range-checked buffer loads (the element's own row and one
+// node of each x-neighbour; zeros outside the domain); every later pass reads
+// lines that the previous pass wrote contiguously into the wave's LDS buffer
+// (16-byte reads).  The z pass divides by the eigenvalue sums of eq. 9 in
+// registers and goes straight back along z; the backward passes form only the
+// nodes RAS keeps, and the last one writes the element's rows times the RAS
+// weight.
 #include "sem_internal.h"
 
 namespace sem {
