@@ -29,7 +29,10 @@ Module map (paper passage each one follows):
             used for the Arnoldi start vector.
   hierarchy convenience wrapper assembling the above into a solver.
 
-Parity unpinned: the V-cycle output for a real (p, p_c, ..., 1) schedule has
-no closed form; only its special cases (schedule (p, p), two-level contraction)
-and the final solve are pinned.
+The V-cycle output for a real (p, p_c, ..., 1) schedule has no closed form;
+it is pinned through its special cases (schedule (p, p) is the exact solve,
+two-level contraction), its matrix composition from the separately pinned
+smoother, transfers and dense coarse solve (the multiplicative cycle of
+Algorithm 1 and the additive cycle of the unaccelerated smoothers), and the
+final solve.
 """

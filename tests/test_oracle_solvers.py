@@ -273,3 +273,40 @@ def test_unaccelerated_smoother_is_plain_schwarz():
     b = L.num.mask * L.num.Q(rng.standard_normal(L.num.n))
     x = L.num.mask * L.num.Q(rng.standard_normal(L.num.n))
     np.testing.assert_allclose(L.smooth(b, x), L.apply_S(b - L.apply_A(x)), atol=1e-14)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ras", "asm"])
+def test_vcycle_is_the_two_grid_composition(smoother):
+    """Algorithm 1 with Chebyshev smoothing (order 2) over three levels, as
+    matrices on the free nodes: with Q_l the smoother from a zero start (its
+    correction is Q_l applied to the residual), C_l = P_l M_{l+1} P_l^T the
+    coarse-grid correction and M_2 = A_2^{-1}, one V-cycle from x = 0 is
+        M_l = Q_l + (I - Q_l A_l) Q_l + (I - Q_l A_l) C_l (I - A_l Q_l)
+    (pre-smooth, correct, post-smooth).  A dropped residual update, a
+    correction with the wrong sign or in the wrong place fails this."""
+    S = _small_solver([4, 2, 1], smoother=smoother, coarse="dense", lam=[2.2, 2.4])
+    Ls = S.levels
+    frees = [np.nonzero(L.num.mask_global > 0)[0] for L in Ls]
+
+    def columns(apply, num_in, num_out, free_in, free_out):
+        out = np.zeros((free_out.size, free_in.size))
+        for j, g in enumerate(free_in):
+            e = np.zeros(num_in.n)
+            e[g] = 1.0
+            out[:, j] = num_out.to_global(apply(num_in.Q(e)))[free_out]
+        return out
+
+    A2, _ = _dense_operator(S, level=2)
+    M = np.linalg.inv(A2)
+    for l in (1, 0):
+        L, C = Ls[l], Ls[l + 1]
+        f, fc = frees[l], frees[l + 1]
+        A, _ = _dense_operator(S, level=l)
+        Q = columns(lambda v: L.smooth(v, None), L.num, L.num, f, f)
+        R = columns(lambda v: mg.restrict(L.num, C.num, L.J_to_coarse, v), L.num, C.num, f, fc)
+        P = columns(lambda v: mg.prolong(L.J_to_coarse, v), C.num, L.num, fc, f)
+        np.testing.assert_allclose(R, P.T, atol=1e-13)
+        I = np.eye(f.size)
+        M = Q + (I - Q @ A) @ Q + (I - Q @ A) @ (P @ M @ R) @ (I - A @ Q)
+    Mv = columns(S.vcycle, Ls[0].num, Ls[0].num, frees[0], frees[0])
+    np.testing.assert_allclose(Mv, M, atol=1e-10 * np.abs(M).max())
