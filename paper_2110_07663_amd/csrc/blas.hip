@@ -9,6 +9,7 @@
 // E-vector coarse CG (a coarsest level other than the assembled p = 1 one)
 // keeps the single-launch form, where the last block to finish, found with a
 // ticket counter, sums them (last_block_sum).
+#include <algorithm>
 #include <initializer_list>
 #include <type_traits>
 
@@ -18,6 +19,20 @@ namespace sem {
 
 static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Streams read or written once per pass may go non-temporal (NT): they then
+// do not displace the lines that a kernel's neighbour reads hit in L2 (the
+// deferred-step forms below: 1-2 ms per solve on the 32^3, p = 7 benchmark).
+template <bool NT, typename T>
+__device__ inline T ldn(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ inline void stn(T *p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // 16-byte vectors (4 floats or 2 doubles) for the pointwise kernels: one load
 // or store instruction per operand and thread; arithmetic acts per element
@@ -246,15 +261,15 @@ template void launch_cheb_update<float>(int64_t, float *, float *, float *, cons
 // and S are linear, so the caller applies them to r_0 and this pass scales
 // (tv = S A r_0).  x += d_0; r -= tv / theta; d = a d_0 + c r; with `last` the
 // closing x += d as well (r and d then unwritten).  xz: x is zero on entry.
-template <typename T, typename XD = std::false_type>
+template <typename T, typename XD = std::false_type, bool NTL = false>
 __global__ void k_cheb_first(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ d,
                              const T *__restrict__ tv, T inv_theta, T a, T c, int xz, int last,
                              XDev f) {
   int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const T r0 = r[t];
+  const T r0 = ldn<NTL>(r + t);
   const T d0 = r0 * inv_theta;
-  const T x1 = xz ? d0 : x[t] + d0;
+  const T x1 = xz ? d0 : ldn<NTL>(x + t) + d0;
   const T rn = r0 - read_t<XD>(tv, t, f) * inv_theta;
   const T dn = a * d0 + c * rn;
   if (last) {
@@ -272,10 +287,10 @@ void launch_cheb_first(int64_t n, T *x, T *r, T *d, const T *t, T inv_theta, T a
   if (vec16_ok<T>(n, {x, r, d, t})) {
     using VT = typename V16<T>::type;
     const int64_t m = n / (int64_t)(16 / sizeof(T));
-    if (xd.on)
-      hipLaunchKernelGGL((k_cheb_first<VT, std::true_type>), dim3(nb(m, 256)), dim3(256), 0, s, m,
-                         (VT *)x, (VT *)r, (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c,
-                         (int)x_zero, (int)last, f);
+    if (xd.on)  // r and x streamed non-temporally
+      hipLaunchKernelGGL((k_cheb_first<VT, std::true_type, true>), dim3(nb(m, 256)), dim3(256), 0,
+                         s, m, (VT *)x, (VT *)r, (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a,
+                         (VT)c, (int)x_zero, (int)last, f);
     else
       hipLaunchKernelGGL((k_cheb_first<VT>), dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
                          (VT *)r, (VT *)d, (const VT *)t, (VT)inv_theta, (VT)a, (VT)c,
@@ -295,17 +310,17 @@ template void launch_cheb_first<float>(int64_t, float *, float *, float *, const
 
 // the last pass of the loop and the closing x += d in one: r and d are not
 // needed afterwards, so only x is written (same roundings as the two passes)
-template <typename T, typename XD = std::false_type>
+template <typename T, typename XD = std::false_type, bool NTL = false, bool NTS = false>
 __global__ void k_cheb_last(int64_t n, T *__restrict__ x, const T *__restrict__ r,
                             const T *__restrict__ d, const T *__restrict__ tv, T a, T c, int xz,
                             XDev f) {
   int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const T dk = d[t];
-  const T x1 = xz ? dk : x[t] + dk;
-  const T rn = r[t] - read_t<XD>(tv, t, f);
+  const T dk = ldn<NTL>(d + t);
+  const T x1 = xz ? dk : ldn<NTL>(x + t) + dk;
+  const T rn = ldn<NTL>(r + t) - read_t<XD>(tv, t, f);
   const T dn = a * dk + c * rn;
-  x[t] = dn + x1;
+  stn<NTS>(x + t, dn + x1);
 }
 template <typename T>
 void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, T c, hipStream_t s,
@@ -314,10 +329,10 @@ void launch_cheb_last(int64_t n, T *x, const T *r, const T *d, const T *t, T a, 
   if (vec16_ok<T>(n, {x, r, d, t})) {
     using VT = typename V16<T>::type;
     const int64_t m = n / (int64_t)(16 / sizeof(T));
-    if (xd.on)
-      hipLaunchKernelGGL((k_cheb_last<VT, std::true_type>), dim3(nb(m, 256)), dim3(256), 0, s, m,
-                         (VT *)x, (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c,
-                         (int)x_zero, f);
+    if (xd.on)  // d, x, r and the new x streamed non-temporally
+      hipLaunchKernelGGL((k_cheb_last<VT, std::true_type, true, true>), dim3(nb(m, 256)),
+                         dim3(256), 0, s, m, (VT *)x, (const VT *)r, (const VT *)d, (const VT *)t,
+                         (VT)a, (VT)c, (int)x_zero, f);
     else
       hipLaunchKernelGGL((k_cheb_last<VT>), dim3(nb(m, 256)), dim3(256), 0, s, m, (VT *)x,
                          (const VT *)r, (const VT *)d, (const VT *)t, (VT)a, (VT)c, (int)x_zero,
@@ -435,24 +450,27 @@ __device__ inline bool last_block_sum(double (&acc)[ND], double *partials, unsig
 // every block serialises on one address (about 45 ns a block), which at 1024
 // blocks costs more than the second launch.
 template <int ND>
-__device__ inline void block_partials(double (&acc)[ND], double *partials) {
+__device__ inline void block_partials(double (&acc)[ND], double *partials, int stride = 8) {
   __shared__ double sh[ND][256];
   block_reduce<ND>(acc, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int j = 0; j < ND; ++j) partials[blockIdx.x * 8 + j] = sh[j][0];
+    for (int j = 0; j < ND; ++j) partials[blockIdx.x * stride + j] = sh[j][0];
   }
 }
+// block b's partials at partials[b * stride + j]: stride 8 for up to eight
+// sums over at most kRedBlocks blocks; a single sum may pack them densely
+// (stride 1) over up to 8 kRedBlocks blocks
 template <int ND>
 __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict__ partials,
-                                                double *out) {
+                                                double *out, int stride) {
   __shared__ double sh[ND][256];
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) {
 #pragma unroll
-    for (int j = 0; j < ND; ++j) acc[j] += partials[b * 8 + j];
+    for (int j = 0; j < ND; ++j) acc[j] += partials[b * stride + j];
   }
   block_reduce<ND>(acc, sh);
   if (threadIdx.x == 0) {
@@ -461,16 +479,20 @@ __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict
   }
 }
 static void launch_finish(int nd, unsigned nblocks, const double *partials, double *out,
-                          hipStream_t s) {
+                          hipStream_t s, int stride = 8) {
+  if (stride != 8 && (nd != 1 || stride != 1 || nblocks > 8u * kRedBlocks))
+    fail(SEM_EINVAL, "reduction partials: dense packing holds one sum");
+  if (stride == 8 && nblocks > (unsigned)kRedBlocks)
+    fail(SEM_EINVAL, "reduction partials: too many blocks");
   switch (nd) {
-    case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 3: hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 5: hipLaunchKernelGGL(k_finish<5>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 6: hipLaunchKernelGGL(k_finish<6>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    case 7: hipLaunchKernelGGL(k_finish<7>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
-    default: hipLaunchKernelGGL(k_finish<8>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out); break;
+    case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 3: hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 5: hipLaunchKernelGGL(k_finish<5>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 6: hipLaunchKernelGGL(k_finish<6>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    case 7: hipLaunchKernelGGL(k_finish<7>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
+    default: hipLaunchKernelGGL(k_finish<8>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
   }
   SEM_LAUNCH("k_finish");
 }
@@ -569,14 +591,27 @@ __device__ inline void st2(double *p, int64_t t, double2 v) {
 }
 // XD: q arrives without the x and y steps of its gather-scatter, which are
 // taken as it is read (the Chebyshev updates' read_t)
-template <typename V, typename WT, typename XD = std::false_type>
+// NT-capable reads of the 16-byte vector form
+template <bool NT>
+__device__ inline double2 ld2n(const double *p, int64_t t) {
+  using VT = V16<double>::type;
+  const VT v = ldn<NT>(reinterpret_cast<const VT *>(p) + t);
+  return make_double2(v[0], v[1]);
+}
+template <bool NT>
+__device__ inline double2 ld2n(const float *p, int64_t t) {
+  typedef float F2 __attribute__((ext_vector_type(2)));
+  const F2 v = ldn<NT>(reinterpret_cast<const F2 *>(p) + t);
+  return make_double2((double)v[0], (double)v[1]);
+}
+template <typename V, typename WT, typename XD = std::false_type, bool NTL = false>
 __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restrict__ rz,
                                                 const double *__restrict__ pq,
                                                 const WT *__restrict__ w,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, float *__restrict__ rf,
-                                                double *partials, XDev f) {
+                                                double *partials, int pstride, XDev f) {
   const double pqv = *pq;
   const double alpha = pqv > 0.0 ? *rz / pqv : 0.0;
   double acc[1] = {0.0}, acc2 = 0.0;
@@ -591,8 +626,19 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
     } else {
       qv = ld2<V>(q, t);
     }
-    const double2 pv = ld2<V>(p, t), wt = ld2<V>(w, t);
-    double2 xv = ld2<V>(x, t), rv = ld2<V>(r, t);
+    double2 pv, wt, xv, rv;
+    if constexpr (NTL) {
+      static_assert(V::value, "non-temporal reads take the vector form");
+      pv = ld2n<true>(p, t);
+      wt = ld2n<true>(w, t);
+      xv = ld2n<true>(x, t);
+      rv = ld2n<true>(r, t);
+    } else {
+      pv = ld2<V>(p, t);
+      wt = ld2<V>(w, t);
+      xv = ld2<V>(x, t);
+      rv = ld2<V>(r, t);
+    }
     xv.x += alpha * pv.x;
     xv.y += alpha * pv.y;
     rv.x -= alpha * qv.x;
@@ -613,31 +659,37 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int64_t n, const double *__restr
     acc[0] += (double)w[n - 1] * r[n - 1] * r[n - 1];
   }
   acc[0] += acc2;
-  block_partials<1>(acc, partials);
+  block_partials<1>(acc, partials, pstride);
 }
 
 void launch_fcg_xr(const Ctx &c, int64_t n, const double *rz, const double *pq, const double *w,
                    const double *p, const double *q, double *x, double *r, double *out,
                    hipStream_t s, const float *w32, float *rf, const XDefer &xq) {
   const bool al = aligned16(p) && aligned16(q) && aligned16(x) && aligned16(r);
-  const unsigned g = red_grid(n);
   const XDev f = xdev<double>(xq);
+  unsigned g = red_grid(n);
+  int ps = 8;
   if (xq.on) {
     if (!(w32 && al && ((uintptr_t)w32 & 7) == 0) || (n & 1))
       fail(SEM_EINVAL, "FCG update: a deferred gather-scatter step needs aligned vectors");
-    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float, std::true_type>), dim3(g), dim3(256), 0,
-                       s, n, rz, pq, w32, p, q, x, r, rf, c.partials, f);
+    // one sum, so its partials pack densely: up to 4 kRedBlocks blocks (at
+    // 2^24 nodes, 16 waves per SIMD over the launch against 4 at kRedBlocks),
+    // with p, w, x and r streamed non-temporally
+    g = std::max(1u, std::min(nb(n / 2, 256), 4u * kRedBlocks));
+    ps = 1;
+    hipLaunchKernelGGL((k_fcg_xr<std::true_type, float, std::true_type, true>), dim3(g),
+                       dim3(256), 0, s, n, rz, pq, w32, p, q, x, r, rf, c.partials, ps, f);
   } else if (w32 && al && ((uintptr_t)w32 & 7) == 0)
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, float>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w32, p, q, x, r, rf, c.partials, f);
+                       w32, p, q, x, r, rf, c.partials, ps, f);
   else if (al && aligned16(w))
     hipLaunchKernelGGL((k_fcg_xr<std::true_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq, w,
-                       p, q, x, r, rf, c.partials, f);
+                       p, q, x, r, rf, c.partials, ps, f);
   else
     hipLaunchKernelGGL((k_fcg_xr<std::false_type, double>), dim3(g), dim3(256), 0, s, n, rz, pq,
-                       w, p, q, x, r, rf, c.partials, f);
+                       w, p, q, x, r, rf, c.partials, ps, f);
   SEM_LAUNCH("k_fcg_xr");
-  launch_finish(1, g, c.partials, out, s);
+  launch_finish(1, g, c.partials, out, s, ps);
 }
 
 void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double *const *a,
