@@ -135,3 +135,43 @@ def test_chebyshev_ras_full_size_compact_support(mesh, prec, centre):
     # the support really stays inside: the window's outer layer holds zeros
     w_shape = [len(set(v)) for v in (els % n, (els // n) % n, els // (n * n))]
     assert np.abs(ref).max() > 0 and all(s >= 9 for s in w_shape)
+
+
+@pytest.fixture(scope="module")
+def oracle_full(mesh):
+    """The oracle's finest level of the full mesh (FP64 operator and right side;
+    about 20 s and 6 GB of host memory)."""
+    return Level(N_FULL, N_FULL, N_FULL, mesh, 1, P_FULL, (1,) * 6, "jacobi")
+
+
+@pytest.mark.parametrize("prec", [sem.F32, sem.F64])
+def test_pmg_fcg_solve_full_size_oracle_residual(mesh, oracle_full, prec):
+    """The benchmark's solve at full size (FCG + pMG (7, 3, 1) Cheby-RAS(2),
+    exact coarse solve, tol 1e-8; FP32 smoother or all FP64), in the launch
+    shapes the benchmark times: the FCG update over 4096 blocks taking the
+    deferred gather-scatter steps of A p, the 32768-wavefront Ax and FDM
+    kernels, the finest-level reductions.  The right side matches the oracle's
+    (sem_rhs, mask QQ^T B f), and the oracle's FP64 residual of the GPU's
+    solution, ||b - A x|| / ||b|| over unique free nodes, is at most 1e-8 and
+    equals the residual the solver reports."""
+    from oracle.operator import rhs as orhs
+    f = wl.sinusoid(1, 1, 1)[0]
+    n, p = N_FULL, P_FULL
+    opts = sem.make_opts(schedule=(p, 3, 1), smoother=sem.SMOOTH_RAS, cheb_order=2,
+                         smoother_prec=prec, fdm_prec=prec, krylov=sem.KRYLOV_FCG)
+    s = sem.Solver(n, n, n, mesh, 1, p, opts=opts)
+    try:
+        X = host(s.coords(0))
+        b = s.rhs(dev(f(X[0], X[1], X[2])))
+        x, info = s.solve(b, rtol=1e-8, maxit=200)
+        bg, xg = host(b), host(x)
+    finally:
+        s.close()
+    L = oracle_full
+    bo = orhs(L.num, L.BL, f(L.X[0], L.X[1], L.X[2]))
+    assert rel_err(bg.reshape(bo.shape), bo) < 1e-12
+    r = bo - L.apply_A(xg.reshape(bo.shape))
+    rel = float(np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)))
+    assert info.converged and info.iters < 80, info.iters
+    assert rel <= 1e-8, rel
+    assert abs(rel - info.true_rel_res) <= 1e-3 * rel, (rel, info.true_rel_res)
