@@ -58,6 +58,45 @@ def test_batched_solve_matches_individual_solves():
             assert rel_err(xb, host(xi)) < 1e-6
 
 
+def test_batched_solve_uneven_convergence():
+    """Lanes that converge at very different iterations (layer-shift meshes,
+    whose trapezoidal elements need many iterations, beside smooth sine maps):
+    the batch records again as problems finish, and every lane still converges,
+    meets the oracle's residual and follows its own individual solve."""
+    import torch
+    probs = [(4, 7, (7, 3, 1), "ras", "shift"), (3, 5, (5, 3, 1), "ras", "shift"),
+             ((2, 2, 2), 3, (3, 1), "jacobi", "sin"), ((3, 2, 2), 5, (5, 3, 1), "ras", "sin")]
+    freqs = [(1, 1, 1), (2, 1, 3)]
+    pairs, bs, bos = [], [], []
+    for n, p, sched, sm, mesh in probs:
+        P = Pair(n, p, mesh=mesh, schedule=sched, smoother=sm, smoother_prec=sem.F32)
+        shape = P.shape
+        if mesh == "shift":
+            xyz, pg = wl.layer_shift_vertices(shape[0], seed=3), 1
+        else:
+            xyz, pg = wl.sampled_mesh(*shape, sem.gll_nodes(p)[0], wl.sin_map(0.05)), p
+        opts = sem.make_opts(schedule=sched, smoother={"ras": sem.SMOOTH_RAS, "jacobi": sem.SMOOTH_JACOBI}[sm],
+                             smoother_prec=sem.F32, batch_rhs=len(freqs))
+        P.batch = sem.Solver(*shape, xyz, pg, p, opts=opts)
+        pairs.append(P)
+        row, orow = zip(*[_rhs_pair(P, *fr) for fr in freqs])
+        bs.append(list(row))
+        bos.append(list(orow))
+    xs = [[torch.zeros_like(b) for b in row] for row in bs]
+    infos = sem.batch_solve([P.batch for P in pairs], bs, xs, rtol=1e-8, maxit=300)
+    its = [i.iters for i in infos]
+    assert max(its) >= 2 * min(its), its
+    for i, P in enumerate(pairs):
+        for k in range(len(freqs)):
+            inf = infos[i * len(freqs) + k]
+            assert inf.converged and inf.true_rel_res <= 1e-8, (i, k, inf.iters)
+            xb = host(xs[i][k])
+            assert _oracle_rel_res(P, xb, bos[i][k]) <= 1e-8
+            xi, ii = P.gpu.solve(bs[i][k], rtol=1e-8, maxit=300)
+            assert abs(inf.iters - ii.iters) <= 3, (inf.iters, ii.iters)
+            assert rel_err(xb, host(xi)) < 1e-6
+
+
 def test_batched_solve_repeatable():
     """Identical lanes give identical results, and a second batched call repeats the first."""
     import torch
