@@ -458,9 +458,9 @@ __device__ inline void block_partials(double (&acc)[ND], double *partials, int s
     for (int j = 0; j < ND; ++j) partials[blockIdx.x * stride + j] = sh[j][0];
   }
 }
-// block b's partials at partials[b * stride + j]: stride 8 for up to eight
-// sums over at most kRedBlocks blocks; a single sum may pack them densely
-// (stride 1) over up to 8 kRedBlocks blocks
+// block b's partials at partials[b * stride + j], nd <= stride <= 8, within
+// the buffer's 8 kRedBlocks doubles: stride 8 for up to eight sums over
+// kRedBlocks blocks, or densely packed (stride nd) over more blocks
 template <int ND>
 __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict__ partials,
                                                 double *out, int stride) {
@@ -480,10 +480,8 @@ __global__ __launch_bounds__(256) void k_finish(int nb, const double *__restrict
 }
 static void launch_finish(int nd, unsigned nblocks, const double *partials, double *out,
                           hipStream_t s, int stride = 8) {
-  if (stride != 8 && (nd != 1 || stride != 1 || nblocks > 8u * kRedBlocks))
-    fail(SEM_EINVAL, "reduction partials: dense packing holds one sum");
-  if (stride == 8 && nblocks > (unsigned)kRedBlocks)
-    fail(SEM_EINVAL, "reduction partials: too many blocks");
+  if (stride < nd || stride > 8 || (uint64_t)nblocks * stride > 8u * kRedBlocks)
+    fail(SEM_EINVAL, "reduction partials: more than the buffer holds");
   switch (nd) {
     case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
     case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(256), 0, s, (int)nblocks, partials, out, stride); break;
@@ -725,7 +723,9 @@ void launch_wdots(const Ctx &c, int64_t n, const double *w, int nd, const double
 
 // (r, z_j)_w for FP32 z_j (j < ND): the preconditioned residual of the mixed
 // path is the exact FP64 widening of the V-cycle's FP32 output, so it is read
-// in FP32; same pairing and partial sums as k_wdots (the same results)
+// in FP32; the pairing of k_wdots, over up to 8 kRedBlocks / ND blocks whose
+// partials pack densely (stride ND); r, w and z_old are streamed
+// non-temporally (z is read again by the p update that follows)
 template <int ND, typename WT>
 __global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restrict__ w,
                                                   const double *__restrict__ r,
@@ -735,14 +735,13 @@ __global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restric
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = acc2[j] = 0.0;
   const int64_t n2 = n / 2;
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t0 = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t t = t0; t < n2; t += (int64_t)gridDim.x * blockDim.x) {
-    const double2 wt = ld2<std::true_type>(w, t);
-    const double2 x = ld2<std::true_type>(r, t);
-    const float *zs[2] = {z0, z1};
+    const double2 wt = ld2n<true>(w, t);
+    const double2 x = ld2n<true>(r, t);
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
-      const double2 y = ld2<std::true_type>(zs[j], t);
+      const double2 y = j == 0 ? ld2n<false>(z0, t) : ld2n<true>(z1, t);
       acc[j] += wt.x * x.x * y.x;
       acc2[j] += wt.y * x.y * y.y;
     }
@@ -754,13 +753,13 @@ __global__ __launch_bounds__(256) void k_wdots_rz(int64_t n, const WT *__restric
   }
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] += acc2[j];
-  block_partials<ND>(acc, partials);
+  block_partials<ND>(acc, partials, ND);
 }
 
 void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32, const double *r,
                      const float *z0, const float *z1, double *out, hipStream_t s) {
   const int nd = z1 ? 2 : 1;
-  const unsigned g = red_grid(n);
+  const unsigned g = std::max(1u, std::min(nb(n / 2, 256), 8u * kRedBlocks / nd));
   if (!aligned16(r) || ((uintptr_t)z0 & 7) || (z1 && ((uintptr_t)z1 & 7)))
     fail(SEM_EINVAL, "wdots_rz: misaligned vectors");
   if (w32 && ((uintptr_t)w32 & 7) == 0) {
@@ -780,24 +779,35 @@ void launch_wdots_rz(const Ctx &c, int64_t n, const double *w, const float *w32,
                          c.partials);
   }
   SEM_LAUNCH("k_wdots_rz");
-  launch_finish(nd, g, c.partials, out, s);
+  launch_finish(nd, g, c.partials, out, s, nd);
 }
 
 // p = z + beta p (FP64 p; z in FP32 on the mixed path), beta from the device
 // scalars: (r, z) / rz_old, or ((r, z) - (r, z_old)) / rz_old when flexible
+// (two nodes per thread: z non-temporal, its last read; p stays cached for
+// the product A p that follows)
 template <typename ZT>
 __global__ void k_zp(int64_t n, const ZT *__restrict__ z, const double *__restrict__ rzn,
                      const double *__restrict__ rzo, int flexible, double *__restrict__ p) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= n) return;
+  const int64_t t = xcd_block() * (int64_t)blockDim.x + threadIdx.x;
   const double beta = (flexible ? rzn[0] - rzn[1] : rzn[0]) / rzo[0];
   const double a = 1.0;
-  p[t] = a * (double)z[t] + beta * p[t];
+  if (2 * t + 1 < n) {
+    const double2 zv = ld2n<true>(z, t);
+    double2 pv = reinterpret_cast<const double2 *>(p)[t];
+    pv.x = a * zv.x + beta * pv.x;
+    pv.y = a * zv.y + beta * pv.y;
+    reinterpret_cast<double2 *>(p)[t] = pv;
+  } else if (2 * t < n) {
+    p[2 * t] = a * (double)z[2 * t] + beta * p[2 * t];
+  }
 }
 template <typename ZT>
 void launch_zp(int64_t n, const ZT *z, const double *rzn, const double *rzo, bool flexible,
                double *p, hipStream_t s) {
-  hipLaunchKernelGGL(k_zp<ZT>, dim3(nb(n, 256)), dim3(256), 0, s, n, z, rzn, rzo,
+  if (!aligned16(p) || ((uintptr_t)z & (2 * sizeof(ZT) - 1)))
+    fail(SEM_EINVAL, "p update: misaligned vectors");
+  hipLaunchKernelGGL(k_zp<ZT>, dim3(nb((n + 1) / 2, 256)), dim3(256), 0, s, n, z, rzn, rzo,
                      flexible ? 1 : 0, p);
   SEM_LAUNCH("k_zp");
 }
