@@ -1,5 +1,6 @@
 // RAS local solves by the fast diagonalisation method (Sec. 2.2.2, eqs. 8-9)
-// in FP32 on the matrix cores.
+// on the matrix cores: FP32 operands, or FP16 / BF16 operands with FP32
+// accumulation (k_fdm_mf16, the same kernel forms with v_mfma_f32_4x4x4).
 //
 // Each of the six 1D contractions of the (p+3)^3 box is a product of the box
 // lines with a (p+3)x(p+3) factor: out[line][m] = sum_k in[line][k] S[k][m].
@@ -24,7 +25,10 @@
 // (16-byte reads).  The z pass divides by the eigenvalue sums of eq. 9 in
 // registers and goes straight back along z; the backward passes form only the
 // nodes RAS keeps, and the last one writes the element's rows times the RAS
-// weight.
+// weight.  The 16-bit forms take four k per instruction (84 instead of 280
+// matrix instructions per element at p = 7); their operands are kept in range
+// by powers of two (the box, and the eigenvalue-scaled tensor, over their
+// largest entry) and by factors stored over their largest entries.
 #include "sem_internal.h"
 
 namespace sem {
@@ -56,6 +60,73 @@ __device__ __attribute__((always_inline)) inline mf4_t mfma_bq(float a, float b,
   }
 }
 
+// Operand formats of the contractions: FP32 (v_mfma_f32_4x4x1, one k per
+// instruction) or FP16 / BF16 (v_mfma_f32_4x4x4, four k per instruction, FP32
+// accumulation).  In the 16-bit forms lane 4q + i of the broadcast block holds
+// four consecutive k of row i of A, and lane 4b + j four consecutive k of
+// column j of B (its line), packed two per register.
+enum : int { kOpF32 = 0, kOpF16 = 1, kOpBF16 = 2 };
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));  // four 16-bit operands
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+template <int OP>
+__device__ inline uint32_t pack2(float a, float b) {  // round to nearest even
+  if constexpr (OP == kOpF16) {
+    typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{a, b}, h2_t));
+  } else {
+    typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{a, b}, b2_t));
+  }
+}
+
+template <int OP, int Q>
+__device__ __attribute__((always_inline)) inline mf4_t mfma16_q(u2_t a, u2_t b, mf4_t c) {
+  typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+  typedef short s4_t __attribute__((ext_vector_type(4)));
+  if constexpr (OP == kOpF16)
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(h4_t, a),
+                                              __builtin_bit_cast(h4_t, b), c, 4, Q, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s4_t, a),
+                                                  __builtin_bit_cast(s4_t, b), c, 4, Q, 0);
+}
+// D += A_q B (four k) on the 16 blocks, A broadcast from block q
+template <int OP>
+__device__ __attribute__((always_inline)) inline mf4_t mfma16(u2_t a, u2_t b, mf4_t c, int q) {
+  switch (q) {
+    case 0: return mfma16_q<OP, 0>(a, b, c);
+    case 1: return mfma16_q<OP, 1>(a, b, c);
+    case 2: return mfma16_q<OP, 2>(a, b, c);
+    case 3: return mfma16_q<OP, 3>(a, b, c);
+    case 4: return mfma16_q<OP, 4>(a, b, c);
+    case 5: return mfma16_q<OP, 5>(a, b, c);
+    case 6: return mfma16_q<OP, 6>(a, b, c);
+    case 7: return mfma16_q<OP, 7>(a, b, c);
+    case 8: return mfma16_q<OP, 8>(a, b, c);
+    case 9: return mfma16_q<OP, 9>(a, b, c);
+    case 10: return mfma16_q<OP, 10>(a, b, c);
+    case 11: return mfma16_q<OP, 11>(a, b, c);
+    case 12: return mfma16_q<OP, 12>(a, b, c);
+    case 13: return mfma16_q<OP, 13>(a, b, c);
+    case 14: return mfma16_q<OP, 14>(a, b, c);
+    default: return mfma16_q<OP, 15>(a, b, c);
+  }
+}
+
+// the largest |value| over the wavefront
+__device__ inline float wave_absmax(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// 2^-e with m = f 2^e, 0.5 <= f < 1: a scale that brings m into [0.5, 1)
+// exactly (0 for m = 0)
+__device__ inline float pow2_below(float m, int &e) {
+  e = __builtin_amdgcn_frexp_expf(m);
+  return m > 0.f ? __builtin_amdgcn_ldexpf(1.0f, -e) : 0.f;
+}
+
 template <int P>
 struct Mf {
   static constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
@@ -69,6 +140,11 @@ struct Mf {
   static constexpr int NLX = N * N, SX = (NLX + 63) / 64;   // backward x lines (kept rows)
   static constexpr int BUF = NL * LS;                        // floats per wavefront
   static constexpr int WAVES = 4;
+  // 16-bit operands: k in groups of four (forward: the line's nodes; backward:
+  // the modes), one register pair of A operands per direction and pass kind
+  static constexpr int K4 = (PB + 3) / 4;
+  static constexpr int QF16 = K4 * MG, QB16 = K4 * KG;
+  static_assert(QF16 <= 16 && QB16 <= 16, "16-bit A operands exceed one broadcast register");
 };
 
 // 1 / (lambda_x + lambda_y + lambda_z): +inf (a decoupled node) gives 0.  A
@@ -128,6 +204,44 @@ __device__ __attribute__((always_inline)) inline void mf_backward(const float *A
     }
 }
 
+// the 16-bit forms of the two contractions: the B operands are the line's
+// values (times sc when SC), four k per operand, zero past PB
+template <int P, int OP, bool SC>
+__device__ __attribute__((always_inline)) inline void mf16_operands(const float *v, float sc,
+                                                                     u2_t *b) {
+  using F = Mf<P>;
+  auto at = [&](int k) { return k < F::PB ? (SC ? v[k] * sc : v[k]) : 0.f; };
+#pragma unroll
+  for (int kg = 0; kg < F::K4; ++kg)
+    b[kg] = u2_t{pack2<OP>(at(4 * kg), at(4 * kg + 1)), pack2<OP>(at(4 * kg + 2), at(4 * kg + 3))};
+}
+template <int P, int OP, bool SC>
+__device__ __attribute__((always_inline)) inline void mf16_forward(u2_t A, const float *v,
+                                                                   float sc, mf4_t *acc) {
+  using F = Mf<P>;
+  u2_t b[F::K4];
+  mf16_operands<P, OP, SC>(v, sc, b);
+#pragma unroll
+  for (int g = 0; g < F::MG; ++g) acc[g] = mf4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kg = 0; kg < F::K4; ++kg)
+#pragma unroll
+    for (int g = 0; g < F::MG; ++g) acc[g] = mfma16<OP>(A, b[kg], acc[g], kg * F::MG + g);
+}
+template <int P, int OP, bool SC>
+__device__ __attribute__((always_inline)) inline void mf16_backward(u2_t A, const float *h,
+                                                                    float sc, mf4_t *acc) {
+  using F = Mf<P>;
+  u2_t b[F::K4];
+  mf16_operands<P, OP, SC>(h, sc, b);
+#pragma unroll
+  for (int g = 0; g < F::KG; ++g) acc[g] = mf4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mg = 0; mg < F::K4; ++mg)
+#pragma unroll
+    for (int g = 0; g < F::KG; ++g) acc[g] = mfma16<OP>(A, b[mg], acc[g], mg * F::KG + g);
+}
+
 template <int P>
 __device__ __attribute__((always_inline)) inline void mf_read_line(const float *buf, int line,
                                                                    float *v) {
@@ -173,17 +287,55 @@ struct MfIn {
   float yxl[YSF], yxr[YSF];        // ... of the x-partners of its nodes 0 and p
   float ylf[YSF], yrg[YSF];        // ... of the halo nodes (left node p-1, right node 1)
   float Af[3][F::UF], Ab[3][F::UB];
+  u2_t Af16[3], Ab16[3];     // 16-bit forms: the factors over their largest entry
+  float ssc[3];              // ... and those largest entries s_d
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
   mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
 };
 
-template <int P, bool RS, int XS, bool YS>
+// Raw-buffer view of 16-bit patterns (zero at or past nbytes, as BufF32)
+struct BufU16 {
+  __amdgpu_buffer_rsrc_t rsrc;
+  __device__ BufU16(const uint16_t *p, uint32_t nbytes)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(p), (short)0, (int)nbytes,
+                                               0x00020000)) {}
+  __device__ uint32_t ld(uint32_t off) const {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsrc, off, 0, 0);
+  }
+};
+
+template <int P, bool RS, int XS, bool YS, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_load(
     MfIn<P, RS, XS, YS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
     int64_t eb, const float *__restrict__ Sg, const float *__restrict__ lamg,
-    const float *__restrict__ W, int lane) {
+    const float *__restrict__ W, int lane, const uint16_t *__restrict__ S16 = nullptr,
+    const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, MG = F::MG, KG = F::KG;
+  if constexpr (OP != kOpF32) {
+    // 16-bit A operands of S_d / s_d: forward pair q = (kg, g) -> lane 4q + i
+    // holds S_d[4kg + kk][4g + i], kk < 4; backward q = (mg, g) -> S_d[1 + 4g +
+    // i][4mg + kk]; zero where an index runs past the factor
+    const BufU16 Sh(S16 + e * 3 * PB * PB, 3 * PB * PB * 2);
+    const int i = lane & 3, q = lane >> 2;
+    const int kg = q / MG, gf = q % MG, mg = q / KG, gb = q % KG;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      uint32_t hf[4], hb[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kg + kk, m = 4 * gf + i;
+        hf[kk] = Sh.ld(q < F::QF16 && k < PB && m < PB ? (uint32_t)((d * PB + k) * PB + m) * 2
+                                                        : kOutside);
+        const int kn = 1 + 4 * gb + i, mm = 4 * mg + kk;
+        hb[kk] = Sh.ld(q < F::QB16 && kn <= N && mm < PB ? (uint32_t)((d * PB + kn) * PB + mm) * 2
+                                                         : kOutside);
+      }
+      in.Af16[d] = u2_t{hf[0] | hf[1] << 16, hf[2] | hf[3] << 16};
+      in.Ab16[d] = u2_t{hb[0] | hb[1] << 16, hb[2] | hb[3] << 16};
+      in.ssc[d] = ssc[e * 3 + d];
+    }
+  } else {
   const BufF32 Se(Sg + e * 3 * PB * PB, 3 * PB * PB * 4);  // the element's three factors
   // A operands: forward (k, g) -> lane 4q + i holds S_d[k][4g + i]; backward
   // (m, g) -> S_d[1 + 4g + i][m]; zero where the index runs past the factor
@@ -203,6 +355,7 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 #pragma unroll
       for (int d = 0; d < 3; ++d) in.Ab[d][u] = Se.ld(at + d * PB * PB * 4);
     }
+  }
   }
   // eigenvalue sums of the z pass (line (a', b') of slot s) and the RAS weights
   // of the rows the last pass writes; loaded here so that a solve issues no
@@ -312,7 +465,12 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 // shared by the workgroup) before the store, each pair as (p-face + 0-face),
 // the order of the gather-scatter's x step, which then covers only the faces
 // between workgroups.
-template <int P, bool RS, int XS, bool YS, bool XF>
+// 16-bit operands (OP): the element's box is brought into [0.5, 1) by a power
+// of two from its largest entry before the forward passes, the eigenvalue-
+// scaled tensor likewise before the backward passes, and the factors are
+// stored over their largest entries s_d; the output is scaled back by the two
+// powers of two and (s_x s_y s_z)^2.
+template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_solve(
     const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
     float *buf, int lane, float *xfx, int wave) {
@@ -358,9 +516,25 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     for (int i = 0; i < N; ++i) v[s][i + 1] = RS ? ro[i] - so[i] : ro[i];
   }
 
+  int e_in = 0, e_h = 0;
+  float sc_in = 1.f;
+  if constexpr (OP != kOpF32) {
+    float m = 0.f;
+#pragma unroll
+    for (int s = 0; s < F::SF; ++s)
+#pragma unroll
+      for (int k = 0; k < PB; ++k) m = fmaxf(m, fabsf(v[s][k]));
+    sc_in = pow2_below(wave_absmax(m), e_in);
+  }
+
   // x: line (b, c) -> modes a'; written as y-lines (a', c), position b
 #pragma unroll
-  for (int s = 0; s < F::SF; ++s) mf_forward<P>(in.Af[0], v[s], acc[s]);
+  for (int s = 0; s < F::SF; ++s) {
+    if constexpr (OP != kOpF32)
+      mf16_forward<P, OP, true>(in.Af16[0], v[s], sc_in, acc[s]);
+    else
+      mf_forward<P>(in.Af[0], v[s], acc[s]);
+  }
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
@@ -382,7 +556,12 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     mf_read_line<P>(buf, l < F::NL ? l : 0, v[s]);
   }
 #pragma unroll
-  for (int s = 0; s < F::SF; ++s) mf_forward<P>(in.Af[1], v[s], acc[s]);
+  for (int s = 0; s < F::SF; ++s) {
+    if constexpr (OP != kOpF32)
+      mf16_forward<P, OP, false>(in.Af16[1], v[s], 1.f, acc[s]);
+    else
+      mf_forward<P>(in.Af[1], v[s], acc[s]);
+  }
   mf_sync();
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
@@ -406,14 +585,31 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     const int l = 64 * s + lane;
     mf_read_line<P>(buf, l < F::NL ? l : 0, v[s]);
   }
+  if constexpr (OP != kOpF32) {
+    float h[F::SF][PB], m = 0.f;
 #pragma unroll
-  for (int s = 0; s < F::SF; ++s) {
-    mf_forward<P>(in.Af[2], v[s], acc[s]);
-    const float lxy = in.lxy[s];
-    float h[PB];
+    for (int s = 0; s < F::SF; ++s) {
+      mf16_forward<P, OP, false>(in.Af16[2], v[s], 1.f, acc[s]);
+      const float lxy = in.lxy[s];
 #pragma unroll
-    for (int m = 0; m < PB; ++m) h[m] = acc[s][m >> 2][m & 3] * mf_inv(lxy + le[2 * PB + m]);
-    mf_backward<P>(in.Ab[2], h, bk[s]);
+      for (int k = 0; k < PB; ++k) {
+        h[s][k] = acc[s][k >> 2][k & 3] * mf_inv(lxy + le[2 * PB + k]);
+        m = fmaxf(m, fabsf(h[s][k]));
+      }
+    }
+    const float sc_h = pow2_below(wave_absmax(m), e_h);
+#pragma unroll
+    for (int s = 0; s < F::SF; ++s) mf16_backward<P, OP, true>(in.Ab16[2], h[s], sc_h, bk[s]);
+  } else {
+#pragma unroll
+    for (int s = 0; s < F::SF; ++s) {
+      mf_forward<P>(in.Af[2], v[s], acc[s]);
+      const float lxy = in.lxy[s];
+      float h[PB];
+#pragma unroll
+      for (int m = 0; m < PB; ++m) h[m] = acc[s][m >> 2][m & 3] * mf_inv(lxy + le[2 * PB + m]);
+      mf_backward<P>(in.Ab[2], h, bk[s]);
+    }
   }
   mf_sync();
 #pragma unroll
@@ -439,7 +635,12 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     mf_read_line<P>(buf, l < F::NLY ? l : 0, w[s]);
   }
 #pragma unroll
-  for (int s = 0; s < F::SY; ++s) mf_backward<P>(in.Ab[1], w[s], by[s]);
+  for (int s = 0; s < F::SY; ++s) {
+    if constexpr (OP != kOpF32)
+      mf16_backward<P, OP, false>(in.Ab16[1], w[s], 1.f, by[s]);
+    else
+      mf_backward<P>(in.Ab[1], w[s], by[s]);
+  }
   mf_sync();
 #pragma unroll
   for (int s = 0; s < F::SY; ++s) {
@@ -458,15 +659,26 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
   // back along x: line (j, k) -> kept nodes i = 1..N: the element's row (j, k)
   // times the RAS weight
   mf4_t o[F::SX][KG];
+  float osc = 1.f;
+  if constexpr (OP != kOpF32) {
+    const float s3 = in.ssc[0] * in.ssc[1] * in.ssc[2];
+    osc = __builtin_amdgcn_ldexpf(s3 * s3, e_in + e_h);
+  }
 #pragma unroll
   for (int s = 0; s < F::SX; ++s) {
     const int l = 64 * s + lane;
     float u[PB];
     mf4_t bx[KG];
     mf_read_line<P>(buf, l < F::NLX ? l : 0, u);
-    mf_backward<P>(in.Ab[0], u, bx);
+    if constexpr (OP != kOpF32) {
+      mf16_backward<P, OP, false>(in.Ab16[0], u, 1.f, bx);
 #pragma unroll
-    for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * bx[g];
+      for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * (bx[g] * osc);
+    } else {
+      mf_backward<P>(in.Ab[0], u, bx);
+#pragma unroll
+      for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * bx[g];
+    }
   }
   if constexpr (XF) {
     constexpr int NLX = F::NLX, GL = (N - 1) / 4, IL = (N - 1) % 4;
@@ -556,26 +768,69 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
   }
 }
 
-template <int P, bool RS, int XS, bool YS, bool XF>
+// The same solve with FP16 or BF16 operands (OP), one element per wave:
+// S16 = S_d / s_d as 16-bit patterns, ssc = s_d per element and direction.
+template <int P, bool RS, int XS, bool YS, bool XF, int OP>
+__global__ __launch_bounds__(256) void k_fdm_mf16(int64_t E, int nex, int ney, int nez,
+                                                  const float *__restrict__ r,
+                                                  const float *__restrict__ rs,
+                                                  const uint16_t *__restrict__ S16,
+                                                  const float *__restrict__ ssc,
+                                                  const float *__restrict__ lamg,
+                                                  const float *__restrict__ W,
+                                                  float *__restrict__ z, int nv) {
+  using F = Mf<P>;
+  constexpr int N3 = F::N3;
+  __shared__ mf4_t lds4[F::WAVES * F::BUF / 4];
+  __shared__ float xfx[XF ? 2 * F::WAVES * F::NLX : 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int vec;
+  const int64_t e = (int64_t)split_rhs(xcd_block(), nv, vec) * F::WAVES + wave;
+  if (e >= E) return;  // whole wave; XF launches only whole workgroups (E % 4 == 0)
+  r += (int64_t)vec * E * N3;
+  if (RS) rs += (int64_t)vec * E * N3;
+  z += (int64_t)vec * E * N3;
+  float *buf = reinterpret_cast<float *>(lds4) + wave * F::BUF;
+  const int64_t eb = e > (int64_t)nex * ney + nex + 1 ? e - ((int64_t)nex * ney + nex + 1) : 0;
+  const int64_t wb = (E - eb) * N3 * 4;
+  const uint32_t wn = wb < (int64_t)kWindowMax ? (uint32_t)wb : kWindowMax;
+  const BufF32 rb(r + eb * N3, wn), rsb(RS ? rs + eb * N3 : r + eb * N3, wn);
+  MfIn<P, RS, XS, YS> in;
+  mf_load<P, RS, XS, YS, OP>(in, e, nex, ney, nez, rb, rsb, eb, nullptr, lamg, W, lane, S16, ssc);
+  mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave);
+}
+
+template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                    hipStream_t s, int nv) {
   using F = Mf<P>;
-  const int C = XF ? 1 : c.fdm_mf32_chain;
-  if (XF && (L.E % F::WAVES != 0 || c.nex % F::WAVES != 0))
-    fail(SEM_EINVAL, "FDM: x-face sums need whole groups of four elements along x");
-  const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
-  const dim3 block(64 * F::WAVES);
-  if constexpr (XF) {
-    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, true>), grid, block, 0, s, L.E, c.nex,
-                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
-  } else if (C == 2) {
-    hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
-                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+  if constexpr (OP != kOpF32) {
+    if (XF && (L.E % F::WAVES != 0 || c.nex % F::WAVES != 0))
+      fail(SEM_EINVAL, "FDM: x-face sums need whole groups of four elements along x");
+    if (!L.S16 || !L.sscale) fail(SEM_EINVAL, "16-bit FDM data were not built");
+    const dim3 grid((unsigned)((L.E + F::WAVES - 1) / F::WAVES * nv));
+    hipLaunchKernelGGL((k_fdm_mf16<P, RS, XS, YS, XF, OP>), grid, dim3(64 * F::WAVES), 0, s, L.E,
+                       c.nex, c.ney, c.nez, r, rs, L.S16, L.sscale, L.lam32, L.w32, z, nv);
+    SEM_LAUNCH("k_fdm_mf16");
   } else {
-    hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
-                       c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+    const int C = XF ? 1 : c.fdm_mf32_chain;
+    if (XF && (L.E % F::WAVES != 0 || c.nex % F::WAVES != 0))
+      fail(SEM_EINVAL, "FDM: x-face sums need whole groups of four elements along x");
+    const dim3 grid((unsigned)((L.E + F::WAVES * C - 1) / (F::WAVES * C) * nv));
+    const dim3 block(64 * F::WAVES);
+    if constexpr (XF) {
+      hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, true>), grid, block, 0, s, L.E, c.nex,
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+    } else if (C == 2) {
+      hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+    } else {
+      hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+    }
+    SEM_LAUNCH("k_fdm_mf32");
   }
-  SEM_LAUNCH("k_fdm_mf32");
 }
 
 // xin: 0 the inputs are assembled; 1 r, 2 rs lacks the x step of its
@@ -584,7 +839,7 @@ void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs
 // + 8: sum the output's x-faces inside each workgroup (assembled r, or rs
 // as above), for a gather-scatter that then covers only the faces between
 // workgroups
-template <int P>
+template <int P, int OP>
 void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                  hipStream_t s, int nv, int xin) {
   const int which = xin & 3;
@@ -595,19 +850,19 @@ void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, 
   if (rs) {
     if (which == 1) fail(SEM_EINVAL, "FDM: the x step is taken on the subtrahend only");
     if (xf) {
-      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, true>(c, L, r, rs, z, s, nv);
-      else if (which == 2) mf32_launch_x<P, true, 2, false, true>(c, L, r, rs, z, s, nv);
-      else mf32_launch_x<P, true, 0, false, true>(c, L, r, rs, z, s, nv);
+      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, true, OP>(c, L, r, rs, z, s, nv);
+      else if (which == 2) mf32_launch_x<P, true, 2, false, true, OP>(c, L, r, rs, z, s, nv);
+      else mf32_launch_x<P, true, 0, false, true, OP>(c, L, r, rs, z, s, nv);
     } else {
-      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, false>(c, L, r, rs, z, s, nv);
-      else if (which == 2) mf32_launch_x<P, true, 2, false, false>(c, L, r, rs, z, s, nv);
-      else mf32_launch_x<P, true, 0, false, false>(c, L, r, rs, z, s, nv);
+      if (which == 2 && ys) mf32_launch_x<P, true, 2, true, false, OP>(c, L, r, rs, z, s, nv);
+      else if (which == 2) mf32_launch_x<P, true, 2, false, false, OP>(c, L, r, rs, z, s, nv);
+      else mf32_launch_x<P, true, 0, false, false, OP>(c, L, r, rs, z, s, nv);
     }
   } else {
-    if (xf) mf32_launch_x<P, false, 0, false, true>(c, L, r, rs, z, s, nv);
-    else if (which == 1 && ys) mf32_launch_x<P, false, 1, true, false>(c, L, r, rs, z, s, nv);
-    else if (which == 1) mf32_launch_x<P, false, 1, false, false>(c, L, r, rs, z, s, nv);
-    else mf32_launch_x<P, false, 0, false, false>(c, L, r, rs, z, s, nv);
+    if (xf) mf32_launch_x<P, false, 0, false, true, OP>(c, L, r, rs, z, s, nv);
+    else if (which == 1 && ys) mf32_launch_x<P, false, 1, true, false, OP>(c, L, r, rs, z, s, nv);
+    else if (which == 1) mf32_launch_x<P, false, 1, false, false, OP>(c, L, r, rs, z, s, nv);
+    else mf32_launch_x<P, false, 0, false, false, OP>(c, L, r, rs, z, s, nv);
   }
 }
 
@@ -626,20 +881,31 @@ bool fdm_mf32_supported(const Ctx &c, int p) {
   return p >= 2 && p <= 9 && !floating && span * (p + 1) * (p + 1) * (p + 1) * 4 < kWindowMax;
 }
 
-void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
-                     const float *rs, int xin) {
-  if (!L.S32 || !L.lam32 || !L.w32) fail(SEM_EINVAL, "FP32 FDM data were not built");
+template <int OP>
+static void mf_launch_p(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s,
+                        int nv, const float *rs, int xin) {
   switch (L.p) {
-    case 2: mf32_launch<2>(c, L, r, rs, z, s, nv, xin); break;
-    case 3: mf32_launch<3>(c, L, r, rs, z, s, nv, xin); break;
-    case 4: mf32_launch<4>(c, L, r, rs, z, s, nv, xin); break;
-    case 5: mf32_launch<5>(c, L, r, rs, z, s, nv, xin); break;
-    case 6: mf32_launch<6>(c, L, r, rs, z, s, nv, xin); break;
-    case 7: mf32_launch<7>(c, L, r, rs, z, s, nv, xin); break;
-    case 8: mf32_launch<8>(c, L, r, rs, z, s, nv, xin); break;
-    case 9: mf32_launch<9>(c, L, r, rs, z, s, nv, xin); break;
-    default: fail(SEM_EUNSUPPORTED, "FP32 matrix-core FDM: unsupported degree");
+    case 2: mf32_launch<2, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 3: mf32_launch<3, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 4: mf32_launch<4, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 5: mf32_launch<5, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 6: mf32_launch<6, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 7: mf32_launch<7, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 8: mf32_launch<8, OP>(c, L, r, rs, z, s, nv, xin); break;
+    case 9: mf32_launch<9, OP>(c, L, r, rs, z, s, nv, xin); break;
+    default: fail(SEM_EUNSUPPORTED, "matrix-core FDM: unsupported degree");
   }
+}
+
+void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
+                     const float *rs, int xin, int prec) {
+  if (!L.S32 || !L.lam32 || !L.w32) fail(SEM_EINVAL, "FP32 FDM data were not built");
+  if (prec == SEM_F16)
+    mf_launch_p<kOpF16>(c, L, r, z, s, nv, rs, xin);
+  else if (prec == SEM_BF16)
+    mf_launch_p<kOpBF16>(c, L, r, z, s, nv, rs, xin);
+  else
+    mf_launch_p<kOpF32>(c, L, r, z, s, nv, rs, xin);
 }
 
 }  // namespace sem

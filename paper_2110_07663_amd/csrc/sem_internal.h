@@ -249,6 +249,7 @@ struct Ctx {
   bool fdm_mfma1 = false; // first matrix-core FDM form (LDS FP32 box) instead of the second
   bool fdm_mf32 = true;   // FP32 RAS local solves on the matrix cores (fdm_mf32.hip)
   int fdm_mf32_chain = 1; // elements per wavefront there (1 or 2), next one's loads ahead
+  bool fdm_mf16 = true;   // FP16 / BF16 RAS operands in that kernel's 4x4x4 form
   bool fdm_xstep = true;  // that kernel takes the x step of A's gather-scatter as it reads
   bool fdm_ystep = true;  // ... and the y step as well (A's gather-scatter takes only z)
   bool fdm_xfaces = true;  // ... and sums its output's x-faces inside each workgroup
@@ -394,8 +395,10 @@ void launch_asm_sum(const Ctx &c, const Level &L, const T *box, T *z, hipStream_
 // fdm_mf32.hip: FP32 RAS local solves on the matrix cores (2 <= p <= 9, no
 // floating box)
 bool fdm_mf32_supported(const Ctx &c, int p);
+// prec: the operand format of the contractions (SEM_F32, or SEM_F16 /
+// SEM_BF16 with the level's 16-bit factors)
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
-                     const float *rs, int xin);
+                     const float *rs, int xin, int prec = SEM_F32);
 
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);

@@ -345,6 +345,8 @@ static void init_ctx(Ctx &c, const sem_mesh *m, int p, const int8_t *bc, const s
   c.fdm_mfma1 = fm && fm[0] == '1';
   const char *f32 = getenv("SEM_FDM_MF32");
   c.fdm_mf32 = !(f32 && f32[0] == '0');
+  const char *f16 = getenv("SEM_FDM_MF16");
+  c.fdm_mf16 = !(f16 && f16[0] == '0');
   const char *fch = getenv("SEM_FDM_MF32_CHAIN");
   c.fdm_mf32_chain = fch && fch[0] == '2' ? 2 : 1;
   const char *fxs = getenv("SEM_FDM_XSTEP");
@@ -489,11 +491,19 @@ static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, do
 // Whether the level's Schwarz smoother in precision T reads A's output with
 // the x step of its gather-scatter left out and takes that step itself (the
 // FP32 matrix-core RAS kernel); then the products that only feed it skip it.
+// Whether the level's RAS local solves run in the matrix-core line kernel
+// (fdm_mf32.hip): FP32 operands, or FP16 / BF16 operands in its 4x4x4 form
+// (otherwise the 16-bit tile kernel of fdm_mfma.hip)
+static bool fdm_in_mf(const Ctx &c, const Level &L) {
+  const bool b16 = c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16;
+  return (b16 ? c.fdm_mf16 && L.S16 && L.sscale : c.fdm_mf32) &&
+         c.opts.smoother == SEM_SMOOTH_RAS && !L.coarse && fdm_mf32_supported(c, L.p);
+}
+
 template <typename T>
 static bool fdm_takes_x_step(const Ctx &c, const Level &L) {
-  return sizeof(T) == 4 && c.fdm_xstep && c.fdm_mf32 && c.opts.precond == SEM_PRECOND_PMG &&
-         c.opts.smoother == SEM_SMOOTH_RAS && c.fdm_prec != SEM_BF16 && c.fdm_prec != SEM_F16 &&
-         !L.coarse && L.gs_struct && fdm_mf32_supported(c, L.p);
+  return sizeof(T) == 4 && c.fdm_xstep && c.opts.precond == SEM_PRECOND_PMG && fdm_in_mf(c, L) &&
+         L.gs_struct;
 }
 
 // ... and the y step too: only the z step of A's gather-scatter is taken
@@ -506,9 +516,8 @@ static bool fdm_takes_y_step(const Ctx &c, const Level &L) {
 // shares (four consecutive elements along x) before it stores
 template <typename T>
 static bool fdm_sums_x_faces(const Ctx &c, const Level &L) {
-  return sizeof(T) == 4 && c.fdm_xfaces && c.fdm_mf32 && c.opts.smoother == SEM_SMOOTH_RAS &&
-         c.fdm_prec != SEM_BF16 && c.fdm_prec != SEM_F16 && !L.coarse && L.gs_struct &&
-         L.nex % 4 == 0 && L.E % 4 == 0 && fdm_mf32_supported(c, L.p);
+  return sizeof(T) == 4 && c.fdm_xfaces && fdm_in_mf(c, L) && L.gs_struct && L.nex % 4 == 0 &&
+         L.E % 4 == 0;
 }
 
 // A u with the x step (and, when the smoother takes it, the y step) of the
@@ -531,7 +540,9 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
   const bool schwarz = c.opts.precond == SEM_PRECOND_PMG && c.opts.smoother != SEM_SMOOTH_JACOBI &&
                        !L.coarse;
   const bool asm_mode = c.opts.smoother == SEM_SMOOTH_ASM;
-  const bool mfma = sizeof(T) == 4 && (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16);
+  const bool b16 = sizeof(T) == 4 && (c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16);
+  const bool mf16 = b16 && !asm_mode && fdm_in_mf(c, L);  // 16-bit line kernel
+  const bool mfma = b16 && !mf16;                         // 16-bit tile kernel
   if (xin && !fdm_takes_x_step<T>(c, L)) fail(SEM_EINVAL, "smoother: inputs must be assembled");
   if (rs && (!schwarz || asm_mode || mfma)) {  // form r - rs in rs, then apply S to it
     launch_sub<T>(L.nloc * nv, r, rs, rs, s);
@@ -553,8 +564,11 @@ static void opS(const Ctx &c, const Level &L, const T *r, T *z, hipStream_t s, i
     ProfScope ps(c, L, SEM_PROF_FDM, s);
     if constexpr (sizeof(T) == 4) {
       if (mfma) launch_fdm_mfma(c, L, (const float *)r, (float *)z, asm_mode, c.fdm_prec, s, nv);
+      if (mf16)
+        launch_fdm_mf32(c, L, (const float *)r, (float *)z, s, nv, (const float *)rs,
+                        xin | (fxf ? 8 : 0), c.fdm_prec);
     }
-    if (!mfma) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs, xin | (fxf ? 8 : 0));
+    if (!mfma && !mf16) launch_fdm<T>(c, L, r, z, asm_mode, s, nv, rs, xin | (fxf ? 8 : 0));
   }
   if (asm_mode) return;  // the overlap sum already produced a consistent, masked vector
   if (defer) {
