@@ -145,6 +145,7 @@ struct Mf {
   static constexpr int K4 = (PB + 3) / 4;
   static constexpr int QF16 = K4 * MG, QB16 = K4 * KG;
   static_assert(QF16 <= 16 && QB16 <= 16, "16-bit A operands exceed one broadcast register");
+  static_assert(K4 == MG, "16-bit forward pairs: k groups and mode groups both cover PB");
 };
 
 // 1 / (lambda_x + lambda_y + lambda_z): +inf (a decoupled node) gives 0.  A
@@ -166,6 +167,9 @@ struct BufF32 {
                                                0x00020000)) {}
   __device__ float ld(uint32_t off) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+  }
+  __device__ f2_t ld2(uint32_t off) const {  // off a multiple of 8
+    return __builtin_bit_cast(f2_t, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
   }
   __device__ mf4_t ld4(uint32_t off) const {
     return __builtin_bit_cast(mf4_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
@@ -287,20 +291,19 @@ struct MfIn {
   float yxl[YSF], yxr[YSF];        // ... of the x-partners of its nodes 0 and p
   float ylf[YSF], yrg[YSF];        // ... of the halo nodes (left node p-1, right node 1)
   float Af[3][F::UF], Ab[3][F::UB];
-  u2_t Af16[3], Ab16[3];     // 16-bit forms: the factors over their largest entry
-  float ssc[3];              // ... and those largest entries s_d
+  u2_t Af16[3], Ab16z;       // 16-bit forms: forward and z backward A operands (factors / s_d)
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
   mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
 };
 
-// Raw-buffer view of 16-bit patterns (zero at or past nbytes, as BufF32)
-struct BufU16 {
+// Raw-buffer view of the packed 16-bit A operands (zero at or past nbytes)
+struct BufU2 {
   __amdgpu_buffer_rsrc_t rsrc;
-  __device__ BufU16(const uint16_t *p, uint32_t nbytes)
-      : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(p), (short)0, (int)nbytes,
+  __device__ BufU2(const uint32_t *p, uint32_t nbytes)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(p), (short)0, (int)nbytes,
                                                0x00020000)) {}
-  __device__ uint32_t ld(uint32_t off) const {
-    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsrc, off, 0, 0);
+  __device__ u2_t ld(uint32_t off) const {
+    return __builtin_bit_cast(u2_t, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
   }
 };
 
@@ -308,33 +311,22 @@ template <int P, bool RS, int XS, bool YS, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_load(
     MfIn<P, RS, XS, YS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
     int64_t eb, const float *__restrict__ Sg, const float *__restrict__ lamg,
-    const float *__restrict__ W, int lane, const uint16_t *__restrict__ S16 = nullptr,
+    const float *__restrict__ W, int lane, const uint32_t *__restrict__ A16 = nullptr,
     const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, MG = F::MG, KG = F::KG;
   if constexpr (OP != kOpF32) {
-    // 16-bit A operands of S_d / s_d: forward pair q = (kg, g) -> lane 4q + i
-    // holds S_d[4kg + kk][4g + i], kk < 4; backward q = (mg, g) -> S_d[1 + 4g +
-    // i][4mg + kk]; zero where an index runs past the factor
-    const BufU16 Sh(S16 + e * 3 * PB * PB, 3 * PB * PB * 2);
-    const int i = lane & 3, q = lane >> 2;
-    const int kg = q / MG, gf = q % MG, mg = q / KG, gb = q % KG;
+    // 16-bit A operands, packed at setup in lane order (k_fdm_mf16_pack): the
+    // lanes of the forward pairs, then those of the backward pairs, per
+    // direction; the other lanes read zeros
+    constexpr int NF = 4 * F::QF16, NE = 4 * (F::QF16 + F::QB16);
+    const BufU2 At(A16 + e * 3 * NE * 2, 3 * NE * 8);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      uint32_t hf[4], hb[4];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int k = 4 * kg + kk, m = 4 * gf + i;
-        hf[kk] = Sh.ld(q < F::QF16 && k < PB && m < PB ? (uint32_t)((d * PB + k) * PB + m) * 2
-                                                        : kOutside);
-        const int kn = 1 + 4 * gb + i, mm = 4 * mg + kk;
-        hb[kk] = Sh.ld(q < F::QB16 && kn <= N && mm < PB ? (uint32_t)((d * PB + kn) * PB + mm) * 2
-                                                         : kOutside);
-      }
-      in.Af16[d] = u2_t{hf[0] | hf[1] << 16, hf[2] | hf[3] << 16};
-      in.Ab16[d] = u2_t{hb[0] | hb[1] << 16, hb[2] | hb[3] << 16};
-      in.ssc[d] = ssc[e * 3 + d];
-    }
+    for (int d = 0; d < 3; ++d)
+      in.Af16[d] = At.ld(lane < NF ? (uint32_t)(d * NE + lane) * 8 : kOutside);
+    in.Ab16z = At.ld(lane < NE - NF ? (uint32_t)(2 * NE + NF + lane) * 8 : kOutside);
+    // (what the last two passes read is loaded by the solve once its first
+    // pass is issued)
   } else {
   const BufF32 Se(Sg + e * 3 * PB * PB, 3 * PB * PB * 4);  // the element's three factors
   // A operands: forward (k, g) -> lane 4q + i holds S_d[k][4g + i]; backward
@@ -367,6 +359,8 @@ __device__ __attribute__((always_inline)) inline void mf_load(
       const int l = 64 * s + lane, lc = l < F::NL ? l : 0;
       in.lxy[s] = le[lc % PB] + le[PB + lc / PB];
     }
+  }
+  if constexpr (OP == kOpF32) {
 #pragma unroll
     for (int s = 0; s < F::SX; ++s) {
       const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
@@ -398,12 +392,26 @@ __device__ __attribute__((always_inline)) inline void mf_load(
     const uint32_t orow = okyz ? row : kOutside;
     const uint32_t il = okl ? row - (N3 - P + 1) * 4 : kOutside;  // left neighbour's node p-1
     const uint32_t ir = okr ? row + (N3 + 1) * 4 : kOutside;      // right neighbour's node 1
-    in.lft[s] = r.ld(il);
-    in.rgt[s] = r.ld(ir);
+    // 16-bit forms, odd p: a neighbour's halo node and its x-partner node are
+    // adjacent and 8-byte aligned (even p - 1), one load for both
+    constexpr bool PAIR = OP != kOpF32 && P % 2 == 1 && XS == 1;
+    if constexpr (PAIR) {
+      const f2_t lp = r.ld2(il);                            // left neighbour's nodes p-1, p
+      const f2_t rp = r.ld2(okr ? row + N3 * 4 : kOutside);  // right neighbour's nodes 0, 1
+      in.lft[s] = lp[0];
+      in.xlp[s] = lp[1];
+      in.xrp[s] = rp[0];
+      in.rgt[s] = rp[1];
+    } else {
+      in.lft[s] = r.ld(il);
+      in.rgt[s] = r.ld(ir);
+    }
     if constexpr (XS != 0) {
       const BufF32 &xs = XS == 1 ? r : rs;
-      in.xlp[s] = xs.ld(okl ? row - (N3 - P) * 4 : kOutside);  // left neighbour's node p
-      in.xrp[s] = xs.ld(okr ? row + N3 * 4 : kOutside);        // right neighbour's node 0
+      if constexpr (!PAIR) {
+        in.xlp[s] = xs.ld(okl ? row - (N3 - P) * 4 : kOutside);  // left neighbour's node p
+        in.xrp[s] = xs.ld(okr ? row + N3 * 4 : kOutside);        // right neighbour's node 0
+      }
       if constexpr (YS) {
         // own row j = 0 (b = 1) pairs with row j = p of the element below in
         // y, row j = p (b = PB - 2) with row j = 0 of the one above
@@ -424,10 +432,19 @@ __device__ __attribute__((always_inline)) inline void mf_load(
           for (int i = 0; i < N; ++i) in.yrow[s][i] = xs.ld(yrow + 4 * i);
         }
         const bool yl = yp && ex > 0, yh = yp && ex < nex - 1;
-        in.yxl[s] = xs.ld(yl ? yr - (N3 - P) * 4 : kOutside);
-        in.yxr[s] = xs.ld(yh ? yr + N3 * 4 : kOutside);
-        in.ylf[s] = xs.ld(yl ? yr - (N3 - P + 1) * 4 : kOutside);
-        in.yrg[s] = xs.ld(yh ? yr + (N3 + 1) * 4 : kOutside);
+        if constexpr (PAIR) {
+          const f2_t lp = xs.ld2(yl ? yr - (N3 - P + 1) * 4 : kOutside);
+          const f2_t rp = xs.ld2(yh ? yr + N3 * 4 : kOutside);
+          in.ylf[s] = lp[0];
+          in.yxl[s] = lp[1];
+          in.yxr[s] = rp[0];
+          in.yrg[s] = rp[1];
+        } else {
+          in.yxl[s] = xs.ld(yl ? yr - (N3 - P) * 4 : kOutside);
+          in.yxr[s] = xs.ld(yh ? yr + N3 * 4 : kOutside);
+          in.ylf[s] = xs.ld(yl ? yr - (N3 - P + 1) * 4 : kOutside);
+          in.yrg[s] = xs.ld(yh ? yr + (N3 + 1) * 4 : kOutside);
+        }
       }
     }
     if constexpr (N % 4 == 0) {
@@ -465,15 +482,57 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 // shared by the workgroup) before the store, each pair as (p-face + 0-face),
 // the order of the gather-scatter's x step, which then covers only the faces
 // between workgroups.
-// 16-bit operands (OP): the element's box is brought into [0.5, 1) by a power
-// of two from its largest entry before the forward passes, the eigenvalue-
-// scaled tensor likewise before the backward passes, and the factors are
-// stored over their largest entries s_d; the output is scaled back by the two
-// powers of two and (s_x s_y s_z)^2.
+// What the 16-bit forms' last two passes read, loaded once the first pass is
+// issued (fewer registers live while the box arrives): the y and x backward
+// A operands, the factor scales s_d and the RAS weights of the output rows
+template <int P>
+struct MfLate {
+  using F = Mf<P>;
+  u2_t Ab16[2];
+  float ssc[3];
+  mf4_t wrow[F::SX][F::KG];
+};
+template <int P>
+__device__ __attribute__((always_inline)) inline void mf_load_late(
+    MfLate<P> &lt, int64_t e, const float *__restrict__ lamg, const float *__restrict__ W,
+    const uint32_t *__restrict__ A16, const float *__restrict__ ssc, int lane) {
+  using F = Mf<P>;
+  constexpr int PB = F::PB, N = F::N, N3 = F::N3;
+  constexpr int NF = 4 * F::QF16, NE = 4 * (F::QF16 + F::QB16);
+  const BufU2 At(A16 + e * 3 * NE * 2, 3 * NE * 8);
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+    lt.Ab16[d] = At.ld(lane < NE - NF ? (uint32_t)(d * NE + NF + lane) * 8 : kOutside);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lt.ssc[d] = ssc[e * 3 + d];
+#pragma unroll
+  for (int s = 0; s < F::SX; ++s) {
+    const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
+    const int64_t row = e * N3 + (int64_t)lc * N;
+#pragma unroll
+    for (int g = 0; g < F::KG; ++g) {
+      if constexpr (N % 4 == 0) {
+        lt.wrow[s][g] = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lt.wrow[s][g][i] = 4 * g + i < N ? W[row + 4 * g + i] : 0.f;
+      }
+    }
+  }
+}
+
+// 16-bit operands (OP): the factors are stored over their largest entries s_d
+// and the output is scaled back by (s_x s_y s_z)^2.  FP16 has a narrow
+// exponent range, so there the element's box is also brought into [0.5, 1)
+// by a power of two from its largest entry before the forward passes, and the
+// eigenvalue-scaled tensor likewise before the backward passes (the output
+// then takes both powers of two back); BF16 keeps FP32's exponent range and
+// needs neither.
 template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_solve(
     const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
-    float *buf, int lane, float *xfx, int wave) {
+    float *buf, int lane, float *xfx, int wave, const float *__restrict__ W = nullptr,
+    const uint32_t *__restrict__ A16 = nullptr, const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
   const float *le = lamg + e * 3 * PB;
@@ -518,7 +577,8 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 
   int e_in = 0, e_h = 0;
   float sc_in = 1.f;
-  if constexpr (OP != kOpF32) {
+  constexpr bool NORM = OP == kOpF16;  // range scaling of the 16-bit operands
+  if constexpr (NORM) {
     float m = 0.f;
 #pragma unroll
     for (int s = 0; s < F::SF; ++s)
@@ -531,10 +591,12 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     if constexpr (OP != kOpF32)
-      mf16_forward<P, OP, true>(in.Af16[0], v[s], sc_in, acc[s]);
+      mf16_forward<P, OP, NORM>(in.Af16[0], v[s], sc_in, acc[s]);
     else
       mf_forward<P>(in.Af[0], v[s], acc[s]);
   }
+  MfLate<P> lt;
+  if constexpr (OP != kOpF32) mf_load_late<P>(lt, e, lamg, W, A16, ssc, lane);
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
@@ -594,12 +656,13 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 #pragma unroll
       for (int k = 0; k < PB; ++k) {
         h[s][k] = acc[s][k >> 2][k & 3] * mf_inv(lxy + le[2 * PB + k]);
-        m = fmaxf(m, fabsf(h[s][k]));
+        if constexpr (NORM) m = fmaxf(m, fabsf(h[s][k]));
       }
     }
-    const float sc_h = pow2_below(wave_absmax(m), e_h);
+    float sc_h = 1.f;
+    if constexpr (NORM) sc_h = pow2_below(wave_absmax(m), e_h);
 #pragma unroll
-    for (int s = 0; s < F::SF; ++s) mf16_backward<P, OP, true>(in.Ab16[2], h[s], sc_h, bk[s]);
+    for (int s = 0; s < F::SF; ++s) mf16_backward<P, OP, NORM>(in.Ab16z, h[s], sc_h, bk[s]);
   } else {
 #pragma unroll
     for (int s = 0; s < F::SF; ++s) {
@@ -637,7 +700,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 #pragma unroll
   for (int s = 0; s < F::SY; ++s) {
     if constexpr (OP != kOpF32)
-      mf16_backward<P, OP, false>(in.Ab16[1], w[s], 1.f, by[s]);
+      mf16_backward<P, OP, false>(lt.Ab16[1], w[s], 1.f, by[s]);
     else
       mf_backward<P>(in.Ab[1], w[s], by[s]);
   }
@@ -661,7 +724,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
   mf4_t o[F::SX][KG];
   float osc = 1.f;
   if constexpr (OP != kOpF32) {
-    const float s3 = in.ssc[0] * in.ssc[1] * in.ssc[2];
+    const float s3 = lt.ssc[0] * lt.ssc[1] * lt.ssc[2];
     osc = __builtin_amdgcn_ldexpf(s3 * s3, e_in + e_h);
   }
 #pragma unroll
@@ -671,9 +734,9 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     mf4_t bx[KG];
     mf_read_line<P>(buf, l < F::NLX ? l : 0, u);
     if constexpr (OP != kOpF32) {
-      mf16_backward<P, OP, false>(in.Ab16[0], u, 1.f, bx);
+      mf16_backward<P, OP, false>(lt.Ab16[0], u, 1.f, bx);
 #pragma unroll
-      for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * (bx[g] * osc);
+      for (int g = 0; g < KG; ++g) o[s][g] = lt.wrow[s][g] * (bx[g] * osc);
     } else {
       mf_backward<P>(in.Ab[0], u, bx);
 #pragma unroll
@@ -774,7 +837,7 @@ template <int P, bool RS, int XS, bool YS, bool XF, int OP>
 __global__ __launch_bounds__(256) void k_fdm_mf16(int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ rs,
-                                                  const uint16_t *__restrict__ S16,
+                                                  const uint32_t *__restrict__ A16,
                                                   const float *__restrict__ ssc,
                                                   const float *__restrict__ lamg,
                                                   const float *__restrict__ W,
@@ -797,8 +860,8 @@ __global__ __launch_bounds__(256) void k_fdm_mf16(int64_t E, int nex, int ney, i
   const uint32_t wn = wb < (int64_t)kWindowMax ? (uint32_t)wb : kWindowMax;
   const BufF32 rb(r + eb * N3, wn), rsb(RS ? rs + eb * N3 : r + eb * N3, wn);
   MfIn<P, RS, XS, YS> in;
-  mf_load<P, RS, XS, YS, OP>(in, e, nex, ney, nez, rb, rsb, eb, nullptr, lamg, W, lane, S16, ssc);
-  mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave);
+  mf_load<P, RS, XS, YS, OP>(in, e, nex, ney, nez, rb, rsb, eb, nullptr, lamg, W, lane, A16, ssc);
+  mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave, W, A16, ssc);
 }
 
 template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
@@ -808,10 +871,10 @@ void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs
   if constexpr (OP != kOpF32) {
     if (XF && (L.E % F::WAVES != 0 || c.nex % F::WAVES != 0))
       fail(SEM_EINVAL, "FDM: x-face sums need whole groups of four elements along x");
-    if (!L.S16 || !L.sscale) fail(SEM_EINVAL, "16-bit FDM data were not built");
+    if (!L.A16 || !L.sscale) fail(SEM_EINVAL, "16-bit FDM data were not built");
     const dim3 grid((unsigned)((L.E + F::WAVES - 1) / F::WAVES * nv));
     hipLaunchKernelGGL((k_fdm_mf16<P, RS, XS, YS, XF, OP>), grid, dim3(64 * F::WAVES), 0, s, L.E,
-                       c.nex, c.ney, c.nez, r, rs, L.S16, L.sscale, L.lam32, L.w32, z, nv);
+                       c.nex, c.ney, c.nez, r, rs, L.A16, L.sscale, L.lam32, L.w32, z, nv);
     SEM_LAUNCH("k_fdm_mf16");
   } else {
     const int C = XF ? 1 : c.fdm_mf32_chain;
@@ -866,7 +929,60 @@ void mf32_launch(const Ctx &c, const Level &L, const float *r, const float *rs, 
   }
 }
 
+// Setup of L.A16 from the 16-bit factors S16 = S_d / s_d ([E][3][pb][pb]):
+// for element e and direction d, the 4 QF16 lanes of the forward pairs (lane
+// 4q + i, q = (kg, g): S16_d[4kg + kk][4g + i], kk < 4) and the 4 QB16 lanes of
+// the backward pairs (q = (mg, g): S16_d[1 + 4g + i][4mg + kk]), four 16-bit
+// patterns per lane in two words, zero past the factor.  One thread per lane
+// entry.
+__global__ void k_fdm_mf16_pack(int64_t E, int pb, int n, int mg, int kg, int nf, int nb,
+                                const uint16_t *__restrict__ S16, uint32_t *__restrict__ A16) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int ne = nf + nb;
+  if (t >= E * 3 * ne) return;
+  const int64_t ed = t / ne;  // e * 3 + d
+  const int j = (int)(t - ed * ne);
+  const uint16_t *Sd = S16 + ed * pb * pb;
+  uint32_t h[4];
+  if (j < nf) {
+    const int q = j >> 2, i = j & 3, k4 = q / mg, g = q % mg;
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * k4 + kk, m = 4 * g + i;
+      h[kk] = k < pb && m < pb ? Sd[k * pb + m] : 0u;
+    }
+  } else {
+    const int q = (j - nf) >> 2, i = (j - nf) & 3, m4 = q / kg, g = q % kg;
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kn = 1 + 4 * g + i, m = 4 * m4 + kk;
+      h[kk] = kn <= n && m < pb ? Sd[kn * pb + m] : 0u;
+    }
+  }
+  A16[2 * t] = h[0] | h[1] << 16;
+  A16[2 * t + 1] = h[2] | h[3] << 16;
+}
+
+struct Mf16Dims {
+  int pb, n, mg, kg, nf, nb;
+  explicit Mf16Dims(int p)
+      : pb(p + 3), n(p + 1), mg((p + 6) / 4), kg((p + 4) / 4),
+        nf(4 * ((p + 6) / 4) * ((p + 6) / 4)), nb(4 * ((p + 6) / 4) * ((p + 4) / 4)) {}
+};
+
 }  // namespace
+
+size_t mf16_table_words(int p) {
+  const Mf16Dims D(p);
+  return (size_t)3 * (D.nf + D.nb) * 2;
+}
+
+void launch_fdm_mf16_pack(const Level &L, hipStream_t s) {
+  if (!L.S16 || !L.A16) fail(SEM_EINVAL, "16-bit FDM data were not built");
+  const Mf16Dims D(L.p);
+  const int64_t n = L.E * 3 * (D.nf + D.nb);
+  hipLaunchKernelGGL(k_fdm_mf16_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L.E, D.pb,
+                     D.n, D.mg, D.kg, D.nf, D.nb, L.S16, L.A16);
+  SEM_LAUNCH("k_fdm_mf16_pack");
+}
 
 // A box floats (a zero eigenvalue sum) only when every direction has one
 // element and Neumann faces at both ends: then the 1D problem of each

@@ -128,6 +128,7 @@ struct Level {
   float *S32 = nullptr, *lam32 = nullptr;
   uint16_t *S16 = nullptr;  // S / s_d in BF16 or FP16 bit patterns (MFMA path)
   float *sscale = nullptr;  // [E][3] s_d = max |S_d|
+  uint32_t *A16 = nullptr;  // the 16-bit line kernel's A operands of S16, in lane order
   double *boxlen = nullptr; // [E][3]
   double *box64 = nullptr;  // [E][pb^3] ASM local-solve outputs before the overlap sum
   float *box32 = nullptr;
@@ -399,6 +400,10 @@ bool fdm_mf32_supported(const Ctx &c, int p);
 // SEM_BF16 with the level's 16-bit factors)
 void launch_fdm_mf32(const Ctx &c, const Level &L, const float *r, float *z, hipStream_t s, int nv,
                      const float *rs, int xin, int prec = SEM_F32);
+// 32-bit words per element of L.A16 (degree p, 2 <= p <= 9), and its setup
+// from L.S16
+size_t mf16_table_words(int p);
+void launch_fdm_mf16_pack(const Level &L, hipStream_t s);
 
 // coarse.hip
 bool coarse_assembled_ok(const Ctx &c, const Level &C);

@@ -152,6 +152,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
         if (o.fdm_prec == SEM_BF16 || o.fdm_prec == SEM_F16) {
           L.S16 = A.take<uint16_t>(3 * L.E * pb * pb);
           L.sscale = A.take<float>(3 * L.E);
+          if (L.p >= 2 && L.p <= 9) L.A16 = A.take<uint32_t>(L.E * mf16_table_words(L.p));
         }
       }
       if (asm_on) {
@@ -496,7 +497,7 @@ static void opA_dot(const Ctx &c, const Level &L, const double *p, double *q, do
 // (otherwise the 16-bit tile kernel of fdm_mfma.hip)
 static bool fdm_in_mf(const Ctx &c, const Level &L) {
   const bool b16 = c.fdm_prec == SEM_BF16 || c.fdm_prec == SEM_F16;
-  return (b16 ? c.fdm_mf16 && L.S16 && L.sscale : c.fdm_mf32) &&
+  return (b16 ? c.fdm_mf16 && L.A16 && L.sscale : c.fdm_mf32) &&
          c.opts.smoother == SEM_SMOOTH_RAS && !L.coarse && fdm_mf32_supported(c, L.p);
 }
 
@@ -885,7 +886,10 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
   if (bad) fail(SEM_EGEOM, "an element has a non-positive Jacobian determinant");
   if (c.lowp) {
     for (int l = 0; l < c.nlev; ++l)
-      if (c.lev[l].S16) launch_fdm_mfma(c, c.lev[l], nullptr, nullptr, false, -1, s);  // pack S
+      if (c.lev[l].S16) {
+        launch_fdm_mfma(c, c.lev[l], nullptr, nullptr, false, -1, s);  // pack S
+        if (c.lev[l].A16) launch_fdm_mf16_pack(c.lev[l], s);
+      }
   }
 
   if (c.opts.precond == SEM_PRECOND_PMG) {
