@@ -270,7 +270,9 @@ __device__ inline void mf_sync() {
 // What one element's solve reads from global memory, loaded ahead of its use:
 // the x-lines of the box (the element's own row of a y/z neighbour or itself,
 // and one node of each x-neighbour; RS: also those of the subtrahend), zero
-// where they lie outside the domain, and the A operands of its six passes.
+// where they lie outside the domain, the A operands of its first four passes
+// and the eigenvalue sums of the z pass (what the last two passes read comes
+// later, mf_load_late).
 // XS = 1 (r) or 2 (rs): that input comes from A with the x step of its
 // gather-scatter left out (its y and z steps done), so the x-neighbours'
 // copies of the row's end nodes (their nodes p and 0) are read as well and
@@ -293,7 +295,6 @@ struct MfIn {
   float Af[3][F::UF], Ab[3][F::UB];
   u2_t Af16[3], Ab16z;       // 16-bit forms: forward and z backward A operands (factors / s_d)
   float lxy[F::SF];          // lambda_x + lambda_y of the slot's z-line
-  mf4_t wrow[F::SX][F::KG];  // RAS weights of the slot's output row
 };
 
 // Raw-buffer view of the packed 16-bit A operands (zero at or past nbytes)
@@ -344,36 +345,17 @@ __device__ __attribute__((always_inline)) inline void mf_load(
     for (int u = 0; u < F::UB; ++u) {
       const int q = 16 * u + qb, m = q / KG, k = 1 + 4 * (q % KG) + i;
       const uint32_t at = q < F::QB && k <= N ? (uint32_t)(k * PB + m) * 4 : kOutside;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) in.Ab[d][u] = Se.ld(at + d * PB * PB * 4);
+      in.Ab[2][u] = Se.ld(at + 2 * PB * PB * 4);  // (x and y: loaded by the solve)
     }
   }
   }
-  // eigenvalue sums of the z pass (line (a', b') of slot s) and the RAS weights
-  // of the rows the last pass writes; loaded here so that a solve issues no
-  // vector loads of its own (they would wait behind the next element's)
+  // eigenvalue sums of the z pass (line (a', b') of slot s)
   {
     const float *le = lamg + e * 3 * PB;
 #pragma unroll
     for (int s = 0; s < F::SF; ++s) {
       const int l = 64 * s + lane, lc = l < F::NL ? l : 0;
       in.lxy[s] = le[lc % PB] + le[PB + lc / PB];
-    }
-  }
-  if constexpr (OP == kOpF32) {
-#pragma unroll
-    for (int s = 0; s < F::SX; ++s) {
-      const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
-      const int64_t row = e * N3 + (int64_t)lc * N;
-#pragma unroll
-      for (int g = 0; g < F::KG; ++g) {
-        if constexpr (N % 4 == 0) {
-          in.wrow[s][g] = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) in.wrow[s][g][i] = 4 * g + i < N ? W[row + 4 * g + i] : 0.f;
-        }
-      }
     }
   }
   int64_t ex, ey, ez;
@@ -392,9 +374,9 @@ __device__ __attribute__((always_inline)) inline void mf_load(
     const uint32_t orow = okyz ? row : kOutside;
     const uint32_t il = okl ? row - (N3 - P + 1) * 4 : kOutside;  // left neighbour's node p-1
     const uint32_t ir = okr ? row + (N3 + 1) * 4 : kOutside;      // right neighbour's node 1
-    // 16-bit forms, odd p: a neighbour's halo node and its x-partner node are
-    // adjacent and 8-byte aligned (even p - 1), one load for both
-    constexpr bool PAIR = OP != kOpF32 && P % 2 == 1 && XS == 1;
+    // odd p: a neighbour's halo node and its x-partner node are adjacent and
+    // 8-byte aligned (even p - 1), one load for both
+    constexpr bool PAIR = P % 2 == 1 && XS == 1;
     if constexpr (PAIR) {
       const f2_t lp = r.ld2(il);                            // left neighbour's nodes p-1, p
       const f2_t rp = r.ld2(okr ? row + N3 * 4 : kOutside);  // right neighbour's nodes 0, 1
@@ -482,29 +464,44 @@ __device__ __attribute__((always_inline)) inline void mf_load(
 // shared by the workgroup) before the store, each pair as (p-face + 0-face),
 // the order of the gather-scatter's x step, which then covers only the faces
 // between workgroups.
-// What the 16-bit forms' last two passes read, loaded once the first pass is
-// issued (fewer registers live while the box arrives): the y and x backward
-// A operands, the factor scales s_d and the RAS weights of the output rows
+// What the last two passes read, loaded once the first pass is issued, so
+// that fewer registers are live while the box arrives (at p = 7: 78 instead of
+// 85 for the x/y-step form, 6 wavefronts per SIMD instead of 5): the y and x
+// backward A operands, the 16-bit forms' factor scales s_d, and the RAS
+// weights of the output rows
 template <int P>
 struct MfLate {
   using F = Mf<P>;
-  u2_t Ab16[2];
+  float Ab[2][F::UB];  // FP32 operands
+  u2_t Ab16[2];        // 16-bit operands
   float ssc[3];
   mf4_t wrow[F::SX][F::KG];
 };
-template <int P>
+template <int P, int OP>
 __device__ __attribute__((always_inline)) inline void mf_load_late(
-    MfLate<P> &lt, int64_t e, const float *__restrict__ lamg, const float *__restrict__ W,
+    MfLate<P> &lt, int64_t e, const float *__restrict__ Sg, const float *__restrict__ W,
     const uint32_t *__restrict__ A16, const float *__restrict__ ssc, int lane) {
   using F = Mf<P>;
-  constexpr int PB = F::PB, N = F::N, N3 = F::N3;
-  constexpr int NF = 4 * F::QF16, NE = 4 * (F::QF16 + F::QB16);
-  const BufU2 At(A16 + e * 3 * NE * 2, 3 * NE * 8);
+  constexpr int PB = F::PB, N = F::N, N3 = F::N3, KG = F::KG;
+  if constexpr (OP != kOpF32) {
+    constexpr int NF = 4 * F::QF16, NE = 4 * (F::QF16 + F::QB16);
+    const BufU2 At(A16 + e * 3 * NE * 2, 3 * NE * 8);
 #pragma unroll
-  for (int d = 0; d < 2; ++d)
-    lt.Ab16[d] = At.ld(lane < NE - NF ? (uint32_t)(d * NE + NF + lane) * 8 : kOutside);
+    for (int d = 0; d < 2; ++d)
+      lt.Ab16[d] = At.ld(lane < NE - NF ? (uint32_t)(d * NE + NF + lane) * 8 : kOutside);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) lt.ssc[d] = ssc[e * 3 + d];
+    for (int d = 0; d < 3; ++d) lt.ssc[d] = ssc[e * 3 + d];
+  } else {
+    const BufF32 Se(Sg + e * 3 * PB * PB, 3 * PB * PB * 4);
+    const int i = lane & 3, qb = lane >> 2;
+#pragma unroll
+    for (int u = 0; u < F::UB; ++u) {
+      const int q = 16 * u + qb, m = q / KG, k = 1 + 4 * (q % KG) + i;
+      const uint32_t at = q < F::QB && k <= N ? (uint32_t)(k * PB + m) * 4 : kOutside;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) lt.Ab[d][u] = Se.ld(at + d * PB * PB * 4);
+    }
+  }
 #pragma unroll
   for (int s = 0; s < F::SX; ++s) {
     const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
@@ -531,8 +528,9 @@ __device__ __attribute__((always_inline)) inline void mf_load_late(
 template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_solve(
     const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
-    float *buf, int lane, float *xfx, int wave, const float *__restrict__ W = nullptr,
-    const uint32_t *__restrict__ A16 = nullptr, const float *__restrict__ ssc = nullptr) {
+    float *buf, int lane, float *xfx, int wave, const float *__restrict__ Sg,
+    const float *__restrict__ W, const uint32_t *__restrict__ A16 = nullptr,
+    const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
   const float *le = lamg + e * 3 * PB;
@@ -596,7 +594,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
       mf_forward<P>(in.Af[0], v[s], acc[s]);
   }
   MfLate<P> lt;
-  if constexpr (OP != kOpF32) mf_load_late<P>(lt, e, lamg, W, A16, ssc, lane);
+  mf_load_late<P, OP>(lt, e, Sg, W, A16, ssc, lane);
 #pragma unroll
   for (int s = 0; s < F::SF; ++s) {
     const int l = 64 * s + lane;
@@ -702,7 +700,7 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
     if constexpr (OP != kOpF32)
       mf16_backward<P, OP, false>(lt.Ab16[1], w[s], 1.f, by[s]);
     else
-      mf_backward<P>(in.Ab[1], w[s], by[s]);
+      mf_backward<P>(lt.Ab[1], w[s], by[s]);
   }
   mf_sync();
 #pragma unroll
@@ -738,9 +736,9 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
 #pragma unroll
       for (int g = 0; g < KG; ++g) o[s][g] = lt.wrow[s][g] * (bx[g] * osc);
     } else {
-      mf_backward<P>(in.Ab[0], u, bx);
+      mf_backward<P>(lt.Ab[0], u, bx);
 #pragma unroll
-      for (int g = 0; g < KG; ++g) o[s][g] = in.wrow[s][g] * bx[g];
+      for (int g = 0; g < KG; ++g) o[s][g] = lt.wrow[s][g] * bx[g];
     }
   }
   if constexpr (XF) {
@@ -827,7 +825,7 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
     if (it + 1 < C)  // (past the last element: reloads it, unused)
       mf_load<P, RS, XS, YS>(in[(it + 1) & 1], e + 1 < E ? e + 1 : e, nex, ney, nez, rb, rsb, eb, Sg,
                          lamg, W, lane);
-    mf_solve<P, RS, XS, YS, XF>(in[it & 1], e, lamg, z, buf, lane, xfx, wave);
+    mf_solve<P, RS, XS, YS, XF>(in[it & 1], e, lamg, z, buf, lane, xfx, wave, Sg, W);
   }
 }
 
@@ -861,7 +859,7 @@ __global__ __launch_bounds__(256) void k_fdm_mf16(int64_t E, int nex, int ney, i
   const BufF32 rb(r + eb * N3, wn), rsb(RS ? rs + eb * N3 : r + eb * N3, wn);
   MfIn<P, RS, XS, YS> in;
   mf_load<P, RS, XS, YS, OP>(in, e, nex, ney, nez, rb, rsb, eb, nullptr, lamg, W, lane, A16, ssc);
-  mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave, W, A16, ssc);
+  mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave, nullptr, W, A16, ssc);
 }
 
 template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
