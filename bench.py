@@ -413,10 +413,10 @@ TRAFFIC_32CUBE_P7 = {
     "ax64": 1072564224,   # k_ax8_f64<true,false> as the solve runs it (x-faces left to the FCG update)
     "ax32": 536990080,    # k_ax8_f32<true,false> (the smoother's A, 5 of 6 launches per V-cycle)
     # matrix-core RAS local solves per finest-level launch as a V-cycle mixes
-    # them: 4 x k_fdm_mf32<7,1,false,1,true,false> (260,947,435 B), 1 x the
-    # residual form <7,1,true,2,true,true> (344,633,216 B), 1 x the zero-start
-    # form <7,1,false,0,false,true> (261,229,696 B)
-    "fdm": 274942109,
+    # them: 4 x k_fdm_mf32<7,1,false,1,true,false> (262,436,075 B), 1 x the
+    # residual form <7,1,true,2,true,true> (350,971,989 B), 1 x the zero-start
+    # form <7,1,false,0,false,true> (261,656,405 B)
+    "fdm": 277062116,
 }
 # dense FP32 on the matrix cores (the FDM contractions run there)
 FP32_MATRIX_PEAK_TFLOPS = 157.3

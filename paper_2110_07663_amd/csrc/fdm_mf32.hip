@@ -831,8 +831,11 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
 
 // The same solve with FP16 or BF16 operands (OP), one element per wave:
 // S16 = S_d / s_d as 16-bit patterns, ssc = s_d per element and direction.
+// (at most 6 wavefronts per SIMD asked of the register allocator: aiming
+// higher made it spill some BF16 forms at p = 7)
 template <int P, bool RS, int XS, bool YS, bool XF, int OP>
-__global__ __launch_bounds__(256) void k_fdm_mf16(int64_t E, int nex, int ney, int nez,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 6))) void k_fdm_mf16(
+    int64_t E, int nex, int ney, int nez,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ rs,
                                                   const uint32_t *__restrict__ A16,
