@@ -114,7 +114,8 @@ __device__ __attribute__((always_inline)) inline mf4_t mfma16(u2_t a, u2_t b, mf
   }
 }
 
-// the largest |value| over the wavefront
+// the largest of the lanes' values over the wavefront (the callers pass
+// each lane's largest |entry|)
 __device__ inline float wave_absmax(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
