@@ -25,6 +25,8 @@
 // its entries of the CG vectors in registers and the phases are separated by
 // grid barriers that carry the partial sums.  On an 8-XCD device a grid
 // barrier costs more than a kernel boundary, so this is not the default.
+#include <algorithm>
+
 #include "sem_internal.h"
 
 namespace sem {
@@ -326,11 +328,12 @@ __device__ inline void wave_sum(double (&acc)[ND]) {
     for (int j = 0; j < ND; ++j) acc[j] += __shfl_xor(acc[j], o, 64);
 }
 
-// cg_last_block for 1024-thread blocks: wave sums, then the 16 wave sums in
-// order; the last block sums the block partials the same way.
-template <int ND>
-__device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, unsigned *counter) {
-  __shared__ double sh[ND][16];
+// cg_last_block for blocks of NW wavefronts: wave sums, then the NW wave sums
+// in order; the last block sums the block partials the same way.
+template <int ND, int NW>
+__device__ inline bool cg_last_block_waves(double (&acc)[ND], double *partials,
+                                           unsigned *counter) {
+  __shared__ double sh[ND][NW];
   __shared__ bool is_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   wave_sum<ND>(acc);
@@ -343,7 +346,7 @@ __device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, uns
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
       double t = 0.0;
-      for (int w = 0; w < 16; ++w) t += sh[j][w];
+      for (int w = 0; w < NW; ++w) t += sh[j][w];
       partials[blockIdx.x * 4 + j] = t;
     }
     __threadfence();
@@ -354,7 +357,7 @@ __device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, uns
   __threadfence();
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  for (int b = tid; b < (int)gridDim.x; b += 1024)
+  for (int b = tid; b < (int)gridDim.x; b += 64 * NW)
 #pragma unroll
     for (int j = 0; j < ND; ++j)
       acc[j] += __hip_atomic_load(&partials[b * 4 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -367,7 +370,7 @@ __device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, uns
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
     double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += sh[j][w];
+    for (int w = 0; w < NW; ++w) t += sh[j][w];
     acc[j] = t;
   }
   if (tid == 0) *counter = 0u;
@@ -377,17 +380,22 @@ __device__ inline bool cg_last_block_1k(double (&acc)[ND], double *partials, uns
 // One iteration: p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s,
 // z = D^{-1} r, w = A z, then (r,z), (r,r), (w,z) -> gamma, rr, delta and the
 // next alpha, beta.  Reads r, s, w from copy `par`, writes them to copy 1-par.
-// Four lanes share a row (lane q takes stencil entries q, q+4, ...), 256 rows
-// per 1024-thread block; every load is issued before the scalars are known, so
-// the kernel waits on memory about once.
-constexpr int kCgRows = 256;
-__global__ __launch_bounds__(1024) void k_cg_iter(int64_t n, CoarseGrid g, CgPtrs P, int par) {
+// Four lanes share a row (lane q takes stencil entries q, q+4, ...), 64 rows
+// per 256-thread block (four times as many blocks as 256-row, 1024-thread
+// ones: at 17^3 unknowns 77 compute units share the stencil reads instead of
+// 20); every load is issued before the scalars are known, so the kernel waits
+// on memory about once.
+constexpr int kCgRows = 256;     // rows per block of the start kernels
+constexpr int kCgIterWaves = 4;  // wavefronts per block of the iteration
+constexpr int kCgIterRows = 16 * kCgIterWaves;
+__global__ __launch_bounds__(64 * kCgIterWaves) void k_cg_iter(int64_t n, CoarseGrid g, CgPtrs P,
+                                                                int par) {
   CoarseScalars *c = P.sc;
   const double *__restrict__ R = par ? P.r2 : P.r;
   const double *__restrict__ Wv = par ? P.w2 : P.w;
   const double *__restrict__ Sv = par ? P.s2 : P.s;
   const int q = threadIdx.x & 3;
-  const int64_t t = blockIdx.x * (int64_t)kCgRows + (threadIdx.x >> 2);
+  const int64_t t = blockIdx.x * (int64_t)kCgIterRows + (threadIdx.x >> 2);
   const bool row = t < n;
   const int64_t tt = row ? t : 0;
   const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(1024) void k_cg_iter(int64_t n, CoarseGrid g, CgPtr
     acc[1] = rv * rv;
     acc[2] = wq * zv;
   }
-  if (cg_last_block_1k<3>(acc, P.partials, P.counter) && threadIdx.x == 0) {
+  if (cg_last_block_waves<3, kCgIterWaves>(acc, P.partials, P.counter) && threadIdx.x == 0) {
     c->gamma_old = c->gamma;
     c->gamma = acc[0];
     c->rr = acc[1];
@@ -644,8 +652,17 @@ __global__ __launch_bounds__(256) void k_cg_persistent(CoarseGrid g, CgPtrs P, d
 }
 
 static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
-// CG kernels: one block per 256 rows (256 threads for the start kernels, 1024
-// for the iteration); the grid is fixed per solver, so is the summation order
+
+size_t coarse_cg_partials(int64_t n) {
+  const int64_t iter = 4 * ((n + kCgIterRows - 1) / kCgIterRows);  // k_cg_iter's blocks
+  const int64_t persistent = 8 * ((n + 255) / 256);               // two epochs of 256-row blocks
+  const int64_t start = 4 * ((n + kCgRows - 1) / kCgRows);
+  return (size_t)std::max(iter, std::max(persistent, start));
+}
+
+// CG start kernels: one 256-thread block per 256 rows (the iteration: one per
+// 64 rows, k_cg_iter); the grids are fixed per solver, so is the summation
+// order
 static inline unsigned cg_grid(const CoarseSolver &S) {
   return (unsigned)((S.n + kCgRows - 1) / kCgRows);
 }
@@ -691,7 +708,8 @@ static void enqueue_iterations(const Ctx &c, int k, int done, hipStream_t s) {
   CoarseGrid g = cgrid(c);
   const int64_t n = c.cs->n;
   for (int it = 0; it < k; ++it) {
-    hipLaunchKernelGGL(k_cg_iter, dim3(cg_grid(*c.cs)), dim3(1024), 0, s, n, g, P, (done + it) & 1);
+    hipLaunchKernelGGL(k_cg_iter, dim3((unsigned)((n + kCgIterRows - 1) / kCgIterRows)),
+                       dim3(64 * kCgIterWaves), 0, s, n, g, P, (done + it) & 1);
     SEM_LAUNCH("k_cg_iter");
   }
 }

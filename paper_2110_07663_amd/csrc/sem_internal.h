@@ -406,6 +406,8 @@ size_t mf16_table_words(int p);
 void launch_fdm_mf16_pack(const Level &L, hipStream_t s);
 
 // coarse.hip
+// doubles of block partials the coarse Jacobi-PCG kernels need for n unknowns
+size_t coarse_cg_partials(int64_t n);
 bool coarse_assembled_ok(const Ctx &c, const Level &C);
 void coarse_setup(Ctx &c, Level &C, hipStream_t s);
 // The coarse right side as the restriction leaves it, before its

@@ -234,7 +234,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     S.r2 = A.take<double>(S.n);
     S.w2 = A.take<double>(S.n);
     S.s2 = A.take<double>(S.n);
-    S.partials = A.take<double>(8 * ((S.n + 255) / 256));
+    S.partials = A.take<double>(coarse_cg_partials(S.n));
     // exact block-tridiagonal solve of the p = 1 level (chosen, or by size)
     {
       const int64_t nx = m->nex + 1, ny = m->ney + 1, nz = m->nez + 1;
