@@ -110,6 +110,13 @@ def kernels_mode(a):
         for _ in range(a.reps):
             s16.apply_S(u32, out=v32)
         s16.close()
+    # the FP32 Ax reading FP16 geometric factors (p = 7)
+    og = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, smoother_prec=sem.F32,
+                       lambda_override=[2.0, 2.0], geom_prec=sem.F16)
+    sg = sem.Solver(n, n, n, wl.layer_shift_vertices(n, seed=3), 1, p, opts=og)
+    for _ in range(a.reps):
+        sg.apply_A(u32, out=v32)
+    sg.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(a.reps):
@@ -560,10 +567,11 @@ def main():
     def note(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    def make(prec, fdm_prec=None):
+    def make(prec, fdm_prec=None, geom_prec=sem.F32):
         opts = sem.make_opts(schedule=sched, smoother=sem.SMOOTH_RAS, cheb_order=2,
                              smoother_prec=prec, krylov=sem.KRYLOV_FCG, coarse_tol=a.coarse_tol,
-                             coarse_solver=coarse, fdm_prec=fdm_prec if fdm_prec else prec)
+                             coarse_solver=coarse, fdm_prec=fdm_prec if fdm_prec else prec,
+                             geom_prec=geom_prec)
         t0 = time.perf_counter()
         s = sem.Solver(n, n, n, xyz, 1, p, opts=opts)
         torch.cuda.synchronize()
@@ -647,11 +655,15 @@ def main():
                     "frac": round(fdm_k["TFLOPs"] / FP32_MATRIX_PEAK_TFLOPS, 4),
                     "traffic": TRAFFIC_32CUBE_P7.get("fdm") if (n, p) == (32, 7) else None}
 
-    # plain FP64 solve, and the FDM contractions in FP16 / BF16 on the matrix cores
+    # plain FP64 solve, the FDM contractions in FP16 / BF16 on the matrix cores,
+    # the smoother's A reading FP16 geometric factors, and both FP16 options
     if not a.no_fp64:
-        for name, prec, fp in (("fp64", sem.F64, None), ("fp16_fdm", sem.F32, sem.F16),
-                               ("bf16_fdm", sem.F32, sem.BF16)):
-            sm, _ = make(prec, fp)
+        for name, prec, fp, gp in (("fp64", sem.F64, None, sem.F32),
+                                   ("fp16_fdm", sem.F32, sem.F16, sem.F32),
+                                   ("bf16_fdm", sem.F32, sem.BF16, sem.F32),
+                                   ("fp16_geom", sem.F32, None, sem.F16),
+                                   ("fp16_fdm_geom", sem.F32, sem.F16, sem.F16)):
+            sm, _ = make(prec, fp, gp)
             sm.solve(b, rtol=1e-8, maxit=200)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

@@ -161,11 +161,24 @@ __device__ __forceinline__ void st(T *p, T v) {
 // dotp[e].  For u consistent and zero on Dirichlet nodes the element shares add
 // up to (u, Au) over the unique free nodes, the product the gather-scatter
 // completes (the copies of a node sum to its assembled row).
-template <typename T, bool NT, bool XF>
+//
+// GH (FP32 only): the factors come as FP16 pairs G16[e][c][point] = (G_2c,
+// G_2c+1) scaled by 2^s per element, and the element's result is multiplied by
+// gsc[e] = 2^-s before the x-face sums and the store.
+__device__ __forceinline__ float half_lo(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+template <typename T, bool NT, bool XF, bool GH = false>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
                                          const T *__restrict__ G, const T *__restrict__ Dg,
                                          T *__restrict__ v, int nv, T *sD, T (*sU)[72],
-                                         T (*sR)[72], T (*sS)[72], double *dotp = nullptr) {
+                                         T (*sR)[72], T (*sS)[72], double *dotp = nullptr,
+                                         const uint32_t *__restrict__ G16 = nullptr,
+                                         const float *__restrict__ gsc = nullptr) {
   constexpr int N = 8, NN = 64, N3 = 512, RS = 9;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 7, j = lane >> 3;
@@ -184,7 +197,8 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
     Dj[l] = sD[j * N + l];
   }
   const T *ue = u + e * N3 + lane;
-  const T *Ge = G + e * 6 * N3 + lane;
+  const T *Ge = GH ? nullptr : G + e * 6 * N3 + lane;
+  const uint32_t *He = GH ? G16 + e * 3 * N3 + lane : nullptr;
   T uk[N], acc[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -194,9 +208,18 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
   T *su = sU[w], *sr = sR[w], *ss = sS[w];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const T g0 = ld<NT>(Ge + 0 * N3 + k * NN), g1 = ld<NT>(Ge + 1 * N3 + k * NN);
-    const T g2 = ld<NT>(Ge + 2 * N3 + k * NN), g3 = ld<NT>(Ge + 3 * N3 + k * NN);
-    const T g4 = ld<NT>(Ge + 4 * N3 + k * NN), g5 = ld<NT>(Ge + 5 * N3 + k * NN);
+    T g0, g1, g2, g3, g4, g5;
+    if constexpr (GH) {
+      const uint32_t h01 = ld<NT>(He + 0 * N3 + k * NN), h23 = ld<NT>(He + 1 * N3 + k * NN);
+      const uint32_t h45 = ld<NT>(He + 2 * N3 + k * NN);
+      g0 = half_lo(h01); g1 = half_hi(h01);
+      g2 = half_lo(h23); g3 = half_hi(h23);
+      g4 = half_lo(h45); g5 = half_hi(h45);
+    } else {
+      g0 = ld<NT>(Ge + 0 * N3 + k * NN); g1 = ld<NT>(Ge + 1 * N3 + k * NN);
+      g2 = ld<NT>(Ge + 2 * N3 + k * NN); g3 = ld<NT>(Ge + 3 * N3 + k * NN);
+      g4 = ld<NT>(Ge + 4 * N3 + k * NN); g5 = ld<NT>(Ge + 5 * N3 + k * NN);
+    }
     su[j * RS + i] = uk[k];
     __builtin_amdgcn_wave_barrier();
     T ur = 0, us = 0, ut = 0;
@@ -222,6 +245,11 @@ __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
     }
     acc[k] += a;
     __builtin_amdgcn_wave_barrier();
+  }
+  if constexpr (GH) {
+    const float sc = gsc[e];
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k] *= sc;
   }
   if (dotp) {  // fixed order: the lane's k-line, then a butterfly over the wave
     double d = 0.0;
@@ -271,6 +299,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   ax8_body<float, NT, XF>(E, u, G, Dg, v, nv, sD, sU, sR, sS);
 }
 
+template <bool NT, bool XF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ax8_f32h(
+    int64_t E, const float *__restrict__ u, const uint32_t *__restrict__ G16,
+    const float *__restrict__ gsc, const float *__restrict__ Dg, float *__restrict__ v, int nv) {
+  __shared__ float sD[64], sU[4][72], sR[4][72], sS[4][72];
+  ax8_body<float, NT, XF, true>(E, u, nullptr, Dg, v, nv, sD, sU, sR, sS, nullptr, G16, gsc);
+}
+
 template <typename T, bool XF>
 static void ax8_launch(const Level &L, const T *u, T *v, const T *G, const T *D, int nv,
                        hipStream_t s, double *dotp) {
@@ -283,6 +319,13 @@ static void ax8_launch(const Level &L, const T *u, T *v, const T *G, const T *D,
     else
       hipLaunchKernelGGL((k_ax8_f64<false, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv,
                          dotp);
+  } else if (L.G16) {  // FP16 factors
+    if (nt)
+      hipLaunchKernelGGL((k_ax8_f32h<true, XF>), grid, dim3(256), 0, s, L.E, u, L.G16, L.gscale,
+                         D, v, nv);
+    else
+      hipLaunchKernelGGL((k_ax8_f32h<false, XF>), grid, dim3(256), 0, s, L.E, u, L.G16, L.gscale,
+                         D, v, nv);
   } else {
     if (nt)
       hipLaunchKernelGGL((k_ax8_f32<true, XF>), grid, dim3(256), 0, s, L.E, u, G, D, v, nv);

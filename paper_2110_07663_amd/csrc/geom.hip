@@ -150,6 +150,42 @@ void launch_geom(const Ctx &c, Level &L, int *bad, hipStream_t s) {
   SEM_LAUNCH("k_geom");
 }
 
+// FP16 storage of an element's factors for the FP32 smoother's A: one
+// wavefront per element takes the largest |G| of the element's six factors,
+// scales them all by 2^s so that it falls in [2^13, 2^14) (FP16's largest
+// finite value is 65504), and stores pairs (G0,G1), (G2,G3), (G4,G5) rounded
+// to nearest; gscale[e] = 2^-s.  A power of two commutes with FP32 rounding, so
+// scaling the product instead of every factor gives the same result.
+__global__ __launch_bounds__(256) void k_geom16(int64_t E, int N3, const double *__restrict__ G,
+                                                uint32_t *__restrict__ G16,
+                                                float *__restrict__ gscale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= E) return;  // whole wave
+  const double *Ge = G + e * 6 * N3;
+  double mx = 0.0;
+  for (int q = lane; q < 6 * N3; q += 64) mx = fmax(mx, fabs(Ge[q]));
+  for (int sh = 32; sh > 0; sh >>= 1) mx = fmax(mx, __shfl_xor(mx, sh, 64));
+  int ex = 0;
+  if (mx > 0.0) frexp(mx, &ex);  // mx < 2^ex
+  const int sh = 14 - ex;
+  if (lane == 0) gscale[e] = (float)ldexp(1.0, -sh);
+  for (int q = lane; q < N3; q += 64)
+    for (int c = 0; c < 3; ++c) {
+      const _Float16 a = (_Float16)ldexp(Ge[(2 * c) * N3 + q], sh);
+      const _Float16 b = (_Float16)ldexp(Ge[(2 * c + 1) * N3 + q], sh);
+      G16[(e * 3 + c) * N3 + q] = (uint32_t)__builtin_bit_cast(uint16_t, a) |
+                                  ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+    }
+}
+
+void launch_geom16(Level &L, hipStream_t s) {
+  if (!L.G16) return;
+  hipLaunchKernelGGL(k_geom16, dim3(nblocks(L.E, 4)), dim3(256), 0, s, L.E, L.N * L.N * L.N,
+                     (const double *)L.G64, L.G16, L.gscale);
+  SEM_LAUNCH("k_geom16");
+}
+
 void launch_boxlen(const Ctx &c, Level &L, hipStream_t s) {
   (void)c;
   hipLaunchKernelGGL(k_boxlen, dim3(nblocks(L.E, 256)), dim3(256), 0, s, L.E, L.N, L.X, L.boxlen);

@@ -112,6 +112,8 @@ struct Level {
   double *X = nullptr;     // [3][nloc] node coordinates
   double *G64 = nullptr;   // [E][6][N3] (rr, rs, rt, ss, st, tt)
   float *G32 = nullptr;    // FP32 copy for the smoother
+  uint32_t *G16 = nullptr;  // FP16 pairs (G0,G1), (G2,G3), (G4,G5): [E][3][N^3], scaled per element
+  float *gscale = nullptr;  // [E]: the power of two that undoes an element's G16 scaling
   double *BL = nullptr;    // [nloc] diagonal mass (finest level)
   double *w64 = nullptr;   // [nloc] mask / multiplicity (dot weight, RAS weight)
   float *w32 = nullptr;
@@ -271,6 +273,7 @@ void launch_interp(int pc, int pf, const double *xic, const double *xif, double 
 void launch_level_coords(const Ctx &c, const double *xyz_in, int p_geom, const double *Jg,
                          Level &L, hipStream_t s);
 void launch_geom(const Ctx &c, Level &L, int *bad_flag, hipStream_t s);
+void launch_geom16(Level &L, hipStream_t s);  // FP16 copy of G for the FP32 smoother (p = 7)
 void launch_boxlen(const Ctx &c, Level &L, hipStream_t s);
 void launch_rhs(const Level &L, const double *f, double *b, hipStream_t s);
 

@@ -98,6 +98,10 @@ static void validate(const sem_mesh *m, int p, const int8_t *bc, const sem_opts 
   if (o->batch_rhs < 0 || o->batch_rhs > 64) fail(SEM_EINVAL, "batch_rhs must be in [0, 64]");
   if (o->coarse_solver < -1 || o->coarse_solver > 1) fail(SEM_EINVAL, "coarse_solver must be in [-1, 1]");
   if (o->proj_max < 0 || o->proj_max > 32) fail(SEM_EINVAL, "proj_max must be in [0, 32]");
+  if (o->geom_prec != SEM_F32 && o->geom_prec != SEM_F16)
+    fail(SEM_EINVAL, "geom_prec must be SEM_F32 or SEM_F16");
+  if (o->geom_prec == SEM_F16 && o->smoother_prec != SEM_F32)
+    fail(SEM_EINVAL, "FP16 geometric factors need smoother_prec = SEM_F32");
   for (int f = 0; f < 6; ++f)
     if (bc[f] != 0 && bc[f] != 1) fail(SEM_EINVAL, "bc flags must be 0 or 1");
   int64_t E = (int64_t)m->nex * m->ney * m->nez;
@@ -133,6 +137,10 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     L.X = A.take<double>(3 * L.nloc);
     L.G64 = A.take<double>(6 * L.nloc);
     if (lowp) L.G32 = A.take<float>(6 * L.nloc);
+    if (lowp && o.geom_prec == SEM_F16 && L.N == 8 && smoothed) {
+      L.G16 = A.take<uint32_t>(3 * L.nloc);
+      L.gscale = A.take<float>(L.E);
+    }
     if (L.fine) L.BL = A.take<double>(L.nloc);
     if (L.fine) L.dotpart = A.take<double>(L.E);
     L.w64 = A.take<double>(L.nloc);
@@ -861,6 +869,7 @@ static void setup(Ctx &c, const sem_mesh *m, void *ws, size_t bytes, hipStream_t
     launch_interp(m->p_geom, L.p, sc.xig, L.xi, sc.Jg, nullptr, s);
     launch_level_coords(c, sc.xyz, m->p_geom, sc.Jg, L, s);
     launch_geom(c, L, sc.bad, s);
+    launch_geom16(L, s);
     sc.gs.off = 0;
     build_gather_scatter(c, L, sc.gs, s);
     launch_weights(L, s);
@@ -1263,6 +1272,7 @@ void sem_default_opts(sem_opts *o) {
   o->batch_rhs = 0;
   o->coarse_solver = -1;
   o->proj_max = 0;
+  o->geom_prec = SEM_F32;
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }

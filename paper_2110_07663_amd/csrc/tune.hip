@@ -62,15 +62,22 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
   req->rtol = 1e-8;
   req->maxit = 200;
   const int smoothers[3] = {SEM_SMOOTH_ASM, SEM_SMOOTH_RAS, SEM_SMOOTH_JACOBI};
-  const int precs[3][2] = {{SEM_F64, SEM_F64}, {SEM_F32, SEM_F32}, {SEM_F32, SEM_F16}};
+  // (smoother, FDM contraction inputs, geometric factors at p = 7); the FP16
+  // factors only matter to the one-wavefront Ax shapes (ax_variant 1, 2)
+  const int precs[4][3] = {{SEM_F64, SEM_F64, SEM_F32},
+                           {SEM_F32, SEM_F32, SEM_F32},
+                           {SEM_F32, SEM_F16, SEM_F32},
+                           {SEM_F32, SEM_F32, SEM_F16}};
   const int nax = p == 7 ? 3 : 1;
   for (int sm = 0; sm < 3; ++sm) {
     const TuneSched &t = smoothers[sm] == SEM_SMOOTH_JACOBI ? jac : sch;
     if (smoothers[sm] != SEM_SMOOTH_JACOBI && t.n > 1 && t.p[t.n - 2] < 2) continue;
     for (int order = 1; order <= 3; ++order)
-      for (int pr = 0; pr < 3; ++pr) {
+      for (int pr = 0; pr < 4; ++pr) {
         if (smoothers[sm] == SEM_SMOOTH_JACOBI && precs[pr][1] == SEM_F16) continue;
-        for (int ax = 0; ax < nax; ++ax) {
+        const bool g16 = precs[pr][2] == SEM_F16;
+        if (g16 && p != 7) continue;
+        for (int ax = g16 ? 1 : 0; ax < nax; ++ax) {
           if (req->ncand >= SEM_TUNE_MAX) return SEM_OK;
           sem_opts o = *base;
           o.precond = SEM_PRECOND_PMG;
@@ -80,6 +87,7 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
           o.cheb_order = order;
           o.smoother_prec = precs[pr][0];
           o.fdm_prec = precs[pr][1];
+          o.geom_prec = precs[pr][2];
           o.ax_variant = nax > 1 ? ax : -1;
           for (int l = 0; l < 8; ++l) o.lambda_override[l] = 0.0;
           req->cand[req->ncand++] = o;

@@ -50,7 +50,8 @@ class Opts(ctypes.Structure):
                 ("krylov", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxit", ctypes.c_int32),
                 ("ax_variant", ctypes.c_int32), ("batch_rhs", ctypes.c_int32),
-                ("coarse_solver", ctypes.c_int32), ("proj_max", ctypes.c_int32)]
+                ("coarse_solver", ctypes.c_int32), ("proj_max", ctypes.c_int32),
+                ("geom_prec", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -225,7 +226,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
               lmax_fac=1.1, arnoldi_steps=10, seed=0, lambda_override=None, smoother_prec=F64,
               fdm_prec=F64, krylov=KRYLOV_FCG, gmres_restart=20, coarse_tol=1e-10,
               coarse_maxit=2000, precond=PRECOND_PMG, ax_variant=-1, batch_rhs=0,
-              coarse_solver=-1, proj_max=0):
+              coarse_solver=-1, proj_max=0, geom_prec=F32):
     o = default_opts()
     o.nlevels = len(schedule)
     for l, p in enumerate(schedule):
@@ -243,6 +244,7 @@ def make_opts(schedule=(7, 3, 1), smoother=SMOOTH_JACOBI, cheb_order=2, lmin_fac
     o.batch_rhs = batch_rhs
     o.coarse_solver = coarse_solver
     o.proj_max = proj_max
+    o.geom_prec = geom_prec
     return o
 
 

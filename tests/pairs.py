@@ -33,7 +33,7 @@ class Pair:
                  cheb_order=2, lambda_override=None, smoother_prec=sem.F64, fdm_prec=sem.F64,
                  krylov=sem.KRYLOV_FCG, coarse_tol=1e-10, coarse_maxit=2000, seed=0,
                  precond=sem.PRECOND_PMG, oracle=True, lmin_fac=0.1, lmax_fac=1.1,
-                 gmres_restart=20, coarse="pcg", proj_max=0):
+                 gmres_restart=20, coarse="pcg", proj_max=0, geom_prec=sem.F32):
         nex, ney, nez = (n, n, n) if np.isscalar(n) else n
         self.shape = (nex, ney, nez)
         schedule = tuple(schedule) if schedule else (p,)
@@ -57,7 +57,7 @@ class Pair:
                              coarse_maxit=coarse_maxit, seed=seed, precond=precond,
                              lmin_fac=lmin_fac, lmax_fac=lmax_fac, gmres_restart=gmres_restart,
                              coarse_solver={"pcg": sem.COARSE_PCG, "dense": sem.COARSE_DIRECT}[coarse],
-                             proj_max=proj_max)
+                             proj_max=proj_max, geom_prec=geom_prec)
         self.gpu = sem.Solver(nex, ney, nez, xyz_g, pg, p, bc=bc, opts=opts)
         self.ora = None
         if oracle:

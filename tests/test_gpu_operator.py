@@ -99,6 +99,42 @@ def test_apply_A_fp32(p):
     assert rel_err(Ag, Ao) < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(4, 3, 2), (5, 2, 3)])
+def test_apply_A_fp16_geometry(shape):
+    """The FP32 product with the geometric factors stored in FP16 (p = 7).
+
+    Each stored factor is the FP64 one scaled by a power of two and rounded to
+    nearest in FP16, so it is within 2^-11 of it, relative.  By the sum
+    factorisation of Sec. 2.1, the error of every entry of Au is then at most
+    2^-11 times the same product taken over absolute values,
+    mask * QQ^T (|D|^T |G| |D| |u|), plus the FP32 arithmetic's own share.  A
+    factor read in the wrong slot, or an element left unscaled, breaks the
+    bound by orders of magnitude.
+    """
+    t = __import__("torch")
+    from oracle import gll as og
+    from oracle.geom import reference_gradient
+    from oracle.operator import G_full
+    # level 0 must be a smoothed level (the coarsest keeps FP32 factors)
+    P = Pair(shape, 7, mesh="sin", schedule=(7, 1), smoother_prec=sem.F32, geom_prec=sem.F16)
+    g, o = P.random_local(11, masked=True)
+    Ag = host(P.gpu.apply_A(g.to(t.float32)))
+    lev = P.ora.levels[0]
+    Ao = lev.apply_A(o)
+    Dabs = np.abs(og.gll(7)[2])
+    ga = reference_gradient(Dabs, np.abs(o))
+    Gf = G_full([np.abs(c) for c in lev.G])
+    w = [sum(Gf[a][b] * ga[b] for b in range(3)) for a in range(3)]
+    va = np.einsum('li,ekjl->ekji', Dabs, w[0])
+    va += np.einsum('mj,ekmi->ekji', Dabs, w[1])
+    va += np.einsum('nk,enji->ekji', Dabs, w[2])
+    bound = (lev.num.mask * lev.num.QQt(va)).reshape(-1)
+    err = np.abs(Ag - Ao.reshape(-1))
+    assert np.all(err <= (2.0 ** -11 + 1e-5) * bound + 1e-7 * bound.max())
+    # the rounding is really there: above the FP32 path's 1e-5 (test_apply_A_fp32)
+    assert 1e-5 < rel_err(Ag, Ao) < 2e-3
+
+
 def test_apply_A_neumann_annihilates_constants():
     t = __import__("torch")
     P = Pair(3, 6, mesh="sin", bc=(0,) * 6, oracle=False)

@@ -273,6 +273,27 @@ def test_solve_with_direct_coarse():
     assert abs(info.iters - res.iters) <= 1
 
 
+@pytest.mark.parametrize("shape", [4, (3, 2, 2)])
+def test_solve_fp16_geometry(shape):
+    """FP32 Cheby-RAS pMG whose A at p = 7 reads FP16 geometric factors (with
+    x-face sums in the Ax kernel when nex is a multiple of 4, without them
+    otherwise): the FP64 outer FCG still reaches 1e-8 measured with the oracle's
+    A, in at most one iteration more than with FP32 factors."""
+    base = dict(mesh="sin", schedule=(7, 3, 1), smoother="ras", smoother_prec=sem.F32,
+                coarse="dense")
+    P = Pair(shape, 7, geom_prec=sem.F16, **base)
+    P32 = Pair(shape, 7, oracle=False, **base)
+    bg, bo = _rhs(P)
+    xg, info = P.gpu.solve(bg, rtol=1e-8, maxit=100)
+    _, info32 = P32.gpu.solve(bg, rtol=1e-8, maxit=100)
+    assert info.converged and info.true_rel_res <= 1e-8
+    L = P.ora.fine
+    x = host(xg).reshape(bo.shape)
+    r = bo - L.apply_A(x)
+    assert np.sqrt(L.wdot(r, r) / L.wdot(bo, bo)) <= 1e-8
+    assert info.iters <= info32.iters + 1
+
+
 def test_jacobi_pcg_config1_small():
     """Plain Jacobi-PCG on the undeformed cube, p = 3 (the oracle-size workload)."""
     P = Pair(4, 3, mesh="box", krylov=sem.KRYLOV_PCG, precond=sem.PRECOND_JACOBI)

@@ -60,6 +60,18 @@ def test_host_side_validation_without_gpu():
     n_plain = ctypes.c_size_t(0)
     assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o), ctypes.byref(n_plain)) == sem.SEM_OK
     assert n_proj.value >= n_plain.value + 20 * 8 * 8 ** 3 * 8  # 20 vectors of E (p+1)^3 doubles
+    # FP16 geometric factors: only under the FP32 smoother; 12 more bytes per p = 7 point
+    o_g16 = sem.make_opts(schedule=(7, 3, 1), smoother_prec=sem.F64, geom_prec=sem.F16)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_g16), ctypes.byref(n)) == sem.SEM_EINVAL
+    assert b"geom" in L.sem_last_error().lower()
+    o_g16.geom_prec = 7
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_g16), ctypes.byref(n)) == sem.SEM_EINVAL
+    o_f32 = sem.make_opts(schedule=(7, 3, 1), smoother_prec=sem.F32)
+    o_g16 = sem.make_opts(schedule=(7, 3, 1), smoother_prec=sem.F32, geom_prec=sem.F16)
+    n_f32, n_g16 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_f32), ctypes.byref(n_f32)) == sem.SEM_OK
+    assert L.sem_plan(ctypes.byref(mesh), 7, bc, ctypes.byref(o_g16), ctypes.byref(n_g16)) == sem.SEM_OK
+    assert n_g16.value >= n_f32.value + 8 * 8 ** 3 * 12
     bad_bc = (ctypes.c_int8 * 6)(1, 1, 2, 1, 1, 1)
     assert L.sem_plan(ctypes.byref(mesh), 7, bad_bc, ctypes.byref(o), ctypes.byref(n)) == sem.SEM_EINVAL
     # plan grows with the problem
@@ -87,12 +99,15 @@ def test_tune_space_follows_the_papers_table():
                 assert o.fdm_prec != sem.F16
             else:
                 assert sched == short
-            seen.add((o.smoother, o.cheb_order, o.smoother_prec, o.fdm_prec, o.ax_variant))
+            if o.geom_prec == sem.F16:  # FP16 factors: p = 7, one-wavefront Ax, FP32 smoother
+                assert p == 7 and o.ax_variant >= 1 and o.smoother_prec == sem.F32
+            seen.add((o.smoother, o.cheb_order, o.smoother_prec, o.fdm_prec, o.ax_variant,
+                      o.geom_prec))
         assert len(seen) == req.ncand  # no duplicates
         orders = {s[1] for s in seen}
         assert orders == {1, 2, 3}
         assert {s[0] for s in seen} == {sem.SMOOTH_ASM, sem.SMOOTH_RAS, sem.SMOOTH_JACOBI}
-        assert req.ncand == (72 if p == 7 else 24)
+        assert req.ncand == (90 if p == 7 else 24)
     # plan covers the largest candidate
     import numpy as np
     from paper_2110_07663_amd import workloads as wl
