@@ -141,22 +141,25 @@ def test_autotuner_picks_a_converged_fast_candidate():
     assert info.converged
 
 
-@pytest.mark.parametrize("shape,p,sched,sm,prec,fdm,coarse", [
-    ((3, 3, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO),
+@pytest.mark.parametrize("shape,p,sched,sm,prec,fdm,coarse,geom", [
+    ((3, 3, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO, sem.F32),
     # four elements along x: the FDM and Ax sum their in-workgroup x-faces
-    ((4, 2, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO),
-    ((2, 3, 3), 5, (5, 3, 1), sem.SMOOTH_RAS, sem.F32, sem.BF16, sem.COARSE_AUTO),
-    ((3, 2, 2), 5, (5, 1), sem.SMOOTH_ASM, sem.F64, None, sem.COARSE_AUTO),
-    ((2, 2, 3), 4, (4, 2, 1), sem.SMOOTH_JACOBI, sem.F32, None, sem.COARSE_PCG),
+    ((4, 2, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO, sem.F32),
+    ((2, 3, 3), 5, (5, 3, 1), sem.SMOOTH_RAS, sem.F32, sem.BF16, sem.COARSE_AUTO, sem.F32),
+    ((3, 2, 2), 5, (5, 1), sem.SMOOTH_ASM, sem.F64, None, sem.COARSE_AUTO, sem.F32),
+    ((2, 2, 3), 4, (4, 2, 1), sem.SMOOTH_JACOBI, sem.F32, None, sem.COARSE_PCG, sem.F32),
+    # FP16 geometric factors in the p = 7 smoother's A, with and without x-face sums
+    ((3, 3, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, None, sem.COARSE_AUTO, sem.F16),
+    ((4, 2, 2), 7, (7, 3, 1), sem.SMOOTH_RAS, sem.F32, sem.F16, sem.COARSE_AUTO, sem.F16),
 ])
-def test_joint_lanes_equal_lanes_in_turn(monkeypatch, shape, p, sched, sm, prec, fdm, coarse):
+def test_joint_lanes_equal_lanes_in_turn(monkeypatch, shape, p, sched, sm, prec, fdm, coarse, geom):
     """The right sides of one problem sharing each operator application and
     V-cycle (nv vectors per launch) give bit-for-bit the results of running the
     lanes one at a time (same iteration counts, same iterates), both converged."""
     import torch
     freqs = [(1, 1, 1), (2, 1, 3), (1, 3, 2)]
     opts = sem.make_opts(schedule=sched, smoother=sm, smoother_prec=prec, batch_rhs=len(freqs),
-                         coarse_solver=coarse, fdm_prec=fdm if fdm else prec)
+                         coarse_solver=coarse, fdm_prec=fdm if fdm else prec, geom_prec=geom)
     xyz = wl.sampled_mesh(*shape, sem.gll_nodes(p)[0], wl.sin_map(0.05))
     S = sem.Solver(*shape, xyz, p, p, opts=opts)
     X = host(S.coords(0))
