@@ -114,12 +114,12 @@ typedef struct {
                               /* sides, Sec. 3.2 / 4.2) and stops at ||r|| <= rtol ||b||; */
                               /* 0: off (the default).  At most 32.                       */
   int32_t geom_prec;          /* storage of the geometric factors G (Sec. 2.1) that the   */
-                              /* FP32 smoother's A reads on p = 7 levels: SEM_F32 (the    */
-                              /* default) or SEM_F16 (12 instead of 24 bytes per point:   */
-                              /* each element's six factors scaled by one power of two    */
-                              /* and rounded to FP16, the products still in FP32; about   */
-                              /* 5e-4 relative error per factor).  SEM_F16 needs          */
-                              /* smoother_prec = SEM_F32; other levels keep FP32 G.       */
+                              /* FP32 smoother's A reads on its smoothed levels: SEM_F32  */
+                              /* (the default) or SEM_F16 (12 instead of 24 bytes per     */
+                              /* point: each element's six factors scaled by one power of */
+                              /* two and rounded to FP16, the products still in FP32;     */
+                              /* at most 2^-11 relative error per factor).  SEM_F16 needs */
+                              /* smoother_prec = SEM_F32; the coarsest level keeps FP32.  */
 } sem_opts;
 
 typedef struct {

@@ -35,11 +35,24 @@ __device__ inline unsigned rhs_block(int nv, int &vec) {
   return split_rhs(xcd_block(), nv, vec);
 }
 
-template <int N, typename T>
+// FP16 geometric factors (FP32 smoother, geom_prec = SEM_F16): pairs
+// G16[e][c][point] = (G_2c, G_2c+1) scaled by 2^s per element; the element's
+// result is multiplied by gsc[e] = 2^-s, which commutes with FP32 rounding.
+__device__ __forceinline__ float half_lo(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// GH: the factors come from G16 / gsc instead of G (FP32 only)
+template <int N, typename T, bool GH>
 __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__restrict__ u,
                                                        const T *__restrict__ G,
                                                        const T *__restrict__ Dg,
-                                                       T *__restrict__ v, int nv) {
+                                                       T *__restrict__ v, int nv,
+                                                       const uint32_t *__restrict__ G16,
+                                                       const float *__restrict__ gsc) {
   using S = AxShape<N>;
   constexpr int NN = S::NN, N3 = S::N3, EPB = S::EPB, RS = S::RS, PS = S::PS;
   __shared__ T sD[NN];
@@ -94,14 +107,24 @@ __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__res
   // phase 3: t derivative in registers, h = G g; h_r, h_s to LDS, h_t stays
   T wt[N];
   if (active) {
-    const T *Ge = G + e * 6 * N3 + ij;
+    const T *Ge = GH ? nullptr : G + e * 6 * N3 + ij;
+    const uint32_t *He = GH ? G16 + e * 3 * N3 + ij : nullptr;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       T ut = 0;
 #pragma unroll
       for (int l = 0; l < N; ++l) ut += sD[k * N + l] * uk[l];
-      const T g0 = Ge[0 * N3 + k * NN], g1 = Ge[1 * N3 + k * NN], g2 = Ge[2 * N3 + k * NN];
-      const T g3 = Ge[3 * N3 + k * NN], g4 = Ge[4 * N3 + k * NN], g5 = Ge[5 * N3 + k * NN];
+      T g0, g1, g2, g3, g4, g5;
+      if constexpr (GH) {
+        const uint32_t h01 = He[0 * N3 + k * NN], h23 = He[1 * N3 + k * NN];
+        const uint32_t h45 = He[2 * N3 + k * NN];
+        g0 = half_lo(h01); g1 = half_hi(h01);
+        g2 = half_lo(h23); g3 = half_hi(h23);
+        g4 = half_lo(h45); g5 = half_hi(h45);
+      } else {
+        g0 = Ge[0 * N3 + k * NN]; g1 = Ge[1 * N3 + k * NN]; g2 = Ge[2 * N3 + k * NN];
+        g3 = Ge[3 * N3 + k * NN]; g4 = Ge[4 * N3 + k * NN]; g5 = Ge[5 * N3 + k * NN];
+      }
       s_a[le][k * PS + j * RS + i] = g0 * ur[k] + g1 * us[k] + g2 * ut;
       s_b[le][k * PS + j * RS + i] = g1 * ur[k] + g3 * us[k] + g4 * ut;
       wt[k] = g2 * ur[k] + g4 * us[k] + g5 * ut;
@@ -126,6 +149,7 @@ __global__ __launch_bounds__(AxShape<N>::BS) void k_ax(int64_t E, const T *__res
       acc += Dj[l] * s_b[le][k * PS + l * RS + i];
       acc += sD[l * N + k] * wt[l];
     }
+    if constexpr (GH) acc *= gsc[e];
     ve[k * NN] = acc;
   }
 }
@@ -162,15 +186,8 @@ __device__ __forceinline__ void st(T *p, T v) {
 // up to (u, Au) over the unique free nodes, the product the gather-scatter
 // completes (the copies of a node sum to its assembled row).
 //
-// GH (FP32 only): the factors come as FP16 pairs G16[e][c][point] = (G_2c,
-// G_2c+1) scaled by 2^s per element, and the element's result is multiplied by
-// gsc[e] = 2^-s before the x-face sums and the store.
-__device__ __forceinline__ float half_lo(uint32_t w) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-}
-__device__ __forceinline__ float half_hi(uint32_t w) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
-}
+// GH (FP32 only): the factors come as FP16 pairs from G16, and the element's
+// result is multiplied by gsc[e] before the x-face sums and the store.
 
 template <typename T, bool NT, bool XF, bool GH = false>
 __device__ __forceinline__ void ax8_body(int64_t E, const T *__restrict__ u,
@@ -350,7 +367,16 @@ static void ax_n(const Level &L, const T *u, T *v, const T *G, const T *D, int n
   if (xf) fail(SEM_EINVAL, "x-face summation in Ax needs the p = 7 one-wave kernel");
   using S = AxShape<N>;
   unsigned grid = (unsigned)((L.E + S::EPB - 1) / S::EPB * nv);
-  hipLaunchKernelGGL((k_ax<N, T>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v, nv);
+  if constexpr (sizeof(T) == 4) {
+    if (L.G16) {  // FP16 factors
+      hipLaunchKernelGGL((k_ax<N, float, true>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v,
+                         nv, (const uint32_t *)L.G16, (const float *)L.gscale);
+      SEM_LAUNCH("k_ax");
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_ax<N, T, false>), dim3(grid), dim3(S::BS), 0, s, L.E, u, G, D, v, nv,
+                     (const uint32_t *)nullptr, (const float *)nullptr);
   SEM_LAUNCH("k_ax");
 }
 

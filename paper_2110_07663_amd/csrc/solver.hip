@@ -137,7 +137,7 @@ static void layout(Ctx &c, const sem_mesh *m, Arena &A, SetupScratch &sc) {
     L.X = A.take<double>(3 * L.nloc);
     L.G64 = A.take<double>(6 * L.nloc);
     if (lowp) L.G32 = A.take<float>(6 * L.nloc);
-    if (lowp && o.geom_prec == SEM_F16 && L.N == 8 && smoothed) {
+    if (lowp && o.geom_prec == SEM_F16 && smoothed) {
       L.G16 = A.take<uint32_t>(3 * L.nloc);
       L.gscale = A.take<float>(L.E);
     }

@@ -62,8 +62,9 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
   req->rtol = 1e-8;
   req->maxit = 200;
   const int smoothers[3] = {SEM_SMOOTH_ASM, SEM_SMOOTH_RAS, SEM_SMOOTH_JACOBI};
-  // (smoother, FDM contraction inputs, geometric factors at p = 7); the FP16
-  // factors only matter to the one-wavefront Ax shapes (ax_variant 1, 2)
+  // (smoother, FDM contraction inputs, geometric factors of the smoothed
+  // levels); at p = 7 the FP16 factors are tried with the one-wavefront Ax
+  // shapes (ax_variant 1, 2) only, which keeps the space within SEM_TUNE_MAX
   const int precs[4][3] = {{SEM_F64, SEM_F64, SEM_F32},
                            {SEM_F32, SEM_F32, SEM_F32},
                            {SEM_F32, SEM_F16, SEM_F32},
@@ -76,8 +77,7 @@ sem_status sem_tune_space(int32_t p, const sem_opts *base, sem_tune_request *req
       for (int pr = 0; pr < 4; ++pr) {
         if (smoothers[sm] == SEM_SMOOTH_JACOBI && precs[pr][1] == SEM_F16) continue;
         const bool g16 = precs[pr][2] == SEM_F16;
-        if (g16 && p != 7) continue;
-        for (int ax = g16 ? 1 : 0; ax < nax; ++ax) {
+        for (int ax = g16 && nax > 1 ? 1 : 0; ax < nax; ++ax) {
           if (req->ncand >= SEM_TUNE_MAX) return SEM_OK;
           sem_opts o = *base;
           o.precond = SEM_PRECOND_PMG;

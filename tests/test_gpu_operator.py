@@ -99,9 +99,10 @@ def test_apply_A_fp32(p):
     assert rel_err(Ag, Ao) < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(4, 3, 2), (5, 2, 3)])
-def test_apply_A_fp16_geometry(shape):
-    """The FP32 product with the geometric factors stored in FP16 (p = 7).
+@pytest.mark.parametrize("shape,p", [((4, 3, 2), 7), ((5, 2, 3), 7), ((3, 2, 2), 5), ((2, 3, 2), 3)])
+def test_apply_A_fp16_geometry(shape, p):
+    """The FP32 product with the geometric factors stored in FP16 (the
+    one-wavefront kernel at p = 7, the slab kernel otherwise).
 
     Each stored factor is the FP64 one scaled by a power of two and rounded to
     nearest in FP16, so it is within 2^-11 of it, relative.  By the sum
@@ -116,12 +117,12 @@ def test_apply_A_fp16_geometry(shape):
     from oracle.geom import reference_gradient
     from oracle.operator import G_full
     # level 0 must be a smoothed level (the coarsest keeps FP32 factors)
-    P = Pair(shape, 7, mesh="sin", schedule=(7, 1), smoother_prec=sem.F32, geom_prec=sem.F16)
+    P = Pair(shape, p, mesh="sin", schedule=(p, 1), smoother_prec=sem.F32, geom_prec=sem.F16)
     g, o = P.random_local(11, masked=True)
     Ag = host(P.gpu.apply_A(g.to(t.float32)))
     lev = P.ora.levels[0]
     Ao = lev.apply_A(o)
-    Dabs = np.abs(og.gll(7)[2])
+    Dabs = np.abs(og.gll(p)[2])
     ga = reference_gradient(Dabs, np.abs(o))
     Gf = G_full([np.abs(c) for c in lev.G])
     w = [sum(Gf[a][b] * ga[b] for b in range(3)) for a in range(3)]
