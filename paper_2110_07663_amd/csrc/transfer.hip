@@ -26,6 +26,17 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf_, int Nc_, const T *__re
   const int Nc3 = Nc * Nc * Nc, Nf3 = Nf * Nf * Nf;
   xc += blockIdx.y * (int64_t)gridDim.x * Nc3;  // right side blockIdx.y
   xf += blockIdx.y * (int64_t)gridDim.x * Nf3;
+  // two neighbouring fine points per thread when the element has 512: their
+  // old values are requested first (streamed, no reuse) and arrive while the
+  // contractions run
+  constexpr bool two = NF > 0 && NF * NF * NF == 2 * 256;
+  using T2 = T __attribute__((ext_vector_type(2)));
+  T2 *dst = nullptr;
+  T2 old{};
+  if constexpr (two) {
+    dst = reinterpret_cast<T2 *>(xf + e * Nf3 + 2 * tid);
+    old = __builtin_nontemporal_load(dst);
+  }
   for (int t = tid; t < Nf * Nc; t += bs) sJ[t] = J[t];
   for (int t = tid; t < Nc3; t += bs) a[t] = xc[e * Nc3 + t];
   __syncthreads();
@@ -48,8 +59,8 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf_, int Nc_, const T *__re
   }
   __syncthreads();
   // xf[k][j][i] += sum_c J[k][c] a[c][j][i]
-  if constexpr (NF > 0 && (NF * NF) % 2 == 0 && NF * NF * NF == 2 * 256) {
-    // two neighbouring points per thread (same k), one 2-wide load and store
+  if constexpr (two) {
+    // the thread's two points share k (NF^2 is even), one 2-wide store
     const int t = 2 * tid, ji = t % (NF * NF), k = t / (NF * NF);
     T s0 = 0, s1 = 0;
 #pragma unroll
@@ -57,12 +68,9 @@ __global__ __launch_bounds__(256) void k_prolong(int Nf_, int Nc_, const T *__re
       s0 += sJ[k * NC + q] * a[q * NF * NF + ji];
       s1 += sJ[k * NC + q] * a[q * NF * NF + ji + 1];
     }
-    using T2 = T __attribute__((ext_vector_type(2)));
-    T2 *dst = reinterpret_cast<T2 *>(xf + e * Nf3 + t);
-    T2 v = *dst;
-    v[0] += s0;
-    v[1] += s1;
-    *dst = v;
+    old[0] += s0;
+    old[1] += s1;
+    __builtin_nontemporal_store(old, dst);
   } else {
     for (int t = tid; t < Nf3; t += bs) {
       int ji = t % (Nf * Nf), k = t / (Nf * Nf);
