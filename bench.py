@@ -134,8 +134,8 @@ def batch_run(a, oracle_lanes=True):
     sinusoidal map, E = side^3 with side in {8, 12, 16, 24} and p in {5, 7, 9}
     drawn by seed 5, each with 4 sinusoidal right sides of random frequencies
     1..4; mixed precision Cheby-RAS pMG, tol 1e-8.  The auto-tuner picks the
-    Chebyshev order and the Ax kernel shape per (p, side) bucket on its first
-    problem.  Reports the time of the batched solve (one recorded graph per
+    Chebyshev order, the Ax kernel shape and the storage of the geometric
+    factors (FP32 or FP16) per (p, side) bucket on its first problem.  Reports the time of the batched solve (one recorded graph per
     outer iteration of all 4*nprob lanes) against solving every lane in turn,
     and the FP64 oracle's residual of the lanes of the four smallest problems."""
     import torch
@@ -164,15 +164,17 @@ def batch_run(a, oracle_lanes=True):
             req.ncand = 0
             for order in (1, 2, 3):
                 for av in ((0, 1) if p == 7 else (-1,)):
-                    o = sem.make_opts(schedule=sched_of[p], smoother=sem.SMOOTH_RAS,
-                                      cheb_order=order, smoother_prec=sem.F32, batch_rhs=4,
-                                      ax_variant=av)
-                    req.cand[req.ncand] = o
-                    req.ncand += 1
+                    for gp in (sem.F32, sem.F16):
+                        o = sem.make_opts(schedule=sched_of[p], smoother=sem.SMOOTH_RAS,
+                                          cheb_order=order, smoother_prec=sem.F32, batch_rhs=4,
+                                          ax_variant=av, geom_prec=gp)
+                        req.cand[req.ncand] = o
+                        req.ncand += 1
             t0 = time.perf_counter()
             best, res, _ = sem.tune(side, side, side, xyz, p, p, b0, request=req, repeats=1)
             t_tune += time.perf_counter() - t0
             note(f"tuned p={p} side={side}: order {best.cheb_order} ax {best.ax_variant} "
+                 f"geom {'f16' if best.geom_prec == sem.F16 else 'f32'} "
                  f"({time.perf_counter() - t0:.1f} s)")
             probe.close()
             best.batch_rhs = 4
@@ -258,7 +260,8 @@ def batch_run(a, oracle_lanes=True):
            "worst_true_rel_res": worst, "all_converged": all(i.converged for i in infos),
            "iters_batched_max": max(i.iters for i in infos),
            "iters_sequential_max": max(iters_seq), "tune_s": round(t_tune, 2),
-           "tuned": {f"p{k[0]}_side{k[1]}": {"cheb_order": v.cheb_order, "ax_variant": v.ax_variant}
+           "tuned": {f"p{k[0]}_side{k[1]}": {"cheb_order": v.cheb_order, "ax_variant": v.ax_variant,
+                                              "geom": "f16" if v.geom_prec == sem.F16 else "f32"}
                      for k, v in tuned.items()}}
     if oracle_lanes:
         # the FP64 oracle's residual of every lane of the four smallest problems
