@@ -185,7 +185,9 @@ sem_status sem_rhs(sem_ctx *ctx, const double *f_dev, double *b_dev, void *strea
 
 /* Au = mask * QQ^T A_L u on `level` (Sec. 2.1, A = Q^T A_L Q applied by sum
  * factorisation).  prec SEM_F64 (double E-vectors, FP64 G) or SEM_F32 (float
- * E-vectors, G stored in FP32).  u and Au must not alias. */
+ * E-vectors, FP32 arithmetic; G stored in FP32, or in FP16 on the smoothed
+ * levels of a context set up with geom_prec = SEM_F16).  u and Au must not
+ * alias. */
 sem_status sem_apply_A(sem_ctx *ctx, int32_t level, int32_t prec, const void *u, void *Au,
                        void *stream);
 
