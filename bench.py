@@ -399,8 +399,9 @@ def algorithmic_bytes(kind, L):
         return E * N3 * 8 * 8
     if kind == "ax32":   # FP32 u, v, G
         return E * N3 * 8 * 4
-    if kind == "fdm":    # FP32: input, RAS weight, output E-vectors; S (3 pb^2); lambda (3 pb)
-        return E * (3 * N3 * 4 + 3 * pb * pb * 4 + 3 * pb * 4)
+    if kind == "fdm":    # FP32: input and output E-vectors (and the stored RAS weight at
+        # p <= 3; from p = 4 the kernel computes it); S (3 pb^2); lambda (3 pb)
+        return E * ((2 if p >= 4 else 3) * N3 * 4 + 3 * pb * pb * 4 + 3 * pb * 4)
     if kind in ("gs32", "gs64"):
         w = 4 if kind == "gs32" else 8
         if os.environ.get("SEM_GS_SORTED") == "1":  # + index per member, offset per segment
@@ -423,10 +424,10 @@ TRAFFIC_32CUBE_P7 = {
     "ax64": 1072564224,   # k_ax8_f64<true,false> as the solve runs it (x-faces left to the FCG update)
     "ax32": 536990080,    # k_ax8_f32<true,false> (the smoother's A, 5 of 6 launches per V-cycle)
     # matrix-core RAS local solves per finest-level launch as a V-cycle mixes
-    # them: 4 x k_fdm_mf32<7,1,false,1,true,false> (262,436,075 B), 1 x the
-    # residual form <7,1,true,2,true,true> (350,971,989 B), 1 x the zero-start
-    # form <7,1,false,0,false,true> (261,656,405 B)
-    "fdm": 277062116,
+    # them: 4 x k_fdm_mf32<7,1,false,1,true,false> (192,954,816 B), 1 x the
+    # residual form <7,1,true,2,true,true> (279,285,589 B), 1 x the zero-start
+    # form <7,1,false,0,false,true> (194,233,173 B)
+    "fdm": 207556338,
 }
 # dense FP32 on the matrix cores (the FDM contractions run there)
 FP32_MATRIX_PEAK_TFLOPS = 157.3

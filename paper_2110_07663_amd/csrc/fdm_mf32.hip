@@ -128,6 +128,27 @@ __device__ inline float pow2_below(float m, int &e) {
   return m > 0.f ? __builtin_amdgcn_ldexpf(1.0f, -e) : 0.f;
 }
 
+// The RAS weight of an element's own node (Sec. 2.2.2: mask / multiplicity)
+// on the structured element grid is a product over the three directions of
+// 1 (inside the element, or on a Neumann face of the domain), 1/2 (on a face
+// shared with a neighbour) and 0 (on a Dirichlet face): exact in FP32 and
+// equal to the assembled weight, so from p = 4 on the solve computes it
+// instead of loading it (at p <= 3 the element's rows are short and one load
+// costs less than the arithmetic: 21.0 against 23.8 us per launch at p = 3).
+// bcm: bit f set when domain face f (x-, x+, y-, y+, z-, z+) is Dirichlet;
+// w: the stored weights (mask / multiplicity, an E-vector).
+struct RasW {
+  int nex, ney, nez, bcm;
+  const float *w;
+};
+template <int P>
+constexpr bool kRasWComputed = P >= 4;
+__device__ inline float ras_w1(int i, int N, int64_t c, int n, int bcm, int f) {
+  if (i == 0) return c > 0 ? 0.5f : ((bcm >> f) & 1 ? 0.f : 1.f);
+  if (i == N - 1) return c + 1 < n ? 0.5f : ((bcm >> (f + 1)) & 1 ? 0.f : 1.f);
+  return 1.f;
+}
+
 template <int P>
 struct Mf {
   static constexpr int PB = P + 3, N = P + 1, N3 = N * N * N;
@@ -313,7 +334,7 @@ template <int P, bool RS, int XS, bool YS, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_load(
     MfIn<P, RS, XS, YS> &in, int64_t e, int nex, int ney, int nez, const BufF32 &r, const BufF32 &rs,
     int64_t eb, const float *__restrict__ Sg, const float *__restrict__ lamg,
-    const float *__restrict__ W, int lane, const uint32_t *__restrict__ A16 = nullptr,
+    const RasW &W, int lane, const uint32_t *__restrict__ A16 = nullptr,
     const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, MG = F::MG, KG = F::KG;
@@ -480,7 +501,7 @@ struct MfLate {
 };
 template <int P, int OP>
 __device__ __attribute__((always_inline)) inline void mf_load_late(
-    MfLate<P> &lt, int64_t e, const float *__restrict__ Sg, const float *__restrict__ W,
+    MfLate<P> &lt, int64_t e, const float *__restrict__ Sg, const RasW &W,
     const uint32_t *__restrict__ A16, const float *__restrict__ ssc, int lane) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, KG = F::KG;
@@ -503,17 +524,34 @@ __device__ __attribute__((always_inline)) inline void mf_load_late(
       for (int d = 0; d < 2; ++d) lt.Ab[d][u] = Se.ld(at + d * PB * PB * 4);
     }
   }
+  if constexpr (kRasWComputed<P>) {
+    int64_t ex, ey, ez;
+    elem_coords(e, W.nex, W.ney, ex, ey, ez);
 #pragma unroll
-  for (int s = 0; s < F::SX; ++s) {
-    const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
-    const int64_t row = e * N3 + (int64_t)lc * N;
+    for (int s = 0; s < F::SX; ++s) {
+      const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
+      const int j = lc % N, k = lc / N;
+      const float wjk = ras_w1(j, N, ey, W.ney, W.bcm, 2) * ras_w1(k, N, ez, W.nez, W.bcm, 4);
 #pragma unroll
-    for (int g = 0; g < F::KG; ++g) {
-      if constexpr (N % 4 == 0) {
-        lt.wrow[s][g] = *reinterpret_cast<const mf4_t *>(W + row + 4 * g);
-      } else {
+      for (int g = 0; g < F::KG; ++g)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lt.wrow[s][g][i] = 4 * g + i < N ? W[row + 4 * g + i] : 0.f;
+        for (int i = 0; i < 4; ++i)
+          lt.wrow[s][g][i] = 4 * g + i < N ? wjk * ras_w1(4 * g + i, N, ex, W.nex, W.bcm, 0) : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < F::SX; ++s) {
+      const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
+      const int64_t row = e * N3 + (int64_t)lc * N;
+#pragma unroll
+      for (int g = 0; g < F::KG; ++g) {
+        if constexpr (N % 4 == 0) {
+          lt.wrow[s][g] = *reinterpret_cast<const mf4_t *>(W.w + row + 4 * g);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            lt.wrow[s][g][i] = 4 * g + i < N ? W.w[row + 4 * g + i] : 0.f;
+        }
       }
     }
   }
@@ -530,7 +568,7 @@ template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 __device__ __attribute__((always_inline)) inline void mf_solve(
     const MfIn<P, RS, XS, YS> &in, int64_t e, const float *__restrict__ lamg, float *__restrict__ z,
     float *buf, int lane, float *xfx, int wave, const float *__restrict__ Sg,
-    const float *__restrict__ W, const uint32_t *__restrict__ A16 = nullptr,
+    const RasW &W, const uint32_t *__restrict__ A16 = nullptr,
     const float *__restrict__ ssc = nullptr) {
   using F = Mf<P>;
   constexpr int PB = F::PB, N = F::N, N3 = F::N3, LS = F::LS, MG = F::MG, KG = F::KG;
@@ -782,8 +820,8 @@ __device__ __attribute__((always_inline)) inline void mf_solve(
   mf_sync();  // the next element's first pass rewrites the buffer
 }
 
-// r, rs (RS: solve on r - rs), S and lambda of the level (FP32), W = RAS
-// weight (mask / multiplicity), z = output E-vector(s).  Each wavefront
+// r, rs (RS: solve on r - rs), S and lambda of the level (FP32), W = the
+// grid and Dirichlet faces that give the RAS weight, z = output E-vector(s).  Each wavefront
 // solves C consecutive elements, loading the next element's inputs before it
 // solves the current one, so that the loads of one overlap the other's work.
 template <int P, int C, bool RS, int XS, bool YS, bool XF>
@@ -792,7 +830,7 @@ __global__ __launch_bounds__(256) void k_fdm_mf32(int64_t E, int nex, int ney, i
                                                   const float *__restrict__ rs,
                                                   const float *__restrict__ Sg,
                                                   const float *__restrict__ lamg,
-                                                  const float *__restrict__ W,
+                                                  RasW W,
                                                   float *__restrict__ z, int nv) {
   using F = Mf<P>;
   constexpr int N3 = F::N3;
@@ -842,7 +880,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 6))) voi
                                                   const uint32_t *__restrict__ A16,
                                                   const float *__restrict__ ssc,
                                                   const float *__restrict__ lamg,
-                                                  const float *__restrict__ W,
+                                                  RasW W,
                                                   float *__restrict__ z, int nv) {
   using F = Mf<P>;
   constexpr int N3 = F::N3;
@@ -866,6 +904,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 6))) voi
   mf_solve<P, RS, XS, YS, XF, OP>(in, e, lamg, z, buf, lane, xfx, wave, nullptr, W, A16, ssc);
 }
 
+static RasW ras_w(const Level &L) {
+  RasW w{L.nex, L.ney, L.nez, 0, L.w32};
+  for (int f = 0; f < 6; ++f) w.bcm |= (L.bc[f] ? 1 : 0) << f;
+  return w;
+}
+
 template <int P, bool RS, int XS, bool YS, bool XF, int OP = kOpF32>
 void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs, float *z,
                    hipStream_t s, int nv) {
@@ -876,7 +920,7 @@ void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs
     if (!L.A16 || !L.sscale) fail(SEM_EINVAL, "16-bit FDM data were not built");
     const dim3 grid((unsigned)((L.E + F::WAVES - 1) / F::WAVES * nv));
     hipLaunchKernelGGL((k_fdm_mf16<P, RS, XS, YS, XF, OP>), grid, dim3(64 * F::WAVES), 0, s, L.E,
-                       c.nex, c.ney, c.nez, r, rs, L.A16, L.sscale, L.lam32, L.w32, z, nv);
+                       c.nex, c.ney, c.nez, r, rs, L.A16, L.sscale, L.lam32, ras_w(L), z, nv);
     SEM_LAUNCH("k_fdm_mf16");
   } else {
     const int C = XF ? 1 : c.fdm_mf32_chain;
@@ -886,13 +930,13 @@ void mf32_launch_x(const Ctx &c, const Level &L, const float *r, const float *rs
     const dim3 block(64 * F::WAVES);
     if constexpr (XF) {
       hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, true>), grid, block, 0, s, L.E, c.nex,
-                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, ras_w(L), z, nv);
     } else if (C == 2) {
       hipLaunchKernelGGL((k_fdm_mf32<P, 2, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
-                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, ras_w(L), z, nv);
     } else {
       hipLaunchKernelGGL((k_fdm_mf32<P, 1, RS, XS, YS, false>), grid, block, 0, s, L.E, c.nex,
-                         c.ney, c.nez, r, rs, L.S32, L.lam32, L.w32, z, nv);
+                         c.ney, c.nez, r, rs, L.S32, L.lam32, ras_w(L), z, nv);
     }
     SEM_LAUNCH("k_fdm_mf32");
   }
