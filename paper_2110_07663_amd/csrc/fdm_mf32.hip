@@ -128,11 +128,9 @@ __device__ inline float pow2_below(float m, int &e) {
   return m > 0.f ? __builtin_amdgcn_ldexpf(1.0f, -e) : 0.f;
 }
 
-// The RAS weight of an element's own node (Sec. 2.2.2: mask / multiplicity)
-// on the structured element grid is a product over the three directions of
-// 1 (inside the element, or on a Neumann face of the domain), 1/2 (on a face
-// shared with a neighbour) and 0 (on a Dirichlet face): exact in FP32 and
-// equal to the assembled weight, so from p = 4 on the solve computes it
+// The RAS weight of an element's own node (Sec. 2.2.2: mask / multiplicity,
+// node_w1 per direction) is exact in FP32 and equal to the assembled weight,
+// so from p = 4 on the solve computes it
 // instead of loading it (at p <= 3 the element's rows are short and one load
 // costs less than the arithmetic: 21.0 against 23.8 us per launch at p = 3).
 // bcm: bit f set when domain face f (x-, x+, y-, y+, z-, z+) is Dirichlet;
@@ -143,11 +141,6 @@ struct RasW {
 };
 template <int P>
 constexpr bool kRasWComputed = P >= 4;
-__device__ inline float ras_w1(int i, int N, int64_t c, int n, int bcm, int f) {
-  if (i == 0) return c > 0 ? 0.5f : ((bcm >> f) & 1 ? 0.f : 1.f);
-  if (i == N - 1) return c + 1 < n ? 0.5f : ((bcm >> (f + 1)) & 1 ? 0.f : 1.f);
-  return 1.f;
-}
 
 template <int P>
 struct Mf {
@@ -531,12 +524,12 @@ __device__ __attribute__((always_inline)) inline void mf_load_late(
     for (int s = 0; s < F::SX; ++s) {
       const int l = 64 * s + lane, lc = l < F::NLX ? l : 0;
       const int j = lc % N, k = lc / N;
-      const float wjk = ras_w1(j, N, ey, W.ney, W.bcm, 2) * ras_w1(k, N, ez, W.nez, W.bcm, 4);
+      const float wjk = node_w1(j, N, ey, W.ney, W.bcm, 2) * node_w1(k, N, ez, W.nez, W.bcm, 4);
 #pragma unroll
       for (int g = 0; g < F::KG; ++g)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          lt.wrow[s][g][i] = 4 * g + i < N ? wjk * ras_w1(4 * g + i, N, ex, W.nex, W.bcm, 0) : 0.f;
+          lt.wrow[s][g][i] = 4 * g + i < N ? wjk * node_w1(4 * g + i, N, ex, W.nex, W.bcm, 0) : 0.f;
     }
   } else {
 #pragma unroll

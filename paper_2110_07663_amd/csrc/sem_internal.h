@@ -41,6 +41,18 @@ __device__ inline void elem_coords(int64_t e, int nex, int ney, int64_t &ex, int
   ez = q / (unsigned)ney;
 }
 
+// The weight of a level's local node, mask / multiplicity, on the structured
+// element grid: a product over the three directions of 1 (inside the
+// element, or on a Neumann face of the domain), 1/2 (on a face shared with a
+// neighbour) and 0 (on a Dirichlet face), exact in floating point and equal
+// to the assembled weight.  Per-direction factor of index i (0..N-1) in the
+// element at grid position c of n; bcm bit f (f + 1) set when the low (high)
+// domain face of the direction is Dirichlet.
+__device__ inline float node_w1(int i, int N, int64_t c, int n, int bcm, int f) {
+  if (i == 0) return c > 0 ? 0.5f : ((bcm >> f) & 1 ? 0.f : 1.f);
+  if (i == N - 1) return c + 1 < n ? 0.5f : ((bcm >> (f + 1)) & 1 ? 0.f : 1.f);
+  return 1.f;
+}
 // Workgroups are dispatched to the device's 8 XCDs round-robin (block b runs on
 // XCD b % 8), and each XCD has its own L2.  Kernels whose blocks read their
 // neighbours' data (gather-scatter segments, Schwarz boxes) renumber their
