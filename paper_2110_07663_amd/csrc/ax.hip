@@ -5,7 +5,9 @@
 //   h = G g                         3x3 symmetric factors (6 per point)
 //   v = D_r^T h_r + D_s^T h_s + D_t^T h_t
 //
-// Layout: u, v E-vectors [E][N][N][N] (i fastest); G [E][6][N^3].
+// Layout: u, v E-vectors [E][N][N][N] (i fastest); G [E][6][N^3], or for
+// the FP32 smoother optionally G16 [E][3][N^3] FP16 pairs with a power-of-two
+// scale per element (12 instead of 24 bytes per point).
 // Mapping: one (i, j) column per thread with the t-line (k) in registers, so
 // only the r and s contractions go through LDS; N^2 threads per element, EPB
 // elements per workgroup.  Every G entry, u and v value is touched once per

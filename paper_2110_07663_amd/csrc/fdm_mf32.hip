@@ -130,11 +130,11 @@ __device__ inline float pow2_below(float m, int &e) {
 
 // The RAS weight of an element's own node (Sec. 2.2.2: mask / multiplicity,
 // node_w1 per direction) is exact in FP32 and equal to the assembled weight,
-// so from p = 4 on the solve computes it
-// instead of loading it (at p <= 3 the element's rows are short and one load
-// costs less than the arithmetic: 21.0 against 23.8 us per launch at p = 3).
-// bcm: bit f set when domain face f (x-, x+, y-, y+, z-, z+) is Dirichlet;
-// w: the stored weights (mask / multiplicity, an E-vector).
+// so from p = 4 on the solve computes it instead of loading it (at p <= 3
+// the element's rows are short and one load costs less than the arithmetic:
+// 21.0 against 23.8 us per launch at p = 3).  bcm: bit f set when domain
+// face f (x-, x+, y-, y+, z-, z+) is Dirichlet; w: the stored weights
+// (an E-vector), read at p <= 3.
 struct RasW {
   int nex, ney, nez, bcm;
   const float *w;
